@@ -1,0 +1,167 @@
+"""Pins of oracle.fixed: integer tables, error bounds, closed forms, roundtrip."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fixed as F
+from oracle import fp as P
+from oracle import transforms as T
+from oracle.adjust import round_half_away
+from tests import cfgs
+
+SIZES = [4, 8, 16, 32, 64]
+
+
+def test_rs_and_clip_worked_values():
+    # RS(v, s) = floor((v + 2^(s-1)) / 2^s): half rounds up (towards +inf)
+    v = np.array([5, -5, 6, -6, 7, -7, 0, 1, -1])
+    assert F.rs(v, 1).tolist() == [3, -2, 3, -3, 4, -3, 0, 1, 0]
+    assert F.rs(v, 2).tolist() == [1, -1, 2, -1, 2, -2, 0, 0, 0]
+    assert F.rs(v, 0).tolist() == v.tolist()
+    assert F.clip16(np.array([40000, -40000, 5])).tolist() == [32767, -32768, 5]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_integer_table_invariants(n):
+    c2 = F.int_table("C2", n)
+    # DC row is exactly 2^m: 2^m sqrt(N) sqrt(2/N) / sqrt2 = 2^m
+    assert (c2[0] == 256).all()
+    # row symmetry: T[k][N-1-n] = (-1)^k T[k][n]
+    for k in range(n):
+        assert (c2[k, ::-1] == ((-1) ** k) * c2[k]).all()
+    # nesting: even rows of size N are the rows of size N/2 (left half)
+    if n > 4:
+        half = F.int_table("C2", n // 2)
+        assert (c2[0::2, : n // 2] == half).all()
+    # magnitude bound 2^m sqrt2 = 362.04; the largest entry is row 1, column 0
+    assert np.abs(c2).max() == c2[1, 0] <= 362
+    # derived DST-2/DST-3 equal their own directly rounded formulas
+    for kind in ("S2", "S3", "C3"):
+        direct = round_half_away(256.0 * np.sqrt(n) * T.matrix(kind, n))
+        assert (F.int_table(kind, n) == direct).all(), kind
+    # DCT-8 integer table equals S DST-7_int R (eq. 3 on the rounded tables)
+    s, r = T.signs(n).astype(np.int64), T.reversal(n).astype(np.int64)
+    assert (F.int_table("C8", n) == s @ F.int_table("S7", n) @ r).all()
+
+
+def _rational_and_bound(x, ax_h, ax_v, bd, m, a, inverse=False):
+    """Un-rounded product of the integer stages (exact rational, in FP64) and
+    the worst-case propagated rounding error (0.5 LSB per stage, amplified by
+    the later stages' absolute row sums)."""
+    nb, h, w = x.shape
+    s1, s2, s3, s4 = F.shifts(int(np.log2(w)), int(np.log2(h)), bd, m)
+    sh, sv = F.forward_stages(ax_h, w, m, a), F.forward_stages(ax_v, h, m, a)
+    if inverse:
+        seq = [("v", st.T, s3 if r == "core" else a) for st, r in reversed(sv)] + \
+              [("h", st.T, s4 if r == "core" else a) for st, r in reversed(sh)]
+    else:
+        seq = [("h", st, s1 if r == "core" else a) for st, r in sh] + \
+              [("v", st, s2 if r == "core" else a) for st, r in sv]
+    v = x.astype(np.float64)
+    err = 0.0
+    for axis, mat, s in seq:
+        mf = mat.astype(np.float64) / (2.0 ** s)
+        if axis == "h":
+            v = np.einsum("bij,kj->bik", v, mf)
+        else:
+            v = np.einsum("kj,bji->bki", mf, v)
+        err = np.abs(mf).sum(axis=1).max() * err + 0.5
+    return v, err
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2", "cfg3", "c2plain", "s7direct"])
+def test_fixed_equals_rational_within_rounding_bound(params, which, rng):
+    if which == "cfg1":
+        ax_h, ax_v = cfgs.cfg1(params); n = 16
+    elif which == "cfg2":
+        ax_h, ax_v = cfgs.cfg2(params); n = 32
+    elif which == "cfg3":
+        ax_h, ax_v = cfgs.cfg3(params); n = 64
+    elif which == "c2plain":
+        ax_h = ax_v = cfgs.plain_axis("C2"); n = 32
+    else:
+        ax_h = ax_v = cfgs.plain_axis("S7"); n = 16
+    x = synth.ar1_blocks(24, n, n, 0.95, 16.0, seed=7)
+    y = F.fwd2d(x, ax_h, ax_v)
+    ref, bound = _rational_and_bound(x, ax_h, ax_v, 8, 8, 10)
+    assert np.abs(ref).max() < 32767          # no clipping on this data
+    d = y - ref
+    assert np.abs(d).max() <= bound + 1e-9
+    assert abs(d.mean()) < 0.1                 # round-to-nearest, unbiased
+    xi = F.inv2d(y, ax_h, ax_v)
+    ref, bound = _rational_and_bound(y, ax_h, ax_v, 8, 8, 10, inverse=True)
+    assert np.abs(xi - ref).max() <= bound + 1e-9
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2", "cfg3"])
+def test_fixed_tracks_fp64_transform(params, which):
+    # forward gain 2^(15-bd)/sqrt(WH): the integer result is the FP64 adjusted
+    # transform scaled, up to table/parameter quantisation
+    ax_h, ax_v = {"cfg1": cfgs.cfg1, "cfg2": cfgs.cfg2, "cfg3": cfgs.cfg3}[which](params)
+    n = {"cfg1": 16, "cfg2": 32, "cfg3": 64}[which]
+    x = synth.ar1_blocks(16, n, n, 0.95, 16.0, seed=3)
+    y = F.fwd2d(x, ax_h, ax_v)
+    g = 2.0 ** (15 - 8) / n
+    yf = g * P.fwd2d(x, ax_h, ax_v)
+    rel = np.abs(y - yf).max() / np.abs(yf).max()
+    assert rel < 5e-3
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_constant_block_dct2_closed_form(n):
+    # a constant block c through the plain 2-D DCT-2 gives only a DC value;
+    # row pass: RS(N * c * 2^m, s1); column pass: RS(N * dc1 * 2^m, s2)
+    c = 200
+    x = np.full((1, n, n), c, np.int16)
+    ax = cfgs.plain_axis("C2")
+    y = F.fwd2d(x, ax, ax)
+    l2 = int(np.log2(n))
+    s1, s2 = l2 + 8 + 8 - 15, l2 + 8
+    dc1 = (n * c * 256 + (1 << (s1 - 1))) >> s1
+    dc = (n * dc1 * 256 + (1 << (s2 - 1))) >> s2
+    assert y[0, 0, 0] == dc
+    # other outputs vanish up to the rounding of the even rows' sums
+    rest = y.copy()
+    rest[0, 0, 0] = 0
+    assert np.abs(rest).max() <= 1
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2", "cfg3"])
+def test_roundtrip_statistics(params, which):
+    ax_h, ax_v = {"cfg1": cfgs.cfg1, "cfg2": cfgs.cfg2, "cfg3": cfgs.cfg3}[which](params)
+    n = {"cfg1": 16, "cfg2": 32, "cfg3": 64}[which]
+    x = synth.ar1_blocks(32, n, n, 0.95, 16.0, seed=11)
+    xr = F.inv2d(F.fwd2d(x, ax_h, ax_v), ax_h, ax_v)
+    err = np.abs(xr - x)
+    assert err.max() <= 8
+    assert err.mean() < 0.5
+
+
+@pytest.mark.parametrize("kind", ["pos", "neg", "checker", "full16", "extreme16"])
+def test_adversarial_inputs_stay_in_range_and_headroom(params, kind):
+    # the headroom assertion inside the oracle must hold for any int16 input
+    ax_h, ax_v = cfgs.cfg2(params)
+    x = synth.adversarial_blocks(32, 32, kind)
+    y = F.fwd2d(x, ax_h, ax_v)
+    assert y.min() >= -32768 and y.max() <= 32767
+    z = F.inv2d(x, ax_h, ax_v)
+    assert z.min() >= -32768 and z.max() <= 32767
+
+
+def test_flip_band_equals_flipped_matrices(params):
+    # adjusted DCT-8 by flip: integer stages compose to S (B_int A_int) R
+    ax = cfgs.band_axis(params, "S3", 16, 4, flip=True)
+    st = F.forward_stages(ax, 16, 8, 10)
+    ax0 = cfgs.band_axis(params, "S3", 16, 4, flip=False)
+    st0 = F.forward_stages(ax0, 16, 8, 10)
+    s, r = T.signs(16).astype(np.int64), T.reversal(16).astype(np.int64)
+    assert (st[1][0] @ st[0][0] == s @ st0[1][0] @ st0[0][0] @ r).all()
+
+
+def test_single_pass_headroom_holds_for_all_int16():
+    # worst case: every input at +-32768 aligned with the row signs
+    for n in SIZES:
+        for kind in ("C2", "C3", "S7"):
+            t = F.int_table(kind, n)
+            assert int(np.abs(t).sum(axis=1).max()) * 32768 < (1 << 31)
