@@ -1,0 +1,143 @@
+/*
+ * tadj.h -- C ABI of libtadj: batched separable 2-D adjusted DCT/DST
+ * transforms of residual blocks on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (Said, Egilmez, Chao, "Low-complexity transform
+ * adjustments for video coding"):
+ *   eq. 1        H = C B A approximates a desired transform D (DST-7/DCT-8),
+ *                B in {DCT-2, DCT-3, DST-2, DST-3} (section 2.1), A a sparse
+ *                band ("K-tap") orthogonal pre-adjustment, C a top-left
+ *                B x B sub-block orthogonal post-adjustment; only one of A, C
+ *                per axis (section 2.2).
+ *   eq. 3/4/5    DCT-8 from a DST-7 design: H -> S H R; for the sub-block
+ *                after the DCT-2 the adjustment becomes S C S.
+ *   section 2.2  separable application: every row of a W x H block by the
+ *                horizontal H_h, every column by the vertical H_v, i.e.
+ *                Y = H_v X H_h^T; the inverse is X = H_v^T Y H_h.
+ *
+ * Arithmetic.
+ *   TA_I16 (fixed point): int16 in, int32 accumulation, int16 out.  Integer
+ *   tables T_int = round_half_away(2^m sqrt(N) T) (m = 8); adjustments at
+ *   scale 2^a.  Each stage computes clip16((sum + 2^(s-1)) >> s).  Core
+ *   shifts: forward rows first with s = log2 W + bd + m - 15, then columns
+ *   with s = log2 H + m; inverse columns first with s = m + 1, then rows with
+ *   s = m + 14 - bd; adjustment stages shift by a.  The library returns the
+ *   exact integers of that definition (any int16 input).
+ *   TA_F32: the same stages in fp32 on orthonormal tables, no rounding.
+ *
+ * Layout.  Blocks are row-major (index r*W + c), int16 or fp32.  A "packed
+ * batch" is nblocks contiguous W x H blocks.  A "block list" is an array of
+ * ta_block descriptors in device memory, each naming its own offsets,
+ * strides, size and per-axis transform.
+ *
+ * Ownership.  The caller owns every input/output buffer (device memory, for
+ * example from torch).  The context owns its parameter tables (device memory
+ * allocated by ta_create / ta_set_*).  in and out must not alias.
+ *
+ * Streams.  Transform calls are asynchronous on the given hipStream_t (0 =
+ * null stream), allocate nothing, never synchronise, and may be captured in
+ * a HIP graph.  Configuration calls (ta_set_*) are synchronous.
+ *
+ * Errors.  Every call returns 0 on success or a negative TA_E* code; nothing
+ * is launched when a call fails.  ta_last_error() returns a thread-local
+ * message describing the last failure.
+ */
+#ifndef TADJ_H
+#define TADJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ta_ctx ta_ctx;
+typedef struct ihipStream_t* ta_stream_t;   /* hipStream_t */
+
+enum {
+  TA_OK = 0,
+  TA_EINVAL = -1,        /* null pointer, negative count, bad enum value, aliasing */
+  TA_EUNSUPPORTED = -2,  /* size not a power of two in 4..64, K/B out of range,
+                            combination without a kernel */
+  TA_ENOPARAMS = -3,     /* axis or parameter id not registered */
+  TA_EHIP = -4           /* HIP runtime error (message in ta_last_error) */
+};
+
+/* Data types of transform inputs/outputs. */
+enum { TA_I16 = 0, TA_F32 = 1 };
+
+/* Base transforms (section 2.1; DST-7/DCT-8 as full matrices, eq. 3). */
+enum { TA_DCT2 = 0, TA_DCT3 = 1, TA_DST2 = 2, TA_DST3 = 3, TA_DST7 = 4, TA_DCT8 = 5 };
+
+/* Adjustment kinds (eq. 1, Fig. 2): none, band A before B, sub-block C after B. */
+enum { TA_ADJ_NONE = 0, TA_ADJ_BAND = 1, TA_ADJ_POST = 2 };
+
+/* One axis of a separable transform. */
+typedef struct {
+  int32_t base;      /* TA_DCT2 .. TA_DCT8 */
+  int32_t adj;       /* TA_ADJ_* ; TA_DST7/TA_DCT8 require TA_ADJ_NONE */
+  int32_t flip;      /* 1: use S H R (the DCT-8 version of a DST-7 design, eq. 3, eq. 5) */
+  int32_t param_id;  /* parameter set for adj != NONE (ta_set_band / ta_set_post) */
+} ta_axis;
+
+/* Block descriptor for block lists (32 bytes, device memory). */
+typedef struct {
+  int64_t in_off;      /* element offset of the block's (0,0) in the input buffer */
+  int64_t out_off;     /* element offset of the block's (0,0) in the output buffer */
+  int32_t in_stride;   /* elements between rows in the input (>= W) */
+  int32_t out_stride;  /* elements between rows in the output (>= W) */
+  uint8_t log2w;       /* 2..6 */
+  uint8_t log2h;       /* 2..6 */
+  uint16_t axis_h;     /* axis id (ta_set_axis) of the horizontal (row) transform */
+  uint16_t axis_v;     /* axis id of the vertical (column) transform */
+  uint16_t reserved;
+} ta_block;
+
+/* Create a context on HIP device `device`.  bit_depth (bd) in 6..16 sets the
+ * fixed-point shifts; m (integer-matrix precision) must be 8; a (adjustment
+ * precision) in 6..14 is the scale 2^a of integer adjustment parameters. */
+int ta_create(ta_ctx** out, int device, int bit_depth, int m, int a);
+int ta_destroy(ta_ctx* ctx);
+
+/* Register a K-tap band pre-adjustment A (section 2.2 item 1, Fig. 2a) for
+ * size n (4..64), K in {2,4,6,8}, as dense row-major n x n host arrays:
+ * a_int at scale 2^a (int16) and a_f32 (orthonormal, fp32).  Row i may have
+ * non-zeros only in columns [s_i, s_i + K) with
+ * s_i = i - K/2 + ((i + K/2) mod 2), the support of K/2 layers of parallel
+ * Givens rotations on adjacent pairs (even pairs first); otherwise
+ * TA_EUNSUPPORTED.  Copied synchronously; param_id in 0..255. */
+int ta_set_band(ta_ctx* ctx, int param_id, int n, int taps,
+                const int16_t* a_int, const float* a_f32);
+
+/* Register a B x B sub-block post-adjustment Q (section 2.2 item 2, Fig. 2b):
+ * C = blkdiag(Q, I_{n-B}), 2 <= B <= n, B even; q_int at scale 2^a. */
+int ta_set_post(ta_ctx* ctx, int param_id, int n, int b,
+                const int16_t* q_int, const float* q_f32);
+
+/* Register axis configuration `axis_id` (0..255).  The size of the axis is
+ * taken from the block; parameter sets must match that size. */
+int ta_set_axis(ta_ctx* ctx, int axis_id, const ta_axis* axis);
+
+/* Forward / inverse transform of a packed batch of nblocks W x H blocks
+ * (W = 2^log2w, H = 2^log2h), horizontal axis axis_h, vertical axis_v.
+ * in/out: device pointers to nblocks*W*H elements of dtype. */
+int ta_fwd_packed(ta_ctx* ctx, int axis_h, int axis_v, int log2w, int log2h,
+                  int64_t nblocks, const void* in, void* out, int dtype, ta_stream_t stream);
+int ta_inv_packed(ta_ctx* ctx, int axis_h, int axis_v, int log2w, int log2h,
+                  int64_t nblocks, const void* in, void* out, int dtype, ta_stream_t stream);
+
+/* Select the implementation used for direct DST-7/DCT-8 axes in packed
+ * batches: 0 = automatic (MFMA where available), 1 = MFMA, 2 = VALU. */
+int ta_set_direct_impl(ta_ctx* ctx, int impl);
+
+/* Library version string. */
+const char* ta_version(void);
+
+/* Thread-local description of the last error. */
+const char* ta_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TADJ_H */

@@ -1,0 +1,183 @@
+"""Python binding of libtadj (batched 2-D adjusted DCT/DST transforms, gfx950).
+
+A thin ctypes layer over the C ABI in include/tadj.h: it marshals torch
+tensors (device memory) and the current HIP stream into the library calls.
+All transform arithmetic runs in the library's HIP kernels; if the library
+has not been built this module raises instead of falling back to anything.
+
+    import paper_2505_23618_amd as ta
+    ctx = ta.Context(device=0)
+    ids = ta.load_params(ctx)                      # frozen adjustment parameters
+    ax = ctx.axis(1, base=ta.DST3, adj=ta.ADJ_BAND, param=ids["band_S3_S7_N32_K4"])
+    y = ctx.fwd(x_int16_cuda, ax, ax)              # x: [nblocks, H, W]
+    x2 = ctx.inv(y, ax, ax)
+"""
+
+from __future__ import annotations
+
+import ctypes
+import json
+from pathlib import Path
+
+import numpy as np
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "libtadj.so"
+PARAMS_PATH = _PKG / "params" / "adjust_params.json"
+
+# enums of tadj.h
+I16, F32 = 0, 1
+DCT2, DCT3, DST2, DST3, DST7, DCT8 = range(6)
+ADJ_NONE, ADJ_BAND, ADJ_POST = range(3)
+BASES = {"C2": DCT2, "C3": DCT3, "S2": DST2, "S3": DST3, "S7": DST7, "C8": DCT8}
+
+TA_OK, TA_EINVAL, TA_EUNSUPPORTED, TA_ENOPARAMS, TA_EHIP = 0, -1, -2, -3, -4
+
+EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis",
+           "ta_fwd_packed", "ta_inv_packed", "ta_set_direct_impl", "ta_version", "ta_last_error")
+
+
+class TadjError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tadj error {code}: {msg}")
+        self.code = code
+
+
+class _Axis(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_int32), ("adj", ctypes.c_int32),
+                ("flip", ctypes.c_int32), ("param_id", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libtadj.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_23618_amd.build`")
+    L = ctypes.CDLL(str(LIB_PATH))
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    L.ta_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32]
+    L.ta_destroy.argtypes = [vp]
+    L.ta_set_band.argtypes = [vp, i32, i32, i32, vp, vp]
+    L.ta_set_post.argtypes = [vp, i32, i32, i32, vp, vp]
+    L.ta_set_axis.argtypes = [vp, i32, ctypes.POINTER(_Axis)]
+    for f in (L.ta_fwd_packed, L.ta_inv_packed):
+        f.argtypes = [vp, i32, i32, i32, i32, i64, vp, vp, i32, vp]
+    L.ta_set_direct_impl.argtypes = [vp, i32]
+    L.ta_version.restype = ctypes.c_char_p
+    L.ta_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("ta_version", "ta_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != 0:
+        raise TadjError(code, lib().ta_last_error().decode())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A libtadj context on one GPU (owns the device parameter tables)."""
+
+    def __init__(self, device: int = 0, bit_depth: int = 8, m: int = 8, a: int = 10):
+        self._h = ctypes.c_void_p()
+        _check(lib().ta_create(ctypes.byref(self._h), device, bit_depth, m, a))
+        self.device, self.bit_depth, self.m, self.a = device, bit_depth, m, a
+
+    def close(self):
+        if self._h:
+            lib().ta_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- configuration --------------------------------------------------------
+    def set_band(self, pid: int, a_int: np.ndarray, a_f32: np.ndarray, taps: int):
+        a_int = np.ascontiguousarray(a_int, dtype=np.int16)
+        a_f32 = np.ascontiguousarray(a_f32, dtype=np.float32)
+        n = a_int.shape[0]
+        _check(lib().ta_set_band(self._h, pid, n, taps, a_int.ctypes.data, a_f32.ctypes.data))
+
+    def set_post(self, pid: int, q_int: np.ndarray, q_f32: np.ndarray, n: int):
+        q_int = np.ascontiguousarray(q_int, dtype=np.int16)
+        q_f32 = np.ascontiguousarray(q_f32, dtype=np.float32)
+        _check(lib().ta_set_post(self._h, pid, n, q_int.shape[0], q_int.ctypes.data, q_f32.ctypes.data))
+
+    def axis(self, aid: int, base: int, adj: int = ADJ_NONE, flip: bool = False, param: int = 0) -> int:
+        ax = _Axis(base, adj, int(bool(flip)), param)
+        _check(lib().ta_set_axis(self._h, aid, ctypes.byref(ax)))
+        return aid
+
+    def set_direct_impl(self, impl: int):
+        _check(lib().ta_set_direct_impl(self._h, impl))
+
+    # -- transforms -------------------------------------------------------------
+    def _run(self, fn, x, axis_h, axis_v, out):
+        import torch
+        if x.dim() != 3:
+            raise ValueError("expected [nblocks, H, W]")
+        nb, h, w = x.shape
+        lw, lh = w.bit_length() - 1, h.bit_length() - 1
+        dt = {torch.int16: I16, torch.float32: F32}.get(x.dtype)
+        if dt is None:
+            raise TypeError(f"unsupported dtype {x.dtype}")
+        if not x.is_cuda:
+            raise ValueError("input must be a GPU tensor")
+        x = x.contiguous()
+        if out is None:
+            out = torch.empty_like(x)
+        _check(fn(self._h, axis_h, axis_v, lw, lh, nb, ctypes.c_void_p(x.data_ptr()),
+                  ctypes.c_void_p(out.data_ptr()), dt, _stream_handle(None)))
+        return out
+
+    def fwd(self, x, axis_h: int, axis_v: int, out=None):
+        """Forward 2-D transform of a packed batch [nblocks, H, W] (rows first)."""
+        return self._run(lib().ta_fwd_packed, x, axis_h, axis_v, out)
+
+    def inv(self, y, axis_h: int, axis_v: int, out=None):
+        """Inverse 2-D transform of a packed batch (columns first)."""
+        return self._run(lib().ta_inv_packed, y, axis_h, axis_v, out)
+
+    # raw pointer variants (no allocation; for graphs and benchmarks)
+    def fwd_ptr(self, axis_h, axis_v, log2w, log2h, nblocks, in_ptr, out_ptr, dtype, stream_handle):
+        _check(lib().ta_fwd_packed(self._h, axis_h, axis_v, log2w, log2h, nblocks,
+                                   ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr), dtype,
+                                   ctypes.c_void_p(stream_handle)))
+
+    def inv_ptr(self, axis_h, axis_v, log2w, log2h, nblocks, in_ptr, out_ptr, dtype, stream_handle):
+        _check(lib().ta_inv_packed(self._h, axis_h, axis_v, log2w, log2h, nblocks,
+                                   ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr), dtype,
+                                   ctypes.c_void_p(stream_handle)))
+
+
+def load_param_file(path: Path = PARAMS_PATH) -> dict:
+    with open(path) as f:
+        return {e["name"]: e for e in json.load(f)["entries"]}
+
+
+def load_params(ctx: Context, path: Path = PARAMS_PATH) -> dict:
+    """Register every frozen parameter set with the context; returns name -> id."""
+    ids = {}
+    for pid, (name, e) in enumerate(sorted(load_param_file(path).items())):
+        if e["kind"] == "band":
+            ctx.set_band(pid, np.asarray(e["a_int"]), np.asarray(e["a_f64"]), e["taps"])
+        else:
+            ctx.set_post(pid, np.asarray(e["q_int"]), np.asarray(e["q_f64"]), e["n"])
+        ids[name] = pid
+    return ids

@@ -1,0 +1,70 @@
+// Shared definitions of the libtadj device code (gfx950 / CDNA4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tables_gen.h"
+
+#define TA_DEV __device__ __forceinline__
+
+namespace ta {
+
+typedef short s2v __attribute__((ext_vector_type(2)));
+
+// Transform kinds of one 1-D pass (forward orientation).  The DST-2/DST-3
+// are the section 2.1 relations around the DCT-2/DCT-3 butterflies:
+//   DST-2 = R DCT-2 S,  DST-3 = S DCT-3 R;  DCT-8 = S DST-7 R (eq. 3).
+enum Core : int { C_DCT2 = 0, C_DCT3 = 1, C_DST2 = 2, C_DST3 = 3, C_DST7 = 4, C_DCT8 = 5 };
+enum Adj : int { ADJ_NONE = 0, ADJ_BAND = 1, ADJ_POST = 2 };
+
+// Transpose of a core (used by the inverse): DCT-2^T = DCT-3, DST-2^T = DST-3.
+constexpr int core_transpose(int c) {
+  return c == C_DCT2 ? C_DCT3 : c == C_DCT3 ? C_DCT2 : c == C_DST2 ? C_DST3 : c == C_DST3 ? C_DST2 : c;
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n >> 1); }
+
+// Integer DCT-2 coefficient of the N-point table (nested in the 64-point one).
+template <int N>
+TA_DEV constexpr int c2i(int k, int n) { return ta_c2_64[k * (64 / N)][n]; }
+
+template <int N>
+TA_DEV constexpr int s7i(int k, int n) {
+  if constexpr (N == 4) return ta_s7_4[k][n];
+  else if constexpr (N == 8) return ta_s7_8[k][n];
+  else if constexpr (N == 16) return ta_s7_16[k][n];
+  else if constexpr (N == 32) return ta_s7_32[k][n];
+  else return ta_s7_64[k][n];
+}
+
+template <int N>
+TA_DEV constexpr double s7f(int k, int n) {
+  if constexpr (N == 4) return ta_s7f_4[k][n];
+  else if constexpr (N == 8) return ta_s7f_8[k][n];
+  else if constexpr (N == 16) return ta_s7f_16[k][n];
+  else if constexpr (N == 32) return ta_s7f_32[k][n];
+  else return ta_s7f_64[k][n];
+}
+
+// Pack two int16 constants into a dot2 operand (lo = a, hi = b).
+TA_DEV constexpr uint32_t pk2(int a, int b) {
+  return (uint32_t)(uint16_t)(int16_t)a | ((uint32_t)(uint16_t)(int16_t)b << 16);
+}
+
+// acc + a.lo*b.lo + a.hi*b.hi, int16 x int16 products, int32 accumulation.
+TA_DEV int dot2(uint32_t a, uint32_t b, int acc) {
+  return __builtin_amdgcn_sdot2(__builtin_bit_cast(s2v, a), __builtin_bit_cast(s2v, b), acc, false);
+}
+
+// Saturating pack of two int32 into int16 lanes (lo = a, hi = b): clip16.
+TA_DEV uint32_t satpk(int a, int b) {
+  return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pk_i16(a, b));
+}
+
+// Byte permute: bytes 0-3 of `lo`, 4-7 of `hi`, selector per output byte.
+TA_DEV uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+}  // namespace ta

@@ -1,0 +1,332 @@
+// Fixed-point 1-D stages of the adjusted transforms (int16 data, int32 sums).
+//
+// Every stage computes sums of int16 x int16 products with v_dot2_i32_i16
+// (two products per instruction) or, inside the DCT-2 butterfly where the
+// operands are int32 partial sums, with 24-bit multiply-adds.  A stage's
+// result is kept as int32 sums that already include the rounding offset
+// 2^(s-1); the consumer applies ">> s" and packs two values with the
+// saturating v_cvt_pk_i16_i32, which is exactly clip16((sum + 2^(s-1)) >> s)
+// and lets the consumer choose the pairing it needs for its own dot2 operands.
+#pragma once
+
+#include "common.hpp"
+
+namespace ta {
+namespace fx {
+
+// N int16 values held as natural pairs: element 2j in the low half of p[j].
+template <int N>
+struct Packed {
+  uint32_t p[N / 2];
+  TA_DEV int value(int i) const {
+    const uint32_t w = p[i >> 1];
+    return (i & 1) ? ((int)w >> 16) : (int)(short)(w & 0xffffu);
+  }
+  // (value(i), value(j)) packed; an index of -1 stands for zero.
+  TA_DEV uint32_t pair(int i, int j) const {
+    if (i >= 0 && (i & 1) == 0 && j == i + 1) return p[i >> 1];
+    const uint32_t lo = i >= 0 ? p[i >> 1] : 0u;
+    const uint32_t hi = j >= 0 ? p[j >> 1] : 0u;
+    const uint32_t sl = i >= 0 ? ((i & 1) ? 0x0302u : 0x0100u) : 0x0c0cu;
+    const uint32_t sh = j >= 0 ? ((j & 1) ? 0x0706u : 0x0504u) : 0x0c0cu;
+    return perm(hi, lo, sl | (sh << 16));
+  }
+};
+
+// Stage result: pre-shift sums (offset included).  Elements below SPLIT
+// shift by s0, the others by s1 (a post-adjustment leaves rows >= B alone).
+template <int N, int SPLIT = N>
+struct Acc {
+  int a[N];
+  int s0, s1;
+  TA_DEV int value(int i) const { return a[i] >> (i < SPLIT ? s0 : s1); }
+  TA_DEV uint32_t pair(int i, int j) const {
+    return satpk(i >= 0 ? value(i) : 0, j >= 0 ? value(j) : 0);
+  }
+};
+
+// Elements < B come from `lo`, the rest from `hi` (inverse sub-block stage).
+template <int N, int B, class SL, class SH>
+struct Split {
+  const SL& lo;
+  const SH& hi;
+  TA_DEV int value(int i) const { return i < B ? lo.value(i) : hi.value(i); }
+  TA_DEV uint32_t pair(int i, int j) const {
+    const bool il = i < B, jl = j < B;
+    if ((i < 0 || il) && (j < 0 || jl)) return lo.pair(i, j);
+    if ((i < 0 || !il) && (j < 0 || !jl)) return hi.pair(i, j);
+    return satpk(i >= 0 ? value(i) : 0, j >= 0 ? value(j) : 0);
+  }
+};
+
+// Input view of a core: w[k] = src[N-1-k] when REV.
+template <int N, bool REV, class S>
+struct Rev {
+  const S& s;
+  TA_DEV uint32_t pair(int i, int j) const {
+    return REV ? s.pair(i >= 0 ? N - 1 - i : -1, j >= 0 ? N - 1 - j : -1) : s.pair(i, j);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Band pre-adjustment (K taps per row).  Row i of the forward band A has its
+// taps in columns [i - K/2 + ((i + K/2) & 1), +K): the support of K/2 layers
+// of Givens rotations on adjacent pairs, even pairs first.  Its transpose
+// (used by the inverse) meets the even-pair layer first, so its rows start
+// at i - K/2 + 1 - (i & 1).  taps[i*K/2 + t] holds the packed pair
+// of columns (start + 2t, start + 2t + 1), zero outside 0..N-1.
+// ---------------------------------------------------------------------------
+template <int K, bool TR>
+TA_DEV constexpr int band_start(int i) {
+  return TR ? i - K / 2 + 1 - (i & 1) : i - K / 2 + ((i + K / 2) & 1);
+}
+
+template <int N, int K, bool TR, class S>
+TA_DEV Acc<N> band(const S& src, const uint32_t* __restrict__ taps, int shift) {
+  Acc<N> r;
+  r.s0 = r.s1 = shift;
+  const int off = 1 << (shift - 1);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int st = band_start<K, TR>(i);
+    int acc = off;
+#pragma unroll
+    for (int t = 0; t < K / 2; ++t) {
+      const int c0 = st + 2 * t, c1 = c0 + 1;
+      if (c1 < 0 || c0 >= N) continue;
+      acc = dot2(src.pair(c0 >= 0 ? c0 : -1, c1 < N ? c1 : -1), taps[i * (K / 2) + t], acc);
+    }
+    r.a[i] = acc;
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// DCT-3 (inverse DCT-2) butterfly: z[n] = sum_k C2_N[k][n] w[k].
+// Even part: the N/2-point DCT-3 of w[0], w[2], ...; odd part:
+// O[n] = sum_j C2_N[2j+1][n] w[2j+1]; z[n] = E[n] + O[n], z[N-1-n] = E[n] - O[n].
+// ---------------------------------------------------------------------------
+template <int N, int M, class W>
+TA_DEV void c3_even(const W& w, int (&e)[M], int off) {
+  constexpr int ST = N / M;
+  if constexpr (M == 2) {
+    const uint32_t p = w.pair(0, ST);
+    e[0] = dot2(p, pk2(c2i<2>(0, 0), c2i<2>(1, 0)), off);
+    e[1] = dot2(p, pk2(c2i<2>(0, 1), c2i<2>(1, 1)), off);
+  } else {
+    int ee[M / 2];
+    c3_even<N, M / 2>(w, ee, off);
+#pragma unroll
+    for (int n = 0; n < M / 2; ++n) {
+      int o = 0;
+#pragma unroll
+      for (int i = 0; i < M / 4; ++i) {
+        const int k1 = 4 * i + 1, k2 = 4 * i + 3;
+        o = dot2(w.pair(k1 * ST, k2 * ST), pk2(c2i<M>(k1, n), c2i<M>(k2, n)), o);
+      }
+      e[n] = ee[n] + o;
+      e[M - 1 - n] = ee[n] - o;
+    }
+  }
+}
+
+// OSIGN applies S to the output before rounding (DST-3 = S DCT-3 R);
+// IREV reverses the input.  The rounding offset enters once per output.
+template <int N, bool IREV, bool OSIGN, class S>
+TA_DEV Acc<N> core_c3(const S& src, int shift) {
+  const Rev<N, IREV, S> w{src};
+  const int off = 1 << (shift - 1);
+  Acc<N> r;
+  r.s0 = r.s1 = shift;
+  int ee[N / 2];
+  c3_even<N, N / 2>(w, ee, OSIGN ? 0 : off);
+#pragma unroll
+  for (int n = 0; n < N / 2; ++n) {
+    const int sg = (OSIGN && (n & 1)) ? -1 : 1;
+    int o = OSIGN ? off : 0;
+#pragma unroll
+    for (int i = 0; i < N / 4; ++i) {
+      const int k1 = 4 * i + 1, k2 = 4 * i + 3;
+      o = dot2(w.pair(k1, k2), pk2(sg * c2i<N>(k1, n), sg * c2i<N>(k2, n)), o);
+    }
+    if (!OSIGN) {
+      r.a[n] = ee[n] + o;
+      r.a[N - 1 - n] = ee[n] - o;
+    } else if (sg > 0) {      // o = O + off: y_n = E + O + off, y_{N-1-n} = -(E - O) + off
+      r.a[n] = ee[n] + o;
+      r.a[N - 1 - n] = o - ee[n];
+    } else {                  // o = -O + off: y_n = -(E + O) + off, y_{N-1-n} = E - O + off
+      r.a[n] = o - ee[n];
+      r.a[N - 1 - n] = o + ee[n];
+    }
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// DCT-2 butterfly: z[k] = sum_n C2_N[k][n] x[n].  The first level works on
+// the int16 inputs with dot2 over the pairs (x[n], x[N-1-n]); deeper levels
+// work on int32 partial sums (|v| < 2^21) with 24-bit multiply-adds.
+// ---------------------------------------------------------------------------
+template <int M>
+TA_DEV void c2_int(const int (&v)[M], int (&z)[M], int off) {
+  if constexpr (M == 2) {
+    z[0] = ((v[0] + v[1]) << 8) + off;     // row 0 = 2^8
+    z[1] = ((v[0] - v[1]) << 8) + off;     // 2-point row 1 = (+2^8, -2^8)
+  } else {
+    int e[M / 2], o[M / 2];
+#pragma unroll
+    for (int n = 0; n < M / 2; ++n) {
+      e[n] = v[n] + v[M - 1 - n];
+      o[n] = v[n] - v[M - 1 - n];
+    }
+#pragma unroll
+    for (int k = 1; k < M; k += 2) {
+      int acc = off;
+#pragma unroll
+      for (int n = 0; n < M / 2; ++n) acc = __mul24(o[n], c2i<M>(k, n)) + acc;
+      z[k] = acc;
+    }
+    int ze[M / 2];
+    c2_int<M / 2>(e, ze, off);
+#pragma unroll
+    for (int k = 0; k < M / 2; ++k) z[2 * k] = ze[k];
+  }
+}
+
+// ISIGN applies S to the input, OREV reverses the output (DST-2 = R DCT-2 S).
+template <int N, bool ISIGN, bool OREV, class S>
+TA_DEV Acc<N> core_c2(const S& src, int shift) {
+  const int off = 1 << (shift - 1);
+  Acc<N> r;
+  r.s0 = r.s1 = shift;
+  uint32_t pr[N / 2];
+#pragma unroll
+  for (int n = 0; n < N / 2; ++n) pr[n] = src.pair(n, N - 1 - n);
+  int z[N];
+#pragma unroll
+  for (int k = 1; k < N; k += 2) {
+    int acc = off;
+#pragma unroll
+    for (int n = 0; n < N / 2; ++n) {
+      const int sa = (ISIGN && (n & 1)) ? -1 : 1;
+      const int sb = (ISIGN && ((N - 1 - n) & 1)) ? -1 : 1;
+      acc = dot2(pr[n], pk2(sa * c2i<N>(k, n), sb * c2i<N>(k, N - 1 - n)), acc);
+    }
+    z[k] = acc;
+  }
+  int e[N / 2];
+#pragma unroll
+  for (int n = 0; n < N / 2; ++n) {
+    const int sa = (ISIGN && (n & 1)) ? -1 : 1;
+    const int sb = (ISIGN && ((N - 1 - n) & 1)) ? -1 : 1;
+    e[n] = dot2(pr[n], pk2(sa, sb), 0);
+  }
+  int ze[N / 2];
+  c2_int<N / 2>(e, ze, off);
+#pragma unroll
+  for (int k = 0; k < N / 2; ++k) z[2 * k] = ze[k];
+#pragma unroll
+  for (int m = 0; m < N; ++m) r.a[m] = z[OREV ? N - 1 - m : m];
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Direct DST-7 / DCT-8 (full matrix, the comparison path of Table 1).
+// DCT-8[k][n] = (-1)^k DST-7[k][N-1-n] (eq. 3).  TR uses the transpose.
+// ---------------------------------------------------------------------------
+template <int N, int KIND>
+TA_DEV constexpr int dmat(int k, int n) {
+  return KIND == C_DST7 ? s7i<N>(k, n) : ((k & 1) ? -s7i<N>(k, N - 1 - n) : s7i<N>(k, N - 1 - n));
+}
+
+template <int N, int KIND, bool TR, class S>
+TA_DEV Acc<N> core_direct(const S& src, int shift) {
+  const int off = 1 << (shift - 1);
+  Acc<N> r;
+  r.s0 = r.s1 = shift;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    int acc = off;
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+      const int c0 = TR ? dmat<N, KIND>(2 * j, k) : dmat<N, KIND>(k, 2 * j);
+      const int c1 = TR ? dmat<N, KIND>(2 * j + 1, k) : dmat<N, KIND>(k, 2 * j + 1);
+      acc = dot2(src.pair(2 * j, 2 * j + 1), pk2(c0, c1), acc);
+    }
+    r.a[k] = acc;
+  }
+  return r;
+}
+
+template <int N, int CORE, bool TR, class S>
+TA_DEV Acc<N> core(const S& src, int shift) {
+  constexpr int C = (CORE == C_DST7 || CORE == C_DCT8) ? CORE : (TR ? core_transpose(CORE) : CORE);
+  if constexpr (C == C_DCT2) return core_c2<N, false, false>(src, shift);
+  else if constexpr (C == C_DST2) return core_c2<N, true, true>(src, shift);
+  else if constexpr (C == C_DCT3) return core_c3<N, false, false>(src, shift);
+  else if constexpr (C == C_DST3) return core_c3<N, true, true>(src, shift);
+  else return core_direct<N, C, TR>(src, shift);
+}
+
+// ---------------------------------------------------------------------------
+// Sub-block post-adjustment: the first B outputs become Q y_{<B}, the rest
+// pass through.  q[i*B/2 + j] holds the packed pair (Q[i][2j], Q[i][2j+1]).
+// ---------------------------------------------------------------------------
+template <int N, int B, class S>
+TA_DEV void post_rows(const S& src, const uint32_t* __restrict__ q, int shift, int (&out)[B]) {
+  const int off = 1 << (shift - 1);
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    int acc = off;
+#pragma unroll
+    for (int j = 0; j < B / 2; ++j) acc = dot2(src.pair(2 * j, 2 * j + 1), q[i * (B / 2) + j], acc);
+    out[i] = acc;
+  }
+}
+
+// One axis: compile-time core, adjustment and K (taps) or B (block).
+template <int CORE_, int ADJ_, int KB_>
+struct Axis {
+  static constexpr int CORE = CORE_, ADJ = ADJ_, KB = KB_;
+};
+
+// Run the forward (INV = false) or inverse pass of axis AX on `in`.
+// pf: forward parameters (band taps / Q pairs), pi: transposed parameters.
+template <int N, class AX, bool INV, class S>
+TA_DEV auto run_pass(const S& in, const uint32_t* __restrict__ pf, const uint32_t* __restrict__ pi,
+                     int s_core, int a) {
+  if constexpr (AX::ADJ == ADJ_NONE) {
+    return core<N, AX::CORE, INV>(in, s_core);
+  } else if constexpr (AX::ADJ == ADJ_BAND) {
+    if constexpr (!INV) {
+      const Acc<N> u = band<N, AX::KB, false>(in, pf, a);
+      return core<N, AX::CORE, false>(u, s_core);
+    } else {
+      const Acc<N> u = core<N, AX::CORE, true>(in, s_core);
+      return band<N, AX::KB, true>(u, pi, a);
+    }
+  } else {
+    constexpr int B = AX::KB;
+    if constexpr (!INV) {
+      const Acc<N> y = core<N, AX::CORE, false>(in, s_core);
+      Acc<N, B> r;
+      r.s0 = a;
+      r.s1 = s_core;
+      int z[B];
+      post_rows<N, B>(y, pf, a, z);
+#pragma unroll
+      for (int i = 0; i < N; ++i) r.a[i] = i < B ? z[i] : y.a[i];
+      return r;
+    } else {
+      Acc<B> z;
+      z.s0 = z.s1 = a;
+      post_rows<N, B>(in, pi, a, z.a);
+      const Split<N, B, Acc<B>, S> comp{z, in};
+      return core<N, AX::CORE, true>(comp, s_core);
+    }
+  }
+}
+
+}  // namespace fx
+}  // namespace ta

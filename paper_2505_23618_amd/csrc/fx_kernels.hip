@@ -1,0 +1,260 @@
+// Fixed-point packed-batch kernels: forward (rows, then columns) and inverse
+// (columns, then rows) of W x H int16 blocks.
+//
+// One 256-thread workgroup transforms a tile of NB = 256 / max(W, H) blocks.
+// Each thread owns one row in the row pass and one column in the column pass
+// and keeps the whole 1-D vector in registers.  The row/column exchange goes
+// through LDS in two layouts, chosen so that every LDS read is a full dword
+// or wider and all scattering happens on the write side (ds_write_b16 and
+// ds_write_b16_d16_hi cost no VALU work):
+//   PC ("pair-column"): dword (r/2)*PP + c of a block holds rows r, r+1 of
+//      column c, so a column thread reads its vector as natural int16 pairs;
+//      PP = W + 1 keeps the 16 pair-rows of a column in distinct banks.
+//   RM ("row-major"): row pitch W + 8 halfwords so that ds_read_b128 of
+//      consecutive rows hits distinct banks.
+// Forward: global rows -> registers -> row pass -> PC -> column pass -> RM ->
+// coalesced 16-byte stores.  Inverse: coalesced 16-byte loads -> PC ->
+// column pass -> RM -> row pass -> global rows.
+#include "fx.hpp"
+#include "kernels.hpp"
+
+namespace ta {
+namespace {
+
+template <int LW, int LH>
+struct Tile {
+  static constexpr int W = 1 << LW, H = 1 << LH;
+  static constexpr int NB = 256 / (W > H ? W : H);
+  static constexpr int PP = W + 1;
+  static constexpr int PCB = (H / 2) * PP;                 // dwords per block, PC
+  static constexpr int RP = W >= 8 ? W + 8 : W;            // halfwords per row, RM
+  static constexpr int RMB = H * RP + (W >= 8 ? 32 : 0);   // halfwords per block, RM
+  static constexpr int CH = W >= 8 ? 8 : 4;                // halfwords per global chunk
+  static constexpr int CPB = W * H / CH;                   // chunks per block
+};
+
+template <int W>
+TA_DEV void load_row(const int16_t* __restrict__ src, fx::Packed<W>& x) {
+  if constexpr (W >= 8) {
+#pragma unroll
+    for (int q = 0; q < W / 8; ++q) {
+      const uint4 v = reinterpret_cast<const uint4*>(src)[q];
+      x.p[4 * q + 0] = v.x;
+      x.p[4 * q + 1] = v.y;
+      x.p[4 * q + 2] = v.z;
+      x.p[4 * q + 3] = v.w;
+    }
+  } else {
+    const uint2 v = *reinterpret_cast<const uint2*>(src);
+    x.p[0] = v.x;
+    x.p[1] = v.y;
+  }
+}
+
+template <int W>
+TA_DEV void store_row(int16_t* __restrict__ dst, const uint32_t (&p)[W / 2]) {
+  if constexpr (W >= 8) {
+#pragma unroll
+    for (int q = 0; q < W / 8; ++q)
+      reinterpret_cast<uint4*>(dst)[q] = make_uint4(p[4 * q], p[4 * q + 1], p[4 * q + 2], p[4 * q + 3]);
+  } else {
+    *reinterpret_cast<uint2*>(dst) = make_uint2(p[0], p[1]);
+  }
+}
+
+template <int LW, int LH, class AH, class AV>
+__global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
+  using T = Tile<LW, LH>;
+  constexpr int W = T::W, H = T::H, NB = T::NB;
+  __shared__ __align__(16) uint32_t pc[NB * T::PCB];
+  __shared__ __align__(16) uint16_t rm[NB * T::RMB];
+  uint16_t* pch = reinterpret_cast<uint16_t*>(pc);
+
+  const int tid = threadIdx.x;
+  const int64_t blk0 = (int64_t)blockIdx.x * NB;
+  const int nbh = (int)min<int64_t>(NB, p.nblocks - blk0);
+  const int16_t* __restrict__ in = static_cast<const int16_t*>(p.in) + blk0 * (W * H);
+  int16_t* __restrict__ out = static_cast<int16_t*>(p.out) + blk0 * (W * H);
+  const uint32_t* ph_f = static_cast<const uint32_t*>(p.ph_f);
+  const uint32_t* ph_i = static_cast<const uint32_t*>(p.ph_i);
+  const uint32_t* pv_f = static_cast<const uint32_t*>(p.pv_f);
+  const uint32_t* pv_i = static_cast<const uint32_t*>(p.pv_i);
+
+  // row pass (horizontal transform of every row)
+  if (tid < NB * H) {
+    const int b = tid / H, r = tid % H;
+    fx::Packed<W> x;
+    if (b < nbh) {
+      load_row<W>(in + (b * H + r) * W, x);
+    } else {
+#pragma unroll
+      for (int j = 0; j < W / 2; ++j) x.p[j] = 0u;
+    }
+    const auto y = fx::run_pass<W, AH, false>(x, ph_f, ph_i, p.s_row, p.a);
+    const int base = (b * T::PCB + (r >> 1) * T::PP) * 2 + (r & 1);
+#pragma unroll
+    for (int j = 0; j < W / 2; ++j) {
+      const uint32_t v = y.pair(2 * j, 2 * j + 1);
+      pch[base + (2 * j) * 2] = (uint16_t)v;
+      pch[base + (2 * j + 1) * 2] = (uint16_t)(v >> 16);
+    }
+  }
+  __syncthreads();
+
+  // column pass (vertical transform of every column)
+  if (tid < NB * W) {
+    const int b = tid / W, c = tid % W;
+    fx::Packed<H> z;
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) z.p[i] = pc[b * T::PCB + i * T::PP + c];
+    const auto y = fx::run_pass<H, AV, false>(z, pv_f, pv_i, p.s_col, p.a);
+    const int base = b * T::RMB + c;
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) {
+      const uint32_t v = y.pair(2 * i, 2 * i + 1);
+      rm[base + (2 * i) * T::RP] = (uint16_t)v;
+      rm[base + (2 * i + 1) * T::RP] = (uint16_t)(v >> 16);
+    }
+  }
+  __syncthreads();
+
+  // coalesced store of the tile
+  const int nch = nbh * T::CPB;
+  for (int c = tid; c < nch; c += 256) {
+    const int b = c / T::CPB, q = c % T::CPB;
+    const int r = q / (W / T::CH), c0 = (q % (W / T::CH)) * T::CH;
+    const uint16_t* s = rm + b * T::RMB + r * T::RP + c0;
+    if constexpr (T::CH == 8)
+      reinterpret_cast<uint4*>(out)[c] = *reinterpret_cast<const uint4*>(s);
+    else
+      reinterpret_cast<uint2*>(out)[c] = *reinterpret_cast<const uint2*>(s);
+  }
+}
+
+template <int LW, int LH, class AH, class AV>
+__global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
+  using T = Tile<LW, LH>;
+  constexpr int W = T::W, H = T::H, NB = T::NB;
+  __shared__ __align__(16) uint32_t pc[NB * T::PCB];
+  __shared__ __align__(16) uint16_t rm[NB * T::RMB];
+  uint16_t* pch = reinterpret_cast<uint16_t*>(pc);
+
+  const int tid = threadIdx.x;
+  const int64_t blk0 = (int64_t)blockIdx.x * NB;
+  const int nbh = (int)min<int64_t>(NB, p.nblocks - blk0);
+  const int16_t* __restrict__ in = static_cast<const int16_t*>(p.in) + blk0 * (W * H);
+  int16_t* __restrict__ out = static_cast<int16_t*>(p.out) + blk0 * (W * H);
+  const uint32_t* ph_f = static_cast<const uint32_t*>(p.ph_f);
+  const uint32_t* ph_i = static_cast<const uint32_t*>(p.ph_i);
+  const uint32_t* pv_f = static_cast<const uint32_t*>(p.pv_f);
+  const uint32_t* pv_i = static_cast<const uint32_t*>(p.pv_i);
+
+  // coalesced load of the tile into the pair-column layout
+  const int nch = nbh * T::CPB;
+  for (int c = tid; c < nch; c += 256) {
+    const int b = c / T::CPB, q = c % T::CPB;
+    const int r = q / (W / T::CH), c0 = (q % (W / T::CH)) * T::CH;
+    uint32_t w[T::CH / 2];
+    if constexpr (T::CH == 8) {
+      const uint4 v = reinterpret_cast<const uint4*>(in)[c];
+      w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    } else {
+      const uint2 v = reinterpret_cast<const uint2*>(in)[c];
+      w[0] = v.x; w[1] = v.y;
+    }
+    const int base = (b * T::PCB + (r >> 1) * T::PP + c0) * 2 + (r & 1);
+#pragma unroll
+    for (int k = 0; k < T::CH / 2; ++k) {
+      pch[base + (2 * k) * 2] = (uint16_t)w[k];
+      pch[base + (2 * k + 1) * 2] = (uint16_t)(w[k] >> 16);
+    }
+  }
+  __syncthreads();
+
+  // column pass (inverse vertical transform first)
+  if (tid < NB * W) {
+    const int b = tid / W, c = tid % W;
+    fx::Packed<H> z;
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) z.p[i] = pc[b * T::PCB + i * T::PP + c];
+    const auto y = fx::run_pass<H, AV, true>(z, pv_f, pv_i, p.s_col, p.a);
+    const int base = b * T::RMB + c;
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) {
+      const uint32_t v = y.pair(2 * i, 2 * i + 1);
+      rm[base + (2 * i) * T::RP] = (uint16_t)v;
+      rm[base + (2 * i + 1) * T::RP] = (uint16_t)(v >> 16);
+    }
+  }
+  __syncthreads();
+
+  // row pass (inverse horizontal transform), stored straight to global
+  if (tid < NB * H) {
+    const int b = tid / H, r = tid % H;
+    fx::Packed<W> x;
+    const uint16_t* s = rm + b * T::RMB + r * T::RP;
+    if constexpr (W >= 8) {
+#pragma unroll
+      for (int q = 0; q < W / 8; ++q) {
+        const uint4 v = reinterpret_cast<const uint4*>(s)[q];
+        x.p[4 * q + 0] = v.x; x.p[4 * q + 1] = v.y; x.p[4 * q + 2] = v.z; x.p[4 * q + 3] = v.w;
+      }
+    } else {
+      const uint2 v = *reinterpret_cast<const uint2*>(s);
+      x.p[0] = v.x; x.p[1] = v.y;
+    }
+    const auto y = fx::run_pass<W, AH, true>(x, ph_f, ph_i, p.s_row, p.a);
+    if (b < nbh) {
+      uint32_t o[W / 2];
+#pragma unroll
+      for (int j = 0; j < W / 2; ++j) o[j] = y.pair(2 * j, 2 * j + 1);
+      store_row<W>(out + (b * H + r) * W, o);
+    }
+  }
+}
+
+using fx::Axis;
+// Axis shorthands: core, adjustment, K taps or B block.
+using A_S3B4 = Axis<C_DST3, ADJ_BAND, 4>;
+using A_C3B4 = Axis<C_DCT3, ADJ_BAND, 4>;
+using A_S3B6 = Axis<C_DST3, ADJ_BAND, 6>;
+using A_C2B4 = Axis<C_DCT2, ADJ_BAND, 4>;
+using A_C2P16 = Axis<C_DCT2, ADJ_POST, 16>;
+using A_C2P8 = Axis<C_DCT2, ADJ_POST, 8>;
+using A_C2 = Axis<C_DCT2, ADJ_NONE, 0>;
+using A_C3 = Axis<C_DCT3, ADJ_NONE, 0>;
+using A_S2 = Axis<C_DST2, ADJ_NONE, 0>;
+using A_S3 = Axis<C_DST3, ADJ_NONE, 0>;
+using A_S7 = Axis<C_DST7, ADJ_NONE, 0>;
+using A_C8 = Axis<C_DCT8, ADJ_NONE, 0>;
+
+#define TA_FX(LW, LH, AH, AV)                                                                     \
+  {{0, 0, LW, LH, AH::CORE, AH::ADJ, AH::KB, AV::CORE, AV::ADJ, AV::KB},                          \
+   reinterpret_cast<const void*>(&fx_fwd<LW, LH, AH, AV>), Tile<LW, LH>::NB, 256},               \
+  {{1, 0, LW, LH, AH::CORE, AH::ADJ, AH::KB, AV::CORE, AV::ADJ, AV::KB},                          \
+   reinterpret_cast<const void*>(&fx_inv<LW, LH, AH, AV>), Tile<LW, LH>::NB, 256}
+
+const KernelEntry kTable[] = {
+    TA_FX(5, 5, A_S3B4, A_S3B4),     // 32x32 adjusted DST-7 (DST-3 + 4-tap band)
+    TA_FX(5, 5, A_C3B4, A_C3B4),     // 32x32 adjusted DCT-8
+    TA_FX(5, 5, A_S3B6, A_S3B6),     // 32x32 DST-3 + 6-tap band
+    TA_FX(5, 5, A_S7, A_S7),         // 32x32 direct DST-7 (VALU)
+    TA_FX(5, 5, A_C2, A_C2),         // 32x32 DCT-2
+    TA_FX(5, 5, A_C2P8, A_C2P8),     // 32x32 DCT-2 + 8x8 sub-block
+    TA_FX(4, 4, A_C2B4, A_C2B4),     // 16x16 DCT-2 + 4-tap band
+    TA_FX(6, 6, A_C2P16, A_C2P16),   // 64x64 DCT-2 + 16x16 sub-block
+    TA_FX(6, 6, A_S7, A_S7),         // 64x64 direct DST-7
+    TA_FX(2, 2, A_S3B4, A_S3B4),     // 4x4 adjusted DST-7
+    TA_FX(3, 3, A_S3, A_C3),         // 8x8 plain DST-3 / DCT-3
+    TA_FX(4, 3, A_S2, A_C8),         // 16x8 DST-2 / direct DCT-8 (rectangular)
+    TA_FX(3, 5, A_C2, A_S3B4),       // 8x32 DCT-2 / adjusted DST-7 (rectangular)
+};
+
+}  // namespace
+
+const KernelEntry* fx_kernels(int* count) {
+  *count = (int)(sizeof(kTable) / sizeof(kTable[0]));
+  return kTable;
+}
+
+}  // namespace ta

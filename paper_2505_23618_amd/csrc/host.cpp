@@ -1,0 +1,374 @@
+// libtadj host side: context, parameter registration, validation, dispatch.
+// Implements the C ABI declared in include/tadj.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tadj.h"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define TA_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) return fail(TA_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kMaxIds = 256;
+
+// Device copies of one parameter set in the four orientations the kernels
+// use: forward / transposed, plain / flipped (DCT-8 version).
+struct ParamSet {
+  int kind = 0;  // TA_ADJ_BAND or TA_ADJ_POST
+  int n = 0, kb = 0;
+  // fixed point (packed int16 pairs) and fp32; index [flip][transposed]
+  void* fx[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  void* f32[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+};
+
+struct AxisCfg {
+  bool set = false;
+  ta_axis user{};
+};
+
+int core_flip(int base) {
+  // S B R for the base kinds (eq. 3, eq. 4): DCT-2 and DST-2 are unchanged,
+  // DCT-3 <-> DST-3, DST-7 <-> DCT-8.
+  switch (base) {
+    case TA_DCT2: return TA_DCT2;
+    case TA_DST2: return TA_DST2;
+    case TA_DCT3: return TA_DST3;
+    case TA_DST3: return TA_DCT3;
+    case TA_DST7: return TA_DCT8;
+    case TA_DCT8: return TA_DST7;
+  }
+  return -1;
+}
+
+}  // namespace
+
+struct ta_ctx {
+  int device = 0;
+  int bd = 8, m = 8, a = 10;
+  int direct_impl = 0;
+  ParamSet params[kMaxIds];
+  AxisCfg axes[kMaxIds];
+  std::vector<void*> allocations;
+  std::mutex mu;
+};
+
+namespace {
+
+int upload(ta_ctx* c, const void* host, size_t bytes, void** dev) {
+  void* p = nullptr;
+  TA_HIP(hipSetDevice(c->device));
+  TA_HIP(hipMalloc(&p, bytes));
+  c->allocations.push_back(p);
+  TA_HIP(hipMemcpy(p, host, bytes, hipMemcpyHostToDevice));
+  *dev = p;
+  return TA_OK;
+}
+
+int log2_exact(int n) {
+  for (int l = 0; l < 31; ++l)
+    if ((1 << l) == n) return l;
+  return -1;
+}
+
+// Window start of row i of a K-tap band A = G_{L-1}...G_0 (L = K/2 layers of
+// adjacent Givens rotations, layer l on pairs starting at l mod 2) or of its
+// transpose.  Row i of a product of layers is {i} expanded by the layers in
+// the order they are met from the left: A meets layer L-1 first, A^T meets
+// layer 0 (even pairs) first; each expansion widens the window by one on
+// both sides after the first, which picks the pair containing i.
+int band_start(int i, int k, bool tr) {
+  const int l = k / 2;
+  return tr ? i - l + 1 - (i & 1) : i - l + ((i + l) & 1);
+}
+
+uint32_t pack2(int lo, int hi) {
+  return (uint32_t)(uint16_t)(int16_t)lo | ((uint32_t)(uint16_t)(int16_t)hi << 16);
+}
+
+struct Resolved {
+  int core, adj, kb;
+  const void* pf;  // forward-orientation parameters
+  const void* pi;  // transposed parameters
+};
+
+// Turn a user axis into the kernel's (core, adjustment, K/B, parameters).
+int resolve_axis(ta_ctx* c, int id, int n, int dtype, Resolved* r) {
+  if (id < 0 || id >= kMaxIds || !c->axes[id].set) return fail(TA_ENOPARAMS, "axis %d not registered", id);
+  const ta_axis& u = c->axes[id].user;
+  const int core = u.flip ? core_flip(u.base) : u.base;
+  r->core = core;
+  r->adj = u.adj;
+  r->kb = 0;
+  r->pf = r->pi = nullptr;
+  if (u.adj == TA_ADJ_NONE) return TA_OK;
+  const ParamSet& ps = c->params[u.param_id];
+  if (ps.kind != u.adj) return fail(TA_ENOPARAMS, "axis %d: parameter set %d missing or of another kind", id, u.param_id);
+  if (ps.n != n)
+    return fail(TA_EUNSUPPORTED, "axis %d: parameter set %d is for size %d, block needs %d", id, u.param_id, ps.n, n);
+  r->kb = ps.kb;
+  const int f = u.flip ? 1 : 0;
+  r->pf = dtype == TA_I16 ? ps.fx[f][0] : ps.f32[f][0];
+  r->pi = dtype == TA_I16 ? ps.fx[f][1] : ps.f32[f][1];
+  return TA_OK;
+}
+
+const ta::KernelEntry* find_kernel(const ta::KernelKey& key, int prefer_mfma) {
+  int cnt = 0;
+  if (prefer_mfma && key.dtype == TA_I16) {
+    const ta::KernelEntry* t = ta::mfma_kernels(&cnt);
+    for (int i = 0; i < cnt; ++i)
+      if (t[i].key == key) return &t[i];
+  }
+  const ta::KernelEntry* t = key.dtype == TA_I16 ? ta::fx_kernels(&cnt) : ta::f32_kernels(&cnt);
+  for (int i = 0; i < cnt; ++i)
+    if (t[i].key == key) return &t[i];
+  return nullptr;
+}
+
+int run_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int log2w, int log2h, int64_t nblocks,
+               const void* in, void* out, int dtype, ta_stream_t stream) {
+  if (!c) return fail(TA_EINVAL, "null context");
+  if (nblocks < 0) return fail(TA_EINVAL, "negative block count");
+  if (dtype != TA_I16 && dtype != TA_F32) return fail(TA_EINVAL, "unknown dtype %d", dtype);
+  if (log2w < 2 || log2w > 6 || log2h < 2 || log2h > 6)
+    return fail(TA_EUNSUPPORTED, "block %dx%d: sizes must be 4..64", 1 << log2w, 1 << log2h);
+  if (nblocks == 0) return TA_OK;
+  if (!in || !out) return fail(TA_EINVAL, "null buffer");
+  const size_t esz = dtype == TA_I16 ? 2 : 4;
+  const size_t bytes = (size_t)nblocks << (log2w + log2h);
+  const char* ib = static_cast<const char*>(in);
+  const char* ob = static_cast<const char*>(out);
+  if (ib < ob + bytes * esz && ob < ib + bytes * esz) return fail(TA_EINVAL, "input and output overlap");
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
+  Resolved rh, rv;
+  int e;
+  if ((e = resolve_axis(c, axis_h, 1 << log2w, dtype, &rh))) return e;
+  if ((e = resolve_axis(c, axis_v, 1 << log2h, dtype, &rv))) return e;
+  const ta::KernelKey key{inv, dtype, log2w, log2h, rh.core, rh.adj, rh.kb, rv.core, rv.adj, rv.kb};
+  const bool direct = (rh.core == TA_DST7 || rh.core == TA_DCT8) && (rv.core == TA_DST7 || rv.core == TA_DCT8);
+  const int prefer_mfma = direct && c->direct_impl != 2;
+  const ta::KernelEntry* k = find_kernel(key, prefer_mfma);
+  if (!k && c->direct_impl == 1 && direct) return fail(TA_EUNSUPPORTED, "no MFMA kernel for this direct transform");
+  if (!k)
+    return fail(TA_EUNSUPPORTED,
+                "no kernel for %s %s %dx%d axes (core %d adj %d k/b %d) x (core %d adj %d k/b %d)",
+                inv ? "inverse" : "forward", dtype == TA_I16 ? "int16" : "fp32", 1 << log2w, 1 << log2h,
+                rh.core, rh.adj, rh.kb, rv.core, rv.adj, rv.kb);
+  ta::PackedArgs args;
+  args.in = in;
+  args.out = out;
+  args.nblocks = nblocks;
+  args.ph_f = rh.pf;
+  args.ph_i = rh.pi;
+  args.pv_f = rv.pf;
+  args.pv_i = rv.pi;
+  if (!inv) {
+    args.s_row = log2w + c->bd + c->m - 15;
+    args.s_col = log2h + c->m;
+  } else {
+    args.s_row = c->m + 14 - c->bd;
+    args.s_col = c->m + 1;
+  }
+  args.a = c->a;
+  const int64_t groups = (nblocks + k->blocks_per_wg - 1) / k->blocks_per_wg;
+  if (groups > 0x7fffffff) return fail(TA_EUNSUPPORTED, "batch too large for one launch");
+  void* kargs[] = {&args};
+  TA_HIP(hipSetDevice(c->device));
+  TA_HIP(hipLaunchKernel(k->fn, dim3((unsigned)groups), dim3(k->threads), kargs, 0,
+                         reinterpret_cast<hipStream_t>(stream)));
+  return TA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ta_version(void) { return "tadj 0.1 (gfx950)"; }
+
+const char* ta_last_error(void) { return g_err.c_str(); }
+
+int ta_create(ta_ctx** out, int device, int bit_depth, int m, int a) {
+  if (!out) return fail(TA_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (m != 8) return fail(TA_EUNSUPPORTED, "integer-matrix precision m=%d: only 8 is built", m);
+  if (bit_depth < 6 || bit_depth > 16) return fail(TA_EUNSUPPORTED, "bit depth %d outside 6..16", bit_depth);
+  if (a < 6 || a > 14) return fail(TA_EUNSUPPORTED, "adjustment precision %d outside 6..14", a);
+  int ndev = 0;
+  TA_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(TA_EINVAL, "device %d not present (%d devices)", device, ndev);
+  auto c = std::make_unique<ta_ctx>();
+  c->device = device;
+  c->bd = bit_depth;
+  c->m = m;
+  c->a = a;
+  *out = c.release();
+  return TA_OK;
+}
+
+int ta_destroy(ta_ctx* c) {
+  if (!c) return fail(TA_EINVAL, "null context");
+  (void)hipSetDevice(c->device);
+  for (void* p : c->allocations) (void)hipFree(p);
+  delete c;
+  return TA_OK;
+}
+
+int ta_set_direct_impl(ta_ctx* c, int impl) {
+  if (!c) return fail(TA_EINVAL, "null context");
+  if (impl < 0 || impl > 2) return fail(TA_EINVAL, "impl %d not in 0..2", impl);
+  c->direct_impl = impl;
+  return TA_OK;
+}
+
+int ta_set_band(ta_ctx* c, int id, int n, int k, const int16_t* a_int, const float* a_f32) {
+  if (!c || !a_int || !a_f32) return fail(TA_EINVAL, "null argument");
+  if (id < 0 || id >= kMaxIds) return fail(TA_EINVAL, "parameter id %d outside 0..255", id);
+  if (log2_exact(n) < 2 || n > 64) return fail(TA_EUNSUPPORTED, "band size %d", n);
+  if (k != 2 && k != 4 && k != 6 && k != 8) return fail(TA_EUNSUPPORTED, "band taps %d not in {2,4,6,8}", k);
+  // check the Givens-band support of A and its transpose
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const int s = band_start(i, k, false);
+      if ((j < s || j >= s + k) && (a_int[i * n + j] != 0 || a_f32[i * n + j] != 0.0f))
+        return fail(TA_EUNSUPPORTED, "band entry (%d,%d) outside the %d-tap Givens band", i, j, k);
+    }
+  std::lock_guard<std::mutex> lk(c->mu);
+  ParamSet& ps = c->params[id];
+  ps = ParamSet{};
+  ps.kind = TA_ADJ_BAND;
+  ps.n = n;
+  ps.kb = k;
+  for (int flip = 0; flip < 2; ++flip)
+    for (int tr = 0; tr < 2; ++tr) {
+      // M = A (flip: R A R), transposed when tr.  M[i][j]:
+      auto at = [&](int i, int j) -> int {
+        int r = i, cc = j;
+        if (tr) std::swap(r, cc);
+        if (flip) { r = n - 1 - r; cc = n - 1 - cc; }
+        return a_int[r * n + cc];
+      };
+      auto atf = [&](int i, int j) -> float {
+        int r = i, cc = j;
+        if (tr) std::swap(r, cc);
+        if (flip) { r = n - 1 - r; cc = n - 1 - cc; }
+        return a_f32[r * n + cc];
+      };
+      std::vector<uint32_t> packed(n * k / 2);
+      std::vector<float> fl(n * k);
+      for (int i = 0; i < n; ++i) {
+        const int s = band_start(i, k, tr != 0);
+        for (int t = 0; t < k / 2; ++t) {
+          const int c0 = s + 2 * t, c1 = c0 + 1;
+          const int v0 = (c0 >= 0 && c0 < n) ? at(i, c0) : 0;
+          const int v1 = (c1 >= 0 && c1 < n) ? at(i, c1) : 0;
+          packed[i * (k / 2) + t] = pack2(v0, v1);
+        }
+        for (int t = 0; t < k; ++t) {
+          const int cc = s + t;
+          fl[i * k + t] = (cc >= 0 && cc < n) ? atf(i, cc) : 0.0f;
+        }
+      }
+      // every non-zero of M must sit inside its row window (true for Givens bands)
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          const int s = band_start(i, k, tr != 0);
+          if ((j < s || j >= s + k) && (at(i, j) != 0 || atf(i, j) != 0.0f))
+            return fail(TA_EUNSUPPORTED, "transposed band entry (%d,%d) outside the window", i, j);
+        }
+      int e;
+      if ((e = upload(c, packed.data(), packed.size() * 4, &ps.fx[flip][tr]))) return e;
+      if ((e = upload(c, fl.data(), fl.size() * 4, &ps.f32[flip][tr]))) return e;
+    }
+  return TA_OK;
+}
+
+int ta_set_post(ta_ctx* c, int id, int n, int b, const int16_t* q_int, const float* q_f32) {
+  if (!c || !q_int || !q_f32) return fail(TA_EINVAL, "null argument");
+  if (id < 0 || id >= kMaxIds) return fail(TA_EINVAL, "parameter id %d outside 0..255", id);
+  if (log2_exact(n) < 2 || n > 64) return fail(TA_EUNSUPPORTED, "post size %d", n);
+  if (b < 2 || b > n || (b & 1)) return fail(TA_EUNSUPPORTED, "sub-block %d for size %d", b, n);
+  std::lock_guard<std::mutex> lk(c->mu);
+  ParamSet& ps = c->params[id];
+  ps = ParamSet{};
+  ps.kind = TA_ADJ_POST;
+  ps.n = n;
+  ps.kb = b;
+  for (int flip = 0; flip < 2; ++flip)
+    for (int tr = 0; tr < 2; ++tr) {
+      // M = Q (flip: S Q S, eq. 5), transposed when tr
+      auto at = [&](int i, int j) -> int {
+        const int r = tr ? j : i, cc = tr ? i : j;
+        const int sg = (flip && ((r + cc) & 1)) ? -1 : 1;
+        return sg * q_int[r * b + cc];
+      };
+      auto atf = [&](int i, int j) -> float {
+        const int r = tr ? j : i, cc = tr ? i : j;
+        const float sg = (flip && ((r + cc) & 1)) ? -1.0f : 1.0f;
+        return sg * q_f32[r * b + cc];
+      };
+      std::vector<uint32_t> packed(b * b / 2);
+      std::vector<float> fl(b * b);
+      for (int i = 0; i < b; ++i) {
+        for (int j = 0; j < b / 2; ++j) packed[i * (b / 2) + j] = pack2(at(i, 2 * j), at(i, 2 * j + 1));
+        for (int j = 0; j < b; ++j) fl[i * b + j] = atf(i, j);
+      }
+      int e;
+      if ((e = upload(c, packed.data(), packed.size() * 4, &ps.fx[flip][tr]))) return e;
+      if ((e = upload(c, fl.data(), fl.size() * 4, &ps.f32[flip][tr]))) return e;
+    }
+  return TA_OK;
+}
+
+int ta_set_axis(ta_ctx* c, int id, const ta_axis* ax) {
+  if (!c || !ax) return fail(TA_EINVAL, "null argument");
+  if (id < 0 || id >= kMaxIds) return fail(TA_EINVAL, "axis id %d outside 0..255", id);
+  if (ax->base < TA_DCT2 || ax->base > TA_DCT8) return fail(TA_EINVAL, "base %d", ax->base);
+  if (ax->adj < TA_ADJ_NONE || ax->adj > TA_ADJ_POST) return fail(TA_EINVAL, "adjustment %d", ax->adj);
+  if (ax->flip != 0 && ax->flip != 1) return fail(TA_EINVAL, "flip %d", ax->flip);
+  if (ax->adj != TA_ADJ_NONE) {
+    if (ax->base > TA_DST3) return fail(TA_EUNSUPPORTED, "DST-7/DCT-8 matrices take no adjustment");
+    if (ax->param_id < 0 || ax->param_id >= kMaxIds || c->params[ax->param_id].kind != ax->adj)
+      return fail(TA_ENOPARAMS, "parameter set %d not registered for this adjustment", ax->param_id);
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->axes[id].set = true;
+  c->axes[id].user = *ax;
+  return TA_OK;
+}
+
+int ta_fwd_packed(ta_ctx* c, int axis_h, int axis_v, int log2w, int log2h, int64_t nblocks,
+                  const void* in, void* out, int dtype, ta_stream_t stream) {
+  return run_packed(c, 0, axis_h, axis_v, log2w, log2h, nblocks, in, out, dtype, stream);
+}
+
+int ta_inv_packed(ta_ctx* c, int axis_h, int axis_v, int log2w, int log2h, int64_t nblocks,
+                  const void* in, void* out, int dtype, ta_stream_t stream) {
+  return run_packed(c, 1, axis_h, axis_v, log2w, log2h, nblocks, in, out, dtype, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,46 @@
+// Kernel registry shared by the kernel translation units and the C ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ta {
+
+// Arguments of the packed-batch kernels (fixed point and fp32).
+struct PackedArgs {
+  const void* in;
+  void* out;
+  int64_t nblocks;
+  const void* ph_f;  // horizontal axis parameters, forward orientation
+  const void* ph_i;  // horizontal axis parameters, transposed (inverse)
+  const void* pv_f;  // vertical axis parameters
+  const void* pv_i;
+  int s_row;         // core shift of the row pass (fixed point)
+  int s_col;         // core shift of the column pass
+  int a;             // adjustment shift
+};
+
+// Identifies one compiled kernel: direction, dtype, block size and both axes.
+struct KernelKey {
+  int inv, dtype, lw, lh;
+  int core_h, adj_h, kb_h;
+  int core_v, adj_v, kb_v;
+  bool operator==(const KernelKey& o) const {
+    return inv == o.inv && dtype == o.dtype && lw == o.lw && lh == o.lh && core_h == o.core_h &&
+           adj_h == o.adj_h && kb_h == o.kb_h && core_v == o.core_v && adj_v == o.adj_v && kb_v == o.kb_v;
+  }
+};
+
+struct KernelEntry {
+  KernelKey key;
+  const void* fn;     // __global__ function
+  int blocks_per_wg;  // blocks of the batch handled by one workgroup
+  int threads;        // workgroup size
+};
+
+// Tables of compiled kernels (defined in the kernel translation units).
+const KernelEntry* fx_kernels(int* count);
+const KernelEntry* f32_kernels(int* count);
+const KernelEntry* mfma_kernels(int* count);
+
+}  // namespace ta

@@ -1,0 +1,55 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU."""
+
+import ctypes
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import paper_2505_23618_amd as ta
+
+HEADER = Path(__file__).resolve().parent.parent / "include" / "tadj.h"
+
+
+def declared_symbols():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ta_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ta.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 10
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(ta.EXPORTS) <= set(syms)
+
+
+def test_version_string():
+    assert b"gfx950" in ta.lib().ta_version()
+
+
+def test_create_rejects_bad_arguments_without_gpu():
+    lib = ta.lib()
+    h = ctypes.c_void_p()
+    assert lib.ta_create(None, 0, 8, 8, 10) == ta.TA_EINVAL
+    assert lib.ta_create(ctypes.byref(h), 0, 8, 6, 10) == ta.TA_EUNSUPPORTED
+    assert b"precision" in lib.ta_last_error()
+    assert lib.ta_create(ctypes.byref(h), 0, 30, 8, 10) == ta.TA_EUNSUPPORTED
+    assert lib.ta_create(ctypes.byref(h), 0, 8, 8, 20) == ta.TA_EUNSUPPORTED
+
+
+def test_null_context_paths():
+    lib = ta.lib()
+    a = np.zeros((8, 8), np.int16)
+    f = np.zeros((8, 8), np.float32)
+    assert lib.ta_destroy(None) == ta.TA_EINVAL
+    assert lib.ta_set_band(None, 0, 8, 4, a.ctypes.data, f.ctypes.data) == ta.TA_EINVAL
+    assert lib.ta_set_post(None, 0, 8, 4, a.ctypes.data, f.ctypes.data) == ta.TA_EINVAL
+    assert lib.ta_set_axis(None, 0, None) == ta.TA_EINVAL
+    assert lib.ta_fwd_packed(None, 0, 0, 5, 5, 1, None, None, 0, None) == ta.TA_EINVAL
+    assert lib.ta_inv_packed(None, 0, 0, 5, 5, 1, None, None, 0, None) == ta.TA_EINVAL
+    assert lib.ta_set_direct_impl(None, 0) == ta.TA_EINVAL

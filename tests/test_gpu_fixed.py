@@ -1,0 +1,142 @@
+"""GPU parity of the fixed-point path: bit-exact against the CPU oracle.
+
+Every case runs through the C ABI (via the ctypes binding) on seeded inputs
+at sizes the oracle finishes quickly, with a ragged last tile, plus the
+adversarial value sets (extreme residuals, full-range int16 coefficients);
+the full 262,144-block 32x32 workload is checked on sampled blocks.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fixed as F
+from tests.libcases import CASES, Registered
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2505_23618_amd as ta  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def reg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return Registered(0)
+
+
+def _ragged(w, h):
+    nb_per_wg = 256 // max(w, h)
+    return 3 * nb_per_wg + 5
+
+
+def _gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _run_case(reg, name, x, inverse):
+    ah, av = reg.axes[name]
+    oh, ov = reg.oracle_axes(name)
+    xd = _gpu(x)
+    if not inverse:
+        got = reg.ctx.fwd(xd, ah, av).cpu().numpy()
+        ref = F.fwd2d(x, oh, ov)
+    else:
+        got = reg.ctx.inv(xd, ah, av).cpu().numpy()
+        ref = F.inv2d(x, oh, ov)
+    torch.cuda.synchronize()
+    return got, ref
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_inverse_bit_exact_ar1(reg, name):
+    w, h = CASES[name][:2]
+    nb = _ragged(w, h)
+    print(f"case {name} {w}x{h} nb={nb}", flush=True)
+    x = synth.ar1_blocks(nb, h, w, 0.95, 16.0, seed=101)
+    got, ref = _run_case(reg, name, x, inverse=False)
+    assert got.dtype == np.int16
+    mism = np.argwhere(got != ref)
+    assert mism.size == 0, f"{len(mism)} mismatches, first at {mism[:3].tolist()}"
+    got2, ref2 = _run_case(reg, name, got, inverse=True)
+    assert (got2 == ref2).all()
+
+
+@pytest.mark.parametrize("kind", ["zeros", "pos", "neg", "checker", "uniform_res", "full16", "extreme16"])
+@pytest.mark.parametrize("name", ["cfg2_dst7_k4", "cfg2_dct8_k4", "cfg3_post16_64", "dct2_32",
+                                  "dst7_band_4", "dst2_dct8_16x8", "direct_dst7_32"])
+def test_adversarial_values(reg, name, kind):
+    w, h = CASES[name][:2]
+    print(f"case {name} {kind}", flush=True)
+    x = synth.adversarial_blocks(h, w, kind, seed=5, n=_ragged(w, h))
+    for inverse in (False, True):
+        got, ref = _run_case(reg, name, x, inverse)
+        assert (got == ref).all(), f"inverse={inverse}"
+
+
+def test_empty_batch_is_noop(reg):
+    ah, av = reg.axes["cfg2_dst7_k4"]
+    x = torch.zeros((0, 32, 32), dtype=torch.int16, device="cuda")
+    y = reg.ctx.fwd(x, ah, av)
+    assert y.shape == (0, 32, 32)
+
+
+def test_single_block(reg):
+    x = synth.ar1_blocks(1, 32, 32, 0.95, 16.0, seed=9)
+    got, ref = _run_case(reg, "cfg2_dst7_k4", x, inverse=False)
+    assert (got == ref).all()
+
+
+def test_deterministic_reruns(reg):
+    ah, av = reg.axes["cfg2_dst7_k4"]
+    x = _gpu(synth.ar1_blocks(1000, 32, 32, 0.95, 16.0, seed=3))
+    a = reg.ctx.fwd(x, ah, av)
+    b = reg.ctx.fwd(x, ah, av)
+    c = reg.ctx.inv(a, ah, av)
+    d = reg.ctx.inv(b, ah, av)
+    assert torch.equal(a, b) and torch.equal(c, d)
+
+
+def test_errors(reg):
+    ah, av = reg.axes["cfg2_dst7_k4"]
+    x = torch.zeros((4, 32, 32), dtype=torch.int16, device="cuda")
+    # parameter set of the wrong size for a 16x16 block
+    with pytest.raises(ta.TadjError) as e:
+        reg.ctx.fwd(torch.zeros((4, 16, 16), dtype=torch.int16, device="cuda"), ah, av)
+    assert e.value.code == ta.TA_EUNSUPPORTED
+    # unregistered axis
+    with pytest.raises(ta.TadjError) as e:
+        reg.ctx.fwd(x, 250, 250)
+    assert e.value.code == ta.TA_ENOPARAMS
+    # aliasing in/out
+    with pytest.raises(ta.TadjError) as e:
+        reg.ctx.fwd(x, ah, av, out=x)
+    assert e.value.code == ta.TA_EINVAL
+    # a combination without a compiled kernel
+    s7 = reg.axes["direct_dst7_32"][0]
+    with pytest.raises(ta.TadjError) as e:
+        reg.ctx.fwd(x, ah, s7)
+    assert e.value.code == ta.TA_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("name,wl", [("cfg2_dst7_k4", "cfg2_32x32"), ("cfg3_post16_64", "cfg3_64x64")])
+def test_full_size_sampled(reg, name, wl):
+    """Full workload in the benchmark's launch configuration; the oracle
+    checks a random sample of blocks of the forward and inverse outputs."""
+    x = synth.workload_blocks(wl)
+    print(f"full {name}: {x.shape}", flush=True)
+    ah, av = reg.axes[name]
+    xd = _gpu(x)
+    y = reg.ctx.fwd(xd, ah, av)
+    z = reg.ctx.inv(y, ah, av)
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(77))
+    idx = np.sort(rng.choice(x.shape[0], size=48, replace=False))
+    idx = np.concatenate([idx, [0, x.shape[0] - 1]])
+    oh, ov = reg.oracle_axes(name)
+    ys = y[torch.from_numpy(idx).cuda()].cpu().numpy()
+    zs = z[torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert (ys == F.fwd2d(x[idx], oh, ov)).all()
+    assert (zs == F.inv2d(ys, oh, ov)).all()
+    del xd, y, z
