@@ -1,0 +1,218 @@
+"""Benchmark: transform coefficients per second, forward + inverse, of the
+32x32 adjusted DST-7 (DST-3 + 4-tap Givens band on rows and columns, fixed
+point) over 262,144 synthetic AR(1) residual blocks, on one MI355X.
+
+One step = one forward and one inverse of the whole batch (inputs resident in
+HBM).  Also timed on the same data: the direct-matrix DST-7 (the paper's
+full-matrix comparison path, Table 1) and a plain device copy of the same
+bytes (the achievable HBM rate).  The dominant kernel's achieved bandwidth is
+its algorithmic bytes (2 B read + 2 B written per coefficient) over its mean
+duration from HIP events on the launch stream.  The CPU baseline is the
+oracle, run on a bounded sample of the same blocks.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "cfg2_32x32"
+PROFILES = ROOT / "profiles"
+
+
+KERNEL_SOURCES = ("paper_2505_23618_amd/csrc/common.hpp", "paper_2505_23618_amd/csrc/fx.hpp",
+                  "paper_2505_23618_amd/csrc/fx_kernels.hip")
+TRAFFIC_FILE = PROFILES / "fx_cfg2_32x32_adjusted_dst7.md"
+
+
+def _traffic_from_profiles():
+    """HBM bytes per launch of the dominant kernel, from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by the copy-kernel
+    calibration), or None when the kernel sources changed since the counters
+    were taken."""
+    import hashlib
+    if not TRAFFIC_FILE.exists():
+        return None
+    kv = {}
+    for line in TRAFFIC_FILE.read_text().splitlines():
+        if "=" in line and line.split("=")[0] in ("traffic_bytes_per_launch", "kernel_sources_sha256"):
+            k, v = line.split("=", 1)
+            kv[k] = v.strip()
+    h = hashlib.sha256(b"".join((ROOT / f).read_bytes() for f in KERNEL_SOURCES)).hexdigest()
+    if kv.get("kernel_sources_sha256") != h or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def _oracle_chunk(args):
+    x, = args
+    import json as _j
+    from oracle import fixed as F
+    from oracle.fixed import Axis
+    with open(ROOT / "paper_2505_23618_amd" / "params" / "adjust_params.json") as fh:
+        e = {p["name"]: p for p in _j.load(fh)["entries"]}["band_S3_S7_N32_K4"]
+    ax = Axis(base="S3", adj="band", a_int=np.asarray(e["a_int"], np.int64), a_f=np.asarray(e["a_f64"]))
+    y = F.fwd2d(x, ax, ax)
+    F.inv2d(y, ax, ax)
+    return x.shape[0]
+
+
+def cpu_baseline(x: np.ndarray, nsample: int = 8192):
+    """The oracle (unchanged) on the first `nsample` blocks, split over a
+    process pool of min(host cores, 16) workers."""
+    from concurrent.futures import ProcessPoolExecutor
+    cores = min(os.cpu_count() or 1, 16)
+    sample = x[:nsample]
+    chunks = np.array_split(sample, cores * 2)
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(cores) as ex:
+        done = sum(ex.map(_oracle_chunk, [(c,) for c in chunks]))
+    dt = time.perf_counter() - t0
+    return {"value": done * 1024 / dt, "unit": "coef/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {done} of the 262,144 blocks, fwd+inv, dense int64 oracle, "
+                      f"{dt:.1f} s wall on {cores} processes"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also launch one plain copy per step (counter calibration runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(blocks are independent; see DESIGN.md for how the batch would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_2505_23618_amd as ta
+
+    dev = torch.device("cuda:0")
+    ctx = ta.Context(0)
+    ids = ta.load_params(ctx)
+    ax = ctx.axis(0, ta.DST3, ta.ADJ_BAND, False, ids["band_S3_S7_N32_K4"])
+    ax7 = ctx.axis(1, ta.DST7, ta.ADJ_NONE, False, 0)
+
+    t0 = time.perf_counter()
+    x_host = synth.workload_blocks(WORKLOAD)
+    print(f"[bench] generated {x_host.shape} int16 in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    nb = x_host.shape[0]
+    ncoef = nb * 32 * 32
+    x = torch.from_numpy(x_host).to(dev)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    def fwd(src, dst, a):
+        ctx.fwd_ptr(a, a, 5, 5, nb, src.data_ptr(), dst.data_ptr(), ta.I16, sh)
+
+    def inv(src, dst, a):
+        ctx.inv_ptr(a, a, 5, 5, nb, src.data_ptr(), dst.data_ptr(), ta.I16, sh)
+
+    def timed(a, steps, warmup, with_copy=False):
+        for _ in range(warmup):
+            fwd(x, y, a)
+            inv(y, z, a)
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for s in range(steps):
+            ev[s][0].record(stream)
+            fwd(x, y, a)
+            ev[s][1].record(stream)
+            inv(y, z, a)
+            ev[s][2].record(stream)
+            if with_copy:
+                z.copy_(x)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        tf = np.array([ev[s][0].elapsed_time(ev[s][1]) for s in range(steps)]) * 1e-3
+        ti = np.array([ev[s][1].elapsed_time(ev[s][2]) for s in range(steps)]) * 1e-3
+        return wall, tf, ti
+
+    # adjusted DST-7: the measured workload
+    wall, tf, ti = timed(ax, args.steps, args.warmup, args.calib_copy)
+    print(f"[bench] adjusted: fwd {tf.mean()*1e6:.1f} us inv {ti.mean()*1e6:.1f} us", file=sys.stderr, flush=True)
+    # direct-matrix DST-7 on the same data
+    wall7, tf7, ti7 = timed(ax7, max(10, args.steps // 2), 2)
+    print(f"[bench] direct: fwd {tf7.mean()*1e6:.1f} us inv {ti7.mean()*1e6:.1f} us", file=sys.stderr, flush=True)
+    # plain copy of the same bytes (achievable HBM rate for a 2 B read + 2 B write stream)
+    cev = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
+    for _ in range(3):
+        z.copy_(x)
+    for i in range(10):
+        cev[i].record(stream)
+        z.copy_(x)
+    cev[10].record(stream)
+    torch.cuda.synchronize()
+    tcopy = np.mean([cev[i].elapsed_time(cev[i + 1]) for i in range(10)]) * 1e-3
+
+    steps = args.steps
+    if args.calib_copy:
+        step_time = (tf.sum() + ti.sum()) / steps      # exclude the calibration copies
+    else:
+        step_time = wall / steps
+    value = ncoef / step_time
+    bytes_per_launch = 4.0 * ncoef                    # 2 B in + 2 B out per coefficient
+    dom = "inverse" if ti.mean() >= tf.mean() else "forward"
+    tdom = max(ti.mean(), tf.mean())
+    achieved = bytes_per_launch / tdom / 1e9
+    traffic = _traffic_from_profiles()
+
+    out = {
+        "metric": "transform coeffs/sec (fwd+inv, 32x32 adjusted DST-7) vs direct-matrix DST-7",
+        "value": value,
+        "unit": "coef/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_time * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i16",
+        "data": "synthetic",
+        "config": {
+            "workload": "262,144 blocks of 32x32 int16 AR(1) residuals (rho=0.95, sigma=16, clip 255); "
+                        "DST-3 + 4-tap Givens band (adjusted DST-7) on rows and columns; fixed point "
+                        "(m=8, a=10, bd=8), forward + inverse",
+            "blocks": nb, "block": "32x32", "coefficients": ncoef,
+        },
+        "fwd_us": tf.mean() * 1e6,
+        "inv_us": ti.mean() * 1e6,
+        "direct_dst7": {
+            "value": ncoef / (tf7.mean() + ti7.mean()), "unit": "coef/s",
+            "fwd_us": tf7.mean() * 1e6, "inv_us": ti7.mean() * 1e6,
+            "adjusted_over_direct": (tf7.mean() + ti7.mean()) / (tf.mean() + ti.mean()),
+        },
+        "copy_same_bytes": {"us": tcopy * 1e6, "GB/s": bytes_per_launch / tcopy / 1e9},
+        "roofline": {
+            "bound": "hbm", "kernel": f"fx_{'inv' if dom == 'inverse' else 'fwd'} 32x32 DST-3+4-tap",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x_host)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

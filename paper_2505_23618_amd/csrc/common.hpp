@@ -57,6 +57,29 @@ TA_DEV int dot2(uint32_t a, uint32_t b, int acc) {
   return __builtin_amdgcn_sdot2(__builtin_bit_cast(s2v, a), __builtin_bit_cast(s2v, b), acc, false);
 }
 
+// Head of a dot2 chain: the VOP3P form takes the accumulator from a VGPR
+// (one register holding the rounding offset serves every chain) and the
+// coefficient pair from an SGPR, so starting a chain costs no v_mov.
+TA_DEV int dot2h(uint32_t a, uint32_t coef, int acc) {
+  int r;
+  asm("v_dot2_i32_i16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(coef), "v"(acc));
+  return r;
+}
+
+TA_DEV int dot2h0(uint32_t a, uint32_t coef) {
+  int r;
+  asm("v_dot2_i32_i16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "s"(coef));
+  return r;
+}
+
+// acc + a * coef with 24-bit signed operands (|a| < 2^23), one instruction
+// per product (the compiler would otherwise split chains into mul + add3).
+TA_DEV int mad24(int a, int coef, int acc) {
+  int r;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(coef), "v"(acc));
+  return r;
+}
+
 // Saturating pack of two int32 into int16 lanes (lo = a, hi = b): clip16.
 TA_DEV uint32_t satpk(int a, int b) {
   return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pk_i16(a, b));

@@ -14,21 +14,26 @@
 namespace ta {
 namespace fx {
 
-// N int16 values held as natural pairs: element 2j in the low half of p[j].
-template <int N>
+// N int16 values held in N/2 packed registers.  Natural layout: register s
+// holds elements (2s, 2s+1).  Mirrored layout: register s < N/2 holds
+// (s, N-1-s), the operand pairs of the first DCT-2 butterfly level, so a
+// consumer reading from LDS in that layout needs no repacking.
+template <int N, bool MIRROR = false>
 struct Packed {
   uint32_t p[N / 2];
+  static TA_DEV constexpr int slot(int i) { return MIRROR ? (i < N / 2 ? i : N - 1 - i) : (i >> 1); }
+  static TA_DEV constexpr int half(int i) { return MIRROR ? (i < N / 2 ? 0 : 1) : (i & 1); }
   TA_DEV int value(int i) const {
-    const uint32_t w = p[i >> 1];
-    return (i & 1) ? ((int)w >> 16) : (int)(short)(w & 0xffffu);
+    const uint32_t w = p[slot(i)];
+    return half(i) ? ((int)w >> 16) : (int)(short)(w & 0xffffu);
   }
   // (value(i), value(j)) packed; an index of -1 stands for zero.
   TA_DEV uint32_t pair(int i, int j) const {
-    if (i >= 0 && (i & 1) == 0 && j == i + 1) return p[i >> 1];
-    const uint32_t lo = i >= 0 ? p[i >> 1] : 0u;
-    const uint32_t hi = j >= 0 ? p[j >> 1] : 0u;
-    const uint32_t sl = i >= 0 ? ((i & 1) ? 0x0302u : 0x0100u) : 0x0c0cu;
-    const uint32_t sh = j >= 0 ? ((j & 1) ? 0x0706u : 0x0504u) : 0x0c0cu;
+    if (i >= 0 && j >= 0 && slot(i) == slot(j) && half(i) == 0 && half(j) == 1) return p[slot(i)];
+    const uint32_t lo = i >= 0 ? p[slot(i)] : 0u;
+    const uint32_t hi = j >= 0 ? p[slot(j)] : 0u;
+    const uint32_t sl = i >= 0 ? (half(i) ? 0x0302u : 0x0100u) : 0x0c0cu;
+    const uint32_t sh = j >= 0 ? (half(j) ? 0x0706u : 0x0504u) : 0x0c0cu;
     return perm(hi, lo, sl | (sh << 16));
   }
 };
@@ -90,11 +95,14 @@ TA_DEV Acc<N> band(const S& src, const uint32_t* __restrict__ taps, int shift) {
   for (int i = 0; i < N; ++i) {
     const int st = band_start<K, TR>(i);
     int acc = off;
+    bool head = true;
 #pragma unroll
     for (int t = 0; t < K / 2; ++t) {
       const int c0 = st + 2 * t, c1 = c0 + 1;
       if (c1 < 0 || c0 >= N) continue;
-      acc = dot2(src.pair(c0 >= 0 ? c0 : -1, c1 < N ? c1 : -1), taps[i * (K / 2) + t], acc);
+      const uint32_t pr = src.pair(c0 >= 0 ? c0 : -1, c1 < N ? c1 : -1);
+      acc = head ? dot2h(pr, taps[i * (K / 2) + t], off) : dot2(pr, taps[i * (K / 2) + t], acc);
+      head = false;
     }
     r.a[i] = acc;
   }
@@ -106,23 +114,25 @@ TA_DEV Acc<N> band(const S& src, const uint32_t* __restrict__ taps, int shift) {
 // Even part: the N/2-point DCT-3 of w[0], w[2], ...; odd part:
 // O[n] = sum_j C2_N[2j+1][n] w[2j+1]; z[n] = E[n] + O[n], z[N-1-n] = E[n] - O[n].
 // ---------------------------------------------------------------------------
-template <int N, int M, class W>
+template <int N, int M, bool OFF, class W>
 TA_DEV void c3_even(const W& w, int (&e)[M], int off) {
   constexpr int ST = N / M;
   if constexpr (M == 2) {
     const uint32_t p = w.pair(0, ST);
-    e[0] = dot2(p, pk2(c2i<2>(0, 0), c2i<2>(1, 0)), off);
-    e[1] = dot2(p, pk2(c2i<2>(0, 1), c2i<2>(1, 1)), off);
+    const uint32_t c0 = pk2(c2i<2>(0, 0), c2i<2>(1, 0)), c1 = pk2(c2i<2>(0, 1), c2i<2>(1, 1));
+    e[0] = OFF ? dot2h(p, c0, off) : dot2h0(p, c0);
+    e[1] = OFF ? dot2h(p, c1, off) : dot2h0(p, c1);
   } else {
     int ee[M / 2];
-    c3_even<N, M / 2>(w, ee, off);
+    c3_even<N, M / 2, OFF>(w, ee, off);
 #pragma unroll
     for (int n = 0; n < M / 2; ++n) {
       int o = 0;
 #pragma unroll
       for (int i = 0; i < M / 4; ++i) {
         const int k1 = 4 * i + 1, k2 = 4 * i + 3;
-        o = dot2(w.pair(k1 * ST, k2 * ST), pk2(c2i<M>(k1, n), c2i<M>(k2, n)), o);
+        const uint32_t pr = w.pair(k1 * ST, k2 * ST), cf = pk2(c2i<M>(k1, n), c2i<M>(k2, n));
+        o = i == 0 ? dot2h0(pr, cf) : dot2(pr, cf, o);
       }
       e[n] = ee[n] + o;
       e[M - 1 - n] = ee[n] - o;
@@ -139,15 +149,16 @@ TA_DEV Acc<N> core_c3(const S& src, int shift) {
   Acc<N> r;
   r.s0 = r.s1 = shift;
   int ee[N / 2];
-  c3_even<N, N / 2>(w, ee, OSIGN ? 0 : off);
+  c3_even<N, N / 2, !OSIGN>(w, ee, off);
 #pragma unroll
   for (int n = 0; n < N / 2; ++n) {
     const int sg = (OSIGN && (n & 1)) ? -1 : 1;
-    int o = OSIGN ? off : 0;
+    int o = 0;
 #pragma unroll
     for (int i = 0; i < N / 4; ++i) {
       const int k1 = 4 * i + 1, k2 = 4 * i + 3;
-      o = dot2(w.pair(k1, k2), pk2(sg * c2i<N>(k1, n), sg * c2i<N>(k2, n)), o);
+      const uint32_t pr = w.pair(k1, k2), cf = pk2(sg * c2i<N>(k1, n), sg * c2i<N>(k2, n));
+      o = i > 0 ? dot2(pr, cf, o) : (OSIGN ? dot2h(pr, cf, off) : dot2h0(pr, cf));
     }
     if (!OSIGN) {
       r.a[n] = ee[n] + o;
@@ -184,7 +195,7 @@ TA_DEV void c2_int(const int (&v)[M], int (&z)[M], int off) {
     for (int k = 1; k < M; k += 2) {
       int acc = off;
 #pragma unroll
-      for (int n = 0; n < M / 2; ++n) acc = __mul24(o[n], c2i<M>(k, n)) + acc;
+      for (int n = 0; n < M / 2; ++n) acc = mad24(o[n], c2i<M>(k, n), acc);
       z[k] = acc;
     }
     int ze[M / 2];
@@ -211,7 +222,8 @@ TA_DEV Acc<N> core_c2(const S& src, int shift) {
     for (int n = 0; n < N / 2; ++n) {
       const int sa = (ISIGN && (n & 1)) ? -1 : 1;
       const int sb = (ISIGN && ((N - 1 - n) & 1)) ? -1 : 1;
-      acc = dot2(pr[n], pk2(sa * c2i<N>(k, n), sb * c2i<N>(k, N - 1 - n)), acc);
+      const uint32_t cf = pk2(sa * c2i<N>(k, n), sb * c2i<N>(k, N - 1 - n));
+      acc = n == 0 ? dot2h(pr[n], cf, off) : dot2(pr[n], cf, acc);
     }
     z[k] = acc;
   }
@@ -220,7 +232,7 @@ TA_DEV Acc<N> core_c2(const S& src, int shift) {
   for (int n = 0; n < N / 2; ++n) {
     const int sa = (ISIGN && (n & 1)) ? -1 : 1;
     const int sb = (ISIGN && ((N - 1 - n) & 1)) ? -1 : 1;
-    e[n] = dot2(pr[n], pk2(sa, sb), 0);
+    e[n] = dot2h0(pr[n], pk2(sa, sb));
   }
   int ze[N / 2];
   c2_int<N / 2>(e, ze, off);
@@ -252,7 +264,8 @@ TA_DEV Acc<N> core_direct(const S& src, int shift) {
     for (int j = 0; j < N / 2; ++j) {
       const int c0 = TR ? dmat<N, KIND>(2 * j, k) : dmat<N, KIND>(k, 2 * j);
       const int c1 = TR ? dmat<N, KIND>(2 * j + 1, k) : dmat<N, KIND>(k, 2 * j + 1);
-      acc = dot2(src.pair(2 * j, 2 * j + 1), pk2(c0, c1), acc);
+      const uint32_t pr = src.pair(2 * j, 2 * j + 1);
+      acc = j == 0 ? dot2h(pr, pk2(c0, c1), off) : dot2(pr, pk2(c0, c1), acc);
     }
     r.a[k] = acc;
   }
@@ -280,7 +293,10 @@ TA_DEV void post_rows(const S& src, const uint32_t* __restrict__ q, int shift, i
   for (int i = 0; i < B; ++i) {
     int acc = off;
 #pragma unroll
-    for (int j = 0; j < B / 2; ++j) acc = dot2(src.pair(2 * j, 2 * j + 1), q[i * (B / 2) + j], acc);
+    for (int j = 0; j < B / 2; ++j) {
+      const uint32_t pr = src.pair(2 * j, 2 * j + 1);
+      acc = j == 0 ? dot2h(pr, q[i * (B / 2)], off) : dot2(pr, q[i * (B / 2) + j], acc);
+    }
     out[i] = acc;
   }
 }
@@ -290,6 +306,17 @@ template <int CORE_, int ADJ_, int KB_>
 struct Axis {
   static constexpr int CORE = CORE_, ADJ = ADJ_, KB = KB_;
 };
+
+// Whether the first stage of a pass consumes (x[n], x[N-1-n]) pairs: true
+// when that stage is a DCT-2 butterfly (DCT-2 or DST-2 core, after taking
+// the transpose for the inverse) rather than a band, a sub-block or a DCT-3.
+template <class AX, bool INV>
+constexpr bool wants_mirror() {
+  if (AX::ADJ == ADJ_BAND && !INV) return false;
+  if (AX::ADJ == ADJ_POST && INV) return false;
+  const int c = INV ? core_transpose(AX::CORE) : AX::CORE;
+  return c == C_DCT2 || c == C_DST2;
+}
 
 // Run the forward (INV = false) or inverse pass of axis AX on `in`.
 // pf: forward parameters (band taps / Q pairs), pi: transposed parameters.

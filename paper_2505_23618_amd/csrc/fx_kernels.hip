@@ -7,14 +7,19 @@
 // through LDS in two layouts, chosen so that every LDS read is a full dword
 // or wider and all scattering happens on the write side (ds_write_b16 and
 // ds_write_b16_d16_hi cost no VALU work):
-//   PC ("pair-column"): dword (r/2)*PP + c of a block holds rows r, r+1 of
-//      column c, so a column thread reads its vector as natural int16 pairs;
-//      PP = W + 1 keeps the 16 pair-rows of a column in distinct banks.
+//   PC ("pair-column"): dword s*PP + c of a block holds two elements of
+//      column c, so a column thread reads its vector as packed int16 pairs;
+//      PP = W + 1 keeps the pair-rows of a column in distinct banks.
 //   RM ("row-major"): row pitch W + 8 halfwords so that ds_read_b128 of
 //      consecutive rows hits distinct banks.
+// Which two elements share a dword follows the consumer: natural pairs
+// (2s, 2s+1), or mirrored pairs (s, N-1-s) when the first stage of the pass
+// is a DCT-2 butterfly, whose first level multiplies exactly those pairs.
 // Forward: global rows -> registers -> row pass -> PC -> column pass -> RM ->
 // coalesced 16-byte stores.  Inverse: coalesced 16-byte loads -> PC ->
-// column pass -> RM -> row pass -> global rows.
+// column pass -> RM -> row pass -> global rows.  PC and RM alias the same
+// LDS (a barrier separates the last PC read from the first RM write), which
+// halves the LDS per workgroup and doubles the resident waves per CU.
 #include "fx.hpp"
 #include "kernels.hpp"
 
@@ -27,10 +32,20 @@ struct Tile {
   static constexpr int NB = 256 / (W > H ? W : H);
   static constexpr int PP = W + 1;
   static constexpr int PCB = (H / 2) * PP;                 // dwords per block, PC
-  static constexpr int RP = W >= 8 ? W + 8 : W;            // halfwords per row, RM
-  static constexpr int RMB = H * RP + (W >= 8 ? 32 : 0);   // halfwords per block, RM
+  // RM row pitch: the inverse reads whole rows with ds_read_b128 and pads each
+  // row by 16 bytes; the forward reads consecutive 16-byte chunks and needs no
+  // row padding.  Each block is padded by 64 bytes so that the two blocks a
+  // wave writes in the column pass use different banks.
+  static constexpr int RPF = W;
+  static constexpr int RPI = W >= 8 ? W + 8 : W;
+  static constexpr int RMBF = H * RPF + (W >= 8 ? 32 : 0);
+  static constexpr int RMBI = H * RPI + (W >= 8 ? 32 : 0);
   static constexpr int CH = W >= 8 ? 8 : 4;                // halfwords per global chunk
   static constexpr int CPB = W * H / CH;                   // chunks per block
+  // PC and RM share one LDS buffer (sized in dwords)
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  static constexpr int LDS_F = cmax(NB * PCB, (NB * RMBF + 1) / 2);
+  static constexpr int LDS_I = cmax(NB * PCB, (NB * RMBI + 1) / 2);
 };
 
 template <int W>
@@ -66,9 +81,10 @@ template <int LW, int LH, class AH, class AV>
 __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
   using T = Tile<LW, LH>;
   constexpr int W = T::W, H = T::H, NB = T::NB;
-  __shared__ __align__(16) uint32_t pc[NB * T::PCB];
-  __shared__ __align__(16) uint16_t rm[NB * T::RMB];
-  uint16_t* pch = reinterpret_cast<uint16_t*>(pc);
+  __shared__ __align__(16) uint32_t lds[T::LDS_F];
+  uint32_t* pc = lds;
+  uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
+  uint16_t* rm = reinterpret_cast<uint16_t*>(lds);
 
   const int tid = threadIdx.x;
   const int64_t blk0 = (int64_t)blockIdx.x * NB;
@@ -80,7 +96,10 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
   const uint32_t* pv_f = static_cast<const uint32_t*>(p.pv_f);
   const uint32_t* pv_i = static_cast<const uint32_t*>(p.pv_i);
 
-  // row pass (horizontal transform of every row)
+  constexpr bool MV = fx::wants_mirror<AV, false>();
+  using PV = fx::Packed<H, MV>;
+
+  // row pass (horizontal transform of every row) -> PC
   if (tid < NB * H) {
     const int b = tid / H, r = tid % H;
     fx::Packed<W> x;
@@ -91,7 +110,7 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
       for (int j = 0; j < W / 2; ++j) x.p[j] = 0u;
     }
     const auto y = fx::run_pass<W, AH, false>(x, ph_f, ph_i, p.s_row, p.a);
-    const int base = (b * T::PCB + (r >> 1) * T::PP) * 2 + (r & 1);
+    const int base = (b * T::PCB + PV::slot(r) * T::PP) * 2 + PV::half(r);
 #pragma unroll
     for (int j = 0; j < W / 2; ++j) {
       const uint32_t v = y.pair(2 * j, 2 * j + 1);
@@ -101,19 +120,26 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
   }
   __syncthreads();
 
-  // column pass (vertical transform of every column)
+  // column pass (vertical transform of every column); PC is dead once every
+  // thread has read its column, then the same LDS holds RM
+  uint32_t o[H / 2];
   if (tid < NB * W) {
     const int b = tid / W, c = tid % W;
-    fx::Packed<H> z;
+    PV z;
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) z.p[i] = pc[b * T::PCB + i * T::PP + c];
     const auto y = fx::run_pass<H, AV, false>(z, pv_f, pv_i, p.s_col, p.a);
-    const int base = b * T::RMB + c;
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
+  }
+  __syncthreads();
+  if (tid < NB * W) {
+    const int b = tid / W, c = tid % W;
+    const int base = b * T::RMBF + c;
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) {
-      const uint32_t v = y.pair(2 * i, 2 * i + 1);
-      rm[base + (2 * i) * T::RP] = (uint16_t)v;
-      rm[base + (2 * i + 1) * T::RP] = (uint16_t)(v >> 16);
+      rm[base + (2 * i) * T::RPF] = (uint16_t)o[i];
+      rm[base + (2 * i + 1) * T::RPF] = (uint16_t)(o[i] >> 16);
     }
   }
   __syncthreads();
@@ -122,8 +148,7 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
   const int nch = nbh * T::CPB;
   for (int c = tid; c < nch; c += 256) {
     const int b = c / T::CPB, q = c % T::CPB;
-    const int r = q / (W / T::CH), c0 = (q % (W / T::CH)) * T::CH;
-    const uint16_t* s = rm + b * T::RMB + r * T::RP + c0;
+    const uint16_t* s = rm + b * T::RMBF + q * T::CH;
     if constexpr (T::CH == 8)
       reinterpret_cast<uint4*>(out)[c] = *reinterpret_cast<const uint4*>(s);
     else
@@ -135,9 +160,10 @@ template <int LW, int LH, class AH, class AV>
 __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   using T = Tile<LW, LH>;
   constexpr int W = T::W, H = T::H, NB = T::NB;
-  __shared__ __align__(16) uint32_t pc[NB * T::PCB];
-  __shared__ __align__(16) uint16_t rm[NB * T::RMB];
-  uint16_t* pch = reinterpret_cast<uint16_t*>(pc);
+  __shared__ __align__(16) uint32_t lds[T::LDS_I];
+  uint32_t* pc = lds;
+  uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
+  uint16_t* rm = reinterpret_cast<uint16_t*>(lds);
 
   const int tid = threadIdx.x;
   const int64_t blk0 = (int64_t)blockIdx.x * NB;
@@ -148,6 +174,11 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   const uint32_t* ph_i = static_cast<const uint32_t*>(p.ph_i);
   const uint32_t* pv_f = static_cast<const uint32_t*>(p.pv_f);
   const uint32_t* pv_i = static_cast<const uint32_t*>(p.pv_i);
+
+  constexpr bool MV = fx::wants_mirror<AV, true>();
+  constexpr bool MH = fx::wants_mirror<AH, true>();
+  using PV = fx::Packed<H, MV>;
+  using PH = fx::Packed<W, MH>;
 
   // coalesced load of the tile into the pair-column layout
   const int nch = nbh * T::CPB;
@@ -162,7 +193,7 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
       const uint2 v = reinterpret_cast<const uint2*>(in)[c];
       w[0] = v.x; w[1] = v.y;
     }
-    const int base = (b * T::PCB + (r >> 1) * T::PP + c0) * 2 + (r & 1);
+    const int base = (b * T::PCB + PV::slot(r) * T::PP + c0) * 2 + PV::half(r);
 #pragma unroll
     for (int k = 0; k < T::CH / 2; ++k) {
       pch[base + (2 * k) * 2] = (uint16_t)w[k];
@@ -171,19 +202,27 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   }
   __syncthreads();
 
-  // column pass (inverse vertical transform first)
+  // column pass (inverse vertical transform first); then PC is dead and the
+  // same LDS holds RM
+  uint32_t o[H / 2];
   if (tid < NB * W) {
     const int b = tid / W, c = tid % W;
-    fx::Packed<H> z;
+    PV z;
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) z.p[i] = pc[b * T::PCB + i * T::PP + c];
     const auto y = fx::run_pass<H, AV, true>(z, pv_f, pv_i, p.s_col, p.a);
-    const int base = b * T::RMB + c;
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
+  }
+  __syncthreads();
+  if (tid < NB * W) {
+    const int b = tid / W, c = tid % W;
+    // element (r, c) goes to register slot PH::slot(c) of row r
+    const int base = b * T::RMBI + 2 * PH::slot(c) + PH::half(c);
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) {
-      const uint32_t v = y.pair(2 * i, 2 * i + 1);
-      rm[base + (2 * i) * T::RP] = (uint16_t)v;
-      rm[base + (2 * i + 1) * T::RP] = (uint16_t)(v >> 16);
+      rm[base + (2 * i) * T::RPI] = (uint16_t)o[i];
+      rm[base + (2 * i + 1) * T::RPI] = (uint16_t)(o[i] >> 16);
     }
   }
   __syncthreads();
@@ -191,8 +230,8 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   // row pass (inverse horizontal transform), stored straight to global
   if (tid < NB * H) {
     const int b = tid / H, r = tid % H;
-    fx::Packed<W> x;
-    const uint16_t* s = rm + b * T::RMB + r * T::RP;
+    PH x;
+    const uint16_t* s = rm + b * T::RMBI + r * T::RPI;
     if constexpr (W >= 8) {
 #pragma unroll
       for (int q = 0; q < W / 8; ++q) {
@@ -205,10 +244,10 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
     }
     const auto y = fx::run_pass<W, AH, true>(x, ph_f, ph_i, p.s_row, p.a);
     if (b < nbh) {
-      uint32_t o[W / 2];
+      uint32_t o2[W / 2];
 #pragma unroll
-      for (int j = 0; j < W / 2; ++j) o[j] = y.pair(2 * j, 2 * j + 1);
-      store_row<W>(out + (b * H + r) * W, o);
+      for (int j = 0; j < W / 2; ++j) o2[j] = y.pair(2 * j, 2 * j + 1);
+      store_row<W>(out + (b * H + r) * W, o2);
     }
   }
 }
