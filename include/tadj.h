@@ -126,9 +126,11 @@ int ta_fwd_packed(ta_ctx* ctx, int axis_h, int axis_v, int log2w, int log2h,
 int ta_inv_packed(ta_ctx* ctx, int axis_h, int axis_v, int log2w, int log2h,
                   int64_t nblocks, const void* in, void* out, int dtype, ta_stream_t stream);
 
-/* Select the implementation used for direct DST-7/DCT-8 axes in packed
- * batches: 0 = automatic (MFMA where available), 1 = MFMA, 2 = VALU. */
-int ta_set_direct_impl(ta_ctx* ctx, int impl);
+/* Select the kernels used for packed batches: 0 = automatic (the matrix-core
+ * kernels where one is built for the configuration, otherwise the VALU
+ * butterfly kernels), 1 = matrix-core kernels only (TA_EUNSUPPORTED when
+ * none is built), 2 = VALU kernels only.  Both give identical results. */
+int ta_set_impl(ta_ctx* ctx, int impl);
 
 /* Library version string. */
 const char* ta_version(void);

@@ -34,7 +34,7 @@ BASES = {"C2": DCT2, "C3": DCT3, "S2": DST2, "S3": DST3, "S7": DST7, "C8": DCT8}
 TA_OK, TA_EINVAL, TA_EUNSUPPORTED, TA_ENOPARAMS, TA_EHIP = 0, -1, -2, -3, -4
 
 EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis",
-           "ta_fwd_packed", "ta_inv_packed", "ta_set_direct_impl", "ta_version", "ta_last_error")
+           "ta_fwd_packed", "ta_inv_packed", "ta_set_impl", "ta_version", "ta_last_error")
 
 
 class TadjError(RuntimeError):
@@ -67,7 +67,7 @@ def lib() -> ctypes.CDLL:
     L.ta_set_axis.argtypes = [vp, i32, ctypes.POINTER(_Axis)]
     for f in (L.ta_fwd_packed, L.ta_inv_packed):
         f.argtypes = [vp, i32, i32, i32, i32, i64, vp, vp, i32, vp]
-    L.ta_set_direct_impl.argtypes = [vp, i32]
+    L.ta_set_impl.argtypes = [vp, i32]
     L.ta_version.restype = ctypes.c_char_p
     L.ta_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -124,8 +124,9 @@ class Context:
         _check(lib().ta_set_axis(self._h, aid, ctypes.byref(ax)))
         return aid
 
-    def set_direct_impl(self, impl: int):
-        _check(lib().ta_set_direct_impl(self._h, impl))
+    def set_impl(self, impl: int):
+        """0: matrix-core kernels where built, else VALU; 1: matrix cores only; 2: VALU only."""
+        _check(lib().ta_set_impl(self._h, impl))
 
     # -- transforms -------------------------------------------------------------
     def _run(self, fn, x, axis_h, axis_v, out):

@@ -269,9 +269,9 @@ using A_C8 = Axis<C_DCT8, ADJ_NONE, 0>;
 
 #define TA_FX(LW, LH, AH, AV)                                                                     \
   {{0, 0, LW, LH, AH::CORE, AH::ADJ, AH::KB, AV::CORE, AV::ADJ, AV::KB},                          \
-   reinterpret_cast<const void*>(&fx_fwd<LW, LH, AH, AV>), Tile<LW, LH>::NB, 256},               \
+   reinterpret_cast<const void*>(&fx_fwd<LW, LH, AH, AV>), Tile<LW, LH>::NB, 256, 0, false},               \
   {{1, 0, LW, LH, AH::CORE, AH::ADJ, AH::KB, AV::CORE, AV::ADJ, AV::KB},                          \
-   reinterpret_cast<const void*>(&fx_inv<LW, LH, AH, AV>), Tile<LW, LH>::NB, 256}
+   reinterpret_cast<const void*>(&fx_inv<LW, LH, AH, AV>), Tile<LW, LH>::NB, 256, 0, false}
 
 const KernelEntry kTable[] = {
     TA_FX(5, 5, A_S3B4, A_S3B4),     // 32x32 adjusted DST-7 (DST-3 + 4-tap band)

@@ -70,7 +70,7 @@ int core_flip(int base) {
 struct ta_ctx {
   int device = 0;
   int bd = 8, m = 8, a = 10;
-  int direct_impl = 0;
+  int impl = 0;   // 0 automatic (matrix cores where built), 1 matrix cores only, 2 VALU only
   ParamSet params[kMaxIds];
   AxisCfg axes[kMaxIds];
   std::vector<void*> allocations;
@@ -137,13 +137,19 @@ int resolve_axis(ta_ctx* c, int id, int n, int dtype, Resolved* r) {
   return TA_OK;
 }
 
-const ta::KernelEntry* find_kernel(const ta::KernelKey& key, int prefer_mfma) {
+const ta::KernelEntry* find_kernel(const ta::KernelKey& key, int prefer_mfma, bool mfma_only, bool same) {
   int cnt = 0;
-  if (prefer_mfma && key.dtype == TA_I16) {
+  // Automatic selection uses the matrix-core kernels only where they are the
+  // faster ones on gfx950: cores without a band adjustment.  With a band the
+  // per-lane tap registers limit occupancy and the VALU butterfly kernels win
+  // (both are exact; impl 1 forces the matrix-core kernels).
+  const bool band = key.adj_h == TA_ADJ_BAND || key.adj_v == TA_ADJ_BAND;
+  if (prefer_mfma && key.dtype == TA_I16 && (mfma_only || !band)) {
     const ta::KernelEntry* t = ta::mfma_kernels(&cnt);
     for (int i = 0; i < cnt; ++i)
-      if (t[i].key == key) return &t[i];
+      if (t[i].key == key && (!t[i].same_params || same)) return &t[i];
   }
+  if (mfma_only) return nullptr;
   const ta::KernelEntry* t = key.dtype == TA_I16 ? ta::fx_kernels(&cnt) : ta::f32_kernels(&cnt);
   for (int i = 0; i < cnt; ++i)
     if (t[i].key == key) return &t[i];
@@ -170,10 +176,10 @@ int run_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int log2w, int log2h,
   if ((e = resolve_axis(c, axis_h, 1 << log2w, dtype, &rh))) return e;
   if ((e = resolve_axis(c, axis_v, 1 << log2h, dtype, &rv))) return e;
   const ta::KernelKey key{inv, dtype, log2w, log2h, rh.core, rh.adj, rh.kb, rv.core, rv.adj, rv.kb};
-  const bool direct = (rh.core == TA_DST7 || rh.core == TA_DCT8) && (rv.core == TA_DST7 || rv.core == TA_DCT8);
-  const int prefer_mfma = direct && c->direct_impl != 2;
-  const ta::KernelEntry* k = find_kernel(key, prefer_mfma);
-  if (!k && c->direct_impl == 1 && direct) return fail(TA_EUNSUPPORTED, "no MFMA kernel for this direct transform");
+  const int prefer_mfma = c->impl != 2;
+  const bool same = rh.pf == rv.pf && rh.pi == rv.pi && rh.kb == rv.kb;
+  const ta::KernelEntry* k = find_kernel(key, prefer_mfma, c->impl == 1, same);
+  if (!k && c->impl == 1) return fail(TA_EUNSUPPORTED, "no matrix-core kernel for this transform");
   if (!k)
     return fail(TA_EUNSUPPORTED,
                 "no kernel for %s %s %dx%d axes (core %d adj %d k/b %d) x (core %d adj %d k/b %d)",
@@ -195,7 +201,8 @@ int run_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int log2w, int log2h,
     args.s_col = c->m + 1;
   }
   args.a = c->a;
-  const int64_t groups = (nblocks + k->blocks_per_wg - 1) / k->blocks_per_wg;
+  int64_t groups = (nblocks + k->blocks_per_wg - 1) / k->blocks_per_wg;
+  if (k->max_wgs > 0 && groups > k->max_wgs) groups = k->max_wgs;
   if (groups > 0x7fffffff) return fail(TA_EUNSUPPORTED, "batch too large for one launch");
   void* kargs[] = {&args};
   TA_HIP(hipSetDevice(c->device));
@@ -238,10 +245,10 @@ int ta_destroy(ta_ctx* c) {
   return TA_OK;
 }
 
-int ta_set_direct_impl(ta_ctx* c, int impl) {
+int ta_set_impl(ta_ctx* c, int impl) {
   if (!c) return fail(TA_EINVAL, "null context");
   if (impl < 0 || impl > 2) return fail(TA_EINVAL, "impl %d not in 0..2", impl);
-  c->direct_impl = impl;
+  c->impl = impl;
   return TA_OK;
 }
 

@@ -34,8 +34,10 @@ struct KernelKey {
 struct KernelEntry {
   KernelKey key;
   const void* fn;     // __global__ function
-  int blocks_per_wg;  // blocks of the batch handled by one workgroup
+  int blocks_per_wg;  // blocks of the batch handled by one workgroup (per iteration)
   int threads;        // workgroup size
+  int max_wgs;        // persistent kernels: grid cap (0 = one workgroup per tile)
+  bool same_params;   // requires the horizontal and vertical parameters to be the same set
 };
 
 // Tables of compiled kernels (defined in the kernel translation units).

@@ -26,6 +26,19 @@ def reg():
     return Registered(0)
 
 
+# forward cases that also have a matrix-core (int8 MFMA) kernel
+MFMA_FWD = ["cfg2_dst7_k4", "cfg2_dct8_k4", "cfg2_dst7_k6", "direct_dst7_32", "dct2_32"]
+# inverse cases with a matrix-core kernel
+MFMA_INV = ["direct_dst7_32", "dct2_32"]
+
+
+@pytest.fixture
+def impl(reg, request):
+    reg.ctx.set_impl(request.param)
+    yield request.param
+    reg.ctx.set_impl(0)
+
+
 def _ragged(w, h):
     nb_per_wg = 256 // max(w, h)
     return 3 * nb_per_wg + 5
@@ -140,3 +153,51 @@ def test_full_size_sampled(reg, name, wl):
     assert (ys == F.fwd2d(x[idx], oh, ov)).all()
     assert (zs == F.inv2d(ys, oh, ov)).all()
     del xd, y, z
+
+
+@pytest.mark.parametrize("impl", [1, 2], indirect=True, ids=["matrix", "valu"])
+@pytest.mark.parametrize("name", MFMA_FWD)
+def test_matrix_core_forward_bit_exact(reg, name, impl):
+    """The int8-MFMA forward kernels and the VALU butterfly kernels both match
+    the oracle bit for bit (AR(1) data, ragged count, adversarial sets)."""
+    w, h = CASES[name][:2]
+    ah, av = reg.axes[name]
+    oh, ov = reg.oracle_axes(name)
+    print(f"impl {impl} case {name}", flush=True)
+    sets = [synth.ar1_blocks(61, h, w, 0.95, 16.0, seed=202)]
+    sets += [synth.adversarial_blocks(h, w, k, seed=6, n=7) for k in
+             ("pos", "neg", "checker", "uniform_res", "full16", "extreme16")]
+    for x in sets:
+        got = reg.ctx.fwd(_gpu(x), ah, av).cpu().numpy()
+        ref = F.fwd2d(x, oh, ov)
+        mism = np.argwhere(got != ref)
+        assert mism.size == 0, f"{len(mism)} mismatches, first {mism[:3].tolist()}"
+
+
+@pytest.mark.parametrize("impl", [1], indirect=True, ids=["matrix"])
+def test_matrix_core_full_size_sampled(reg, impl):
+    x = synth.workload_blocks("cfg2_32x32")
+    ah, av = reg.axes["cfg2_dst7_k4"]
+    y = reg.ctx.fwd(_gpu(x), ah, av)
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(78))
+    idx = np.concatenate([np.sort(rng.choice(x.shape[0], size=48, replace=False)), [0, x.shape[0] - 1]])
+    oh, ov = reg.oracle_axes("cfg2_dst7_k4")
+    assert (y[torch.from_numpy(idx).cuda()].cpu().numpy() == F.fwd2d(x[idx], oh, ov)).all()
+
+
+@pytest.mark.parametrize("impl", [1, 2], indirect=True, ids=["matrix", "valu"])
+@pytest.mark.parametrize("name", MFMA_INV)
+def test_matrix_core_inverse_bit_exact(reg, name, impl):
+    w, h = CASES[name][:2]
+    ah, av = reg.axes[name]
+    oh, ov = reg.oracle_axes(name)
+    print(f"impl {impl} inverse case {name}", flush=True)
+    sets = [F.fwd2d(synth.ar1_blocks(61, h, w, 0.95, 16.0, seed=203), oh, ov).astype(np.int16)]
+    sets += [synth.adversarial_blocks(h, w, k, seed=7, n=7) for k in
+             ("pos", "neg", "checker", "uniform_res", "full16", "extreme16")]
+    for x in sets:
+        got = reg.ctx.inv(_gpu(x), ah, av).cpu().numpy()
+        ref = F.inv2d(x, oh, ov)
+        mism = np.argwhere(got != ref)
+        assert mism.size == 0, f"{len(mism)} mismatches, first {mism[:3].tolist()}"
