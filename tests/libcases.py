@@ -51,6 +51,12 @@ CASES = {
     "dct2_dst7band_8x32": (8, 32, (ta.DCT2, ta.ADJ_NONE, False, None), S3B4_32),
 }
 
+# cases built only for the fp32 kernels
+F32_ONLY = {
+    "dst2_dct8_8x16": (8, 16, (ta.DST2, ta.ADJ_NONE, False, None), (ta.DCT8, ta.ADJ_NONE, False, None)),
+}
+ALL_CASES = {**CASES, **F32_ONLY}
+
 
 class Registered:
     """A context with every frozen parameter set and every case's axes."""
@@ -61,7 +67,7 @@ class Registered:
         self.params = ta.load_param_file()
         self.axes = {}
         nxt = 0
-        for name, (w, h, sh, sv) in CASES.items():
+        for name, (w, h, sh, sv) in ALL_CASES.items():
             pair = []
             for spec in (sh, sv):
                 base, adj, flip, pname = spec
@@ -72,5 +78,5 @@ class Registered:
             self.axes[name] = tuple(pair)
 
     def oracle_axes(self, name):
-        w, h, sh, sv = CASES[name]
+        w, h, sh, sv = ALL_CASES[name]
         return (oracle_axis(self.params, *sh), oracle_axis(self.params, *sv))
