@@ -126,6 +126,32 @@ int ta_fwd_packed(ta_ctx* ctx, int axis_h, int axis_v, int log2w, int log2h,
 int ta_inv_packed(ta_ctx* ctx, int axis_h, int axis_v, int log2w, int log2h,
                   int64_t nblocks, const void* in, void* out, int dtype, ta_stream_t stream);
 
+/* ---- Batched uneven blocks (block lists) ----------------------------------
+ * A plan takes a host array of n ta_block descriptors (block sizes 4..64 per
+ * side, any mix) whose axes resolve to DCT-2, or to a DST-3 + 4-tap band
+ * (adjusted DST-7, or with flip = 1 adjusted DCT-8): each axis id names the
+ * parameter set of its size, so a workload registers one axis id per
+ * (type, size).  Offsets and row strides are in elements and must be
+ * multiples of 8 (4 for 4-wide blocks); the forward reads the residual
+ * block at (in_off, in_stride) of `in` and writes its coefficients at
+ * (out_off, out_stride) of `out`; the inverse reads coefficients at
+ * (in_off, in_stride) and writes residuals at (out_off, out_stride).
+ * ta_plan_create copies the descriptors to device memory, grouped by
+ * (size, kinds) into tiles (synchronous, allocates).  ta_plan_fwd/_inv run
+ * the whole plan as one persistent kernel launch on the stream
+ * (asynchronous, no allocation, capturable in a HIP graph).
+ * ta_plan_autotune times the persistent grid sizes on the given buffers,
+ * checks that every candidate's output is bitwise identical, and keeps the
+ * fastest (synchronous, allocates scratch; runs the forward).  Blocks must
+ * not overlap in `out`. */
+typedef struct ta_plan ta_plan;
+int ta_plan_create(ta_ctx* ctx, const ta_block* blocks_host, int64_t n, int dtype, ta_plan** out);
+int ta_plan_destroy(ta_plan* plan);
+int ta_plan_info(const ta_plan* plan, int64_t* nblocks, int64_t* ntiles, int* grid);
+int ta_plan_fwd(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream);
+int ta_plan_inv(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream);
+int ta_plan_autotune(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream, int reps);
+
 /* Select the kernels used for packed batches: 0 = automatic (the matrix-core
  * kernels where one is built for the configuration, otherwise the VALU
  * butterfly kernels), 1 = matrix-core kernels only (TA_EUNSUPPORTED when

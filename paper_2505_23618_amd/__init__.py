@@ -34,7 +34,15 @@ BASES = {"C2": DCT2, "C3": DCT3, "S2": DST2, "S3": DST3, "S7": DST7, "C8": DCT8}
 TA_OK, TA_EINVAL, TA_EUNSUPPORTED, TA_ENOPARAMS, TA_EHIP = 0, -1, -2, -3, -4
 
 EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis",
-           "ta_fwd_packed", "ta_inv_packed", "ta_set_impl", "ta_version", "ta_last_error")
+           "ta_fwd_packed", "ta_inv_packed", "ta_set_impl", "ta_version", "ta_last_error",
+           "ta_plan_create", "ta_plan_destroy", "ta_plan_info", "ta_plan_fwd", "ta_plan_inv",
+           "ta_plan_autotune")
+
+# ta_block (32 bytes), as a numpy structured dtype
+BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
+                        ("log2w", "u1"), ("log2h", "u1"), ("axis_h", "<u2"), ("axis_v", "<u2"),
+                        ("reserved", "<u2")])
+assert BLOCK_DTYPE.itemsize == 32
 
 
 class TadjError(RuntimeError):
@@ -68,6 +76,12 @@ def lib() -> ctypes.CDLL:
     for f in (L.ta_fwd_packed, L.ta_inv_packed):
         f.argtypes = [vp, i32, i32, i32, i32, i64, vp, vp, i32, vp]
     L.ta_set_impl.argtypes = [vp, i32]
+    L.ta_plan_create.argtypes = [vp, vp, i64, i32, ctypes.POINTER(vp)]
+    L.ta_plan_destroy.argtypes = [vp]
+    L.ta_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.ta_plan_fwd.argtypes = [vp, vp, vp, vp, vp]
+    L.ta_plan_inv.argtypes = [vp, vp, vp, vp, vp]
+    L.ta_plan_autotune.argtypes = [vp, vp, vp, vp, vp, i32]
     L.ta_version.restype = ctypes.c_char_p
     L.ta_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -165,6 +179,49 @@ class Context:
         _check(lib().ta_inv_packed(self._h, axis_h, axis_v, log2w, log2h, nblocks,
                                    ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr), dtype,
                                    ctypes.c_void_p(stream_handle)))
+
+
+class Plan:
+    """A batched plan over a list of uneven blocks (``BLOCK_DTYPE`` records)."""
+
+    def __init__(self, ctx: Context, blocks: np.ndarray, dtype: int = I16):
+        blocks = np.ascontiguousarray(blocks, dtype=BLOCK_DTYPE)
+        self.ctx = ctx
+        self._h = ctypes.c_void_p()
+        _check(lib().ta_plan_create(ctx._h, blocks.ctypes.data, len(blocks), dtype, ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().ta_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        nb, nt, g = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        _check(lib().ta_plan_info(self._h, ctypes.byref(nb), ctypes.byref(nt), ctypes.byref(g)))
+        return {"blocks": nb.value, "tiles": nt.value, "grid": g.value}
+
+    def fwd(self, x, out, stream_handle=None):
+        sh = _stream_handle(None) if stream_handle is None else ctypes.c_void_p(stream_handle)
+        _check(lib().ta_plan_fwd(self.ctx._h, self._h, ctypes.c_void_p(x.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()), sh))
+        return out
+
+    def inv(self, y, out, stream_handle=None):
+        sh = _stream_handle(None) if stream_handle is None else ctypes.c_void_p(stream_handle)
+        _check(lib().ta_plan_inv(self.ctx._h, self._h, ctypes.c_void_p(y.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()), sh))
+        return out
+
+    def autotune(self, x, out, reps: int = 3):
+        _check(lib().ta_plan_autotune(self.ctx._h, self._h, ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_handle(None), reps))
+        return self.info()
 
 
 def load_param_file(path: Path = PARAMS_PATH) -> dict:

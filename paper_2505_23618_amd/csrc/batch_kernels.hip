@@ -1,0 +1,331 @@
+// Batched uneven blocks: one persistent launch over a planned list of tiles.
+//
+// The host planner groups blocks by (W, H, horizontal kind, vertical kind)
+// and cuts the groups into tiles of NB = 256 / max(W, H) blocks.  Each
+// workgroup walks the tile list with a grid stride.  Within a tile the
+// forward runs the same phases as the packed kernels (rows -> pair-column
+// LDS -> columns -> row-major LDS -> coalesced stores), but block addresses
+// come from the block descriptors (offsets and row strides into frame
+// buffers) and the block size and kinds are wave-uniform runtime values:
+// the row phase dispatches on (W, row kind), the column phase on (H, column
+// kind), so the kernel holds 15 row bodies and 15 column bodies per
+// direction rather than one body per (W, H, kind, kind).
+//
+// Kinds: 0 = DCT-2, 1 = DST-3 + 4-tap band (adjusted DST-7),
+//        2 = DCT-3 + 4-tap band with flipped taps (adjusted DCT-8, eq. 3).
+#include "fx.hpp"
+#include "kernels.hpp"
+
+namespace ta {
+
+// One tile of the plan (device memory, written by the host planner).
+
+
+namespace {
+
+using fx::Axis;
+using KC2 = Axis<C_DCT2, ADJ_NONE, 0>;
+using KS3 = Axis<C_DST3, ADJ_BAND, 4>;
+using KC3 = Axis<C_DCT3, ADJ_BAND, 4>;
+
+// LDS needed by one tile of W x H blocks (dwords), pair-column and row-major
+// views aliased as in the packed kernels
+constexpr int tile_lds(int lw, int lh) {
+  const int w = 1 << lw, h = 1 << lh, nb = 256 / (w > h ? w : h);
+  const int pc = nb * (h / 2) * (w + 1);
+  const int rmi = nb * (h * (w >= 8 ? w + 8 : w) + (w >= 8 ? 32 : 0));
+  const int rm = (rmi + 1) / 2;
+  return pc > rm ? pc : rm;
+}
+constexpr int max_tile_lds() {
+  int m = 0;
+  for (int lw = 2; lw <= 6; ++lw)
+    for (int lh = 2; lh <= 6; ++lh) m = tile_lds(lw, lh) > m ? tile_lds(lw, lh) : m;
+  return m;
+}
+constexpr int kBatchLds = max_tile_lds();
+
+// Runtime geometry of the tile being processed (wave-uniform).
+struct Geo {
+  int W, H, NB, PP, PCB, RP, RMB, CH;
+  TA_DEV Geo(int lw, int lh) {
+    W = 1 << lw;
+    H = 1 << lh;
+    NB = 256 / (W > H ? W : H);
+    PP = W + 1;
+    PCB = (H / 2) * PP;
+    RP = W >= 8 ? W + 8 : W;
+    RMB = H * RP + (W >= 8 ? 32 : 0);
+    CH = W >= 8 ? 8 : 4;
+  }
+};
+
+// slot/half of element i in a packed vector of length n (mirrored pairs for a
+// DCT-2 butterfly consumer, natural pairs otherwise)
+TA_DEV int slot_of(int i, int n, bool mirror) { return mirror ? (i < n / 2 ? i : n - 1 - i) : (i >> 1); }
+TA_DEV int half_of(int i, int n, bool mirror) { return mirror ? (i < n / 2 ? 0 : 1) : (i & 1); }
+
+template <int W>
+TA_DEV void load_strided_row(const int16_t* __restrict__ src, fx::Packed<W>& x) {
+  if constexpr (W >= 8) {
+#pragma unroll
+    for (int q = 0; q < W / 8; ++q) {
+      const uint4 v = reinterpret_cast<const uint4*>(src)[q];
+      x.p[4 * q] = v.x; x.p[4 * q + 1] = v.y; x.p[4 * q + 2] = v.z; x.p[4 * q + 3] = v.w;
+    }
+  } else {
+    const uint2 v = *reinterpret_cast<const uint2*>(src);
+    x.p[0] = v.x; x.p[1] = v.y;
+  }
+}
+
+// ---------------------------------------------------------------- forward
+// row phase of one tile for kind KH at width W
+template <int W, class KH>
+TA_DEV void fwd_rows(const BatchArgs& a, const BatchTile& t, const Geo& g, uint16_t* pch, bool mirror_v,
+                     int s_row) {
+  const int tid = threadIdx.x;
+  if (tid >= t.count * g.H) return;
+  const int b = tid / g.H, r = tid % g.H;
+  const ta_block d = a.blocks[t.first + b];
+  fx::Packed<W> x;
+  load_strided_row<W>(a.in + d.in_off + (int64_t)r * d.in_stride, x);
+  const auto y = fx::run_pass<W, KH, false>(x, t.ph_f, t.ph_i, s_row, a.a);
+  const int base = (b * g.PCB + slot_of(r, g.H, mirror_v) * g.PP) * 2 + half_of(r, g.H, mirror_v);
+#pragma unroll
+  for (int j = 0; j < W / 2; ++j) {
+    const uint32_t v = y.pair(2 * j, 2 * j + 1);
+    pch[base + (2 * j) * 2] = (uint16_t)v;
+    pch[base + (2 * j + 1) * 2] = (uint16_t)(v >> 16);
+  }
+}
+
+// column phase: read PC, transform, barrier (PC dead), write RM (pitch W)
+template <int H, class KV>
+TA_DEV void fwd_cols(const BatchArgs& a, const BatchTile& t, const Geo& g, uint32_t* lds, int s_col) {
+  constexpr bool MV = fx::wants_mirror<KV, false>();
+  const int tid = threadIdx.x;
+  const bool act = tid < t.count * g.W;
+  const int b = act ? tid / g.W : 0, c = act ? tid % g.W : 0;
+  uint32_t o[H / 2];
+  if (act) {
+    fx::Packed<H, MV> z;
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) z.p[i] = lds[b * g.PCB + i * g.PP + c];
+    const auto y = fx::run_pass<H, KV, false>(z, t.pv_f, t.pv_i, s_col, a.a);
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
+  }
+  __syncthreads();
+  if (act) {
+    uint16_t* rm = reinterpret_cast<uint16_t*>(lds);
+    const int rmb = H * g.W + (g.W >= 8 ? 32 : 0);
+    const int base = b * rmb + c;
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) {
+      rm[base + (2 * i) * g.W] = (uint16_t)o[i];
+      rm[base + (2 * i + 1) * g.W] = (uint16_t)(o[i] >> 16);
+    }
+  }
+}
+
+template <class KH>
+TA_DEV void fwd_rows_w(const BatchArgs& a, const BatchTile& t, const Geo& g, uint16_t* pch, bool mv, int s) {
+  switch (t.lw) {
+    case 2: fwd_rows<4, KH>(a, t, g, pch, mv, s); break;
+    case 3: fwd_rows<8, KH>(a, t, g, pch, mv, s); break;
+    case 4: fwd_rows<16, KH>(a, t, g, pch, mv, s); break;
+    case 5: fwd_rows<32, KH>(a, t, g, pch, mv, s); break;
+    default: fwd_rows<64, KH>(a, t, g, pch, mv, s); break;
+  }
+}
+
+template <class KV>
+TA_DEV void fwd_cols_h(const BatchArgs& a, const BatchTile& t, const Geo& g, uint32_t* lds, int s) {
+  switch (t.lh) {
+    case 2: fwd_cols<4, KV>(a, t, g, lds, s); break;
+    case 3: fwd_cols<8, KV>(a, t, g, lds, s); break;
+    case 4: fwd_cols<16, KV>(a, t, g, lds, s); break;
+    case 5: fwd_cols<32, KV>(a, t, g, lds, s); break;
+    default: fwd_cols<64, KV>(a, t, g, lds, s); break;
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_fwd(BatchArgs a) {
+  __shared__ __align__(16) uint32_t lds[kBatchLds];
+  uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
+  for (int64_t ti = blockIdx.x; ti < a.ntiles; ti += gridDim.x) {
+    const BatchTile t = a.tiles[ti];
+    const Geo g(t.lw, t.lh);
+    const int s_row = t.lw + a.bd + a.m - 15, s_col = t.lh + a.m;
+    // the column consumer's pairing: DCT-2 (kind 0) reads mirrored pairs
+    const bool mv = t.kind_v == 0;
+    switch (t.kind_h) {
+      case 0: fwd_rows_w<KC2>(a, t, g, pch, mv, s_row); break;
+      case 1: fwd_rows_w<KS3>(a, t, g, pch, mv, s_row); break;
+      default: fwd_rows_w<KC3>(a, t, g, pch, mv, s_row); break;
+    }
+    __syncthreads();
+    switch (t.kind_v) {
+      case 0: fwd_cols_h<KC2>(a, t, g, lds, s_col); break;
+      case 1: fwd_cols_h<KS3>(a, t, g, lds, s_col); break;
+      default: fwd_cols_h<KC3>(a, t, g, lds, s_col); break;
+    }
+    __syncthreads();
+    // coalesced store of the tile (RM pitch W, chunks of CH halfwords)
+    const int rmb = g.H * g.W + (g.W >= 8 ? 32 : 0);
+    const int cpr = g.W / g.CH, cpb = g.H * cpr;
+    const int nch = t.count * cpb;
+    for (int c = threadIdx.x; c < nch; c += 256) {
+      const int b = c / cpb, q = c % cpb, r = q / cpr, c0 = (q % cpr) * g.CH;
+      const ta_block d = a.blocks[t.first + b];
+      int16_t* dst = a.out + d.out_off + (int64_t)r * d.out_stride + c0;
+      const uint16_t* src = pch + b * rmb + r * g.W + c0;
+      if (g.CH == 8)
+        *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+      else
+        *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(src);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- inverse
+template <int H, class KV>
+TA_DEV void inv_cols(const BatchArgs& a, const BatchTile& t, const Geo& g, uint32_t* lds, bool mirror_h, int s_col) {
+  constexpr bool MV = fx::wants_mirror<KV, true>();
+  const int tid = threadIdx.x;
+  const bool act = tid < t.count * g.W;
+  const int b = act ? tid / g.W : 0, c = act ? tid % g.W : 0;
+  uint32_t o[H / 2];
+  if (act) {
+    fx::Packed<H, MV> z;
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) z.p[i] = lds[b * g.PCB + i * g.PP + c];
+    const auto y = fx::run_pass<H, KV, true>(z, t.pv_f, t.pv_i, s_col, a.a);
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
+  }
+  __syncthreads();
+  if (act) {
+    uint16_t* rm = reinterpret_cast<uint16_t*>(lds);
+    const int base = b * g.RMB + 2 * slot_of(c, g.W, mirror_h) + half_of(c, g.W, mirror_h);
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) {
+      rm[base + (2 * i) * g.RP] = (uint16_t)o[i];
+      rm[base + (2 * i + 1) * g.RP] = (uint16_t)(o[i] >> 16);
+    }
+  }
+}
+
+template <int W, class KH>
+TA_DEV void inv_rows(const BatchArgs& a, const BatchTile& t, const Geo& g, const uint16_t* rm, int s_row) {
+  constexpr bool MH = fx::wants_mirror<KH, true>();
+  const int tid = threadIdx.x;
+  if (tid >= t.count * g.H) return;
+  const int b = tid / g.H, r = tid % g.H;
+  fx::Packed<W, MH> x;
+  const uint16_t* s = rm + b * g.RMB + r * g.RP;
+  if constexpr (W >= 8) {
+#pragma unroll
+    for (int q = 0; q < W / 8; ++q) {
+      const uint4 v = reinterpret_cast<const uint4*>(s)[q];
+      x.p[4 * q] = v.x; x.p[4 * q + 1] = v.y; x.p[4 * q + 2] = v.z; x.p[4 * q + 3] = v.w;
+    }
+  } else {
+    const uint2 v = *reinterpret_cast<const uint2*>(s);
+    x.p[0] = v.x; x.p[1] = v.y;
+  }
+  const auto y = fx::run_pass<W, KH, true>(x, t.ph_f, t.ph_i, s_row, a.a);
+  const ta_block d = a.blocks[t.first + b];
+  int16_t* dst = a.out + d.out_off + (int64_t)r * d.out_stride;
+  uint32_t o[W / 2];
+#pragma unroll
+  for (int j = 0; j < W / 2; ++j) o[j] = y.pair(2 * j, 2 * j + 1);
+  if constexpr (W >= 8) {
+#pragma unroll
+    for (int q = 0; q < W / 8; ++q)
+      reinterpret_cast<uint4*>(dst)[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+  } else {
+    *reinterpret_cast<uint2*>(dst) = make_uint2(o[0], o[1]);
+  }
+}
+
+template <class KV>
+TA_DEV void inv_cols_h(const BatchArgs& a, const BatchTile& t, const Geo& g, uint32_t* lds, bool mh, int s) {
+  switch (t.lh) {
+    case 2: inv_cols<4, KV>(a, t, g, lds, mh, s); break;
+    case 3: inv_cols<8, KV>(a, t, g, lds, mh, s); break;
+    case 4: inv_cols<16, KV>(a, t, g, lds, mh, s); break;
+    case 5: inv_cols<32, KV>(a, t, g, lds, mh, s); break;
+    default: inv_cols<64, KV>(a, t, g, lds, mh, s); break;
+  }
+}
+
+template <class KH>
+TA_DEV void inv_rows_w(const BatchArgs& a, const BatchTile& t, const Geo& g, const uint16_t* rm, int s) {
+  switch (t.lw) {
+    case 2: inv_rows<4, KH>(a, t, g, rm, s); break;
+    case 3: inv_rows<8, KH>(a, t, g, rm, s); break;
+    case 4: inv_rows<16, KH>(a, t, g, rm, s); break;
+    case 5: inv_rows<32, KH>(a, t, g, rm, s); break;
+    default: inv_rows<64, KH>(a, t, g, rm, s); break;
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_inv(BatchArgs a) {
+  __shared__ __align__(16) uint32_t lds[kBatchLds];
+  uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
+  for (int64_t ti = blockIdx.x; ti < a.ntiles; ti += gridDim.x) {
+    const BatchTile t = a.tiles[ti];
+    const Geo g(t.lw, t.lh);
+    const int s_col = a.m + 1, s_row = a.m + 14 - a.bd;
+    // pairings wanted by the first stage of each inverse pass: the inverse
+    // core of kind 0 is a DCT-3 butterfly (natural pairs); those of kinds 1
+    // and 2 (DST-3^T = DST-2, DCT-3^T = DCT-2) are DCT-2 butterflies, which
+    // take mirrored pairs
+    const bool mv = t.kind_v != 0, mh = t.kind_h != 0;
+    // coalesced load of the tile into the pair-column layout
+    const int cpr = g.W / g.CH, cpb = g.H * cpr;
+    const int nch = t.count * cpb;
+    for (int c = threadIdx.x; c < nch; c += 256) {
+      const int b = c / cpb, q = c % cpb, r = q / cpr, c0 = (q % cpr) * g.CH;
+      const ta_block d = a.blocks[t.first + b];
+      const int16_t* src = a.in + d.in_off + (int64_t)r * d.in_stride + c0;
+      uint32_t w[4];
+      if (g.CH == 8) {
+        const uint4 v = *reinterpret_cast<const uint4*>(src);
+        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+      } else {
+        const uint2 v = *reinterpret_cast<const uint2*>(src);
+        w[0] = v.x; w[1] = v.y; w[2] = 0; w[3] = 0;
+      }
+      const int base = (b * g.PCB + slot_of(r, g.H, mv) * g.PP + c0) * 2 + half_of(r, g.H, mv);
+      for (int k = 0; k < g.CH / 2; ++k) {
+        pch[base + (2 * k) * 2] = (uint16_t)w[k];
+        pch[base + (2 * k + 1) * 2] = (uint16_t)(w[k] >> 16);
+      }
+    }
+    __syncthreads();
+    switch (t.kind_v) {
+      case 0: inv_cols_h<KC2>(a, t, g, lds, mh, s_col); break;
+      case 1: inv_cols_h<KS3>(a, t, g, lds, mh, s_col); break;
+      default: inv_cols_h<KC3>(a, t, g, lds, mh, s_col); break;
+    }
+    __syncthreads();
+    switch (t.kind_h) {
+      case 0: inv_rows_w<KC2>(a, t, g, pch, s_row); break;
+      case 1: inv_rows_w<KS3>(a, t, g, pch, s_row); break;
+      default: inv_rows_w<KC3>(a, t, g, pch, s_row); break;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+const void* batch_kernel(int inv) {
+  return inv ? reinterpret_cast<const void*>(&batch_inv) : reinterpret_cast<const void*>(&batch_fwd);
+}
+
+}  // namespace ta

@@ -4,7 +4,10 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -376,6 +379,206 @@ int ta_fwd_packed(ta_ctx* c, int axis_h, int axis_v, int log2w, int log2h, int64
 int ta_inv_packed(ta_ctx* c, int axis_h, int axis_v, int log2w, int log2h, int64_t nblocks,
                   const void* in, void* out, int dtype, ta_stream_t stream) {
   return run_packed(c, 1, axis_h, axis_v, log2w, log2h, nblocks, in, out, dtype, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched uneven blocks: planning, autotuning, execution
+// ---------------------------------------------------------------------------
+
+struct ta_plan {
+  int device = 0;
+  int64_t nblocks = 0, ntiles = 0;
+  int grid = 2048;                 // persistent workgroups (autotuned)
+  ta_block* blocks_dev = nullptr;  // block descriptors in plan order
+  ta::BatchTile* tiles_dev = nullptr;
+  int64_t max_in_elem = 0, max_out_elem = 0;   // extents touched (for validation)
+};
+
+namespace {
+
+// kind of a resolved axis in the batched kernel (see batch_kernels.hip)
+int batch_kind(const Resolved& r) {
+  if (r.core == TA_DCT2 && r.adj == TA_ADJ_NONE) return 0;
+  if (r.core == TA_DST3 && r.adj == TA_ADJ_BAND && r.kb == 4) return 1;
+  if (r.core == TA_DCT3 && r.adj == TA_ADJ_BAND && r.kb == 4) return 2;
+  return -1;
+}
+
+int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_stream_t stream, int grid) {
+  ta::BatchArgs args;
+  args.tiles = p->tiles_dev;
+  args.ntiles = p->ntiles;
+  args.blocks = p->blocks_dev;
+  args.in = static_cast<const int16_t*>(in);
+  args.out = static_cast<int16_t*>(out);
+  args.bd = c->bd;
+  args.m = c->m;
+  args.a = c->a;
+  void* kargs[] = {&args};
+  const int64_t g = std::min<int64_t>(grid, std::max<int64_t>(1, p->ntiles));
+  TA_HIP(hipSetDevice(c->device));
+  TA_HIP(hipLaunchKernel(ta::batch_kernel(inv), dim3((unsigned)g), dim3(256), kargs, 0,
+                         reinterpret_cast<hipStream_t>(stream)));
+  return TA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_plan** out) {
+  if (!c || !out || (n > 0 && !blocks)) return fail(TA_EINVAL, "null argument");
+  *out = nullptr;
+  if (n < 0) return fail(TA_EINVAL, "negative block count");
+  if (dtype != TA_I16) return fail(TA_EUNSUPPORTED, "batched plans are built for int16 (fixed point) only");
+  // group blocks by (size, kinds, parameter tables)
+  typedef std::tuple<int, int, int, int, const void*, const void*> Key;
+  std::map<Key, std::vector<int64_t>> groups;
+  std::map<Key, std::tuple<Resolved, Resolved>> res;
+  auto plan = std::make_unique<ta_plan>();
+  plan->device = c->device;
+  for (int64_t i = 0; i < n; ++i) {
+    const ta_block& b = blocks[i];
+    if (b.log2w < 2 || b.log2w > 6 || b.log2h < 2 || b.log2h > 6)
+      return fail(TA_EUNSUPPORTED, "block %lld: size %dx%d outside 4..64", (long long)i, 1 << b.log2w, 1 << b.log2h);
+    const int w = 1 << b.log2w, h = 1 << b.log2h, ch = w >= 8 ? 8 : 4;
+    if (b.in_off < 0 || b.out_off < 0 || b.in_stride < w || b.out_stride < w)
+      return fail(TA_EINVAL, "block %lld: negative offset or stride below the width", (long long)i);
+    if (b.in_off % ch || b.out_off % ch || b.in_stride % ch || b.out_stride % ch)
+      return fail(TA_EUNSUPPORTED, "block %lld: offsets and strides must be multiples of %d elements", (long long)i, ch);
+    Resolved rh, rv;
+    int e;
+    if ((e = resolve_axis(c, b.axis_h, w, TA_I16, &rh))) return e;
+    if ((e = resolve_axis(c, b.axis_v, h, TA_I16, &rv))) return e;
+    const int kh = batch_kind(rh), kv = batch_kind(rv);
+    if (kh < 0 || kv < 0)
+      return fail(TA_EUNSUPPORTED, "block %lld: batched kernels take DCT-2, adjusted DST-7 or adjusted DCT-8 "
+                  "(DST-3 + 4-tap band) axes", (long long)i);
+    const Key k{b.log2w, b.log2h, kh, kv, rh.pf, rv.pf};
+    groups[k].push_back(i);
+    res[k] = std::make_tuple(rh, rv);
+    plan->max_in_elem = std::max<int64_t>(plan->max_in_elem, b.in_off + (int64_t)(h - 1) * b.in_stride + w);
+    plan->max_out_elem = std::max<int64_t>(plan->max_out_elem, b.out_off + (int64_t)(h - 1) * b.out_stride + w);
+  }
+  // tiles, largest blocks first
+  std::vector<Key> keys;
+  for (auto& kv : groups) keys.push_back(kv.first);
+  std::stable_sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
+    return std::get<0>(x) + std::get<1>(x) > std::get<0>(y) + std::get<1>(y);
+  });
+  std::vector<ta_block> ordered;
+  std::vector<ta::BatchTile> tiles;
+  ordered.reserve(n);
+  for (const Key& k : keys) {
+    const int lw = std::get<0>(k), lh = std::get<1>(k);
+    const int nb = 256 / std::max(1 << lw, 1 << lh);
+    const Resolved& rh = std::get<0>(res[k]);
+    const Resolved& rv = std::get<1>(res[k]);
+    const auto& idx = groups[k];
+    for (size_t s = 0; s < idx.size(); s += nb) {
+      ta::BatchTile t{};
+      t.lw = lw;
+      t.lh = lh;
+      t.kind_h = std::get<2>(k);
+      t.kind_v = std::get<3>(k);
+      t.first = (int64_t)ordered.size();
+      t.count = (int32_t)std::min<size_t>(nb, idx.size() - s);
+      t.ph_f = static_cast<const uint32_t*>(rh.pf);
+      t.ph_i = static_cast<const uint32_t*>(rh.pi);
+      t.pv_f = static_cast<const uint32_t*>(rv.pf);
+      t.pv_i = static_cast<const uint32_t*>(rv.pi);
+      tiles.push_back(t);
+      for (size_t j = s; j < s + t.count; ++j) ordered.push_back(blocks[idx[j]]);
+    }
+  }
+  plan->nblocks = n;
+  plan->ntiles = (int64_t)tiles.size();
+  TA_HIP(hipSetDevice(c->device));
+  if (n > 0) {
+    TA_HIP(hipMalloc(&plan->blocks_dev, ordered.size() * sizeof(ta_block)));
+    TA_HIP(hipMemcpy(plan->blocks_dev, ordered.data(), ordered.size() * sizeof(ta_block), hipMemcpyHostToDevice));
+    TA_HIP(hipMalloc(&plan->tiles_dev, tiles.size() * sizeof(ta::BatchTile)));
+    TA_HIP(hipMemcpy(plan->tiles_dev, tiles.data(), tiles.size() * sizeof(ta::BatchTile), hipMemcpyHostToDevice));
+  }
+  *out = plan.release();
+  return TA_OK;
+}
+
+int ta_plan_destroy(ta_plan* p) {
+  if (!p) return fail(TA_EINVAL, "null plan");
+  (void)hipSetDevice(p->device);
+  if (p->blocks_dev) (void)hipFree(p->blocks_dev);
+  if (p->tiles_dev) (void)hipFree(p->tiles_dev);
+  delete p;
+  return TA_OK;
+}
+
+int ta_plan_info(const ta_plan* p, int64_t* nblocks, int64_t* ntiles, int* grid) {
+  if (!p) return fail(TA_EINVAL, "null plan");
+  if (nblocks) *nblocks = p->nblocks;
+  if (ntiles) *ntiles = p->ntiles;
+  if (grid) *grid = p->grid;
+  return TA_OK;
+}
+
+int ta_plan_fwd(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t stream) {
+  if (!c || !p) return fail(TA_EINVAL, "null argument");
+  if (p->ntiles == 0) return TA_OK;
+  if (!in || !out) return fail(TA_EINVAL, "null buffer");
+  return launch_plan(c, p, 0, in, out, stream, p->grid);
+}
+
+int ta_plan_inv(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t stream) {
+  if (!c || !p) return fail(TA_EINVAL, "null argument");
+  if (p->ntiles == 0) return TA_OK;
+  if (!in || !out) return fail(TA_EINVAL, "null buffer");
+  return launch_plan(c, p, 1, in, out, stream, p->grid);
+}
+
+int ta_plan_autotune(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t stream, int reps) {
+  if (!c || !p) return fail(TA_EINVAL, "null argument");
+  if (p->ntiles == 0) return TA_OK;
+  if (!in || !out) return fail(TA_EINVAL, "null buffer");
+  if (reps < 1) reps = 3;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TA_HIP(hipSetDevice(c->device));
+  // reference output of the first candidate, to check every candidate bitwise
+  const size_t bytes = (size_t)p->max_out_elem * sizeof(int16_t);
+  void* ref = nullptr;
+  TA_HIP(hipMalloc(&ref, bytes));
+  std::vector<char> ha(bytes), hb(bytes);
+  const int cands[] = {256, 512, 1024, 2048, 4096, 8192};
+  hipEvent_t e0, e1;
+  TA_HIP(hipEventCreate(&e0));
+  TA_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_grid = p->grid;
+  int rc = TA_OK;
+  for (size_t ci = 0; ci < sizeof(cands) / sizeof(cands[0]) && rc == TA_OK; ++ci) {
+    const int g = cands[ci];
+    if ((rc = launch_plan(c, p, 0, in, out, stream, g))) break;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && rc == TA_OK; ++r) rc = launch_plan(c, p, 0, in, out, stream, g);
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(TA_EHIP, "autotune sync failed"); break; }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ci == 0) {
+      if (hipMemcpy(ref, out, bytes, hipMemcpyDeviceToDevice) != hipSuccess) { rc = fail(TA_EHIP, "copy"); break; }
+    } else {
+      if (hipMemcpy(ha.data(), ref, bytes, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(hb.data(), out, bytes, hipMemcpyDeviceToHost) != hipSuccess) { rc = fail(TA_EHIP, "copy"); break; }
+      if (memcmp(ha.data(), hb.data(), bytes) != 0) { rc = fail(TA_EHIP, "autotune candidate %d disagrees", g); break; }
+    }
+    if (ms < best) { best = ms; best_grid = g; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(ref);
+  if (rc == TA_OK) p->grid = best_grid;
+  return rc;
 }
 
 }  // extern "C"

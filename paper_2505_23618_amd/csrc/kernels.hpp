@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/tadj.h"
+
 namespace ta {
 
 // Arguments of the packed-batch kernels (fixed point and fp32).
@@ -39,6 +41,31 @@ struct KernelEntry {
   int max_wgs;        // persistent kernels: grid cap (0 = one workgroup per tile)
   bool same_params;   // requires the horizontal and vertical parameters to be the same set
 };
+
+// One tile of a batched plan (device memory, written by the host planner):
+// up to 256 / max(W, H) blocks of one size and one pair of axis kinds.
+struct BatchTile {
+  int32_t lw, lh, kind_h, kind_v;
+  int64_t first;          // index of the first block descriptor of the tile
+  int32_t count;          // blocks in this tile
+  int32_t pad;
+  const uint32_t* ph_f;   // band taps of the horizontal axis (forward / transposed)
+  const uint32_t* ph_i;
+  const uint32_t* pv_f;   // band taps of the vertical axis
+  const uint32_t* pv_i;
+};
+
+struct BatchArgs {
+  const BatchTile* tiles;
+  int64_t ntiles;
+  const ta_block* blocks;
+  const int16_t* in;
+  int16_t* out;
+  int bd, m, a;
+};
+
+// Persistent batched kernels over a planned tile list (batch_kernels.hip).
+const void* batch_kernel(int inv);
 
 // Tables of compiled kernels (defined in the kernel translation units).
 const KernelEntry* fx_kernels(int* count);
