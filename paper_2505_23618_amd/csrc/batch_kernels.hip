@@ -151,10 +151,14 @@ TA_DEV void fwd_cols_h(const BatchArgs& a, const BatchTile& t, const Geo& g, uin
   }
 }
 
-__global__ __launch_bounds__(256) void batch_fwd(BatchArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_fwd(BatchArgs a) {
   __shared__ __align__(16) uint32_t lds[kBatchLds];
   uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
-  for (int64_t ti = blockIdx.x; ti < a.ntiles; ti += gridDim.x) {
+  // this workgroup's XCD list and its stride within that list
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
+  const int64_t end = a.xstart[xcd + 1];
+  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd) {
     const BatchTile t = a.tiles[ti];
     const Geo g(t.lw, t.lh);
     const int s_row = t.lw + a.bd + a.m - 15, s_col = t.lh + a.m;
@@ -273,10 +277,14 @@ TA_DEV void inv_rows_w(const BatchArgs& a, const BatchTile& t, const Geo& g, con
   }
 }
 
-__global__ __launch_bounds__(256) void batch_inv(BatchArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_inv(BatchArgs a) {
   __shared__ __align__(16) uint32_t lds[kBatchLds];
   uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
-  for (int64_t ti = blockIdx.x; ti < a.ntiles; ti += gridDim.x) {
+  // this workgroup's XCD list and its stride within that list
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
+  const int64_t end = a.xstart[xcd + 1];
+  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd) {
     const BatchTile t = a.tiles[ti];
     const Geo g(t.lw, t.lh);
     const int s_col = a.m + 1, s_row = a.m + 14 - a.bd;

@@ -394,6 +394,7 @@ struct ta_plan {
   ta_block* blocks_dev = nullptr;  // block descriptors in plan order
   ta::BatchTile* tiles_dev = nullptr;
   int64_t max_in_elem = 0, max_out_elem = 0;   // extents touched (for validation)
+  int64_t xstart[ta::kXcds + 1] = {};            // per-XCD tile lists
 };
 
 namespace {
@@ -410,6 +411,7 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
   ta::BatchArgs args;
   args.tiles = p->tiles_dev;
   args.ntiles = p->ntiles;
+  for (int x = 0; x <= ta::kXcds; ++x) args.xstart[x] = p->xstart[x];
   args.blocks = p->blocks_dev;
   args.in = static_cast<const int16_t*>(in);
   args.out = static_cast<int16_t*>(out);
@@ -417,7 +419,8 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
   args.m = c->m;
   args.a = c->a;
   void* kargs[] = {&args};
-  const int64_t g = std::min<int64_t>(grid, std::max<int64_t>(1, p->ntiles));
+  // at least one workgroup per XCD list
+  const int64_t g = std::max<int64_t>(ta::kXcds, std::min<int64_t>(grid, std::max<int64_t>(1, p->ntiles)));
   TA_HIP(hipSetDevice(c->device));
   TA_HIP(hipLaunchKernel(ta::batch_kernel(inv), dim3((unsigned)g), dim3(256), kargs, 0,
                          reinterpret_cast<hipStream_t>(stream)));
@@ -433,8 +436,10 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
   *out = nullptr;
   if (n < 0) return fail(TA_EINVAL, "negative block count");
   if (dtype != TA_I16) return fail(TA_EUNSUPPORTED, "batched plans are built for int16 (fixed point) only");
-  // group blocks by (size, kinds, parameter tables)
-  typedef std::tuple<int, int, int, int, const void*, const void*> Key;
+  // group blocks by (region, size, kinds, parameter tables); a region is a
+  // window of kRegion input elements (about 4 CTU rows of a 3840-wide frame)
+  constexpr int64_t kRegion = int64_t(1) << 20;
+  typedef std::tuple<int64_t, int, int, int, int, const void*, const void*> Key;
   std::map<Key, std::vector<int64_t>> groups;
   std::map<Key, std::tuple<Resolved, Resolved>> res;
   auto plan = std::make_unique<ta_plan>();
@@ -456,23 +461,31 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
     if (kh < 0 || kv < 0)
       return fail(TA_EUNSUPPORTED, "block %lld: batched kernels take DCT-2, adjusted DST-7 or adjusted DCT-8 "
                   "(DST-3 + 4-tap band) axes", (long long)i);
-    const Key k{b.log2w, b.log2h, kh, kv, rh.pf, rv.pf};
+    const Key k{b.in_off / kRegion, b.log2w, b.log2h, kh, kv, rh.pf, rv.pf};
     groups[k].push_back(i);
     res[k] = std::make_tuple(rh, rv);
     plan->max_in_elem = std::max<int64_t>(plan->max_in_elem, b.in_off + (int64_t)(h - 1) * b.in_stride + w);
     plan->max_out_elem = std::max<int64_t>(plan->max_out_elem, b.out_off + (int64_t)(h - 1) * b.out_stride + w);
   }
-  // tiles, largest blocks first
+  // tiles: regions go round-robin to the XCD lists; within a region, larger
+  // blocks first
   std::vector<Key> keys;
   for (auto& kv : groups) keys.push_back(kv.first);
   std::stable_sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
-    return std::get<0>(x) + std::get<1>(x) > std::get<0>(y) + std::get<1>(y);
+    if (std::get<0>(x) != std::get<0>(y)) return std::get<0>(x) < std::get<0>(y);
+    return std::get<1>(x) + std::get<2>(x) > std::get<1>(y) + std::get<2>(y);
   });
   std::vector<ta_block> ordered;
-  std::vector<ta::BatchTile> tiles;
+  std::vector<ta::BatchTile> lists[ta::kXcds];
   ordered.reserve(n);
+  std::map<int64_t, int> region_xcd;
   for (const Key& k : keys) {
-    const int lw = std::get<0>(k), lh = std::get<1>(k);
+    const int64_t region = std::get<0>(k);
+    if (!region_xcd.count(region)) {
+      const int next = (int)region_xcd.size() % ta::kXcds;
+      region_xcd[region] = next;
+    }
+    const int lw = std::get<1>(k), lh = std::get<2>(k);
     const int nb = 256 / std::max(1 << lw, 1 << lh);
     const Resolved& rh = std::get<0>(res[k]);
     const Resolved& rv = std::get<1>(res[k]);
@@ -481,18 +494,24 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
       ta::BatchTile t{};
       t.lw = lw;
       t.lh = lh;
-      t.kind_h = std::get<2>(k);
-      t.kind_v = std::get<3>(k);
+      t.kind_h = std::get<3>(k);
+      t.kind_v = std::get<4>(k);
       t.first = (int64_t)ordered.size();
       t.count = (int32_t)std::min<size_t>(nb, idx.size() - s);
       t.ph_f = static_cast<const uint32_t*>(rh.pf);
       t.ph_i = static_cast<const uint32_t*>(rh.pi);
       t.pv_f = static_cast<const uint32_t*>(rv.pf);
       t.pv_i = static_cast<const uint32_t*>(rv.pi);
-      tiles.push_back(t);
+      lists[region_xcd[region]].push_back(t);
       for (size_t j = s; j < s + t.count; ++j) ordered.push_back(blocks[idx[j]]);
     }
   }
+  std::vector<ta::BatchTile> tiles;
+  for (int x = 0; x < ta::kXcds; ++x) {
+    plan->xstart[x] = (int64_t)tiles.size();
+    tiles.insert(tiles.end(), lists[x].begin(), lists[x].end());
+  }
+  plan->xstart[ta::kXcds] = (int64_t)tiles.size();
   plan->nblocks = n;
   plan->ntiles = (int64_t)tiles.size();
   TA_HIP(hipSetDevice(c->device));

@@ -55,9 +55,16 @@ struct BatchTile {
   const uint32_t* pv_i;
 };
 
+// The plan's tiles form one list per XCD (8 lists, concatenated; list x is
+// tiles[xstart[x] .. xstart[x+1])), ordered region by region, so that the
+// workgroups of one XCD (consecutive workgroup ids go to consecutive XCDs)
+// process the blocks of the same frame region together and share its L2.
+constexpr int kXcds = 8;
+
 struct BatchArgs {
   const BatchTile* tiles;
   int64_t ntiles;
+  int64_t xstart[kXcds + 1];
   const ta_block* blocks;
   const int16_t* in;
   int16_t* out;
