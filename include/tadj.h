@@ -152,6 +152,26 @@ int ta_plan_fwd(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream
 int ta_plan_inv(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream);
 int ta_plan_autotune(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream, int reps);
 
+/* ---- Differentiable refit path (fp32) ---------------------------------------
+ * y_m = B A(theta) x_m for nvec vectors of n floats (x, y: nvec x n, row per
+ * vector), B = TA_DCT2 or TA_DST3, A(theta) = taps/2 layers of parallel
+ * Givens rotations on adjacent pairs (section 2: orthogonality through
+ * sequential sets of parallel Givens rotations), layer l on the pairs
+ * starting at l mod 2, rotation (p, p+1) by t: v_p = cos t u_p - sin t u_p+1,
+ * v_p+1 = sin t u_p + cos t u_p+1; theta holds the angles layer by layer
+ * (31 for n = 32, taps = 4).  n in {16, 32}, taps in {4, 6}.  All pointers
+ * are device memory; calls are asynchronous and allocate nothing.
+ * ta_givens_bwd: given dL/dy (gy), writes dL/dx (gx, may not alias x or gy)
+ * and dL/dtheta (gtheta, overwritten), using a caller-provided device
+ * workspace of ta_givens_workspace(nvec) bytes; the angle gradient is reduced
+ * in a fixed order, so repeated calls are bitwise identical. */
+int ta_givens_workspace(int64_t nvec, int64_t* bytes);
+int ta_givens_fwd(ta_ctx* ctx, int base, int n, int taps, const float* theta, int64_t nvec,
+                  const float* x, float* y, ta_stream_t stream);
+int ta_givens_bwd(ta_ctx* ctx, int base, int n, int taps, const float* theta, int64_t nvec,
+                  const float* x, const float* gy, float* gx, float* gtheta, void* workspace,
+                  ta_stream_t stream);
+
 /* Select the kernels used for packed batches: 0 = automatic (the matrix-core
  * kernels where one is built for the configuration, otherwise the VALU
  * butterfly kernels), 1 = matrix-core kernels only (TA_EUNSUPPORTED when

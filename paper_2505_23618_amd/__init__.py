@@ -36,7 +36,7 @@ TA_OK, TA_EINVAL, TA_EUNSUPPORTED, TA_ENOPARAMS, TA_EHIP = 0, -1, -2, -3, -4
 EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis",
            "ta_fwd_packed", "ta_inv_packed", "ta_set_impl", "ta_version", "ta_last_error",
            "ta_plan_create", "ta_plan_destroy", "ta_plan_info", "ta_plan_fwd", "ta_plan_inv",
-           "ta_plan_autotune")
+           "ta_plan_autotune", "ta_givens_workspace", "ta_givens_fwd", "ta_givens_bwd")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -82,6 +82,9 @@ def lib() -> ctypes.CDLL:
     L.ta_plan_fwd.argtypes = [vp, vp, vp, vp, vp]
     L.ta_plan_inv.argtypes = [vp, vp, vp, vp, vp]
     L.ta_plan_autotune.argtypes = [vp, vp, vp, vp, vp, i32]
+    L.ta_givens_workspace.argtypes = [i64, ctypes.POINTER(i64)]
+    L.ta_givens_fwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp]
+    L.ta_givens_bwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp, vp, vp, vp]
     L.ta_version.restype = ctypes.c_char_p
     L.ta_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:

@@ -601,3 +601,63 @@ int ta_plan_autotune(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Differentiable Givens-band path
+// ---------------------------------------------------------------------------
+namespace {
+int givens_check(ta_ctx* c, int base, int n, int taps, const float* theta, int64_t nvec) {
+  if (!c || !theta) return fail(TA_EINVAL, "null argument");
+  if (nvec < 0) return fail(TA_EINVAL, "negative vector count");
+  if ((n != 16 && n != 32) || (taps != 4 && taps != 6) || (base != TA_DCT2 && base != TA_DST3))
+    return fail(TA_EUNSUPPORTED, "differentiable path: n in {16, 32}, taps in {4, 6}, base DCT-2 or DST-3");
+  return TA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int ta_givens_workspace(int64_t nvec, int64_t* bytes) {
+  if (!bytes || nvec < 0) return fail(TA_EINVAL, "bad argument");
+  *bytes = ((nvec + 255) / 256) * ta::kMaxAng * (int64_t)sizeof(float);
+  return TA_OK;
+}
+
+int ta_givens_fwd(ta_ctx* c, int base, int n, int taps, const float* theta, int64_t nvec, const float* x,
+                  float* y, ta_stream_t stream) {
+  int e;
+  if ((e = givens_check(c, base, n, taps, theta, nvec))) return e;
+  if (nvec == 0) return TA_OK;
+  if (!x || !y) return fail(TA_EINVAL, "null buffer");
+  ta::GivensArgs a{theta, x, nullptr, y, nullptr, nullptr, nvec};
+  void* kargs[] = {&a};
+  TA_HIP(hipSetDevice(c->device));
+  TA_HIP(hipLaunchKernel(ta::givens_kernel(0, n, taps / 2, base), dim3((unsigned)((nvec + 255) / 256)), dim3(256),
+                         kargs, 0, reinterpret_cast<hipStream_t>(stream)));
+  return TA_OK;
+}
+
+int ta_givens_bwd(ta_ctx* c, int base, int n, int taps, const float* theta, int64_t nvec, const float* x,
+                  const float* gy, float* gx, float* gtheta, void* workspace, ta_stream_t stream) {
+  int e;
+  if ((e = givens_check(c, base, n, taps, theta, nvec))) return e;
+  if (!gtheta) return fail(TA_EINVAL, "null gradient buffer");
+  if (nvec > 0 && (!x || !gy || !gx || !workspace)) return fail(TA_EINVAL, "null buffer");
+  const int64_t groups = (nvec + 255) / 256;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TA_HIP(hipSetDevice(c->device));
+  if (groups > 0) {
+    ta::GivensArgs a{theta, x, gy, nullptr, gx, static_cast<float*>(workspace), nvec};
+    void* kargs[] = {&a};
+    TA_HIP(hipLaunchKernel(ta::givens_kernel(1, n, taps / 2, base), dim3((unsigned)groups), dim3(256), kargs, 0, s));
+  }
+  int na = 0;
+  for (int l = 0; l < taps / 2; ++l) na += (n - 2 - (l & 1)) / 2 + 1;
+  const float* part = static_cast<const float*>(workspace);
+  int64_t g64 = groups;
+  void* rargs[] = {&part, &g64, &na, &gtheta};
+  TA_HIP(hipLaunchKernel(ta::givens_reduce_kernel(), dim3(1), dim3(128), rargs, 0, s));
+  return TA_OK;
+}
+
+}  // extern "C"

@@ -74,6 +74,20 @@ struct BatchArgs {
 // Persistent batched kernels over a planned tile list (batch_kernels.hip).
 const void* batch_kernel(int inv);
 
+// Differentiable Givens-band path (givens_kernels.hip).
+constexpr int kMaxAng = 96;   // angle slots per workgroup partial (N <= 32, L <= 3)
+struct GivensArgs {
+  const float* theta;
+  const float* x;
+  const float* gy;
+  float* y;
+  float* gx;
+  float* partial;   // [grid][kMaxAng] per-workgroup angle-gradient partials
+  int64_t nvec;
+};
+const void* givens_kernel(int bwd, int n, int layers, int base);
+const void* givens_reduce_kernel();
+
 // Tables of compiled kernels (defined in the kernel translation units).
 const KernelEntry* fx_kernels(int* count);
 const KernelEntry* f32_kernels(int* count);
