@@ -85,12 +85,89 @@ def cpu_baseline(x: np.ndarray, nsample: int = 8192):
                       f"{dt:.1f} s wall on {cores} processes"}
 
 
+def _events_mean(fn, reps, warm=2):
+    import torch
+    st = torch.cuda.current_stream()
+    for i in range(warm):
+        fn(i)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    for i in range(reps):
+        ev[i].record(st)
+        fn(i)
+    ev[reps].record(st)
+    torch.cuda.synchronize()
+    return float(np.mean([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)])) * 1e-3
+
+
+def secondary(ctx, ids, x32):
+    """The other workloads: 64x64 sub-block (fixed point and fp32), batched
+    uneven frames, and the differentiable refit step."""
+    import torch
+    import synth
+    import paper_2505_23618_amd as ta
+    from paper_2505_23618_amd import refit as RF
+    res = {}
+    # 64x64 blocks, DCT-2 + 16x16 sub-block: DCT-8 rows (eq. 5), DST-7 columns
+    ph = ctx.axis(10, ta.DCT2, ta.ADJ_POST, True, ids["post_C2_S7_N64_B16"])
+    pv = ctx.axis(11, ta.DCT2, ta.ADJ_POST, False, ids["post_C2_S7_N64_B16"])
+    x64 = torch.from_numpy(synth.workload_blocks("cfg3_64x64")).cuda()
+    n64 = x64.numel()
+    y64, z64 = torch.empty_like(x64), torch.empty_like(x64)
+    tf = _events_mean(lambda i: ctx.fwd(x64, ph, pv, out=y64), 10)
+    ti = _events_mean(lambda i: ctx.inv(y64, ph, pv, out=z64), 10)
+    res["subblock_64x64_i16"] = {"value": n64 / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
+                                 "GB/s_fwd": 4 * n64 / tf / 1e9,
+                                 "workload": "65,536 blocks 64x64 AR(1) rho=0.97 sigma=12, DCT-2 + 16x16 sub-block"}
+    xf = x64.float()
+    del y64, z64, x64
+    yf, zf = torch.empty_like(xf), torch.empty_like(xf)
+    tf = _events_mean(lambda i: ctx.fwd(xf, ph, pv, out=yf), 10)
+    ti = _events_mean(lambda i: ctx.inv(yf, ph, pv, out=zf), 10)
+    res["subblock_64x64_f32"] = {"value": n64 / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
+                                 "GB/s_fwd": 8 * n64 / tf / 1e9}
+    del xf, yf, zf
+    torch.cuda.empty_cache()
+    # batched uneven frames: 8 x 3840x2160, 4 buffer sets rotated (> infinity cache)
+    from paper_2505_23618_amd.frames import descriptors as batch_descriptors, register_axes
+    register_axes(ctx, ids)
+    frames, rows = synth.frames_workload()
+    plan = ta.Plan(ctx, batch_descriptors(rows, frames.shape[1], frames.shape[2]))
+    X = [torch.from_numpy(frames).cuda() for _ in range(4)]
+    Y = [torch.empty_like(X[0]) for _ in range(4)]
+    Z = [torch.empty_like(X[0]) for _ in range(4)]
+    info = plan.autotune(X[0], Y[0], reps=3)
+    nco = int((rows[:, 3].astype(np.int64) * rows[:, 4]).sum())
+    tf = _events_mean(lambda i: plan.fwd(X[i % 4], Y[i % 4]), 12)
+    ti = _events_mean(lambda i: plan.inv(Y[i % 4], Z[i % 4]), 12)
+    res["batched_uneven"] = {"value": nco / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
+                             "blocks": len(rows), "coefficients": nco, "tiles": info["tiles"], "grid": info["grid"],
+                             "GB/s_fwd": (4 * nco + 32 * len(rows)) / tf / 1e9,
+                             "workload": "8 frames 3840x2160, QT/BT blocks 4..64, per-axis DCT-2 / adj. DST-7 / adj. DCT-8"}
+    del X, Y, Z, plan
+    torch.cuda.empty_cache()
+    # differentiable refit step: forward + loss + backward on 131,072 vectors
+    xv = torch.tensor(synth.ar1_vectors(131072, 32, 0.85, 0.99, 1.0, seed=synth.SEED_BASE + 4),
+                      dtype=torch.float32, device="cuda")
+    th = torch.zeros(31, dtype=torch.float32, device="cuda", requires_grad=True)
+
+    def step(i):
+        th.grad = None
+        loss, _, _ = RF.refit_loss(xv, th, ctx)
+        loss.backward()
+
+    t = _events_mean(step, 20, warm=3)
+    res["refit_step"] = {"us": t * 1e6, "vectors": 131072, "angles": 31,
+                         "what": "fp32 forward (data + basis) + loss + backward (adjoint and angle gradients)"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also launch one plain copy per step (counter calibration runs)")
     args = ap.parse_args()
@@ -175,6 +252,11 @@ def main():
     tdom = max(ti.mean(), tf.mean())
     achieved = bytes_per_launch / tdom / 1e9
     traffic = _traffic_from_profiles()
+    del y, z
+
+    extra = {} if args.skip_extra else secondary(ctx, ids, x)
+    del x
+    torch.cuda.empty_cache()
 
     out = {
         "metric": "transform coeffs/sec (fwd+inv, 32x32 adjusted DST-7) vs direct-matrix DST-7",
@@ -201,6 +283,7 @@ def main():
             "value": ncoef / (tf7.mean() + ti7.mean()), "unit": "coef/s",
             "fwd_us": tf7.mean() * 1e6, "inv_us": ti7.mean() * 1e6,
             "adjusted_over_direct": (tf7.mean() + ti7.mean()) / (tf.mean() + ti.mean()),
+            "impl": "int8 matrix cores (exact byte-plane split)",
         },
         "copy_same_bytes": {"us": tcopy * 1e6, "GB/s": bytes_per_launch / tcopy / 1e9},
         "roofline": {
@@ -208,6 +291,7 @@ def main():
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
         },
+        **extra,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_host)
