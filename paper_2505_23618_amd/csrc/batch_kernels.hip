@@ -60,11 +60,6 @@ struct Geo {
   }
 };
 
-// slot/half of element i in a packed vector of length n (mirrored pairs for a
-// DCT-2 butterfly consumer, natural pairs otherwise)
-TA_DEV int slot_of(int i, int n, bool mirror) { return mirror ? (i < n / 2 ? i : n - 1 - i) : (i >> 1); }
-TA_DEV int half_of(int i, int n, bool mirror) { return mirror ? (i < n / 2 ? 0 : 1) : (i & 1); }
-
 template <int W>
 TA_DEV void load_strided_row(const int16_t* __restrict__ src, fx::Packed<W>& x) {
   if constexpr (W >= 8) {
@@ -82,16 +77,15 @@ TA_DEV void load_strided_row(const int16_t* __restrict__ src, fx::Packed<W>& x) 
 // ---------------------------------------------------------------- forward
 // row phase of one tile for kind KH at width W
 template <int W, class KH>
-TA_DEV void fwd_rows(const BatchArgs& a, const BatchTile& t, const Geo& g, uint16_t* pch, bool mirror_v,
-                     int s_row) {
+TA_DEV void fwd_rows(const BatchArgs& a, const BatchTile& t, const Geo& g, uint16_t* pch, int s_row) {
   const int tid = threadIdx.x;
   if (tid >= t.count * g.H) return;
   const int b = tid / g.H, r = tid % g.H;
   const ta_block d = a.blocks[t.first + b];
   fx::Packed<W> x;
   load_strided_row<W>(a.in + d.in_off + (int64_t)r * d.in_stride, x);
-  const auto y = fx::run_pass<W, KH, false>(x, t.ph_f, t.ph_i, s_row, a.a);
-  const int base = (b * g.PCB + slot_of(r, g.H, mirror_v) * g.PP) * 2 + half_of(r, g.H, mirror_v);
+  const auto y = fx::run_pass<W, KH, false>(x, as_cparam(t.ph_f), as_cparam(t.ph_i), s_row, a.a);
+  const int base = (b * g.PCB + (r >> 1) * g.PP) * 2 + (r & 1);
 #pragma unroll
   for (int j = 0; j < W / 2; ++j) {
     const uint32_t v = y.pair(2 * j, 2 * j + 1);
@@ -103,16 +97,15 @@ TA_DEV void fwd_rows(const BatchArgs& a, const BatchTile& t, const Geo& g, uint1
 // column phase: read PC, transform, barrier (PC dead), write RM (pitch W)
 template <int H, class KV>
 TA_DEV void fwd_cols(const BatchArgs& a, const BatchTile& t, const Geo& g, uint32_t* lds, int s_col) {
-  constexpr bool MV = fx::wants_mirror<KV, false>();
   const int tid = threadIdx.x;
   const bool act = tid < t.count * g.W;
   const int b = act ? tid / g.W : 0, c = act ? tid % g.W : 0;
   uint32_t o[H / 2];
   if (act) {
-    fx::Packed<H, MV> z;
+    fx::Packed<H> z;
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) z.p[i] = lds[b * g.PCB + i * g.PP + c];
-    const auto y = fx::run_pass<H, KV, false>(z, t.pv_f, t.pv_i, s_col, a.a);
+    const auto y = fx::run_pass<H, KV, false>(z, as_cparam(t.pv_f), as_cparam(t.pv_i), s_col, a.a);
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
   }
@@ -130,13 +123,13 @@ TA_DEV void fwd_cols(const BatchArgs& a, const BatchTile& t, const Geo& g, uint3
 }
 
 template <class KH>
-TA_DEV void fwd_rows_w(const BatchArgs& a, const BatchTile& t, const Geo& g, uint16_t* pch, bool mv, int s) {
+TA_DEV void fwd_rows_w(const BatchArgs& a, const BatchTile& t, const Geo& g, uint16_t* pch, int s) {
   switch (t.lw) {
-    case 2: fwd_rows<4, KH>(a, t, g, pch, mv, s); break;
-    case 3: fwd_rows<8, KH>(a, t, g, pch, mv, s); break;
-    case 4: fwd_rows<16, KH>(a, t, g, pch, mv, s); break;
-    case 5: fwd_rows<32, KH>(a, t, g, pch, mv, s); break;
-    default: fwd_rows<64, KH>(a, t, g, pch, mv, s); break;
+    case 2: fwd_rows<4, KH>(a, t, g, pch, s); break;
+    case 3: fwd_rows<8, KH>(a, t, g, pch, s); break;
+    case 4: fwd_rows<16, KH>(a, t, g, pch, s); break;
+    case 5: fwd_rows<32, KH>(a, t, g, pch, s); break;
+    default: fwd_rows<64, KH>(a, t, g, pch, s); break;
   }
 }
 
@@ -162,12 +155,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
     const BatchTile t = a.tiles[ti];
     const Geo g(t.lw, t.lh);
     const int s_row = t.lw + a.bd + a.m - 15, s_col = t.lh + a.m;
-    // the column consumer's pairing: DCT-2 (kind 0) reads mirrored pairs
-    const bool mv = t.kind_v == 0;
     switch (t.kind_h) {
-      case 0: fwd_rows_w<KC2>(a, t, g, pch, mv, s_row); break;
-      case 1: fwd_rows_w<KS3>(a, t, g, pch, mv, s_row); break;
-      default: fwd_rows_w<KC3>(a, t, g, pch, mv, s_row); break;
+      case 0: fwd_rows_w<KC2>(a, t, g, pch, s_row); break;
+      case 1: fwd_rows_w<KS3>(a, t, g, pch, s_row); break;
+      default: fwd_rows_w<KC3>(a, t, g, pch, s_row); break;
     }
     __syncthreads();
     switch (t.kind_v) {
@@ -196,24 +187,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
 
 // ---------------------------------------------------------------- inverse
 template <int H, class KV>
-TA_DEV void inv_cols(const BatchArgs& a, const BatchTile& t, const Geo& g, uint32_t* lds, bool mirror_h, int s_col) {
-  constexpr bool MV = fx::wants_mirror<KV, true>();
+TA_DEV void inv_cols(const BatchArgs& a, const BatchTile& t, const Geo& g, uint32_t* lds, int s_col) {
   const int tid = threadIdx.x;
   const bool act = tid < t.count * g.W;
   const int b = act ? tid / g.W : 0, c = act ? tid % g.W : 0;
   uint32_t o[H / 2];
   if (act) {
-    fx::Packed<H, MV> z;
+    fx::Packed<H> z;
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) z.p[i] = lds[b * g.PCB + i * g.PP + c];
-    const auto y = fx::run_pass<H, KV, true>(z, t.pv_f, t.pv_i, s_col, a.a);
+    const auto y = fx::run_pass<H, KV, true>(z, as_cparam(t.pv_f), as_cparam(t.pv_i), s_col, a.a);
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
   }
   __syncthreads();
   if (act) {
     uint16_t* rm = reinterpret_cast<uint16_t*>(lds);
-    const int base = b * g.RMB + 2 * slot_of(c, g.W, mirror_h) + half_of(c, g.W, mirror_h);
+    const int base = b * g.RMB + c;
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) {
       rm[base + (2 * i) * g.RP] = (uint16_t)o[i];
@@ -224,11 +214,10 @@ TA_DEV void inv_cols(const BatchArgs& a, const BatchTile& t, const Geo& g, uint3
 
 template <int W, class KH>
 TA_DEV void inv_rows(const BatchArgs& a, const BatchTile& t, const Geo& g, const uint16_t* rm, int s_row) {
-  constexpr bool MH = fx::wants_mirror<KH, true>();
   const int tid = threadIdx.x;
   if (tid >= t.count * g.H) return;
   const int b = tid / g.H, r = tid % g.H;
-  fx::Packed<W, MH> x;
+  fx::Packed<W> x;
   const uint16_t* s = rm + b * g.RMB + r * g.RP;
   if constexpr (W >= 8) {
 #pragma unroll
@@ -240,7 +229,7 @@ TA_DEV void inv_rows(const BatchArgs& a, const BatchTile& t, const Geo& g, const
     const uint2 v = *reinterpret_cast<const uint2*>(s);
     x.p[0] = v.x; x.p[1] = v.y;
   }
-  const auto y = fx::run_pass<W, KH, true>(x, t.ph_f, t.ph_i, s_row, a.a);
+  const auto y = fx::run_pass<W, KH, true>(x, as_cparam(t.ph_f), as_cparam(t.ph_i), s_row, a.a);
   const ta_block d = a.blocks[t.first + b];
   int16_t* dst = a.out + d.out_off + (int64_t)r * d.out_stride;
   uint32_t o[W / 2];
@@ -256,13 +245,13 @@ TA_DEV void inv_rows(const BatchArgs& a, const BatchTile& t, const Geo& g, const
 }
 
 template <class KV>
-TA_DEV void inv_cols_h(const BatchArgs& a, const BatchTile& t, const Geo& g, uint32_t* lds, bool mh, int s) {
+TA_DEV void inv_cols_h(const BatchArgs& a, const BatchTile& t, const Geo& g, uint32_t* lds, int s) {
   switch (t.lh) {
-    case 2: inv_cols<4, KV>(a, t, g, lds, mh, s); break;
-    case 3: inv_cols<8, KV>(a, t, g, lds, mh, s); break;
-    case 4: inv_cols<16, KV>(a, t, g, lds, mh, s); break;
-    case 5: inv_cols<32, KV>(a, t, g, lds, mh, s); break;
-    default: inv_cols<64, KV>(a, t, g, lds, mh, s); break;
+    case 2: inv_cols<4, KV>(a, t, g, lds, s); break;
+    case 3: inv_cols<8, KV>(a, t, g, lds, s); break;
+    case 4: inv_cols<16, KV>(a, t, g, lds, s); break;
+    case 5: inv_cols<32, KV>(a, t, g, lds, s); break;
+    default: inv_cols<64, KV>(a, t, g, lds, s); break;
   }
 }
 
@@ -288,11 +277,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
     const BatchTile t = a.tiles[ti];
     const Geo g(t.lw, t.lh);
     const int s_col = a.m + 1, s_row = a.m + 14 - a.bd;
-    // pairings wanted by the first stage of each inverse pass: the inverse
-    // core of kind 0 is a DCT-3 butterfly (natural pairs); those of kinds 1
-    // and 2 (DST-3^T = DST-2, DCT-3^T = DCT-2) are DCT-2 butterflies, which
-    // take mirrored pairs
-    const bool mv = t.kind_v != 0, mh = t.kind_h != 0;
     // coalesced load of the tile into the pair-column layout
     const int cpr = g.W / g.CH, cpb = g.H * cpr;
     const int nch = t.count * cpb;
@@ -308,7 +292,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
         const uint2 v = *reinterpret_cast<const uint2*>(src);
         w[0] = v.x; w[1] = v.y; w[2] = 0; w[3] = 0;
       }
-      const int base = (b * g.PCB + slot_of(r, g.H, mv) * g.PP + c0) * 2 + half_of(r, g.H, mv);
+      const int base = (b * g.PCB + (r >> 1) * g.PP + c0) * 2 + (r & 1);
       for (int k = 0; k < g.CH / 2; ++k) {
         pch[base + (2 * k) * 2] = (uint16_t)w[k];
         pch[base + (2 * k + 1) * 2] = (uint16_t)(w[k] >> 16);
@@ -316,9 +300,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
     }
     __syncthreads();
     switch (t.kind_v) {
-      case 0: inv_cols_h<KC2>(a, t, g, lds, mh, s_col); break;
-      case 1: inv_cols_h<KS3>(a, t, g, lds, mh, s_col); break;
-      default: inv_cols_h<KC3>(a, t, g, lds, mh, s_col); break;
+      case 0: inv_cols_h<KC2>(a, t, g, lds, s_col); break;
+      case 1: inv_cols_h<KS3>(a, t, g, lds, s_col); break;
+      default: inv_cols_h<KC3>(a, t, g, lds, s_col); break;
     }
     __syncthreads();
     switch (t.kind_h) {

@@ -11,6 +11,7 @@
 namespace ta {
 
 typedef short s2v __attribute__((ext_vector_type(2)));
+typedef unsigned short u2v __attribute__((ext_vector_type(2)));
 
 // Transform kinds of one 1-D pass (forward orientation).  The DST-2/DST-3
 // are the section 2.1 relations around the DCT-2/DCT-3 butterflies:
@@ -46,6 +47,12 @@ TA_DEV constexpr double s7f(int k, int n) {
   else if constexpr (N == 32) return ta_s7f_32[k][n];
   else return ta_s7f_64[k][n];
 }
+
+// Transform parameters (band taps, sub-block matrices) are read through the
+// constant address space: they are wave-uniform and never written by a
+// kernel, so the compiler loads them with scalar loads into SGPRs.
+typedef const __attribute__((address_space(4))) uint32_t* cparam;
+TA_DEV cparam as_cparam(const void* p) { return (cparam)p; }
 
 // Pack two int16 constants into a dot2 operand (lo = a, hi = b).
 TA_DEV constexpr uint32_t pk2(int a, int b) {
@@ -84,6 +91,34 @@ TA_DEV int mad24(int a, int coef, int acc) {
 TA_DEV uint32_t satpk(int a, int b) {
   return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pk_i16(a, b));
 }
+
+// Packed int16 lanes, wrapping: (a.lo - b.hi, a.hi - b.lo) and
+// (a.lo + b.hi, a.hi + b.lo).  One v_pk_sub_i16 / v_pk_add_u16 each: the
+// swap of b's halves is an operand selector, not an instruction.
+TA_DEV uint32_t pk_sub_x(uint32_t a, uint32_t b) {
+  const u2v x = __builtin_bit_cast(u2v, a), y = __builtin_bit_cast(u2v, b);
+  return __builtin_bit_cast(uint32_t, x - __builtin_shufflevector(y, y, 1, 0));
+}
+TA_DEV uint32_t pk_add_x(uint32_t a, uint32_t b) {
+  const u2v x = __builtin_bit_cast(u2v, a), y = __builtin_bit_cast(u2v, b);
+  return __builtin_bit_cast(uint32_t, x + __builtin_shufflevector(y, y, 1, 0));
+}
+
+// Whether every int16 lane of x[0..M) lies in [-2^14, 2^14): then sums and
+// differences of any two lanes fit in int16.  v + 2^14 (mod 2^16) has its
+// top bit clear exactly for v in that range.
+template <int M>
+TA_DEV bool lanes_within_14(const uint32_t (&x)[M]) {
+  const u2v bias = {16384, 16384};
+  uint32_t t = 0;
+#pragma unroll
+  for (int i = 0; i < M; ++i) t |= __builtin_bit_cast(uint32_t, __builtin_bit_cast(u2v, x[i]) + bias);
+  return (t & 0x80008000u) == 0;
+}
+
+// True when `ok` holds in every active lane of the wave (a wave-uniform
+// branch condition).
+TA_DEV bool wave_all(bool ok) { return __ballot(!ok) == 0; }
 
 // Byte permute: bytes 0-3 of `lo`, 4-7 of `hi`, selector per output byte.
 TA_DEV uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {

@@ -14,26 +14,22 @@
 namespace ta {
 namespace fx {
 
-// N int16 values held in N/2 packed registers.  Natural layout: register s
-// holds elements (2s, 2s+1).  Mirrored layout: register s < N/2 holds
-// (s, N-1-s), the operand pairs of the first DCT-2 butterfly level, so a
-// consumer reading from LDS in that layout needs no repacking.
-template <int N, bool MIRROR = false>
+// N int16 values held in N/2 packed registers, register s holding elements
+// (2s, 2s+1).
+template <int N>
 struct Packed {
   uint32_t p[N / 2];
-  static TA_DEV constexpr int slot(int i) { return MIRROR ? (i < N / 2 ? i : N - 1 - i) : (i >> 1); }
-  static TA_DEV constexpr int half(int i) { return MIRROR ? (i < N / 2 ? 0 : 1) : (i & 1); }
   TA_DEV int value(int i) const {
-    const uint32_t w = p[slot(i)];
-    return half(i) ? ((int)w >> 16) : (int)(short)(w & 0xffffu);
+    const uint32_t w = p[i >> 1];
+    return (i & 1) ? ((int)w >> 16) : (int)(short)(w & 0xffffu);
   }
   // (value(i), value(j)) packed; an index of -1 stands for zero.
   TA_DEV uint32_t pair(int i, int j) const {
-    if (i >= 0 && j >= 0 && slot(i) == slot(j) && half(i) == 0 && half(j) == 1) return p[slot(i)];
-    const uint32_t lo = i >= 0 ? p[slot(i)] : 0u;
-    const uint32_t hi = j >= 0 ? p[slot(j)] : 0u;
-    const uint32_t sl = i >= 0 ? (half(i) ? 0x0302u : 0x0100u) : 0x0c0cu;
-    const uint32_t sh = j >= 0 ? (half(j) ? 0x0706u : 0x0504u) : 0x0c0cu;
+    if (i >= 0 && j == i + 1 && (i & 1) == 0) return p[i >> 1];
+    const uint32_t lo = i >= 0 ? p[i >> 1] : 0u;
+    const uint32_t hi = j >= 0 ? p[j >> 1] : 0u;
+    const uint32_t sl = i >= 0 ? ((i & 1) ? 0x0302u : 0x0100u) : 0x0c0cu;
+    const uint32_t sh = j >= 0 ? ((j & 1) ? 0x0706u : 0x0504u) : 0x0c0cu;
     return perm(hi, lo, sl | (sh << 16));
   }
 };
@@ -87,7 +83,7 @@ TA_DEV constexpr int band_start(int i) {
 }
 
 template <int N, int K, bool TR, class S>
-TA_DEV Acc<N> band(const S& src, const uint32_t* __restrict__ taps, int shift) {
+TA_DEV Acc<N> band(const S& src, cparam taps, int shift) {
   Acc<N> r;
   r.s0 = r.s1 = shift;
   const int off = 1 << (shift - 1);
@@ -175,27 +171,40 @@ TA_DEV Acc<N> core_c3(const S& src, int shift) {
 }
 
 // ---------------------------------------------------------------------------
-// DCT-2 butterfly: z[k] = sum_n C2_N[k][n] x[n].  The first level works on
-// the int16 inputs with dot2 over the pairs (x[n], x[N-1-n]); deeper levels
-// work on int32 partial sums (|v| < 2^21) with 24-bit multiply-adds.
+// DCT-2 butterfly: z[k] = sum_n C2_N[k][n] u[n].  Odd rows are odd about the
+// middle, even rows even, so with d[n] = u[n] - u[N-1-n] and
+// e[n] = u[n] + u[N-1-n] (n < N/2):
+//   z[k odd] = sum_n C2_N[k][n] d[n],   z[2k] = (N/2-point DCT-2 of e)[k].
 // ---------------------------------------------------------------------------
-template <int M>
+// N/2-point and smaller levels on int32 partial sums (|v| < 2^21) with 24-bit
+// multiply-adds.  With NEG_ODD the transform input is u[n] = -v[n] for odd n
+// (the sign is folded into the first level's additions and coefficients).
+template <int M, bool NEG_ODD = false>
 TA_DEV void c2_int(const int (&v)[M], int (&z)[M], int off) {
   if constexpr (M == 2) {
-    z[0] = ((v[0] + v[1]) << 8) + off;     // row 0 = 2^8
-    z[1] = ((v[0] - v[1]) << 8) + off;     // 2-point row 1 = (+2^8, -2^8)
+    z[0] = ((NEG_ODD ? v[0] - v[1] : v[0] + v[1]) << 8) + off;     // row 0 = 2^8
+    z[1] = ((NEG_ODD ? v[0] + v[1] : v[0] - v[1]) << 8) + off;     // 2-point row 1 = (+2^8, -2^8)
   } else {
     int e[M / 2], o[M / 2];
 #pragma unroll
     for (int n = 0; n < M / 2; ++n) {
-      e[n] = v[n] + v[M - 1 - n];
-      o[n] = v[n] - v[M - 1 - n];
+      if (!NEG_ODD) {
+        e[n] = v[n] + v[M - 1 - n];
+        o[n] = v[n] - v[M - 1 - n];
+      } else if ((n & 1) == 0) {           // u[n] = v[n], u[M-1-n] = -v[M-1-n]
+        e[n] = v[n] - v[M - 1 - n];
+        o[n] = v[n] + v[M - 1 - n];
+      } else {                             // u[n] = -v[n]: o[n] holds -(u[n] - u[M-1-n])
+        e[n] = v[M - 1 - n] - v[n];
+        o[n] = v[n] + v[M - 1 - n];
+      }
     }
 #pragma unroll
     for (int k = 1; k < M; k += 2) {
       int acc = off;
 #pragma unroll
-      for (int n = 0; n < M / 2; ++n) acc = mad24(o[n], c2i<M>(k, n), acc);
+      for (int n = 0; n < M / 2; ++n)
+        acc = mad24(o[n], (NEG_ODD && (n & 1)) ? -c2i<M>(k, n) : c2i<M>(k, n), acc);
       z[k] = acc;
     }
     int ze[M / 2];
@@ -206,36 +215,71 @@ TA_DEV void c2_int(const int (&v)[M], int (&z)[M], int off) {
 }
 
 // ISIGN applies S to the input, OREV reverses the output (DST-2 = R DCT-2 S).
+//
+// The input arrives as natural int16 pairs x[s] = (x_2s, x_2s+1).  When every
+// |x_n| < 2^14 in the whole wave, the first level stays in int16: one packed
+// add or subtract of x[s] and the half-swapped x[N/2-1-s] yields the pair
+// (d_2s, d_2s+1) (or e), so each odd row costs N/4 dot2 instead of N/2.
+// Otherwise the odd rows are taken as full-length dot products of the input
+// pairs and e is formed in int32.  Both give the same exact integer sums.
 template <int N, bool ISIGN, bool OREV, class S>
 TA_DEV Acc<N> core_c2(const S& src, int shift) {
   const int off = 1 << (shift - 1);
   Acc<N> r;
   r.s0 = r.s1 = shift;
-  uint32_t pr[N / 2];
+  uint32_t x[N / 2];
 #pragma unroll
-  for (int n = 0; n < N / 2; ++n) pr[n] = src.pair(n, N - 1 - n);
+  for (int s = 0; s < N / 2; ++s) x[s] = src.pair(2 * s, 2 * s + 1);
+  // With S applied, u_n = (-1)^n x_n: d_n = (-1)^n (x_n + x_{N-1-n}) and
+  // e_n = (-1)^n (x_n - x_{N-1-n}); the sign of the odd-n lane moves into the
+  // coefficient (odd rows) or into c2_int (even rows).
+  constexpr int SG = ISIGN ? -1 : 1;
   int z[N];
+  int e[N / 2];
+  if (wave_all(lanes_within_14(x))) {
+    uint32_t dp[N / 4], ep[N / 4];
 #pragma unroll
-  for (int k = 1; k < N; k += 2) {
-    int acc = off;
+    for (int s = 0; s < N / 4; ++s) {
+      const uint32_t a = x[s], b = x[N / 2 - 1 - s];
+      dp[s] = ISIGN ? pk_add_x(a, b) : pk_sub_x(a, b);
+      ep[s] = ISIGN ? pk_sub_x(a, b) : pk_add_x(a, b);
+    }
+#pragma unroll
+    for (int k = 1; k < N; k += 2) {
+      int acc = off;
+#pragma unroll
+      for (int s = 0; s < N / 4; ++s) {
+        const uint32_t cf = pk2(c2i<N>(k, 2 * s), SG * c2i<N>(k, 2 * s + 1));
+        acc = s == 0 ? dot2h(dp[s], cf, off) : dot2(dp[s], cf, acc);
+      }
+      z[k] = acc;
+    }
+#pragma unroll
+    for (int s = 0; s < N / 4; ++s) {
+      e[2 * s] = (int)(short)(ep[s] & 0xffffu);
+      e[2 * s + 1] = (int)ep[s] >> 16;
+    }
+  } else {
+#pragma unroll
+    for (int k = 1; k < N; k += 2) {
+      int acc = off;
+#pragma unroll
+      for (int s = 0; s < N / 2; ++s) {
+        const uint32_t cf = pk2(c2i<N>(k, 2 * s), SG * c2i<N>(k, 2 * s + 1));
+        acc = s == 0 ? dot2h(x[s], cf, off) : dot2(x[s], cf, acc);
+      }
+      z[k] = acc;
+    }
 #pragma unroll
     for (int n = 0; n < N / 2; ++n) {
-      const int sa = (ISIGN && (n & 1)) ? -1 : 1;
-      const int sb = (ISIGN && ((N - 1 - n) & 1)) ? -1 : 1;
-      const uint32_t cf = pk2(sa * c2i<N>(k, n), sb * c2i<N>(k, N - 1 - n));
-      acc = n == 0 ? dot2h(pr[n], cf, off) : dot2(pr[n], cf, acc);
+      const int a = (n & 1) ? ((int)x[n >> 1] >> 16) : (int)(short)(x[n >> 1] & 0xffffu);
+      const int m = N - 1 - n;
+      const int b = (m & 1) ? ((int)x[m >> 1] >> 16) : (int)(short)(x[m >> 1] & 0xffffu);
+      e[n] = ISIGN ? a - b : a + b;
     }
-    z[k] = acc;
-  }
-  int e[N / 2];
-#pragma unroll
-  for (int n = 0; n < N / 2; ++n) {
-    const int sa = (ISIGN && (n & 1)) ? -1 : 1;
-    const int sb = (ISIGN && ((N - 1 - n) & 1)) ? -1 : 1;
-    e[n] = dot2h0(pr[n], pk2(sa, sb));
   }
   int ze[N / 2];
-  c2_int<N / 2>(e, ze, off);
+  c2_int<N / 2, ISIGN>(e, ze, off);
 #pragma unroll
   for (int k = 0; k < N / 2; ++k) z[2 * k] = ze[k];
 #pragma unroll
@@ -287,7 +331,7 @@ TA_DEV Acc<N> core(const S& src, int shift) {
 // pass through.  q[i*B/2 + j] holds the packed pair (Q[i][2j], Q[i][2j+1]).
 // ---------------------------------------------------------------------------
 template <int N, int B, class S>
-TA_DEV void post_rows(const S& src, const uint32_t* __restrict__ q, int shift, int (&out)[B]) {
+TA_DEV void post_rows(const S& src, cparam q, int shift, int (&out)[B]) {
   const int off = 1 << (shift - 1);
 #pragma unroll
   for (int i = 0; i < B; ++i) {
@@ -307,21 +351,10 @@ struct Axis {
   static constexpr int CORE = CORE_, ADJ = ADJ_, KB = KB_;
 };
 
-// Whether the first stage of a pass consumes (x[n], x[N-1-n]) pairs: true
-// when that stage is a DCT-2 butterfly (DCT-2 or DST-2 core, after taking
-// the transpose for the inverse) rather than a band, a sub-block or a DCT-3.
-template <class AX, bool INV>
-constexpr bool wants_mirror() {
-  if (AX::ADJ == ADJ_BAND && !INV) return false;
-  if (AX::ADJ == ADJ_POST && INV) return false;
-  const int c = INV ? core_transpose(AX::CORE) : AX::CORE;
-  return c == C_DCT2 || c == C_DST2;
-}
-
 // Run the forward (INV = false) or inverse pass of axis AX on `in`.
 // pf: forward parameters (band taps / Q pairs), pi: transposed parameters.
 template <int N, class AX, bool INV, class S>
-TA_DEV auto run_pass(const S& in, const uint32_t* __restrict__ pf, const uint32_t* __restrict__ pi,
+TA_DEV auto run_pass(const S& in, cparam pf, cparam pi,
                      int s_core, int a) {
   if constexpr (AX::ADJ == ADJ_NONE) {
     return core<N, AX::CORE, INV>(in, s_core);

@@ -12,9 +12,7 @@
 //      PP = W + 1 keeps the pair-rows of a column in distinct banks.
 //   RM ("row-major"): row pitch W + 8 halfwords so that ds_read_b128 of
 //      consecutive rows hits distinct banks.
-// Which two elements share a dword follows the consumer: natural pairs
-// (2s, 2s+1), or mirrored pairs (s, N-1-s) when the first stage of the pass
-// is a DCT-2 butterfly, whose first level multiplies exactly those pairs.
+// A dword always holds the natural pair (2s, 2s+1) of its vector.
 // Forward: global rows -> registers -> row pass -> PC -> column pass -> RM ->
 // coalesced 16-byte stores.  Inverse: coalesced 16-byte loads -> PC ->
 // column pass -> RM -> row pass -> global rows.  PC and RM alias the same
@@ -91,13 +89,10 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
   const int nbh = (int)min<int64_t>(NB, p.nblocks - blk0);
   const int16_t* __restrict__ in = static_cast<const int16_t*>(p.in) + blk0 * (W * H);
   int16_t* __restrict__ out = static_cast<int16_t*>(p.out) + blk0 * (W * H);
-  const uint32_t* ph_f = static_cast<const uint32_t*>(p.ph_f);
-  const uint32_t* ph_i = static_cast<const uint32_t*>(p.ph_i);
-  const uint32_t* pv_f = static_cast<const uint32_t*>(p.pv_f);
-  const uint32_t* pv_i = static_cast<const uint32_t*>(p.pv_i);
+  const cparam ph_f = as_cparam(p.ph_f), ph_i = as_cparam(p.ph_i);
+  const cparam pv_f = as_cparam(p.pv_f), pv_i = as_cparam(p.pv_i);
 
-  constexpr bool MV = fx::wants_mirror<AV, false>();
-  using PV = fx::Packed<H, MV>;
+  using PV = fx::Packed<H>;
 
   // row pass (horizontal transform of every row) -> PC
   if (tid < NB * H) {
@@ -110,7 +105,7 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
       for (int j = 0; j < W / 2; ++j) x.p[j] = 0u;
     }
     const auto y = fx::run_pass<W, AH, false>(x, ph_f, ph_i, p.s_row, p.a);
-    const int base = (b * T::PCB + PV::slot(r) * T::PP) * 2 + PV::half(r);
+    const int base = (b * T::PCB + (r >> 1) * T::PP) * 2 + (r & 1);
 #pragma unroll
     for (int j = 0; j < W / 2; ++j) {
       const uint32_t v = y.pair(2 * j, 2 * j + 1);
@@ -170,15 +165,11 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   const int nbh = (int)min<int64_t>(NB, p.nblocks - blk0);
   const int16_t* __restrict__ in = static_cast<const int16_t*>(p.in) + blk0 * (W * H);
   int16_t* __restrict__ out = static_cast<int16_t*>(p.out) + blk0 * (W * H);
-  const uint32_t* ph_f = static_cast<const uint32_t*>(p.ph_f);
-  const uint32_t* ph_i = static_cast<const uint32_t*>(p.ph_i);
-  const uint32_t* pv_f = static_cast<const uint32_t*>(p.pv_f);
-  const uint32_t* pv_i = static_cast<const uint32_t*>(p.pv_i);
+  const cparam ph_f = as_cparam(p.ph_f), ph_i = as_cparam(p.ph_i);
+  const cparam pv_f = as_cparam(p.pv_f), pv_i = as_cparam(p.pv_i);
 
-  constexpr bool MV = fx::wants_mirror<AV, true>();
-  constexpr bool MH = fx::wants_mirror<AH, true>();
-  using PV = fx::Packed<H, MV>;
-  using PH = fx::Packed<W, MH>;
+  using PV = fx::Packed<H>;
+  using PH = fx::Packed<W>;
 
   // coalesced load of the tile into the pair-column layout
   const int nch = nbh * T::CPB;
@@ -193,7 +184,7 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
       const uint2 v = reinterpret_cast<const uint2*>(in)[c];
       w[0] = v.x; w[1] = v.y;
     }
-    const int base = (b * T::PCB + PV::slot(r) * T::PP + c0) * 2 + PV::half(r);
+    const int base = (b * T::PCB + (r >> 1) * T::PP + c0) * 2 + (r & 1);
 #pragma unroll
     for (int k = 0; k < T::CH / 2; ++k) {
       pch[base + (2 * k) * 2] = (uint16_t)w[k];
@@ -217,8 +208,7 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   __syncthreads();
   if (tid < NB * W) {
     const int b = tid / W, c = tid % W;
-    // element (r, c) goes to register slot PH::slot(c) of row r
-    const int base = b * T::RMBI + 2 * PH::slot(c) + PH::half(c);
+    const int base = b * T::RMBI + c;
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) {
       rm[base + (2 * i) * T::RPI] = (uint16_t)o[i];

@@ -159,6 +159,26 @@ const ta::KernelEntry* find_kernel(const ta::KernelKey& key, int prefer_mfma, bo
   return nullptr;
 }
 
+// Workgroups of kernel k that are resident on device `dev` at once (the grid
+// of a persistent kernel): occupancy per CU times the CU count, cached.
+int resident_groups(const ta::KernelEntry* k, int dev, int* out) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_pair(k->fn, dev);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    int per_cu = 0, cus = 0;
+    TA_HIP(hipSetDevice(dev));
+    TA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->fn, k->threads, 0));
+    TA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (per_cu < 1 || cus < 1) return fail(TA_EHIP, "kernel occupancy query returned %d x %d", per_cu, cus);
+    it = cache.emplace(key, per_cu * cus).first;
+  }
+  *out = it->second;
+  return TA_OK;
+}
+
 int run_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int log2w, int log2h, int64_t nblocks,
                const void* in, void* out, int dtype, ta_stream_t stream) {
   if (!c) return fail(TA_EINVAL, "null context");
@@ -205,7 +225,9 @@ int run_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int log2w, int log2h,
   }
   args.a = c->a;
   int64_t groups = (nblocks + k->blocks_per_wg - 1) / k->blocks_per_wg;
-  if (k->max_wgs > 0 && groups > k->max_wgs) groups = k->max_wgs;
+  int cap = k->max_wgs;
+  if (cap < 0 && (e = resident_groups(k, c->device, &cap))) return e;
+  if (cap > 0 && groups > cap) groups = cap;
   if (groups > 0x7fffffff) return fail(TA_EUNSUPPORTED, "batch too large for one launch");
   void* kargs[] = {&args};
   TA_HIP(hipSetDevice(c->device));

@@ -38,7 +38,8 @@ struct KernelEntry {
   const void* fn;     // __global__ function
   int blocks_per_wg;  // blocks of the batch handled by one workgroup (per iteration)
   int threads;        // workgroup size
-  int max_wgs;        // persistent kernels: grid cap (0 = one workgroup per tile)
+  int max_wgs;        // grid cap: 0 = one workgroup per tile, > 0 a fixed cap,
+                      // -1 = persistent, as many as are resident at once
   bool same_params;   // requires the horizontal and vertical parameters to be the same set
 };
 
