@@ -28,6 +28,8 @@ template <int LW, int LH>
 struct Tile {
   static constexpr int W = 1 << LW, H = 1 << LH;
   static constexpr int NB = 256 / (W > H ? W : H);
+  // whether every thread owns a row (a column) of the tile
+  static constexpr bool ROWS_ALL = NB * H == 256, COLS_ALL = NB * W == 256;
   static constexpr int PP = W + 1;
   static constexpr int PCB = (H / 2) * PP;                 // dwords per block, PC
   // RM row pitch: the inverse reads whole rows with ds_read_b128 and pads each
@@ -40,6 +42,7 @@ struct Tile {
   static constexpr int RMBI = H * RPI + (W >= 8 ? 32 : 0);
   static constexpr int CH = W >= 8 ? 8 : 4;                // halfwords per global chunk
   static constexpr int CPB = W * H / CH;                   // chunks per block
+  static constexpr int CPT = (NB * CPB + 255) / 256;       // chunks per thread (full tile)
   // PC and RM share one LDS buffer (sized in dwords)
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
   static constexpr int LDS_F = cmax(NB * PCB, (NB * RMBF + 1) / 2);
@@ -94,16 +97,13 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
 
   using PV = fx::Packed<H>;
 
-  // row pass (horizontal transform of every row) -> PC
-  if (tid < NB * H) {
+  // row pass (horizontal transform of every row) -> PC.  Rows of blocks
+  // past the end of the batch repeat the last block's rows (computed, never
+  // stored), so no thread needs a separate zero-fill path.
+  if (T::ROWS_ALL || tid < NB * H) {
     const int b = tid / H, r = tid % H;
     fx::Packed<W> x;
-    if (b < nbh) {
-      load_row<W>(in + (b * H + r) * W, x);
-    } else {
-#pragma unroll
-      for (int j = 0; j < W / 2; ++j) x.p[j] = 0u;
-    }
+    load_row<W>(in + (min(b, nbh - 1) * H + r) * W, x);
     const auto y = fx::run_pass<W, AH, false>(x, ph_f, ph_i, p.s_row, p.a);
     const int base = (b * T::PCB + (r >> 1) * T::PP) * 2 + (r & 1);
 #pragma unroll
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
   // column pass (vertical transform of every column); PC is dead once every
   // thread has read its column, then the same LDS holds RM
   uint32_t o[H / 2];
-  if (tid < NB * W) {
+  if (T::COLS_ALL || tid < NB * W) {
     const int b = tid / W, c = tid % W;
     PV z;
 #pragma unroll
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
     for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
   }
   __syncthreads();
-  if (tid < NB * W) {
+  if (T::COLS_ALL || tid < NB * W) {
     const int b = tid / W, c = tid % W;
     const int base = b * T::RMBF + c;
 #pragma unroll
@@ -139,15 +139,19 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
   }
   __syncthreads();
 
-  // coalesced store of the tile
+  // coalesced store of the tile: chunk tid + 256 k, k < CPT
   const int nch = nbh * T::CPB;
-  for (int c = tid; c < nch; c += 256) {
-    const int b = c / T::CPB, q = c % T::CPB;
-    const uint16_t* s = rm + b * T::RMBF + q * T::CH;
-    if constexpr (T::CH == 8)
-      reinterpret_cast<uint4*>(out)[c] = *reinterpret_cast<const uint4*>(s);
-    else
-      reinterpret_cast<uint2*>(out)[c] = *reinterpret_cast<const uint2*>(s);
+#pragma unroll
+  for (int k = 0; k < T::CPT; ++k) {
+    const int c = tid + 256 * k;
+    if (c < nch) {
+      const int b = c / T::CPB, q = c % T::CPB;
+      const uint16_t* s = rm + b * T::RMBF + q * T::CH;
+      if constexpr (T::CH == 8)
+        reinterpret_cast<uint4*>(out)[c] = *reinterpret_cast<const uint4*>(s);
+      else
+        reinterpret_cast<uint2*>(out)[c] = *reinterpret_cast<const uint2*>(s);
+    }
   }
 }
 
@@ -171,9 +175,13 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   using PV = fx::Packed<H>;
   using PH = fx::Packed<W>;
 
-  // coalesced load of the tile into the pair-column layout
+  // coalesced load of the tile into the pair-column layout: chunk
+  // tid + 256 k, k < CPT
   const int nch = nbh * T::CPB;
-  for (int c = tid; c < nch; c += 256) {
+#pragma unroll
+  for (int k = 0; k < T::CPT; ++k) {
+    const int c = tid + 256 * k;
+    if (c >= nch) break;
     const int b = c / T::CPB, q = c % T::CPB;
     const int r = q / (W / T::CH), c0 = (q % (W / T::CH)) * T::CH;
     uint32_t w[T::CH / 2];
@@ -196,7 +204,7 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   // column pass (inverse vertical transform first); then PC is dead and the
   // same LDS holds RM
   uint32_t o[H / 2];
-  if (tid < NB * W) {
+  if (T::COLS_ALL || tid < NB * W) {
     const int b = tid / W, c = tid % W;
     PV z;
 #pragma unroll
@@ -206,7 +214,7 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
     for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
   }
   __syncthreads();
-  if (tid < NB * W) {
+  if (T::COLS_ALL || tid < NB * W) {
     const int b = tid / W, c = tid % W;
     const int base = b * T::RMBI + c;
 #pragma unroll
@@ -218,7 +226,7 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   __syncthreads();
 
   // row pass (inverse horizontal transform), stored straight to global
-  if (tid < NB * H) {
+  if (T::ROWS_ALL || tid < NB * H) {
     const int b = tid / H, r = tid % H;
     PH x;
     const uint16_t* s = rm + b * T::RMBI + r * T::RPI;
