@@ -28,37 +28,20 @@ using KC2 = Axis<C_DCT2, ADJ_NONE, 0>;
 using KS3 = Axis<C_DST3, ADJ_BAND, 4>;
 using KC3 = Axis<C_DCT3, ADJ_BAND, 4>;
 
-// LDS needed by one tile of W x H blocks (dwords), pair-column and row-major
-// views aliased as in the packed kernels
-constexpr int tile_lds(int lw, int lh) {
-  const int w = 1 << lw, h = 1 << lh, nb = 256 / (w > h ? w : h);
-  const int pc = nb * (h / 2) * (w + 1);
-  const int rmi = nb * (h * (w >= 8 ? w + 8 : w) + (w >= 8 ? 32 : 0));
-  const int rm = (rmi + 1) / 2;
-  return pc > rm ? pc : rm;
-}
+// LDS of the largest tile (dwords); every tile fits 20 KiB
 constexpr int max_tile_lds() {
   int m = 0;
   for (int lw = 2; lw <= 6; ++lw)
-    for (int lh = 2; lh <= 6; ++lh) m = tile_lds(lw, lh) > m ? tile_lds(lw, lh) : m;
-  return m;
+    for (int lh = 2; lh <= 6; ++lh) {
+      const int nb = BatchGeo::nb_for(lw, lh);
+      const int v = BatchGeo::lds_bytes(1 << lw, 1 << lh, nb, BatchGeo::pad_for(lw, lh));
+      m = v > m ? v : m;
+    }
+  return (m + 3) / 4;
 }
 constexpr int kBatchLds = max_tile_lds();
-
-// Runtime geometry of the tile being processed (wave-uniform).
-struct Geo {
-  int W, H, NB, PP, PCB, RP, RMB, CH;
-  TA_DEV Geo(int lw, int lh) {
-    W = 1 << lw;
-    H = 1 << lh;
-    NB = 256 / (W > H ? W : H);
-    PP = W + 1;
-    PCB = (H / 2) * PP;
-    RP = W >= 8 ? W + 8 : W;
-    RMB = H * RP + (W >= 8 ? 32 : 0);
-    CH = W >= 8 ? 8 : 4;
-  }
-};
+static_assert(kBatchLds * 4 <= BatchGeo::kLdsBytes, "tile LDS above 20 KiB");
+using Geo = BatchGeo;
 
 template <int W>
 TA_DEV void load_strided_row(const int16_t* __restrict__ src, fx::Packed<W>& x) {
@@ -112,8 +95,7 @@ TA_DEV void fwd_cols(const BatchArgs& a, const BatchTile& t, const Geo& g, uint3
   __syncthreads();
   if (act) {
     uint16_t* rm = reinterpret_cast<uint16_t*>(lds);
-    const int rmb = H * g.W + (g.W >= 8 ? 32 : 0);
-    const int base = b * rmb + c;
+    const int base = b * g.RMBF + c;
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) {
       rm[base + (2 * i) * g.W] = (uint16_t)o[i];
@@ -168,7 +150,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
     }
     __syncthreads();
     // coalesced store of the tile (RM pitch W, chunks of CH halfwords)
-    const int rmb = g.H * g.W + (g.W >= 8 ? 32 : 0);
+    const int rmb = g.RMBF;
     const int cpr = g.W / g.CH, cpb = g.H * cpr;
     const int nch = t.count * cpb;
     for (int c = threadIdx.x; c < nch; c += 256) {

@@ -508,7 +508,7 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
       region_xcd[region] = next;
     }
     const int lw = std::get<1>(k), lh = std::get<2>(k);
-    const int nb = 256 / std::max(1 << lw, 1 << lh);
+    const int nb = ta::BatchGeo::nb_for(lw, lh);
     const Resolved& rh = std::get<0>(res[k]);
     const Resolved& rv = std::get<1>(res[k]);
     const auto& idx = groups[k];
