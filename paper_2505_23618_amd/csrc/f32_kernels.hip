@@ -20,6 +20,8 @@ struct FTile {
   static constexpr int CM = W * (H + 1);   // floats per block, column-major
   static constexpr int RM = H * (W + 1);   // floats per block, row-major
   static constexpr int BS = CM > RM ? CM : RM;
+  static constexpr int Q4 = W * H / 4;     // float4 chunks per block
+  static constexpr int CPT = (NB * Q4 + 255) / 256;   // chunks per thread (full tile)
 };
 
 template <int W>
@@ -29,6 +31,22 @@ TA_DEV void load_rowf(const float* __restrict__ src, fp::Vec<W>& x) {
     for (int q = 0; q < W / 4; ++q) {
       const float4 v = reinterpret_cast<const float4*>(src)[q];
       x.v[4 * q] = v.x; x.v[4 * q + 1] = v.y; x.v[4 * q + 2] = v.z; x.v[4 * q + 3] = v.w;
+    }
+  }
+}
+
+// Coalesced float4 stores of a tile held row-major (pitch W + 1) in LDS.
+template <class T>
+TA_DEV void store_tile(const float* lds, float* __restrict__ out, int nbh, int tid) {
+  constexpr int W = T::W;
+  const int nch = nbh * T::Q4;
+#pragma unroll
+  for (int k = 0; k < T::CPT; ++k) {
+    const int c = tid + 256 * k;
+    if (c < nch) {
+      const int b = c / T::Q4, q = c % T::Q4;
+      const float* s = lds + b * T::BS + (q / (W / 4)) * (W + 1) + (q % (W / 4)) * 4;
+      reinterpret_cast<float4*>(out)[c] = make_float4(s[0], s[1], s[2], s[3]);
     }
   }
 }
@@ -48,15 +66,11 @@ __global__ __launch_bounds__(256) void f32_fwd(PackedArgs p) {
   const float* pv_f = static_cast<const float*>(p.pv_f);
   const float* pv_i = static_cast<const float*>(p.pv_i);
 
+  // row pass: rows of blocks past the batch end repeat the last block (never stored)
   if (tid < NB * H) {
     const int b = tid / H, r = tid % H;
     fp::Vec<W> x;
-    if (b < nbh) {
-      load_rowf<W>(in + (b * H + r) * W, x);
-    } else {
-#pragma unroll
-      for (int c = 0; c < W; ++c) x.v[c] = 0.0f;
-    }
+    load_rowf<W>(in + (min(b, nbh - 1) * H + r) * W, x);
     const fp::Vec<W> y = fp::run_pass<W, AH, false>(x, ph_f, ph_i);
 #pragma unroll
     for (int c = 0; c < W; ++c) lds[b * T::BS + c * (H + 1) + r] = y.v[c];
@@ -76,11 +90,7 @@ __global__ __launch_bounds__(256) void f32_fwd(PackedArgs p) {
     for (int r = 0; r < H; ++r) lds[b * T::BS + r * (W + 1) + c] = z.v[r];
   }
   __syncthreads();
-  const int n = nbh * W * H;
-  for (int e = tid; e < n; e += 256) {
-    const int b = e / (W * H), q = e % (W * H);
-    out[e] = lds[b * T::BS + (q / W) * (W + 1) + (q % W)];
-  }
+  store_tile<T>(lds, out, nbh, tid);
 }
 
 template <int LW, int LH, class AH, class AV>
@@ -98,10 +108,18 @@ __global__ __launch_bounds__(256) void f32_inv(PackedArgs p) {
   const float* pv_f = static_cast<const float*>(p.pv_f);
   const float* pv_i = static_cast<const float*>(p.pv_i);
 
-  const int n = nbh * W * H;
-  for (int e = tid; e < n; e += 256) {
-    const int b = e / (W * H), q = e % (W * H);
-    lds[b * T::BS + (q % W) * (H + 1) + (q / W)] = in[e];
+  // coalesced float4 loads into the column-major layout
+  const int nch = nbh * T::Q4;
+#pragma unroll
+  for (int k = 0; k < T::CPT; ++k) {
+    const int c = tid + 256 * k;
+    if (c < nch) {
+      const int b = c / T::Q4, q = c % T::Q4;
+      const int r = q / (W / 4), c0 = (q % (W / 4)) * 4;
+      const float4 v = reinterpret_cast<const float4*>(in)[c];
+      float* d = lds + b * T::BS + c0 * (H + 1) + r;
+      d[0] = v.x; d[H + 1] = v.y; d[2 * (H + 1)] = v.z; d[3 * (H + 1)] = v.w;
+    }
   }
   __syncthreads();
   fp::Vec<H> z;
@@ -118,19 +136,20 @@ __global__ __launch_bounds__(256) void f32_inv(PackedArgs p) {
     for (int r = 0; r < H; ++r) lds[b * T::BS + r * (W + 1) + c] = z.v[r];
   }
   __syncthreads();
+  // row pass; each thread writes its result back over its own row, then the
+  // tile leaves with coalesced stores
   if (tid < NB * H) {
     const int b = tid / H, r = tid % H;
     fp::Vec<W> x;
+    float* row = lds + b * T::BS + r * (W + 1);
 #pragma unroll
-    for (int c = 0; c < W; ++c) x.v[c] = lds[b * T::BS + r * (W + 1) + c];
+    for (int c = 0; c < W; ++c) x.v[c] = row[c];
     const fp::Vec<W> y = fp::run_pass<W, AH, true>(x, ph_f, ph_i);
-    if (b < nbh) {
-      float* dst = out + (b * H + r) * W;
 #pragma unroll
-      for (int q = 0; q < W / 4; ++q)
-        reinterpret_cast<float4*>(dst)[q] = make_float4(y.v[4 * q], y.v[4 * q + 1], y.v[4 * q + 2], y.v[4 * q + 3]);
-    }
+    for (int c = 0; c < W; ++c) row[c] = y.v[c];
   }
+  __syncthreads();
+  store_tile<T>(lds, out, nbh, tid);
 }
 
 template <int CORE_, int ADJ_, int KB_>

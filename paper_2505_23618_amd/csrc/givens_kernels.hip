@@ -180,13 +180,25 @@ __global__ __launch_bounds__(256) void givens_bwd(GivensArgs a) {
   }
 }
 
-__global__ __launch_bounds__(128) void givens_reduce(const float* __restrict__ partial, int64_t groups, int na,
+// Sum of the per-workgroup partial rows, one workgroup per angle: thread t
+// adds rows t, t + 256, ... in order, then a fixed-shape tree over the 256
+// thread sums; the order never depends on timing, so the result is bitwise
+// reproducible.
+__global__ __launch_bounds__(256) void givens_reduce(const float* __restrict__ partial, int64_t groups, int na,
                                                      float* __restrict__ gtheta) {
-  const int r = threadIdx.x;
+  __shared__ float sum[256];
+  const int r = blockIdx.x, t = threadIdx.x;
   if (r >= na) return;
   float s = 0.0f;
-  for (int64_t g = 0; g < groups; ++g) s += partial[g * kMaxAng + r];
-  gtheta[r] = s;
+  for (int64_t g = t; g < groups; g += 256) s += partial[g * kMaxAng + r];
+  sum[t] = s;
+  __syncthreads();
+#pragma unroll
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sum[t] += sum[t + w];
+    __syncthreads();
+  }
+  if (t == 0) gtheta[r] = sum[0];
 }
 
 }  // namespace

@@ -678,7 +678,7 @@ int ta_givens_bwd(ta_ctx* c, int base, int n, int taps, const float* theta, int6
   const float* part = static_cast<const float*>(workspace);
   int64_t g64 = groups;
   void* rargs[] = {&part, &g64, &na, &gtheta};
-  TA_HIP(hipLaunchKernel(ta::givens_reduce_kernel(), dim3(1), dim3(128), rargs, 0, s));
+  TA_HIP(hipLaunchKernel(ta::givens_reduce_kernel(), dim3((unsigned)na), dim3(256), rargs, 0, s));
   return TA_OK;
 }
 
