@@ -15,7 +15,7 @@
 // A dword always holds the natural pair (2s, 2s+1) of its vector.
 // Forward: global rows -> registers -> row pass -> PC -> column pass -> RM ->
 // coalesced 16-byte stores.  Inverse: coalesced 16-byte loads -> PC ->
-// column pass -> RM -> row pass -> global rows.  PC and RM alias the same
+// column pass -> RM -> row pass -> RM -> coalesced 16-byte stores.  PC and RM alias the same
 // LDS (a barrier separates the last PC read from the first RM write), which
 // halves the LDS per workgroup and doubles the resident waves per CU.
 #include "fx.hpp"
@@ -64,17 +64,6 @@ TA_DEV void load_row(const int16_t* __restrict__ src, fx::Packed<W>& x) {
     const uint2 v = *reinterpret_cast<const uint2*>(src);
     x.p[0] = v.x;
     x.p[1] = v.y;
-  }
-}
-
-template <int W>
-TA_DEV void store_row(int16_t* __restrict__ dst, const uint32_t (&p)[W / 2]) {
-  if constexpr (W >= 8) {
-#pragma unroll
-    for (int q = 0; q < W / 8; ++q)
-      reinterpret_cast<uint4*>(dst)[q] = make_uint4(p[4 * q], p[4 * q + 1], p[4 * q + 2], p[4 * q + 3]);
-  } else {
-    *reinterpret_cast<uint2*>(dst) = make_uint2(p[0], p[1]);
   }
 }
 
@@ -225,7 +214,8 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   }
   __syncthreads();
 
-  // row pass (inverse horizontal transform), stored straight to global
+  // row pass (inverse horizontal transform); the rows go back to RM and
+  // leave the tile with coalesced 16-byte stores
   if (T::ROWS_ALL || tid < NB * H) {
     const int b = tid / H, r = tid % H;
     PH x;
@@ -241,11 +231,32 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
       x.p[0] = v.x; x.p[1] = v.y;
     }
     const auto y = fx::run_pass<W, AH, true>(x, ph_f, ph_i, p.s_row, p.a);
-    if (b < nbh) {
-      uint32_t o2[W / 2];
+    // the result goes back over this thread's own row of RM
+    uint16_t* d = rm + b * T::RMBI + r * T::RPI;
+    uint32_t o2[W / 2];
 #pragma unroll
-      for (int j = 0; j < W / 2; ++j) o2[j] = y.pair(2 * j, 2 * j + 1);
-      store_row<W>(out + (b * H + r) * W, o2);
+    for (int j = 0; j < W / 2; ++j) o2[j] = y.pair(2 * j, 2 * j + 1);
+    if constexpr (W >= 8) {
+#pragma unroll
+      for (int q = 0; q < W / 8; ++q)
+        reinterpret_cast<uint4*>(d)[q] = make_uint4(o2[4 * q], o2[4 * q + 1], o2[4 * q + 2], o2[4 * q + 3]);
+    } else {
+      *reinterpret_cast<uint2*>(d) = make_uint2(o2[0], o2[1]);
+    }
+  }
+  __syncthreads();
+  // coalesced store of the tile from RM: chunk tid + 256 k
+#pragma unroll
+  for (int k = 0; k < T::CPT; ++k) {
+    const int c = tid + 256 * k;
+    if (c < nch) {
+      const int b = c / T::CPB, q = c % T::CPB;
+      const int r = q / (W / T::CH), c0 = (q % (W / T::CH)) * T::CH;
+      const uint16_t* s = rm + b * T::RMBI + r * T::RPI + c0;
+      if constexpr (T::CH == 8)
+        reinterpret_cast<uint4*>(out)[c] = *reinterpret_cast<const uint4*>(s);
+      else
+        reinterpret_cast<uint2*>(out)[c] = *reinterpret_cast<const uint2*>(s);
     }
   }
 }
