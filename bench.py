@@ -107,6 +107,28 @@ def secondary(ctx, ids, x32):
     import paper_2505_23618_amd as ta
     from paper_2505_23618_amd import refit as RF
     res = {}
+    # encoder evaluation of the five transforms (DCT-2 x DCT-2 and the four
+    # DST-7 / DCT-8 pairs, 8x8 sub-block) of the 32x32 workload in one launch,
+    # against the same five outputs from five packed forwards
+    pid = ids["post_C2_S7_N32_B8"]
+    c2 = ctx.axis(20, ta.DCT2, ta.ADJ_NONE, False, 0)
+    s7 = ctx.axis(21, ta.DCT2, ta.ADJ_POST, False, pid)
+    c8 = ctx.axis(22, ta.DCT2, ta.ADJ_POST, True, pid)
+    n32 = x32.numel()
+    out5 = torch.empty((5,) + tuple(x32.shape), dtype=torch.int16, device="cuda")
+    tm = _events_mean(lambda i: ctx.fwd_multi(x32, pid, out=out5), 10)
+    pairs = [(c2, c2), (s7, s7), (c8, s7), (s7, c8), (c8, c8)]     # (horizontal, vertical)
+
+    def five(i):
+        for k, (h, v) in enumerate(pairs):
+            ctx.fwd(x32, h, v, out=out5[k])
+    t5 = _events_mean(five, 5)
+    res["multiple_32x32_b8"] = {"value": 5 * n32 / tm, "unit": "coef/s (5 outputs per input coef)",
+                                "us": tm * 1e6, "five_separate_us": t5 * 1e6, "speedup": t5 / tm,
+                                "GB/s": 12 * n32 / tm / 1e9,
+                                "workload": "262,144 blocks 32x32: DCT-2/DCT-2 and (DST-7|DCT-8)^2 with the 8x8 sub-block"}
+    del out5
+    torch.cuda.empty_cache()
     # 64x64 blocks, DCT-2 + 16x16 sub-block: DCT-8 rows (eq. 5), DST-7 columns
     ph = ctx.axis(10, ta.DCT2, ta.ADJ_POST, True, ids["post_C2_S7_N64_B16"])
     pv = ctx.axis(11, ta.DCT2, ta.ADJ_POST, False, ids["post_C2_S7_N64_B16"])
@@ -230,6 +252,10 @@ def main():
     # direct-matrix DST-7 on the same data
     wall7, tf7, ti7 = timed(ax7, max(10, args.steps // 2), 2)
     print(f"[bench] direct: fwd {tf7.mean()*1e6:.1f} us inv {ti7.mean()*1e6:.1f} us", file=sys.stderr, flush=True)
+    # the adjusted forward with its dense core on the int8 matrix cores (band on VALU)
+    ctx.set_impl(1)
+    tfm = _events_mean(lambda i: fwd(x, y, ax), 10)
+    ctx.set_impl(0)
     # plain copy of the same bytes (achievable HBM rate for a 2 B read + 2 B write stream)
     cev = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
     for _ in range(3):
@@ -285,6 +311,7 @@ def main():
             "adjusted_over_direct": (tf7.mean() + ti7.mean()) / (tf.mean() + ti.mean()),
             "impl": "int8 matrix cores (exact byte-plane split)",
         },
+        "adjusted_fwd_matrix_cores_us": tfm * 1e6,
         "copy_same_bytes": {"us": tcopy * 1e6, "GB/s": bytes_per_launch / tcopy / 1e9},
         "roofline": {
             "bound": "hbm", "kernel": f"fx_{'inv' if dom == 'inverse' else 'fwd'} 32x32 DST-3+4-tap",

@@ -126,6 +126,29 @@ int ta_fwd_packed(ta_ctx* ctx, int axis_h, int axis_v, int log2w, int log2h,
 int ta_inv_packed(ta_ctx* ctx, int axis_h, int axis_v, int log2w, int log2h,
                   int64_t nblocks, const void* in, void* out, int dtype, ta_stream_t stream);
 
+/* ---- Encoder evaluation of the five separable transforms ------------------
+ * Section "Simultaneous transform adjustments for the DCT-8 and DST-7" and
+ * eq. 5: an encoder compares, per block, DCT-2 x DCT-2 and the four
+ * (vertical, horizontal) pairs of DST-7 and DCT-8.  With the sub-block
+ * post-adjustment all five share the DCT-2, and the DCT-8 adjustment S Q S
+ * is computed together with the DST-7 one Q at the cost of one adjustment.
+ * ta_fwd_multi writes, for a packed batch of nblocks N x N int16 blocks
+ * (N = 2^log2n), five consecutive packed int16 batches into out:
+ *   out[0]: DCT-2 rows and columns,
+ *   out[1]: vertical DST-7, horizontal DST-7,
+ *   out[2]: vertical DST-7, horizontal DCT-8,
+ *   out[3]: vertical DCT-8, horizontal DST-7,
+ *   out[4]: vertical DCT-8, horizontal DCT-8,
+ * each (out + k * nblocks * N * N) bit-identical to ta_fwd_packed with the
+ * corresponding axes (DCT-2; DCT-2 + sub-block param_id; the same flipped).
+ * param_id: a set registered with ta_set_post for size N (the DST-7 design).
+ * Built for (N, B) = (32, 8) and (64, 16); fixed point only; out holds
+ * 5 * nblocks * N * N int16 and must not overlap in.  Errors: TA_ENOPARAMS
+ * (not a sub-block set), TA_EINVAL (size mismatch, null, misaligned,
+ * overlap), TA_EUNSUPPORTED (other N, B). */
+int ta_fwd_multi(ta_ctx* ctx, int param_id, int log2n, int64_t nblocks, const void* in, void* out,
+                 ta_stream_t stream);
+
 /* ---- Batched uneven blocks (block lists) ----------------------------------
  * A plan takes a host array of n ta_block descriptors (block sizes 4..64 per
  * side, any mix) whose axes resolve to DCT-2, or to a DST-3 + 4-tap band

@@ -36,7 +36,8 @@ TA_OK, TA_EINVAL, TA_EUNSUPPORTED, TA_ENOPARAMS, TA_EHIP = 0, -1, -2, -3, -4
 EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis",
            "ta_fwd_packed", "ta_inv_packed", "ta_set_impl", "ta_version", "ta_last_error",
            "ta_plan_create", "ta_plan_destroy", "ta_plan_info", "ta_plan_fwd", "ta_plan_inv",
-           "ta_plan_autotune", "ta_givens_workspace", "ta_givens_fwd", "ta_givens_bwd")
+           "ta_plan_autotune", "ta_givens_workspace", "ta_givens_fwd", "ta_givens_bwd",
+           "ta_fwd_multi")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -76,6 +77,7 @@ def lib() -> ctypes.CDLL:
     for f in (L.ta_fwd_packed, L.ta_inv_packed):
         f.argtypes = [vp, i32, i32, i32, i32, i64, vp, vp, i32, vp]
     L.ta_set_impl.argtypes = [vp, i32]
+    L.ta_fwd_multi.argtypes = [vp, i32, i32, i64, vp, vp, vp]
     L.ta_plan_create.argtypes = [vp, vp, i64, i32, ctypes.POINTER(vp)]
     L.ta_plan_destroy.argtypes = [vp]
     L.ta_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
@@ -171,6 +173,22 @@ class Context:
     def inv(self, y, axis_h: int, axis_v: int, out=None):
         """Inverse 2-D transform of a packed batch (columns first)."""
         return self._run(lib().ta_inv_packed, y, axis_h, axis_v, out)
+
+    def fwd_multi(self, x, param_id: int, out=None):
+        """The five encoder transforms of a packed int16 batch [nblocks, N, N]
+        (ta_fwd_multi): returns [5, nblocks, N, N] in the order DCT-2/DCT-2,
+        (DST-7, DST-7), (DST-7, DCT-8), (DCT-8, DST-7), (DCT-8, DCT-8) as
+        (vertical, horizontal)."""
+        import torch
+        if x.dim() != 3 or x.shape[1] != x.shape[2] or x.dtype != torch.int16 or not x.is_cuda:
+            raise ValueError("expected a GPU int16 tensor [nblocks, N, N]")
+        x = x.contiguous()
+        nb, n = x.shape[0], x.shape[1]
+        if out is None:
+            out = torch.empty((5, nb, n, n), dtype=torch.int16, device=x.device)
+        _check(lib().ta_fwd_multi(self._h, param_id, n.bit_length() - 1, nb, ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), _stream_handle(None)))
+        return out
 
     # raw pointer variants (no allocation; for graphs and benchmarks)
     def fwd_ptr(self, axis_h, axis_v, log2w, log2h, nblocks, in_ptr, out_ptr, dtype, stream_handle):

@@ -345,6 +345,38 @@ TA_DEV void post_rows(const S& src, cparam q, int shift, int (&out)[B]) {
   }
 }
 
+// Both sub-block adjustments of one vector at the cost of one (section
+// "Simultaneous transform adjustments", eq. 5): with the even- and
+// odd-column halves E_i = sum_{j even} Q[i][j] y_j and O_i = sum_{j odd}
+// Q[i][j] y_j, the DST-7 rows are Q y = E + O and the DCT-8 rows are
+// S Q S y = (-1)^i (E - O).  q holds, for row i, the pairs
+// (Q[i][4t], Q[i][4t+2]), t < B/4, then (Q[i][4t+1], Q[i][4t+3]).  The
+// rounding offset enters the chain whose sign stays positive, so z7/z8 are
+// the exact pre-shift sums of the two adjusted stages.
+template <int B, class S>
+TA_DEV void post_both(const S& y, cparam q, int shift, int (&z7)[B], int (&z8)[B]) {
+  const int off = 1 << (shift - 1);
+#pragma unroll
+  for (int i = 0; i < B; ++i) {
+    const bool even = (i & 1) == 0;
+    int e = 0, o = 0;
+#pragma unroll
+    for (int t = 0; t < B / 4; ++t) {
+      const uint32_t pe = y.pair(4 * t, 4 * t + 2), po = y.pair(4 * t + 1, 4 * t + 3);
+      const uint32_t qe = q[i * (B / 2) + t], qo = q[i * (B / 2) + B / 4 + t];
+      if (t == 0) {
+        e = even ? dot2h(pe, qe, off) : dot2h0(pe, qe);
+        o = even ? dot2h0(po, qo) : dot2h(po, qo, off);
+      } else {
+        e = dot2(pe, qe, e);
+        o = dot2(po, qo, o);
+      }
+    }
+    z7[i] = e + o;
+    z8[i] = even ? e - o : o - e;
+  }
+}
+
 // One axis: compile-time core, adjustment and K (taps) or B (block).
 template <int CORE_, int ADJ_, int KB_>
 struct Axis {

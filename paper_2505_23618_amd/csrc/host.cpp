@@ -47,6 +47,9 @@ struct ParamSet {
   // fixed point (packed int16 pairs) and fp32; index [flip][transposed]
   void* fx[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   void* f32[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  // sub-block sets: Q (forward, unflipped) as even/odd column pairs, for the
+  // simultaneous DST-7 / DCT-8 adjustment
+  void* fx_eo = nullptr;
 };
 
 struct AxisCfg {
@@ -373,6 +376,17 @@ int ta_set_post(ta_ctx* c, int id, int n, int b, const int16_t* q_int, const flo
       if ((e = upload(c, packed.data(), packed.size() * 4, &ps.fx[flip][tr]))) return e;
       if ((e = upload(c, fl.data(), fl.size() * 4, &ps.f32[flip][tr]))) return e;
     }
+  if (b % 4 == 0) {
+    // row i: (Q[i][4t], Q[i][4t+2]) for t < b/4, then (Q[i][4t+1], Q[i][4t+3])
+    std::vector<uint32_t> eo(b * b / 2);
+    for (int i = 0; i < b; ++i)
+      for (int t = 0; t < b / 4; ++t) {
+        eo[i * (b / 2) + t] = pack2(q_int[i * b + 4 * t], q_int[i * b + 4 * t + 2]);
+        eo[i * (b / 2) + b / 4 + t] = pack2(q_int[i * b + 4 * t + 1], q_int[i * b + 4 * t + 3]);
+      }
+    int e;
+    if ((e = upload(c, eo.data(), eo.size() * 4, &ps.fx_eo))) return e;
+  }
   return TA_OK;
 }
 
@@ -638,6 +652,34 @@ int givens_check(ta_ctx* c, int base, int n, int taps, const float* theta, int64
 }  // namespace
 
 extern "C" {
+
+int ta_fwd_multi(ta_ctx* c, int param_id, int log2n, int64_t nblocks, const void* in, void* out,
+                 ta_stream_t stream) {
+  if (!c) return fail(TA_EINVAL, "null context");
+  if (nblocks < 0) return fail(TA_EINVAL, "negative block count");
+  if (param_id < 0 || param_id >= kMaxIds) return fail(TA_EINVAL, "parameter id %d outside 0..255", param_id);
+  const ParamSet& ps = c->params[param_id];
+  if (ps.kind != TA_ADJ_POST || !ps.fx_eo) return fail(TA_ENOPARAMS, "parameter set %d is not a sub-block set", param_id);
+  if (ps.n != (1 << log2n)) return fail(TA_EINVAL, "parameter set %d is for size %d, not %d", param_id, ps.n, 1 << log2n);
+  int threads = 0, per_wg = 0;
+  const void* fn = ta::multi_kernel(log2n, ps.kb, &threads, &per_wg);
+  if (!fn) return fail(TA_EUNSUPPORTED, "simultaneous evaluation is built for 32x32 with B = 8 and 64x64 with B = 16");
+  if (nblocks == 0) return TA_OK;
+  if (!in || !out) return fail(TA_EINVAL, "null buffer");
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
+  const size_t bytes_in = (size_t)nblocks << (2 * log2n + 1);
+  const char* ib = static_cast<const char*>(in);
+  const char* ob = static_cast<const char*>(out);
+  if (ib < ob + 5 * bytes_in && ob < ib + bytes_in) return fail(TA_EINVAL, "input and output overlap");
+  ta::MultiArgs a{static_cast<const int16_t*>(in), static_cast<int16_t*>(out), nblocks, ps.fx_eo,
+                  log2n + c->bd + c->m - 15, log2n + c->m, c->a};
+  const int64_t groups = (nblocks + per_wg - 1) / per_wg;
+  if (groups > 0x7fffffff) return fail(TA_EUNSUPPORTED, "batch too large for one launch");
+  void* kargs[] = {&a};
+  TA_HIP(hipSetDevice(c->device));
+  TA_HIP(hipLaunchKernel(fn, dim3((unsigned)groups), dim3(threads), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
+  return TA_OK;
+}
 
 int ta_givens_workspace(int64_t nvec, int64_t* bytes) {
   if (!bytes || nvec < 0) return fail(TA_EINVAL, "bad argument");

@@ -107,6 +107,17 @@ struct BatchArgs {
 // Persistent batched kernels over a planned tile list (batch_kernels.hip).
 const void* batch_kernel(int inv);
 
+// Encoder evaluation of the five separable transforms (multi_kernels.hip):
+// out holds 5 consecutive packed batches of nblocks N x N int16 blocks.
+struct MultiArgs {
+  const int16_t* in;
+  int16_t* out;
+  int64_t nblocks;
+  const void* q_eo;   // sub-block Q of the DST-7 design, even/odd column pairs
+  int s_row, s_col, a;
+};
+const void* multi_kernel(int log2n, int b, int* threads, int* blocks);
+
 // Differentiable Givens-band path (givens_kernels.hip).
 constexpr int kMaxAng = 96;   // angle slots per workgroup partial (N <= 32, L <= 3)
 struct GivensArgs {

@@ -53,3 +53,4 @@ def test_null_context_paths():
     assert lib.ta_fwd_packed(None, 0, 0, 5, 5, 1, None, None, 0, None) == ta.TA_EINVAL
     assert lib.ta_inv_packed(None, 0, 0, 5, 5, 1, None, None, 0, None) == ta.TA_EINVAL
     assert lib.ta_set_impl(None, 0) == ta.TA_EINVAL
+    assert lib.ta_fwd_multi(None, 0, 5, 1, None, None, None) == ta.TA_EINVAL
