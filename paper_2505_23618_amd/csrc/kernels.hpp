@@ -63,35 +63,33 @@ struct BatchTile {
 constexpr int kXcds = 8;
 
 // Tile geometry of the batched kernels, shared by the host planner and the
-// device code.  A tile holds NB blocks of one size; NB = 256 / max(W, H)
-// (one thread per row and per column), halved while the tile's LDS would
-// exceed 20 KiB, so that 8 workgroups fit on a CU (160 KiB of LDS).  The
-// LDS holds the tile in the pair-column layout (PC, dwords) and, aliased,
-// in the row-major layout (RM, halfwords; rows padded to W + 8 for W >= 8,
-// blocks padded by 32 halfwords when that still fits).  The inverse reads
-// RM rows (pitch RP, block RMB halfwords); the forward writes RM with pitch W
-// (block RMBF halfwords) for its coalesced stores.
+// device code.  A tile holds NB blocks of one size W x H side by side: in
+// LDS, pair-row i of the tile (rows 2i, 2i+1 of every block, packed in
+// dwords) has pitch PC_PITCH(H) dwords and row r has pitch RM_PITCH(H)
+// halfwords, block b starting at column b * W.  With NB * W <= 256 (<= 128
+// for H = 64) the pitches depend on H only, so a column thread (index
+// b * W + c) finds its values at compile-time offsets from its own index.
+// NB = 256 / max(W, H) (one thread per row and per column), capped by the
+// column limit.
 struct BatchGeo {
-  int W, H, NB, PP, PCB, RP, RMB, RMBF, CH;
-  static constexpr int kLdsBytes = 20480;
-  static constexpr int lds_bytes(int w, int h, int nb, bool pad) {
-    const int pc = nb * (h / 2) * (w + 1) * 4;
-    const int rm = nb * (h * (w >= 8 ? w + 8 : w) + (pad && w >= 8 ? 32 : 0)) * 2;
+  static constexpr int pc_pitch(int lh) { return lh == 6 ? 129 : 257; }
+  static constexpr int rm_pitch(int lh) { return lh == 6 ? 136 : 264; }
+  static constexpr int nb_for(int lw, int lh) {
+    const int nb = 256 >> (lw > lh ? lw : lh);
+    const int cap = (lh == 6 ? 128 : 256) >> lw;
+    return nb < cap ? nb : cap;
+  }
+  // LDS of a tile (dwords): the pair-row and row layouts alias one buffer
+  static constexpr int lds_dwords(int lh) {
+    const int h = 1 << lh;
+    const int pc = (h / 2) * pc_pitch(lh), rm = (h * rm_pitch(lh) + 1) / 2;
     return pc > rm ? pc : rm;
   }
-  static constexpr int nb_for(int lw, int lh) {
-    int nb = 256 >> (lw > lh ? lw : lh);
-    while (nb > 1 && lds_bytes(1 << lw, 1 << lh, nb, false) > kLdsBytes) nb /= 2;
-    return nb;
+  static constexpr int max_lds_dwords() {
+    int m = 0;
+    for (int lh = 2; lh <= 6; ++lh) m = lds_dwords(lh) > m ? lds_dwords(lh) : m;
+    return m;
   }
-  static constexpr bool pad_for(int lw, int lh) {
-    return lds_bytes(1 << lw, 1 << lh, nb_for(lw, lh), true) <= kLdsBytes;
-  }
-  __host__ __device__ constexpr BatchGeo(int lw, int lh)
-      : W(1 << lw), H(1 << lh), NB(nb_for(lw, lh)), PP((1 << lw) + 1), PCB((1 << (lh - 1)) * ((1 << lw) + 1)),
-        RP(lw >= 3 ? (1 << lw) + 8 : (1 << lw)),
-        RMB((1 << lh) * (lw >= 3 ? (1 << lw) + 8 : (1 << lw)) + (lw >= 3 && pad_for(lw, lh) ? 32 : 0)),
-        RMBF((1 << lh) * (1 << lw) + (lw >= 3 && pad_for(lw, lh) ? 32 : 0)), CH(lw >= 3 ? 8 : 4) {}
 };
 
 struct BatchArgs {
