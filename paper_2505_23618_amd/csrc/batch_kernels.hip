@@ -31,6 +31,14 @@ using KS3 = Axis<C_DST3, ADJ_BAND, 4>;
 using KC3 = Axis<C_DCT3, ADJ_BAND, 4>;
 
 constexpr int kBatchLds = BatchGeo::max_lds_dwords();
+
+// Offsets and strides of the blocks of the current tile, in LDS: the chunk
+// loops look them up there instead of loading a descriptor per chunk.
+struct BDesc {
+  int64_t in_off, out_off;
+  int32_t in_stride, out_stride;
+};
+constexpr int kMaxTileBlocks = 64;
 static_assert(kBatchLds * 4 <= 20480, "tile LDS above 20 KiB");
 
 template <int W>
@@ -50,11 +58,12 @@ TA_DEV void load_strided_row(const int16_t* __restrict__ src, fx::Packed<W>& x) 
 // ---------------------------------------------------------------- forward
 // row phase of one tile for kind KH at width W (H = 2^lh rows per block)
 template <int W, class KH>
-TA_DEV void fwd_rows(const BatchArgs& a, const BatchTile& t, uint16_t* pch, int s_row) {
+TA_DEV void fwd_rows(const BatchArgs& a, const BatchTile& t, uint16_t* pch, BDesc* desc, int s_row) {
   const int tid = threadIdx.x;
   if (tid >= (t.count << t.lh)) return;
   const int b = tid >> t.lh, r = tid & ((1 << t.lh) - 1);
   const ta_block d = a.blocks[t.first + b];
+  if (r == 0) desc[b] = BDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
   fx::Packed<W> x;
   load_strided_row<W>(a.in + d.in_off + (int64_t)r * d.in_stride, x);
   const auto y = fx::run_pass<W, KH, false>(x, as_cparam(t.ph_f), as_cparam(t.ph_i), s_row, a.a);
@@ -95,13 +104,13 @@ TA_DEV void fwd_cols(const BatchArgs& a, const BatchTile& t, uint32_t* lds, int 
 }
 
 template <class KH>
-TA_DEV void fwd_rows_w(const BatchArgs& a, const BatchTile& t, uint16_t* pch, int s) {
+TA_DEV void fwd_rows_w(const BatchArgs& a, const BatchTile& t, uint16_t* pch, BDesc* desc, int s) {
   switch (t.lw) {
-    case 2: fwd_rows<4, KH>(a, t, pch, s); break;
-    case 3: fwd_rows<8, KH>(a, t, pch, s); break;
-    case 4: fwd_rows<16, KH>(a, t, pch, s); break;
-    case 5: fwd_rows<32, KH>(a, t, pch, s); break;
-    default: fwd_rows<64, KH>(a, t, pch, s); break;
+    case 2: fwd_rows<4, KH>(a, t, pch, desc, s); break;
+    case 3: fwd_rows<8, KH>(a, t, pch, desc, s); break;
+    case 4: fwd_rows<16, KH>(a, t, pch, desc, s); break;
+    case 5: fwd_rows<32, KH>(a, t, pch, desc, s); break;
+    default: fwd_rows<64, KH>(a, t, pch, desc, s); break;
   }
 }
 
@@ -130,6 +139,7 @@ struct Chunk {
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_fwd(BatchArgs a) {
   __shared__ __align__(16) uint32_t lds[kBatchLds];
+  __shared__ BDesc desc[kMaxTileBlocks];
   uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
   // this workgroup's XCD list and its stride within that list
   const int xcd = blockIdx.x % kXcds;
@@ -139,9 +149,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
     const BatchTile t = a.tiles[ti];
     const int s_row = t.lw + a.bd + a.m - 15, s_col = t.lh + a.m;
     switch (t.kind_h) {
-      case 0: fwd_rows_w<KC2>(a, t, pch, s_row); break;
-      case 1: fwd_rows_w<KS3>(a, t, pch, s_row); break;
-      default: fwd_rows_w<KC3>(a, t, pch, s_row); break;
+      case 0: fwd_rows_w<KC2>(a, t, pch, desc, s_row); break;
+      case 1: fwd_rows_w<KS3>(a, t, pch, desc, s_row); break;
+      default: fwd_rows_w<KC3>(a, t, pch, desc, s_row); break;
     }
     __syncthreads();
     switch (t.kind_v) {
@@ -156,7 +166,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
     const int nch = t.count << (t.lw + t.lh - lch);
     for (int ch = threadIdx.x; ch < nch; ch += 256) {
       const Chunk k(ch, t.lw, t.lh, lch);
-      const ta_block d = a.blocks[t.first + k.b];
+      const BDesc d = desc[k.b];
       int16_t* dst = a.out + d.out_off + (int64_t)k.r * d.out_stride + k.c0;
       const uint16_t* src = pch + k.r * q + (k.b << t.lw) + k.c0;
       if (lch == 3)
@@ -250,6 +260,7 @@ TA_DEV void inv_rows_w(const BatchArgs& a, const BatchTile& t, uint16_t* rm, int
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_inv(BatchArgs a) {
   __shared__ __align__(16) uint32_t lds[kBatchLds];
+  __shared__ BDesc desc[kMaxTileBlocks];
   uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
   // this workgroup's XCD list and its stride within that list
   const int xcd = blockIdx.x % kXcds;
@@ -260,12 +271,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
     const int s_col = a.m + 1, s_row = a.m + 14 - a.bd;
     const int lch = t.lw >= 3 ? 3 : 2;
     const int nch = t.count << (t.lw + t.lh - lch);
+    if ((int)threadIdx.x < t.count) {
+      const ta_block d = a.blocks[t.first + threadIdx.x];
+      desc[threadIdx.x] = BDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
+    }
+    __syncthreads();
     // coalesced load of the tile into the pair-row layout
     {
       const int p = BatchGeo::pc_pitch(t.lh);
       for (int ch = threadIdx.x; ch < nch; ch += 256) {
         const Chunk k(ch, t.lw, t.lh, lch);
-        const ta_block d = a.blocks[t.first + k.b];
+        const BDesc d = desc[k.b];
         const int16_t* src = a.in + d.in_off + (int64_t)k.r * d.in_stride + k.c0;
         uint32_t w[4];
         if (lch == 3) {
@@ -300,7 +316,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
       const int q = BatchGeo::rm_pitch(t.lh);
       for (int ch = threadIdx.x; ch < nch; ch += 256) {
         const Chunk k(ch, t.lw, t.lh, lch);
-        const ta_block d = a.blocks[t.first + k.b];
+        const BDesc d = desc[k.b];
         int16_t* dst = a.out + d.out_off + (int64_t)k.r * d.out_stride + k.c0;
         const uint16_t* src = pch + k.r * q + (k.b << t.lw) + k.c0;
         if (lch == 3)
