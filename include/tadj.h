@@ -105,12 +105,17 @@ int ta_destroy(ta_ctx* ctx);
  * non-zeros only in columns [s_i, s_i + K) with
  * s_i = i - K/2 + ((i + K/2) mod 2), the support of K/2 layers of parallel
  * Givens rotations on adjacent pairs (even pairs first); otherwise
- * TA_EUNSUPPORTED.  Copied synchronously; param_id in 0..255. */
+ * TA_EUNSUPPORTED.  Copied synchronously; param_id in 0..255.
+ * Registering a param_id again stores new device tables; the previous ones
+ * stay allocated until ta_destroy, so a plan built earlier keeps the values
+ * it was built with.  Must not run concurrently with transform calls on the
+ * same context. */
 int ta_set_band(ta_ctx* ctx, int param_id, int n, int taps,
                 const int16_t* a_int, const float* a_f32);
 
 /* Register a B x B sub-block post-adjustment Q (section 2.2 item 2, Fig. 2b):
- * C = blkdiag(Q, I_{n-B}), 2 <= B <= n, B even; q_int at scale 2^a. */
+ * C = blkdiag(Q, I_{n-B}), 2 <= B <= n, B even; q_int at scale 2^a.  Same
+ * copy and re-registration rules as ta_set_band. */
 int ta_set_post(ta_ctx* ctx, int param_id, int n, int b,
                 const int16_t* q_int, const float* q_f32);
 
