@@ -214,15 +214,71 @@ TA_DEV void c2_int(const int (&v)[M], int (&z)[M], int off) {
   }
 }
 
+// Unpack natural int16 pairs into int32 values.
+template <int M>
+TA_DEV void unpack_pairs(const uint32_t (&p)[M / 2], int (&v)[M]) {
+#pragma unroll
+  for (int s = 0; s < M / 2; ++s) {
+    v[2 * s] = (int)(short)(p[s] & 0xffffu);
+    v[2 * s + 1] = (int)p[s] >> 16;
+  }
+}
+
+// M-point DCT-2 of u from natural int16 pairs x of f, u_n = f_n, or
+// u_n = (-1)^n f_n with NEG, all |f_n| < 2^14 in the wave.  The first level
+// stays in int16: one packed add or subtract of x[s] and the half-swapped
+// x[M/2-1-s] gives two values of d_n = u_n - u_{M-1-n} (or of e) at once
+// (with NEG, d_n = (-1)^n (f_n + f_{M-1-n}) and e_n = (-1)^n (f_n - f_{M-1-n}):
+// the lane signs move into the coefficients or into the next level), so
+// each odd row costs M/4 dot2.  With DEEP the even half recurses the same
+// way while the wave's e values stay within +-2^14 (forward passes, whose
+// inputs are residual-sized); otherwise, and below 4 points, it continues
+// on int32 with 24-bit multiply-adds.  z[k] gets the exact sum plus off.
+template <int M, bool NEG, bool DEEP>
+TA_DEV void c2_packed(const uint32_t (&x)[M / 2], int (&z)[M], int off) {
+  constexpr int SG = NEG ? -1 : 1;
+  uint32_t dp[M / 4], ep[M / 4];
+#pragma unroll
+  for (int s = 0; s < M / 4; ++s) {
+    const uint32_t a = x[s], b = x[M / 2 - 1 - s];
+    dp[s] = NEG ? pk_add_x(a, b) : pk_sub_x(a, b);
+    ep[s] = NEG ? pk_sub_x(a, b) : pk_add_x(a, b);
+  }
+#pragma unroll
+  for (int k = 1; k < M; k += 2) {
+    int acc = off;
+#pragma unroll
+    for (int s = 0; s < M / 4; ++s) {
+      const uint32_t cf = pk2(c2i<M>(k, 2 * s), SG * c2i<M>(k, 2 * s + 1));
+      acc = s == 0 ? dot2h(dp[s], cf, off) : dot2(dp[s], cf, acc);
+    }
+    z[k] = acc;
+  }
+  int ze[M / 2];
+  bool packed = false;
+  if constexpr (DEEP && M / 2 >= 4) {
+    if (wave_all(lanes_within_14(ep))) {
+      c2_packed<M / 2, NEG, DEEP>(ep, ze, off);
+      packed = true;
+    }
+  }
+  if (!packed) {
+    int e[M / 2];
+    unpack_pairs<M / 2>(ep, e);
+    c2_int<M / 2, NEG>(e, ze, off);
+  }
+#pragma unroll
+  for (int k = 0; k < M / 2; ++k) z[2 * k] = ze[k];
+}
+
 // ISIGN applies S to the input, OREV reverses the output (DST-2 = R DCT-2 S).
 //
 // The input arrives as natural int16 pairs x[s] = (x_2s, x_2s+1).  When every
-// |x_n| < 2^14 in the whole wave, the first level stays in int16: one packed
-// add or subtract of x[s] and the half-swapped x[N/2-1-s] yields the pair
-// (d_2s, d_2s+1) (or e), so each odd row costs N/4 dot2 instead of N/2.
-// Otherwise the odd rows are taken as full-length dot products of the input
-// pairs and e is formed in int32.  Both give the same exact integer sums.
-template <int N, bool ISIGN, bool OREV, class S>
+// |x_n| < 2^14 in the whole wave, c2_packed runs the first level (and, with
+// DEEP, deeper levels) in int16; otherwise the odd rows are taken as
+// full-length dot products of the input pairs and e is formed in int32.
+// Both give the same exact integer sums.
+template <int N, bool ISIGN, bool OREV, bool DEEP, class S>
 TA_DEV Acc<N> core_c2(const S& src, int shift) {
   const int off = 1 << (shift - 1);
   Acc<N> r;
@@ -230,35 +286,12 @@ TA_DEV Acc<N> core_c2(const S& src, int shift) {
   uint32_t x[N / 2];
 #pragma unroll
   for (int s = 0; s < N / 2; ++s) x[s] = src.pair(2 * s, 2 * s + 1);
-  // With S applied, u_n = (-1)^n x_n: d_n = (-1)^n (x_n + x_{N-1-n}) and
-  // e_n = (-1)^n (x_n - x_{N-1-n}); the sign of the odd-n lane moves into the
-  // coefficient (odd rows) or into c2_int (even rows).
+  // With S applied, u_n = (-1)^n x_n: the sign of the odd-n lane moves into
+  // the coefficient (odd rows) or into c2_int (even rows).
   constexpr int SG = ISIGN ? -1 : 1;
   int z[N];
-  int e[N / 2];
   if (wave_all(lanes_within_14(x))) {
-    uint32_t dp[N / 4], ep[N / 4];
-#pragma unroll
-    for (int s = 0; s < N / 4; ++s) {
-      const uint32_t a = x[s], b = x[N / 2 - 1 - s];
-      dp[s] = ISIGN ? pk_add_x(a, b) : pk_sub_x(a, b);
-      ep[s] = ISIGN ? pk_sub_x(a, b) : pk_add_x(a, b);
-    }
-#pragma unroll
-    for (int k = 1; k < N; k += 2) {
-      int acc = off;
-#pragma unroll
-      for (int s = 0; s < N / 4; ++s) {
-        const uint32_t cf = pk2(c2i<N>(k, 2 * s), SG * c2i<N>(k, 2 * s + 1));
-        acc = s == 0 ? dot2h(dp[s], cf, off) : dot2(dp[s], cf, acc);
-      }
-      z[k] = acc;
-    }
-#pragma unroll
-    for (int s = 0; s < N / 4; ++s) {
-      e[2 * s] = (int)(short)(ep[s] & 0xffffu);
-      e[2 * s + 1] = (int)ep[s] >> 16;
-    }
+    c2_packed<N, ISIGN, DEEP>(x, z, off);
   } else {
 #pragma unroll
     for (int k = 1; k < N; k += 2) {
@@ -270,6 +303,7 @@ TA_DEV Acc<N> core_c2(const S& src, int shift) {
       }
       z[k] = acc;
     }
+    int e[N / 2];
 #pragma unroll
     for (int n = 0; n < N / 2; ++n) {
       const int a = (n & 1) ? ((int)x[n >> 1] >> 16) : (int)(short)(x[n >> 1] & 0xffffu);
@@ -277,11 +311,11 @@ TA_DEV Acc<N> core_c2(const S& src, int shift) {
       const int b = (m & 1) ? ((int)x[m >> 1] >> 16) : (int)(short)(x[m >> 1] & 0xffffu);
       e[n] = ISIGN ? a - b : a + b;
     }
-  }
-  int ze[N / 2];
-  c2_int<N / 2, ISIGN>(e, ze, off);
+    int ze[N / 2];
+    c2_int<N / 2, ISIGN>(e, ze, off);
 #pragma unroll
-  for (int k = 0; k < N / 2; ++k) z[2 * k] = ze[k];
+    for (int k = 0; k < N / 2; ++k) z[2 * k] = ze[k];
+  }
 #pragma unroll
   for (int m = 0; m < N; ++m) r.a[m] = z[OREV ? N - 1 - m : m];
   return r;
@@ -319,8 +353,9 @@ TA_DEV Acc<N> core_direct(const S& src, int shift) {
 template <int N, int CORE, bool TR, class S>
 TA_DEV Acc<N> core(const S& src, int shift) {
   constexpr int C = (CORE == C_DST7 || CORE == C_DCT8) ? CORE : (TR ? core_transpose(CORE) : CORE);
-  if constexpr (C == C_DCT2) return core_c2<N, false, false>(src, shift);
-  else if constexpr (C == C_DST2) return core_c2<N, true, true>(src, shift);
+  // the forward's DCT-2 cores see residual-sized inputs: deeper packed levels
+  if constexpr (C == C_DCT2) return core_c2<N, false, false, !TR>(src, shift);
+  else if constexpr (C == C_DST2) return core_c2<N, true, true, !TR>(src, shift);
   else if constexpr (C == C_DCT3) return core_c3<N, false, false>(src, shift);
   else if constexpr (C == C_DST3) return core_c3<N, true, true>(src, shift);
   else return core_direct<N, C, TR>(src, shift);
