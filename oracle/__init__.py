@@ -16,6 +16,9 @@ Modules
   fixed       integer tables and the fixed-point separable 2-D forward/inverse
   fp          FP64 separable 2-D forward/inverse (H_v X H_h^T)
   refit       the differentiable refit objective and its analytic gradient
+  stats       statistics of quantised coefficients: per-position level
+              histograms, entropy, energy, distortion, coding gain (a proxy
+              for the coding results of Tables 2 and 3)
   fit_params  script that fits and freezes the adjustment parameters
 
 Pins (what fixes each function independently of itself) are listed in the
