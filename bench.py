@@ -129,6 +129,36 @@ def secondary(ctx, ids, x32):
                                 "workload": "262,144 blocks 32x32: DCT-2/DCT-2 and (DST-7|DCT-8)^2 with the 8x8 sub-block"}
     del out5
     torch.cuda.empty_cache()
+    # coding-gain proxy: energy compaction and rate of the quantised
+    # coefficients of the same 32x32 residuals under the DCT-2, the adjusted
+    # DST-7 designs and the exact DST-7 (a codec-free stand-in for Tables 2-3)
+    proxy_axes = {"dct2": c2, "adj_dst7_band4": ctx.axis(23, ta.DST3, ta.ADJ_BAND, False, ids["band_S3_S7_N32_K4"]),
+                  "adj_dst7_band6": ctx.axis(24, ta.DST3, ta.ADJ_BAND, False, ids["band_S3_S7_N32_K6"]),
+                  "adj_dst7_sub8": s7, "dst7": ctx.axis(25, ta.DST7, ta.ADJ_NONE, False, 0)}
+    steps = (32, 64, 128)
+    yq = torch.empty_like(x32)
+    table, ts = {}, None
+    for name, ax in proxy_axes.items():
+        ctx.fwd(x32, ax, ax, out=yq)
+        rows = []
+        for q in steps:
+            sm = ctx.coef_stats(yq, q, q // 2)["summary"].cpu().numpy()
+            rows.append(sm)
+        table[name] = {"coding_gain_db": float(rows[0][3]), "low_band_fraction": float(rows[0][4]),
+                       "bits_per_coef": [float(r[0]) for r in rows], "mse_per_coef": [float(r[1]) for r in rows]}
+        if ts is None:
+            buf = ctx.coef_stats(yq, 64, 32)
+            ts = _events_mean(lambda i: ctx.coef_stats(yq, 64, 32, out=buf), 10)
+    ref = table["dst7"]["bits_per_coef"]
+    for name, row in table.items():
+        row["rate_vs_dst7_pct"] = [100.0 * (b / r - 1.0) for b, r in zip(row["bits_per_coef"], ref)]
+    res["coding_gain_proxy"] = {"value": n32 / ts, "unit": "coef/s", "stats_us": ts * 1e6,
+                                "GB/s": 2 * n32 / ts / 1e9, "hbm_frac": 2 * n32 / ts / 1e9 / HBM_PEAK_GBS,
+                                "quantiser_steps": list(steps), "offset": "step / 2", "transforms": table,
+                                "workload": "262,144 blocks 32x32 AR(1) rho=0.95 sigma=16, forward of each "
+                                            "transform, then per-position symbol histograms, rate, energy"}
+    del yq
+    torch.cuda.empty_cache()
     # 64x64 blocks, DCT-2 + 16x16 sub-block: DCT-8 rows (eq. 5), DST-7 columns
     ph = ctx.axis(10, ta.DCT2, ta.ADJ_POST, True, ids["post_C2_S7_N64_B16"])
     pv = ctx.axis(11, ta.DCT2, ta.ADJ_POST, False, ids["post_C2_S7_N64_B16"])

@@ -180,6 +180,43 @@ int ta_plan_fwd(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream
 int ta_plan_inv(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream);
 int ta_plan_autotune(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream, int reps);
 
+/* ---- Quantised-coefficient statistics (coding-gain proxy) -------------------
+ * A codec-free stand-in for the coding results of the experiments section
+ * (Tables 2 and 3), which compare BD-rates inside a video codec: on the same
+ * residual blocks, how the adjusted and the exact transforms compare in
+ * energy compaction and in the rate of the quantised coefficients.
+ * coef: nblocks packed H x W int16 coefficient blocks (H = 2^log2h,
+ * W = 2^log2w, 2 <= log2h, log2w <= 6), e.g. the output of ta_fwd_packed.
+ * Quantiser: level q = sign(y) floor((|y| + offset) / step), 1 <= step <=
+ * 32768, 0 <= offset < step (offset = step / 2 rounds to nearest, ties away
+ * from zero).  Symbols: q itself for |q| <= 31, else an escape +-32, whose
+ * suffix is the order-0 Exp-Golomb code of |q| - 32 (2 floor(log2(|q| - 31))
+ * + 1 bits).  Positions p = row * W + col, P = H * W.  Outputs (device
+ * memory, overwritten, none may overlap another or coef):
+ *   hist      P x 65 uint32, hist[p][32 + s] = blocks with symbol s at p
+ *   esc_bits  P uint64, suffix bits of the escapes at p
+ *   energy    P uint64, sum of y^2 at p
+ *   dist      P uint64, sum of (y - q step)^2 at p
+ *   rate      P double, entropy of the symbols at p plus esc_bits / nblocks
+ *   summary   7 doubles: mean rate per coefficient (bits), distortion and
+ *             energy per coefficient, transform coding gain in dB (10 log10
+ *             of the arithmetic over the geometric mean of the per-position
+ *             mean energies; 0 with no energy, +inf if some position has
+ *             none), fraction of the energy in the top-left (H/4) x (W/4)
+ *             positions (0 with no energy), fractions of nonzero and of
+ *             escaped levels.  All zero for nblocks = 0.
+ * workspace: device scratch of at least ta_coef_stats_workspace(ctx, nblocks,
+ * log2h, log2w) bytes, 8-byte aligned (partial results per block range;
+ * the size depends on the device's occupancy, so query it per context).
+ * Counts and sums are exact; rate and summary are reduced in a fixed order
+ * (bitwise repeatable).  Asynchronous on the stream, allocates nothing.
+ * Errors: TA_EINVAL (null, misaligned, bad step/offset, workspace too small,
+ * nblocks * P > 2^34), TA_EUNSUPPORTED (block size). */
+int ta_coef_stats_workspace(ta_ctx* ctx, int64_t nblocks, int log2h, int log2w, int64_t* bytes);
+int ta_coef_stats(ta_ctx* ctx, const int16_t* coef, int64_t nblocks, int log2h, int log2w, int32_t step,
+                  int32_t offset, uint32_t* hist, uint64_t* esc_bits, uint64_t* energy, uint64_t* dist, double* rate,
+                  double* summary, void* workspace, int64_t workspace_bytes, ta_stream_t stream);
+
 /* ---- Differentiable refit path (fp32) ---------------------------------------
  * y_m = B A(theta) x_m for nvec vectors of n floats (x, y: nvec x n, row per
  * vector), B = TA_DCT2 or TA_DST3, A(theta) = taps/2 layers of parallel

@@ -37,7 +37,7 @@ EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis
            "ta_fwd_packed", "ta_inv_packed", "ta_set_impl", "ta_version", "ta_last_error",
            "ta_plan_create", "ta_plan_destroy", "ta_plan_info", "ta_plan_fwd", "ta_plan_inv",
            "ta_plan_autotune", "ta_givens_workspace", "ta_givens_fwd", "ta_givens_bwd",
-           "ta_fwd_multi")
+           "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -78,6 +78,8 @@ def lib() -> ctypes.CDLL:
         f.argtypes = [vp, i32, i32, i32, i32, i64, vp, vp, i32, vp]
     L.ta_set_impl.argtypes = [vp, i32]
     L.ta_fwd_multi.argtypes = [vp, i32, i32, i64, vp, vp, vp]
+    L.ta_coef_stats_workspace.argtypes = [vp, i64, i32, i32, ctypes.POINTER(i64)]
+    L.ta_coef_stats.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp]
     L.ta_plan_create.argtypes = [vp, vp, i64, i32, ctypes.POINTER(vp)]
     L.ta_plan_destroy.argtypes = [vp]
     L.ta_plan_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
@@ -94,6 +96,11 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
+
+
+SUMMARY_FIELDS = ("bits_per_coef", "mse_per_coef", "energy_per_coef", "coding_gain_db",
+                  "low_band_fraction", "nonzero_fraction", "escape_fraction")
+STATS_SYMBOLS = 65      # levels -31..31 and the two escapes
 
 
 def _check(code: int):
@@ -188,6 +195,41 @@ class Context:
             out = torch.empty((5, nb, n, n), dtype=torch.int16, device=x.device)
         _check(lib().ta_fwd_multi(self._h, param_id, n.bit_length() - 1, nb, ctypes.c_void_p(x.data_ptr()),
                                   ctypes.c_void_p(out.data_ptr()), _stream_handle(None)))
+        return out
+
+    def coef_stats(self, coef, step: int, offset: int, out=None):
+        """Statistics of the quantised coefficients of a packed int16 batch
+        [nblocks, H, W] (ta_coef_stats): a dict of GPU tensors hist [P, 65]
+        (int32 view of the uint32 symbol counts, column 32 + symbol),
+        esc_bits, energy, dist [P] (int64), rate [P] and summary [7]
+        (float64; fields SUMMARY_FIELDS), P = H * W, plus the device scratch
+        ("workspace").  `out`, a dict from an earlier call with the same
+        block shape, is reused."""
+        import torch
+        if coef.dim() != 3 or coef.dtype != torch.int16 or not coef.is_cuda:
+            raise ValueError("expected a GPU int16 tensor [nblocks, H, W]")
+        coef = coef.contiguous()
+        nb, h, w = coef.shape
+        if h & (h - 1) or w & (w - 1) or h == 0 or w == 0:
+            raise ValueError("block sides must be powers of two")
+        p = h * w
+        lh, lw = h.bit_length() - 1, w.bit_length() - 1
+        ws = ctypes.c_int64(0)
+        _check(lib().ta_coef_stats_workspace(self._h, nb, lh, lw, ctypes.byref(ws)))
+        if out is None or out["workspace"].numel() < ws.value or out["hist"].shape[0] != p:
+            dev = coef.device
+            out = {"hist": torch.empty((p, STATS_SYMBOLS), dtype=torch.int32, device=dev),
+                   "esc_bits": torch.empty(p, dtype=torch.int64, device=dev),
+                   "energy": torch.empty(p, dtype=torch.int64, device=dev),
+                   "dist": torch.empty(p, dtype=torch.int64, device=dev),
+                   "rate": torch.empty(p, dtype=torch.float64, device=dev),
+                   "summary": torch.empty(len(SUMMARY_FIELDS), dtype=torch.float64, device=dev),
+                   "workspace": torch.empty(max(ws.value, 8), dtype=torch.uint8, device=dev)}
+        ptr = {k: ctypes.c_void_p(v.data_ptr()) for k, v in out.items()}
+        _check(lib().ta_coef_stats(self._h, ctypes.c_void_p(coef.data_ptr()), nb, lh, lw, step, offset,
+                                   ptr["hist"], ptr["esc_bits"], ptr["energy"], ptr["dist"], ptr["rate"],
+                                   ptr["summary"], ptr["workspace"], out["workspace"].numel(),
+                                   _stream_handle(None)))
         return out
 
     # raw pointer variants (no allocation; for graphs and benchmarks)

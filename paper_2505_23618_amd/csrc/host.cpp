@@ -725,3 +725,131 @@ int ta_givens_bwd(ta_ctx* c, int base, int n, int taps, const float* theta, int6
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Quantised-coefficient statistics
+// ---------------------------------------------------------------------------
+extern "C" {
+
+}  // extern "C"
+
+namespace {
+
+// Geometry of the statistics launch: workgroups of 4 waves own 64 positions
+// and a range of blocks; the range count fills the device once and keeps
+// every 16-bit LDS counter below 2^16.
+int stats_plan(ta_ctx* c, int64_t nblocks, int log2h, int log2w, ta::StatsArgs* a, int64_t* ws_bytes) {
+  if (!c) return fail(TA_EINVAL, "null context");
+  if (log2h < 2 || log2h > 6 || log2w < 2 || log2w > 6) return fail(TA_EUNSUPPORTED, "block sides 4..64");
+  if (nblocks < 0) return fail(TA_EINVAL, "negative block count");
+  const int positions = 1 << (log2h + log2w);
+  if (nblocks > ((int64_t)1 << 34) / positions) return fail(TA_EINVAL, "more than 2^34 coefficients");
+  *a = ta::StatsArgs{};
+  a->nblocks = nblocks;
+  a->positions = positions;
+  a->log2h = log2h;
+  a->log2w = log2w;
+  a->total = nblocks * positions;
+  const int np = std::min(positions, 64);
+  a->slabs = positions / np;
+  a->wstride = std::max(positions, 64);
+  a->wave_steps = positions >= 64 ? nblocks : (a->total + 63) / 64;
+  const int64_t full_waves = positions >= 64 ? nblocks : a->total / 64;
+  a->steps = (a->wave_steps + 3) / 4;
+  a->full_steps = full_waves / 4;
+  a->ranges = 0;
+  a->steps_per_wg = 0;
+  if (a->steps > 0) {
+    ta::KernelEntry k{};
+    k.fn = ta::stats_kernel(1);
+    k.threads = 256;
+    int resident = 0, e;
+    if ((e = resident_groups(&k, c->device, &resident))) return e;
+    int64_t ranges = std::max<int64_t>(1, (resident + a->slabs - 1) / a->slabs);
+    const int64_t cap = 65535 / (256 / np);   // samples per position per workgroup < 2^16
+    a->steps_per_wg = std::min<int64_t>((a->steps + ranges - 1) / ranges, cap);
+    a->ranges = (a->steps + a->steps_per_wg - 1) / a->steps_per_wg;
+    if (a->ranges * a->slabs > 0x7fffffff) return fail(TA_EUNSUPPORTED, "batch too large for one launch");
+  }
+  // packed counters, then (8-byte aligned) the three sums per slot
+  const int64_t slots = a->ranges * positions;
+  *ws_bytes = ((slots * ta::kStatsPartDwords * 4 + 7) & ~(int64_t)7) + slots * 3 * (int64_t)sizeof(uint64_t) +
+              positions * (int64_t)sizeof(double);
+  return TA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ta_coef_stats_workspace(ta_ctx* c, int64_t nblocks, int log2h, int log2w, int64_t* bytes) {
+  if (!bytes) return fail(TA_EINVAL, "null argument");
+  ta::StatsArgs a;
+  return stats_plan(c, nblocks, log2h, log2w, &a, bytes);
+}
+
+int ta_coef_stats(ta_ctx* c, const int16_t* coef, int64_t nblocks, int log2h, int log2w, int32_t step,
+                  int32_t offset, uint32_t* hist, uint64_t* esc_bits, uint64_t* energy, uint64_t* dist, double* rate,
+                  double* summary, void* workspace, int64_t workspace_bytes, ta_stream_t stream) {
+  ta::StatsArgs a;
+  int64_t need = 0;
+  int e;
+  if ((e = stats_plan(c, nblocks, log2h, log2w, &a, &need))) return e;
+  if (step < 1 || step > 32768 || offset < 0 || offset >= step)
+    return fail(TA_EINVAL, "need 1 <= step <= 32768 and 0 <= offset < step");
+  if (!hist || !esc_bits || !energy || !dist || !rate || !summary || (nblocks > 0 && !coef))
+    return fail(TA_EINVAL, "null buffer");
+  if (workspace_bytes < need || (need > 0 && !workspace))
+    return fail(TA_EINVAL, "workspace of %lld bytes needed", (long long)need);
+  if (((uintptr_t)hist & 3) || (((uintptr_t)esc_bits | (uintptr_t)energy | (uintptr_t)dist | (uintptr_t)rate |
+                                 (uintptr_t)summary | (uintptr_t)workspace) & 7) || ((uintptr_t)coef & 1))
+    return fail(TA_EINVAL, "misaligned buffer");
+  a.in = coef;
+  a.step = step;
+  a.offset = offset;
+  int cl = 0;
+  while ((1 << cl) < step) ++cl;
+  a.magic_shift = 16 + cl;
+  a.magic = (uint32_t)((((uint64_t)1 << a.magic_shift) + (uint64_t)step - 1) / (uint64_t)step);
+  a.hist = hist;
+  a.esc_bits = esc_bits;
+  a.energy = energy;
+  a.dist = dist;
+  a.rate = rate;
+  a.summary = summary;
+  const int64_t slots = a.ranges * a.positions;
+  a.part = static_cast<uint32_t*>(workspace);
+  a.part_e = reinterpret_cast<uint64_t*>(static_cast<char*>(workspace) +
+                                         ((slots * ta::kStatsPartDwords * 4 + 7) & ~(int64_t)7));
+  a.part_d = a.part_e + slots;
+  a.part_b = a.part_d + slots;
+  a.log_energy = reinterpret_cast<double*>(a.part_b + slots);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TA_HIP(hipSetDevice(c->device));
+  void* kargs[] = {&a};
+  if (a.steps > 0) {
+    TA_HIP(hipLaunchKernel(ta::stats_kernel(1), dim3((unsigned)(a.ranges * a.slabs)), dim3(256), kargs, 0, s));
+    const int64_t threads = (int64_t)a.positions * (ta::kStatsPartDwords + 3);
+    TA_HIP(hipLaunchKernel(ta::stats_kernel(4), dim3((unsigned)((threads + 255) / 256)), dim3(256), kargs, 0, s));
+  } else {
+    // empty batch: zero the accumulated outputs with a fill kernel
+    // (capturable, no memset node)
+    const void* zero = ta::stats_kernel(0);
+    auto fill = [&](void* p, int64_t words) -> int {
+      uint32_t* q = static_cast<uint32_t*>(p);
+      int64_t n = words;
+      void* zargs[] = {&q, &n};
+      TA_HIP(hipLaunchKernel(zero, dim3((unsigned)((words + 255) / 256)), dim3(256), zargs, 0, s));
+      return TA_OK;
+    };
+    if ((e = fill(hist, (int64_t)a.positions * ta::kStatsSymbols))) return e;
+    if ((e = fill(esc_bits, 2 * (int64_t)a.positions))) return e;
+    if ((e = fill(energy, 2 * (int64_t)a.positions))) return e;
+    if ((e = fill(dist, 2 * (int64_t)a.positions))) return e;
+  }
+  TA_HIP(hipLaunchKernel(ta::stats_kernel(2), dim3((unsigned)((a.positions + 3) / 4)), dim3(256), kargs, 0, s));
+  TA_HIP(hipLaunchKernel(ta::stats_kernel(3), dim3(1), dim3(256), kargs, 0, s));
+  return TA_OK;
+}
+
+}  // extern "C"

@@ -116,6 +116,39 @@ struct MultiArgs {
 };
 const void* multi_kernel(int log2n, int b, int* threads, int* blocks);
 
+// Quantised-coefficient statistics (stats_kernels.hip).
+struct StatsArgs {
+  const int16_t* in;
+  int64_t nblocks;
+  int64_t total;          // coefficients: nblocks * positions
+  int64_t wave_steps;     // wave steps over the batch (64 positions each)
+  int64_t full_steps;     // workgroup steps wholly inside the batch
+  int64_t steps;          // workgroup steps (4 wave steps each)
+  int64_t steps_per_wg;   // workgroup steps per block range
+  int64_t ranges;         // block ranges (workgroups per 64 positions)
+  int64_t wstride;        // elements between wave steps: max(positions, 64)
+  int positions, log2h, log2w;
+  int slabs;              // workgroups side by side: max(positions / 64, 1)
+  int step, offset;
+  uint32_t magic;         // ceil(2^k / step), k = magic_shift
+  int magic_shift;        // 16 + ceil(log2 step)
+  uint32_t* hist;         // positions x 65 symbol counts
+  uint64_t* esc_bits;
+  uint64_t* energy;
+  uint64_t* dist;
+  double* rate;
+  double* summary;
+  uint32_t* part;         // workspace: ranges x positions x 33 packed counters
+  uint64_t* part_e;       // workspace: ranges x positions each
+  uint64_t* part_d;
+  uint64_t* part_b;
+  double* log_energy;     // workspace: log2(E_p / n) per position
+};
+constexpr int kStatsSymbols = 65;       // levels -31..31 and the two escapes
+constexpr int kStatsPartDwords = 33;    // packed counter dwords per partial
+// 0 fill, 1 accumulate, 2 rate per position, 3 summary, 4 reduce partials
+const void* stats_kernel(int which);
+
 // Differentiable Givens-band path (givens_kernels.hip).
 constexpr int kMaxAng = 96;   // angle slots per workgroup partial (N <= 32, L <= 3)
 struct GivensArgs {

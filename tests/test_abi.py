@@ -54,3 +54,12 @@ def test_null_context_paths():
     assert lib.ta_inv_packed(None, 0, 0, 5, 5, 1, None, None, 0, None) == ta.TA_EINVAL
     assert lib.ta_set_impl(None, 0) == ta.TA_EINVAL
     assert lib.ta_fwd_multi(None, 0, 5, 1, None, None, None) == ta.TA_EINVAL
+
+
+def test_coef_stats_argument_checks_without_gpu():
+    lib = ta.lib()
+    assert lib.ta_coef_stats(None, None, 1, 5, 5, 8, 4, None, None, None, None, None, None, None, 0,
+                             None) == ta.TA_EINVAL
+    assert lib.ta_coef_stats_workspace(None, 1, 5, 5, None) == ta.TA_EINVAL
+    b = ctypes.c_int64(0)
+    assert lib.ta_coef_stats_workspace(None, 1, 5, 5, ctypes.byref(b)) == ta.TA_EINVAL
