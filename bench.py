@@ -99,13 +99,15 @@ def _events_mean(fn, reps, warm=2):
     return float(np.mean([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)])) * 1e-3
 
 
-def secondary(ctx, ids, x32):
-    """The other workloads: 64x64 sub-block (fixed point and fp32), batched
-    uneven frames, and the differentiable refit step."""
+EXTRAS = ("multiple", "proxy", "subblock", "batched", "refit")
+
+
+def secondary(ctx, ids, x32, only=EXTRAS):
+    """The other workloads: the five encoder transforms at once, the
+    coding-gain proxy, 64x64 sub-block (fixed point and fp32), batched uneven
+    frames, and the differentiable refit step (`only` selects some)."""
     import torch
-    import synth
     import paper_2505_23618_amd as ta
-    from paper_2505_23618_amd import refit as RF
     res = {}
     # encoder evaluation of the five transforms (DCT-2 x DCT-2 and the four
     # DST-7 / DCT-8 pairs, 8x8 sub-block) of the 32x32 workload in one launch,
@@ -115,23 +117,40 @@ def secondary(ctx, ids, x32):
     s7 = ctx.axis(21, ta.DCT2, ta.ADJ_POST, False, pid)
     c8 = ctx.axis(22, ta.DCT2, ta.ADJ_POST, True, pid)
     n32 = x32.numel()
-    out5 = torch.empty((5,) + tuple(x32.shape), dtype=torch.int16, device="cuda")
-    tm = _events_mean(lambda i: ctx.fwd_multi(x32, pid, out=out5), 10)
-    pairs = [(c2, c2), (s7, s7), (c8, s7), (s7, c8), (c8, c8)]     # (horizontal, vertical)
+    if "multiple" in only:
+        out5 = torch.empty((5,) + tuple(x32.shape), dtype=torch.int16, device="cuda")
+        tm = _events_mean(lambda i: ctx.fwd_multi(x32, pid, out=out5), 10)
+        pairs = [(c2, c2), (s7, s7), (c8, s7), (s7, c8), (c8, c8)]     # (horizontal, vertical)
 
-    def five(i):
-        for k, (h, v) in enumerate(pairs):
-            ctx.fwd(x32, h, v, out=out5[k])
-    t5 = _events_mean(five, 5)
-    res["multiple_32x32_b8"] = {"value": 5 * n32 / tm, "unit": "coef/s (5 outputs per input coef)",
-                                "us": tm * 1e6, "five_separate_us": t5 * 1e6, "speedup": t5 / tm,
-                                "GB/s": 12 * n32 / tm / 1e9,
-                                "workload": "262,144 blocks 32x32: DCT-2/DCT-2 and (DST-7|DCT-8)^2 with the 8x8 sub-block"}
-    del out5
-    torch.cuda.empty_cache()
-    # coding-gain proxy: energy compaction and rate of the quantised
-    # coefficients of the same 32x32 residuals under the DCT-2, the adjusted
-    # DST-7 designs and the exact DST-7 (a codec-free stand-in for Tables 2-3)
+        def five(i):
+            for k, (h, v) in enumerate(pairs):
+                ctx.fwd(x32, h, v, out=out5[k])
+        t5 = _events_mean(five, 5)
+        res["multiple_32x32_b8"] = {"value": 5 * n32 / tm, "unit": "coef/s (5 outputs per input coef)",
+                                    "us": tm * 1e6, "five_separate_us": t5 * 1e6, "speedup": t5 / tm,
+                                    "GB/s": 12 * n32 / tm / 1e9,
+                                    "workload": "262,144 blocks 32x32: DCT-2/DCT-2 and (DST-7|DCT-8)^2 with the 8x8 "
+                                                "sub-block"}
+        del out5
+        torch.cuda.empty_cache()
+    if "proxy" in only:
+        res["coding_gain_proxy"] = _proxy(ctx, ids, x32, c2, s7)
+    if "subblock" in only:
+        _subblock(ctx, ids, res)
+    if "batched" in only:
+        _batched(ctx, ids, res)
+    if "refit" in only:
+        _refit(ctx, res)
+    return res
+
+
+def _proxy(ctx, ids, x32, c2, s7):
+    import torch
+    import paper_2505_23618_amd as ta
+    n32 = x32.numel()
+    # energy compaction and rate of the quantised coefficients of the same
+    # 32x32 residuals under the DCT-2, the adjusted DST-7 designs and the
+    # exact DST-7 (a codec-free stand-in for Tables 2-3)
     proxy_axes = {"dct2": c2, "adj_dst7_band4": ctx.axis(23, ta.DST3, ta.ADJ_BAND, False, ids["band_S3_S7_N32_K4"]),
                   "adj_dst7_band6": ctx.axis(24, ta.DST3, ta.ADJ_BAND, False, ids["band_S3_S7_N32_K6"]),
                   "adj_dst7_sub8": s7, "dst7": ctx.axis(25, ta.DST7, ta.ADJ_NONE, False, 0)}
@@ -152,13 +171,20 @@ def secondary(ctx, ids, x32):
     ref = table["dst7"]["bits_per_coef"]
     for name, row in table.items():
         row["rate_vs_dst7_pct"] = [100.0 * (b / r - 1.0) for b, r in zip(row["bits_per_coef"], ref)]
-    res["coding_gain_proxy"] = {"value": n32 / ts, "unit": "coef/s", "stats_us": ts * 1e6,
+    out = {"value": n32 / ts, "unit": "coef/s", "stats_us": ts * 1e6,
                                 "GB/s": 2 * n32 / ts / 1e9, "hbm_frac": 2 * n32 / ts / 1e9 / HBM_PEAK_GBS,
                                 "quantiser_steps": list(steps), "offset": "step / 2", "transforms": table,
                                 "workload": "262,144 blocks 32x32 AR(1) rho=0.95 sigma=16, forward of each "
                                             "transform, then per-position symbol histograms, rate, energy"}
     del yq
     torch.cuda.empty_cache()
+    return out
+
+
+def _subblock(ctx, ids, res):
+    import torch
+    import synth
+    import paper_2505_23618_amd as ta
     # 64x64 blocks, DCT-2 + 16x16 sub-block: DCT-8 rows (eq. 5), DST-7 columns
     ph = ctx.axis(10, ta.DCT2, ta.ADJ_POST, True, ids["post_C2_S7_N64_B16"])
     pv = ctx.axis(11, ta.DCT2, ta.ADJ_POST, False, ids["post_C2_S7_N64_B16"])
@@ -179,6 +205,12 @@ def secondary(ctx, ids, x32):
                                  "GB/s_fwd": 8 * n64 / tf / 1e9}
     del xf, yf, zf
     torch.cuda.empty_cache()
+
+
+def _batched(ctx, ids, res):
+    import torch
+    import synth
+    import paper_2505_23618_amd as ta
     # batched uneven frames: 8 x 3840x2160, 4 buffer sets rotated (> infinity cache)
     from paper_2505_23618_amd.frames import descriptors as batch_descriptors, register_axes
     register_axes(ctx, ids)
@@ -197,6 +229,12 @@ def secondary(ctx, ids, x32):
                              "workload": "8 frames 3840x2160, QT/BT blocks 4..64, per-axis DCT-2 / adj. DST-7 / adj. DCT-8"}
     del X, Y, Z, plan
     torch.cuda.empty_cache()
+
+
+def _refit(ctx, res):
+    import torch
+    import synth
+    from paper_2505_23618_amd import refit as RF
     # differentiable refit step: forward + loss + backward on 131,072 vectors
     xv = torch.tensor(synth.ar1_vectors(131072, 32, 0.85, 0.99, 1.0, seed=synth.SEED_BASE + 4),
                       dtype=torch.float32, device="cuda")
@@ -210,7 +248,6 @@ def secondary(ctx, ids, x32):
     t = _events_mean(step, 20, warm=3)
     res["refit_step"] = {"us": t * 1e6, "vectors": 131072, "angles": 31,
                          "what": "fp32 forward (data + basis) + loss + backward (adjoint and angle gradients)"}
-    return res
 
 
 def main():
@@ -220,6 +257,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-extra", action="store_true", help="only the headline workload")
+    ap.add_argument("--extra", default=",".join(EXTRAS),
+                    help="comma-separated secondary workloads to run: " + ", ".join(EXTRAS))
     ap.add_argument("--calib-copy", action="store_true",
                     help="also launch one plain copy per step (counter calibration runs)")
     args = ap.parse_args()
@@ -310,7 +349,7 @@ def main():
     traffic = _traffic_from_profiles()
     del y, z
 
-    extra = {} if args.skip_extra else secondary(ctx, ids, x)
+    extra = {} if args.skip_extra else secondary(ctx, ids, x, tuple(args.extra.split(",")))
     del x
     torch.cuda.empty_cache()
 
