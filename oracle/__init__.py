@@ -16,6 +16,8 @@ Modules
   fixed       integer tables and the fixed-point separable 2-D forward/inverse
   fp          FP64 separable 2-D forward/inverse (H_v X H_h^T)
   refit       the differentiable refit objective and its analytic gradient
+  design      the adjustment design study of Fig. 1: sparsity objective over
+              all orthogonal adjustments, its gradient and an Adam search
   stats       statistics of quantised coefficients: per-position level
               histograms, entropy, energy, distortion, coding gain (a proxy
               for the coding results of Tables 2 and 3)

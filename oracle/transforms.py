@@ -12,6 +12,17 @@ normalisations below are the ones under which those relations hold exactly:
   DST-7  T[k,n] = sqrt(4/(2N+1)) sin(pi (2k+1)(n+1) / (2N+1))
   DCT-8  T[k,n] = sqrt(4/(2N+1)) cos(pi (2k+1)(2n+1) / (4N+2))
 
+The other sine transforms, the "remaining DSTs" the design study of Fig. 1
+targets (section 2, the sparsity-objective example), in their orthonormal
+forms with the same orientation (DST-6 is the transpose of the DST-7 above,
+as the DST-VI / DST-VII pair are):
+
+  DST-1  T[k,n] = sqrt(2/(N+1)) sin(pi (k+1)(n+1) / (N+1))
+  DST-4  T[k,n] = sqrt(2/N) sin(pi (2k+1)(2n+1) / (4N))
+  DST-5  T[k,n] = 2/sqrt(2N+1) sin(2 pi (k+1)(n+1) / (2N+1))
+  DST-6  T[k,n] = 2/sqrt(2N+1) sin(pi (k+1)(2n+1) / (2N+1))
+  DST-8  T[k,n] = sqrt(4/(2N-1)) f_k f_n sin(pi (2k+1)(2n+1) / (4N-2)),  f_{N-1} = 1/sqrt2, else 1
+
   R[m,n] = 1 if m = N-1-n (reversal);  S = diag((-1)^m) (alternating signs).
 
 Pins (tests/test_oracle_transforms.py): orthogonality; the section 2.1
@@ -20,7 +31,8 @@ DCT-8 = S DST-7 R; eq. 4 S DCT-2 = DCT-2 R; agreement with scipy.fft's
 orthonormal DCT/DST types 2 and 3; DST-7 rows equal the eigenvectors of the
 second-difference matrix tridiag(-1, 2, -1) with last diagonal entry 1
 (a textbook characterisation); the recursive even/odd DCT-2 below equals the
-dense product.
+dense product; DST-1 and DST-4 equal scipy.fft's orthonormal types 1 and 4;
+DST-6 is the transpose of DST-7; every matrix is orthogonal.
 """
 
 from __future__ import annotations
@@ -28,6 +40,7 @@ from __future__ import annotations
 import numpy as np
 
 KINDS = ("C2", "C3", "S2", "S3", "S7", "C8")
+OTHER_DSTS = ("S1", "S4", "S5", "S6", "S7", "S8")
 
 
 def dct2(n: int) -> np.ndarray:
@@ -66,6 +79,38 @@ def dct8(n: int) -> np.ndarray:
     return np.sqrt(4.0 / (2 * n + 1)) * np.cos(np.pi * (2 * k + 1) * (2 * i + 1) / (4 * n + 2))
 
 
+def _grid(n: int):
+    return np.arange(n)[:, None].astype(np.float64), np.arange(n)[None, :].astype(np.float64)
+
+
+def dst1(n: int) -> np.ndarray:
+    k, i = _grid(n)
+    return np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * (k + 1) * (i + 1) / (n + 1))
+
+
+def dst4(n: int) -> np.ndarray:
+    k, i = _grid(n)
+    return np.sqrt(2.0 / n) * np.sin(np.pi * (2 * k + 1) * (2 * i + 1) / (4 * n))
+
+
+def dst5(n: int) -> np.ndarray:
+    k, i = _grid(n)
+    return 2.0 / np.sqrt(2 * n + 1) * np.sin(2 * np.pi * (k + 1) * (i + 1) / (2 * n + 1))
+
+
+def dst6(n: int) -> np.ndarray:
+    k, i = _grid(n)
+    return 2.0 / np.sqrt(2 * n + 1) * np.sin(np.pi * (k + 1) * (2 * i + 1) / (2 * n + 1))
+
+
+def dst8(n: int) -> np.ndarray:
+    k, i = _grid(n)
+    t = np.sqrt(4.0 / (2 * n - 1)) * np.sin(np.pi * (2 * k + 1) * (2 * i + 1) / (4 * n - 2))
+    t[n - 1, :] /= np.sqrt(2.0)
+    t[:, n - 1] /= np.sqrt(2.0)
+    return t
+
+
 def reversal(n: int) -> np.ndarray:
     """R of section 2.1: R[m, n] = 1 iff m = N-1-n."""
     return np.eye(n)[::-1].copy()
@@ -77,7 +122,8 @@ def signs(n: int) -> np.ndarray:
 
 
 def matrix(kind: str, n: int) -> np.ndarray:
-    return {"C2": dct2, "C3": dct3, "S2": dst2, "S3": dst3, "S7": dst7, "C8": dct8}[kind](n)
+    return {"C2": dct2, "C3": dct3, "S2": dst2, "S3": dst3, "S7": dst7, "C8": dct8, "S1": dst1, "S4": dst4,
+            "S5": dst5, "S6": dst6, "S8": dst8}[kind](n)
 
 
 def dct2_fast(x: np.ndarray) -> np.ndarray:

@@ -67,3 +67,16 @@ def test_fast_dct2_equals_dense(n, rng):
 def test_dct2_dc_row_is_flat():
     for n in SIZES:
         assert np.allclose(T.dct2(n)[0], 1.0 / np.sqrt(n), atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [4, 8, 16, 32])
+def test_remaining_dsts_orthonormal_and_textbook(n):
+    import scipy.fft
+    for kind in T.OTHER_DSTS:
+        t = T.matrix(kind, n)
+        assert np.abs(t @ t.T - np.eye(n)).max() < 1e-12, kind
+    eye = np.eye(n)
+    # scipy's orthonormal DST-I and DST-IV of the unit vectors are the columns
+    assert np.allclose(scipy.fft.dst(eye, type=1, norm="ortho", axis=0), T.dst1(n), atol=1e-13)
+    assert np.allclose(scipy.fft.dst(eye, type=4, norm="ortho", axis=0), T.dst4(n), atol=1e-13)
+    assert np.allclose(T.dst6(n), T.dst7(n).T, atol=1e-13)
