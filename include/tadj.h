@@ -217,6 +217,34 @@ int ta_coef_stats(ta_ctx* ctx, const int16_t* coef, int64_t nblocks, int log2h, 
                   int32_t offset, uint32_t* hist, uint64_t* esc_bits, uint64_t* energy, uint64_t* dist, double* rate,
                   double* summary, void* workspace, int64_t workspace_bytes, ta_stream_t stream);
 
+/* ---- Batched adjustment design search (FP64) -------------------------------
+ * The design study of section 2 (Fig. 1): for each candidate, minimise
+ *   f(M) = lam sum_ij M_ij^2 / (0.05 + |M_ij|) + sum_ij w_i (H_ij - D_ij)^2,
+ *   w_i = exp(-i ln(100) / n), H = B M (pre-adjustment) or M B (post),
+ * (lam = 1 is the printed sparsity objective, lam = 0 is eq. 2) over
+ * orthogonal M = G(theta) J: G = n layers of parallel Givens rotations on
+ * adjacent pairs, layer l on the pairs starting at l mod 2, rotation (p, p+1)
+ * by t: v_p = cos t u_p - sin t u_p+1, v_p+1 = sin t u_p + cos t u_p+1,
+ * theta (n(n-1)/2 angles) layer by layer; J = diag(sigma, 1, ..., 1).
+ * Each candidate takes `steps` Adam updates (betas 0.9, 0.999, eps 1e-8,
+ * bias-corrected, step size lr) from its theta, then is evaluated at the
+ * final angles.  n in {4, 8, 16, 32}.  All pointers are device memory:
+ *   mats   nmat x n x n row-major matrices (bases and targets)
+ *   cands  ncand x 4 int32: base index, target index, mode (0 pre, 1 post),
+ *          sigma (+1 or -1); a candidate with an index out of range or a bad
+ *          mode or sigma gets NaN objective values and is otherwise skipped
+ *   theta  ncand x n(n-1)/2, read as the start, overwritten with the result
+ *   obj    ncand x 3: f, sparsity term, error term at the final angles
+ *   grad   ncand x n(n-1)/2 gradient at the final angles, or null
+ *   adj    ncand x n x n final M, or null
+ * steps = 0 evaluates f and its gradient at theta.  Asynchronous on the
+ * stream, allocates nothing; results are bitwise repeatable.  Errors:
+ * TA_EINVAL (null, misaligned, negative counts, lr <= 0, lam < 0),
+ * TA_EUNSUPPORTED (n). */
+int ta_design_search(ta_ctx* ctx, int n, int nmat, const double* mats, int64_t ncand, const int32_t* cands,
+                     double* theta, int steps, double lr, double lam, double* grad, double* obj, double* adj,
+                     ta_stream_t stream);
+
 /* ---- Differentiable refit path (fp32) ---------------------------------------
  * y_m = B A(theta) x_m for nvec vectors of n floats (x, y: nvec x n, row per
  * vector), B = TA_DCT2 or TA_DST3, A(theta) = taps/2 layers of parallel

@@ -37,7 +37,7 @@ EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis
            "ta_fwd_packed", "ta_inv_packed", "ta_set_impl", "ta_version", "ta_last_error",
            "ta_plan_create", "ta_plan_destroy", "ta_plan_info", "ta_plan_fwd", "ta_plan_inv",
            "ta_plan_autotune", "ta_givens_workspace", "ta_givens_fwd", "ta_givens_bwd",
-           "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats")
+           "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats", "ta_design_search")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -78,6 +78,8 @@ def lib() -> ctypes.CDLL:
         f.argtypes = [vp, i32, i32, i32, i32, i64, vp, vp, i32, vp]
     L.ta_set_impl.argtypes = [vp, i32]
     L.ta_fwd_multi.argtypes = [vp, i32, i32, i64, vp, vp, vp]
+    L.ta_design_search.argtypes = [vp, i32, i32, vp, i64, vp, vp, i32, ctypes.c_double, ctypes.c_double,
+                                   vp, vp, vp, vp]
     L.ta_coef_stats_workspace.argtypes = [vp, i64, i32, i32, ctypes.POINTER(i64)]
     L.ta_coef_stats.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i64, vp]
     L.ta_plan_create.argtypes = [vp, vp, i64, i32, ctypes.POINTER(vp)]
@@ -230,6 +232,38 @@ class Context:
                                    ptr["hist"], ptr["esc_bits"], ptr["energy"], ptr["dist"], ptr["rate"],
                                    ptr["summary"], ptr["workspace"], out["workspace"].numel(),
                                    _stream_handle(None)))
+        return out
+
+    def design_search(self, mats, cands, theta, steps: int, lr: float, lam: float = 1.0,
+                      want_grad: bool = False, want_adj: bool = True):
+        """Batched adjustment design search (ta_design_search) on GPU tensors:
+        mats [nmat, n, n] float64, cands [ncand, 4] int32 (base, target,
+        mode 0 pre / 1 post, sigma), theta [ncand, n(n-1)/2] float64 (start;
+        overwritten with the result).  Returns a dict with obj [ncand, 3]
+        (f, sparsity, error), and grad / adj when asked for."""
+        import torch
+        n = mats.shape[-1]
+        ncand = cands.shape[0]
+        if mats.dim() != 3 or mats.shape[1] != n or cands.dim() != 2 or cands.shape[1] != 4 or \
+                tuple(theta.shape) != (ncand, n * (n - 1) // 2):
+            raise ValueError("expected mats [nmat, n, n], cands [ncand, 4], theta [ncand, n(n-1)/2]")
+        if mats.dtype != torch.float64 or theta.dtype != torch.float64 or cands.dtype != torch.int32:
+            raise ValueError("mats and theta must be float64, cands int32")
+        if not (mats.is_cuda and cands.is_cuda and theta.is_cuda):
+            raise ValueError("expected GPU tensors")
+        mats, cands = mats.contiguous(), cands.contiguous()
+        if not theta.is_contiguous():
+            raise ValueError("theta must be contiguous (it is overwritten)")
+        dev = mats.device
+        out = {"obj": torch.empty((ncand, 3), dtype=torch.float64, device=dev)}
+        if want_grad:
+            out["grad"] = torch.empty_like(theta)
+        if want_adj:
+            out["adj"] = torch.empty((ncand, n, n), dtype=torch.float64, device=dev)
+        ptr = lambda k: ctypes.c_void_p(out[k].data_ptr()) if k in out else None  # noqa: E731
+        _check(lib().ta_design_search(self._h, n, mats.shape[0], ctypes.c_void_p(mats.data_ptr()), ncand,
+                                      ctypes.c_void_p(cands.data_ptr()), ctypes.c_void_p(theta.data_ptr()), steps,
+                                      lr, lam, ptr("grad"), ptr("obj"), ptr("adj"), _stream_handle(None)))
         return out
 
     # raw pointer variants (no allocation; for graphs and benchmarks)

@@ -1,0 +1,248 @@
+// Batched adjustment design search (section 2, Fig. 1): many independent
+// candidates (base B, target D, pre or post adjustment, random start), each
+// minimising
+//   f(M) = lam sum_ij M_ij^2 / (0.05 + |M_ij|) + sum_ij w_i (H_ij - D_ij)^2,
+//   w_i = exp(-i ln(100) / N),  H = B M (pre) or M B (post),
+// over orthogonal M = G(theta) J, where G is N layers of parallel Givens
+// rotations on adjacent pairs (layer l on the pairs starting at l mod 2, angle
+// order layer by layer) and J = diag(sigma, 1, ..., 1).  Each candidate runs
+// `steps` Adam updates and a final evaluation inside one launch.
+//
+// One workgroup per candidate, N^2/2 threads: thread (r, j) = (pair slot,
+// column) owns rows 2r, 2r+1 of column j of every N x N matrix in LDS.  A
+// layer rotates rows (p, p+1), p = (l mod 2) + 2r, of each column.  The
+// backward pass walks the layers in reverse, recovering each layer's input
+// by the transposed rotation (orthogonal, so nothing is stored), and sums
+// each angle's gradient over the N columns with shuffles inside the slot's
+// N consecutive lanes, in a fixed order.  Everything is FP64.
+#include <math.h>
+
+#include "kernels.hpp"
+
+namespace ta {
+namespace {
+
+constexpr double kSparseEps = 0.05;
+
+// first angle of layer l: even layers have N/2 pairs, odd layers N/2 - 1
+template <int N>
+__device__ inline int layer_start(int l) {
+  return (l >> 1) * (N - 1) + ((l & 1) ? N / 2 : 0);
+}
+
+template <int N>
+__device__ inline double slot_sum(double v) {
+  // lanes of one slot are N consecutive lanes aligned to N (N divides 64)
+#pragma unroll
+  for (int m = N / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, N);
+  return v;
+}
+
+template <int N>
+__global__ __launch_bounds__(N * N / 2) void design_search(DesignArgs a) {
+  constexpr int T = N * N / 2;
+  constexpr int NA = N * (N - 1) / 2;
+  __shared__ double Ms[N * N], Gs[N * N], Bs[N * N], Xs[N * N];
+  __shared__ double th[NA], mo[NA], ve[NA], cs_c[NA], cs_s[NA], gr[NA];
+  __shared__ double red[T / 64 > 0 ? 2 * (T / 64) : 2];
+  __shared__ int bad;
+
+  const int cand = blockIdx.x;
+  const int t = threadIdx.x, r = t / N, j = t % N;
+  const int i0 = 2 * r, i1 = 2 * r + 1;   // rows owned in column j
+
+  if (t == 0) {
+    const int* c = a.cands + 4 * (int64_t)cand;
+    const int b = c[0], d = c[1], mode = c[2], sg = c[3];
+    bad = (b < 0 || b >= a.nmat || d < 0 || d >= a.nmat || (mode != 0 && mode != 1) || (sg != 1 && sg != -1));
+  }
+  __syncthreads();
+  if (bad) {
+    if (t == 0) {
+      const double nan = __builtin_nan("");
+      for (int k = 0; k < 3; ++k) a.obj[3 * (int64_t)cand + k] = nan;
+    }
+    return;
+  }
+  const int* c = a.cands + 4 * (int64_t)cand;
+  const int mode = c[2];
+  const double sigma = (double)c[3];
+  const double* bm = a.mats + (int64_t)c[0] * N * N;
+  const double* dm = a.mats + (int64_t)c[1] * N * N;
+  double* theta = a.theta + (int64_t)cand * NA;
+  for (int k = t; k < N * N; k += T) Bs[k] = bm[k];
+  const double d0 = dm[i0 * N + j], d1 = dm[i1 * N + j];
+  for (int k = t; k < NA; k += T) {
+    th[k] = theta[k];
+    mo[k] = 0.0;
+    ve[k] = 0.0;
+  }
+  const double alpha = log(100.0) / N;
+  const double w0 = exp(-alpha * i0), w1 = exp(-alpha * i1);
+  double b1t = 1.0, b2t = 1.0;   // beta1^t, beta2^t
+  __syncthreads();
+
+  for (int step = 0; step <= a.steps; ++step) {
+    const bool last = step == a.steps;
+    for (int k = t; k < NA; k += T) sincos(th[k], &cs_s[k], &cs_c[k]);
+    Ms[i0 * N + j] = (i0 == j) ? 1.0 : 0.0;
+    Ms[i1 * N + j] = (i1 == j) ? 1.0 : 0.0;
+    __syncthreads();
+    // forward: M = G_{N-1} ... G_0 I
+    for (int l = 0; l < N; ++l) {
+      const int p = (l & 1) + 2 * r;
+      if (p + 1 < N) {
+        const int k = layer_start<N>(l) + r;
+        const double cc = cs_c[k], ss = cs_s[k];
+        const double up = Ms[p * N + j], uq = Ms[(p + 1) * N + j];
+        Ms[p * N + j] = cc * up - ss * uq;
+        Ms[(p + 1) * N + j] = ss * up + cc * uq;
+      }
+      __syncthreads();
+    }
+    // M = G J, J = diag(sigma, 1, ...): kept as G in Ms; the J factor is
+    // applied where M is read (column 0 times sigma)
+    const double js = j == 0 ? sigma : 1.0;
+    // H rows i0, i1 of column j, the error and its adjoint 2 w (H - D)
+    double h0 = 0.0, h1 = 0.0;
+    if (mode == 0) {   // H = B M
+#pragma unroll 8
+      for (int k = 0; k < N; ++k) {
+        const double mk = Ms[k * N + j];
+        h0 += Bs[i0 * N + k] * mk;
+        h1 += Bs[i1 * N + k] * mk;
+      }
+      h0 *= js;
+      h1 *= js;
+    } else {           // H = M B: H[i][j] = sum_k M[i][k] B[k][j], M[i][0] scaled by sigma
+#pragma unroll 8
+      for (int k = 0; k < N; ++k) {
+        const double bk = Bs[k * N + j];
+        const double sk = k == 0 ? sigma : 1.0;
+        h0 += sk * Ms[i0 * N + k] * bk;
+        h1 += sk * Ms[i1 * N + k] * bk;
+      }
+    }
+    const double e0 = h0 - d0, e1 = h1 - d1;
+    const double m0 = js * Ms[i0 * N + j], m1 = js * Ms[i1 * N + j];   // entries of M = G J
+    if (last) {
+      // objective: sparsity of M and weighted error, reduced in a fixed order
+      double sp = m0 * m0 / (kSparseEps + fabs(m0)) + m1 * m1 / (kSparseEps + fabs(m1));
+      double er = w0 * e0 * e0 + w1 * e1 * e1;
+#pragma unroll
+      for (int m = 32; m > 0; m >>= 1) {
+        if (m < T) {
+          sp += __shfl_xor(sp, m);
+          er += __shfl_xor(er, m);
+        }
+      }
+      if ((t & 63) == 0) {
+        red[2 * (t >> 6)] = sp;
+        red[2 * (t >> 6) + 1] = er;
+      }
+      if (a.adj) {
+        double* out = a.adj + (int64_t)cand * N * N;
+        out[i0 * N + j] = m0;
+        out[i1 * N + j] = m1;
+      }
+    }
+    Xs[i0 * N + j] = 2.0 * w0 * e0;
+    Xs[i1 * N + j] = 2.0 * w1 * e1;
+    __syncthreads();
+    if (last && t == 0) {
+      double sp = 0.0, er = 0.0;
+      for (int w = 0; w < (T + 63) / 64; ++w) {
+        sp += red[2 * w];
+        er += red[2 * w + 1];
+      }
+      a.obj[3 * (int64_t)cand] = a.lam * sp + er;
+      a.obj[3 * (int64_t)cand + 1] = sp;
+      a.obj[3 * (int64_t)cand + 2] = er;
+    }
+    // adjoint of M = G J at (i, j): lam phi'(M) + (B^T X or X B^T), then times J
+    double g0, g1;
+    if (mode == 0) {   // dM = B^T X: dM[i][j] = sum_k B[k][i] X[k][j]
+      g0 = 0.0;
+      g1 = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < N; ++k) {
+        const double xk = Xs[k * N + j];
+        g0 += Bs[k * N + i0] * xk;
+        g1 += Bs[k * N + i1] * xk;
+      }
+    } else {           // dM = X B^T: dM[i][j] = sum_k X[i][k] B[j][k]
+      g0 = 0.0;
+      g1 = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < N; ++k) {
+        const double bj = Bs[j * N + k];
+        g0 += Xs[i0 * N + k] * bj;
+        g1 += Xs[i1 * N + k] * bj;
+      }
+    }
+    const double a0 = fabs(m0), a1 = fabs(m1);
+    g0 += a.lam * m0 * (2.0 * kSparseEps + a0) / ((kSparseEps + a0) * (kSparseEps + a0));
+    g1 += a.lam * m1 * (2.0 * kSparseEps + a1) / ((kSparseEps + a1) * (kSparseEps + a1));
+    Gs[i0 * N + j] = js * g0;
+    Gs[i1 * N + j] = js * g1;
+    __syncthreads();
+    // backward through the layers: angle gradient from each layer's outputs,
+    // then step both the activations and the adjoint back through it
+    for (int l = N - 1; l >= 0; --l) {
+      const int p = (l & 1) + 2 * r;
+      const bool valid = p + 1 < N;
+      double contrib = 0.0;
+      double vp = 0.0, vq = 0.0, gp = 0.0, gq = 0.0;
+      if (valid) {
+        vp = Ms[p * N + j];
+        vq = Ms[(p + 1) * N + j];
+        gp = Gs[p * N + j];
+        gq = Gs[(p + 1) * N + j];
+        contrib = -gp * vq + gq * vp;
+      }
+      const double sum = slot_sum<N>(contrib);
+      if (valid) {
+        const int k = layer_start<N>(l) + r;
+        if (j == 0) gr[k] = sum;
+        const double cc = cs_c[k], ss = cs_s[k];
+        Ms[p * N + j] = cc * vp + ss * vq;
+        Ms[(p + 1) * N + j] = -ss * vp + cc * vq;
+        Gs[p * N + j] = cc * gp + ss * gq;
+        Gs[(p + 1) * N + j] = -ss * gp + cc * gq;
+      }
+      __syncthreads();
+    }
+    if (last) break;
+    // Adam (Kingma and Ba) with bias correction
+    b1t *= a.beta1;
+    b2t *= a.beta2;
+    for (int k = t; k < NA; k += T) {
+      const double g = gr[k];
+      mo[k] = a.beta1 * mo[k] + (1.0 - a.beta1) * g;
+      ve[k] = a.beta2 * ve[k] + (1.0 - a.beta2) * g * g;
+      const double mh = mo[k] / (1.0 - b1t);
+      const double vh = ve[k] / (1.0 - b2t);
+      th[k] -= a.lr * mh / (sqrt(vh) + a.eps);
+    }
+    __syncthreads();
+  }
+  for (int k = t; k < NA; k += T) {
+    theta[k] = th[k];
+    if (a.grad) a.grad[(int64_t)cand * NA + k] = gr[k];
+  }
+}
+
+}  // namespace
+
+const void* design_kernel(int n, int* threads) {
+  *threads = n * n / 2;
+  switch (n) {
+    case 4: return reinterpret_cast<const void*>(&design_search<4>);
+    case 8: return reinterpret_cast<const void*>(&design_search<8>);
+    case 16: return reinterpret_cast<const void*>(&design_search<16>);
+    case 32: return reinterpret_cast<const void*>(&design_search<32>);
+    default: return nullptr;
+  }
+}
+
+}  // namespace ta

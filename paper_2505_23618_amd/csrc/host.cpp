@@ -2,6 +2,7 @@
 // Implements the C ABI declared in include/tadj.h.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
@@ -849,6 +850,36 @@ int ta_coef_stats(ta_ctx* c, const int16_t* coef, int64_t nblocks, int log2h, in
   }
   TA_HIP(hipLaunchKernel(ta::stats_kernel(2), dim3((unsigned)((a.positions + 3) / 4)), dim3(256), kargs, 0, s));
   TA_HIP(hipLaunchKernel(ta::stats_kernel(3), dim3(1), dim3(256), kargs, 0, s));
+  return TA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched adjustment design search
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int ta_design_search(ta_ctx* c, int n, int nmat, const double* mats, int64_t ncand, const int32_t* cands,
+                     double* theta, int steps, double lr, double lam, double* grad, double* obj, double* adj,
+                     ta_stream_t stream) {
+  if (!c) return fail(TA_EINVAL, "null context");
+  int threads = 0;
+  const void* fn = ta::design_kernel(n, &threads);
+  if (!fn) return fail(TA_EUNSUPPORTED, "design search is built for n in {4, 8, 16, 32}");
+  if (ncand < 0 || nmat < 1 || steps < 0) return fail(TA_EINVAL, "need ncand >= 0, nmat >= 1, steps >= 0");
+  if (!(lr > 0.0) || !std::isfinite(lr) || !(lam >= 0.0) || !std::isfinite(lam))
+    return fail(TA_EINVAL, "need a finite lr > 0 and lam >= 0");
+  if (ncand > 0x7fffffff) return fail(TA_EUNSUPPORTED, "too many candidates for one launch");
+  if (ncand == 0) return TA_OK;
+  if (!mats || !cands || !theta || !obj) return fail(TA_EINVAL, "null buffer");
+  if ((((uintptr_t)mats | (uintptr_t)theta | (uintptr_t)obj | (uintptr_t)grad | (uintptr_t)adj) & 7) ||
+      ((uintptr_t)cands & 3))
+    return fail(TA_EINVAL, "misaligned buffer");
+  ta::DesignArgs a{mats, nmat, cands, theta, steps, lr, lam, 0.9, 0.999, 1e-8, grad, obj, adj};
+  void* kargs[] = {&a};
+  TA_HIP(hipSetDevice(c->device));
+  TA_HIP(hipLaunchKernel(fn, dim3((unsigned)ncand), dim3(threads), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
   return TA_OK;
 }
 

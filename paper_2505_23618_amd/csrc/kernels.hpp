@@ -149,6 +149,20 @@ constexpr int kStatsPartDwords = 33;    // packed counter dwords per partial
 // 0 fill, 1 accumulate, 2 rate per position, 3 summary, 4 reduce partials
 const void* stats_kernel(int which);
 
+// Batched adjustment design search (design_kernels.hip).
+struct DesignArgs {
+  const double* mats;   // nmat x N x N
+  int nmat;
+  const int* cands;     // ncand x {base index, target index, mode (0 pre, 1 post), sigma (+-1)}
+  double* theta;        // ncand x N(N-1)/2, in: start, out: final angles
+  int steps;
+  double lr, lam, beta1, beta2, eps;
+  double* grad;         // ncand x N(N-1)/2 or null: gradient at the final angles
+  double* obj;          // ncand x 3: objective, sparsity term, error term at the final angles
+  double* adj;          // ncand x N x N or null: the final adjustment M
+};
+const void* design_kernel(int n, int* threads);
+
 // Differentiable Givens-band path (givens_kernels.hip).
 constexpr int kMaxAng = 96;   // angle slots per workgroup partial (N <= 32, L <= 3)
 struct GivensArgs {

@@ -222,3 +222,8 @@ def workload_blocks(name: str, nblocks: int | None = None) -> np.ndarray:
     if nblocks is not None:
         p["nblocks"] = nblocks
     return ar1_blocks(p["nblocks"], p["h"], p["w"], p["rho"], p["sigma"], p["seed"])
+
+
+def design_starts(ncand: int, nangles: int, seed: int, scale: float = 0.3) -> np.ndarray:
+    """Random starting angles of a batched design search: U[-scale, scale]."""
+    return _rng(seed).uniform(-scale, scale, size=(ncand, nangles))

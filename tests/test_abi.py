@@ -63,3 +63,9 @@ def test_coef_stats_argument_checks_without_gpu():
     assert lib.ta_coef_stats_workspace(None, 1, 5, 5, None) == ta.TA_EINVAL
     b = ctypes.c_int64(0)
     assert lib.ta_coef_stats_workspace(None, 1, 5, 5, ctypes.byref(b)) == ta.TA_EINVAL
+
+
+def test_design_search_argument_checks_without_gpu():
+    lib = ta.lib()
+    assert lib.ta_design_search(None, 8, 1, None, 1, None, None, 1, 0.01, 1.0, None, None, None,
+                                None) == ta.TA_EINVAL
