@@ -99,7 +99,7 @@ def _events_mean(fn, reps, warm=2):
     return float(np.mean([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)])) * 1e-3
 
 
-EXTRAS = ("multiple", "proxy", "subblock", "batched", "refit")
+EXTRAS = ("multiple", "proxy", "subblock", "batched", "refit", "design")
 
 
 def secondary(ctx, ids, x32, only=EXTRAS):
@@ -141,7 +141,50 @@ def secondary(ctx, ids, x32, only=EXTRAS):
         _batched(ctx, ids, res)
     if "refit" in only:
         _refit(ctx, res)
+    if "design" in only:
+        _design(ctx, res)
     return res
+
+
+FP64_PEAK_TFLOPS = 78.6
+
+
+def _design(ctx, res):
+    """The Fig. 1 design study: every (target DST, base, pre/post) with
+    random restarts, Adam on the sparsity objective, all in one launch."""
+    import torch
+    import synth
+    from paper_2505_23618_amd import design as PD
+    out = {}
+    for n, restarts, steps in ((16, 32, 500), (32, 8, 300)):
+        mats, cands, labels = PD.study(n, restarts)
+        starts = synth.design_starts(len(cands), PD.n_angles(n), synth.SEED_BASE + 6)
+        m = torch.from_numpy(mats).cuda()
+        c = torch.from_numpy(cands).cuda()
+        th0 = torch.from_numpy(starts).cuda()
+        th = th0.clone()
+        # each timed launch restarts from the same angles (a device copy)
+        t = _events_mean(lambda i: (th.copy_(th0), ctx.design_search(m, c, th, steps, 0.01, 1.0, want_adj=False)),
+                         3, warm=1)
+        flops = PD.algorithmic_flops(n) * len(cands) * (steps + 1)
+        entry = {"candidates": len(cands), "steps": steps, "us": t * 1e6,
+                 "candidate_steps_per_s": len(cands) * steps / t, "fp64_TFLOP/s": flops / t / 1e12,
+                 "fp64_frac": flops / t / 1e12 / FP64_PEAK_TFLOPS}
+        if n == 16:
+            _, table = PD.run_study(ctx, n, restarts, steps, 0.01, 1.0, starts)
+            best = {}
+            for row in table:
+                k = row["target"]
+                if k not in best or row["objective"] < best[k]["objective"]:
+                    best[k] = row
+            entry["best_per_target"] = {k: {"base": v["base"], "mode": v["mode"], "objective": v["objective"],
+                                            "error": v["error"], "nonzeros": v["nonzeros"]} for k, v in best.items()}
+            entry["dst7_by_base"] = {f'{r["base"]}-{r["mode"]}': round(r["error"], 4) for r in table
+                                     if r["target"] == "S7"}
+        out[f"n{n}"] = entry
+    out["what"] = ("sparsity objective (lam 1) over all orthogonal pre/post adjustments, B in {DCT-2, DCT-3, "
+                   "DST-2, DST-3} x D in {DST-1, 4, 5, 6, 7, 8}, Adam lr 0.01, FP64")
+    res["design_search"] = out
 
 
 def _proxy(ctx, ids, x32, c2, s7):
