@@ -144,3 +144,34 @@ def test_full_workload_sampled_positions(ctx):
     assert g["summary"][3] == pytest.approx(S.coding_gain_db(g["energy"] / nb), abs=1e-9)
     assert g["summary"][5] == pytest.approx(1 - g["hist"][:, 32].sum() / ncoef, rel=1e-12)
     assert g["summary"][6] == pytest.approx((g["hist"][:, 0].sum() + g["hist"][:, 64].sum()) / ncoef, rel=1e-12)
+
+
+def test_graph_replay_and_buffer_reuse(ctx):
+    """The statistics launch sequence captured in a HIP graph replays to the
+    eager result (the empty-batch path clears with a kernel, not a memset);
+    a result dict is reused across calls of different batch sizes."""
+    x = _laplace_blocks(3000, 16, 16, seed=21)
+    xd = torch.from_numpy(x).cuda()
+    buf = ctx.coef_stats(xd, 24, 12)
+    ref = {k: v.clone() for k, v in buf.items() if k != "workspace"}
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ctx.coef_stats(xd, 24, 12, out=buf)
+    for rep in range(3):
+        for k in ref:
+            buf[k].fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(buf[k], ref[k]), f"replay {rep}: {k}"
+    # reuse with a smaller and then a larger batch of the same block shape
+    for nb in (17, 4000):
+        xs = _laplace_blocks(nb, 16, 16, seed=nb)
+        got = ctx.coef_stats(torch.from_numpy(xs).cuda(), 24, 12, out=buf)
+        want = S.coef_stats(xs, 24, 12)
+        assert (got["hist"].cpu().numpy().astype(np.int64) == want["hist"]).all()
+        assert (got["energy"].cpu().numpy() == want["energy"]).all()
