@@ -8,13 +8,15 @@
 // order layer by layer) and J = diag(sigma, 1, ..., 1).  Each candidate runs
 // `steps` Adam updates and a final evaluation inside one launch.
 //
-// One workgroup per candidate, N^2/2 threads: thread (r, j) = (pair slot,
-// column) owns rows 2r, 2r+1 of column j of every N x N matrix in LDS.  A
-// layer rotates rows (p, p+1), p = (l mod 2) + 2r, of each column.  The
-// backward pass walks the layers in reverse, recovering each layer's input
-// by the transposed rotation (orthogonal, so nothing is stored), and sums
-// each angle's gradient over the N columns with shuffles inside the slot's
-// N consecutive lanes, in a fixed order.  Everything is FP64.
+// One workgroup per candidate: thread (r, g) = (pair slot, column group)
+// owns rows 2r, 2r+1 of its columns of every N x N matrix in LDS.  A layer
+// rotates rows (p, p+1), p = (l mod 2) + 2r, of each column.  The backward
+// pass walks the layers in reverse, recovering each layer's input by the
+// transposed rotation (orthogonal, so nothing is stored), and sums each
+// angle's gradient over the columns, first within a thread, then with
+// shuffles across the slot's consecutive lanes, in a fixed order.  Up to
+// N = 16 a candidate is a single wave, whose steps need no barrier.
+// Everything is FP64.
 #include <math.h>
 
 #include "kernels.hpp"
@@ -30,17 +32,33 @@ __device__ inline int layer_start(int l) {
   return (l >> 1) * (N - 1) + ((l & 1) ? N / 2 : 0);
 }
 
-template <int N>
+// sum over the NC consecutive lanes of one slot (NC divides 64), fixed order
+template <int NC>
 __device__ inline double slot_sum(double v) {
-  // lanes of one slot are N consecutive lanes aligned to N (N divides 64)
 #pragma unroll
-  for (int m = N / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, N);
+  for (int m = NC / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, NC);
   return v;
 }
 
-template <int N>
-__global__ __launch_bounds__(N * N / 2) void design_search(DesignArgs a) {
-  constexpr int T = N * N / 2;
+// Workgroup-wide barrier; a one-wave workgroup only needs its LDS traffic
+// ordered, which a wavefront-scope fence gives.
+template <int T>
+__device__ inline void group_sync() {
+  if constexpr (T <= 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// CW columns per thread: thread (r, g) owns rows 2r, 2r+1 of the columns
+// g + k N / CW, k < CW, so that N = 16 fits one wave (CW = 2)
+template <int N, int CW>
+__global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a) {
+  constexpr int NC = N / CW;                 // threads per slot
+  constexpr int T = (N / 2) * NC;
   constexpr int NA = N * (N - 1) / 2;
   __shared__ double Ms[N * N], Gs[N * N], Bs[N * N], Xs[N * N];
   __shared__ double th[NA], mo[NA], ve[NA], cs_c[NA], cs_s[NA], gr[NA];
@@ -48,15 +66,15 @@ __global__ __launch_bounds__(N * N / 2) void design_search(DesignArgs a) {
   __shared__ int bad;
 
   const int cand = blockIdx.x;
-  const int t = threadIdx.x, r = t / N, j = t % N;
-  const int i0 = 2 * r, i1 = 2 * r + 1;   // rows owned in column j
+  const int t = threadIdx.x, r = t / NC, jg = t % NC;
+  const int i0 = 2 * r, i1 = 2 * r + 1;   // rows owned in each of the thread's columns
 
   if (t == 0) {
     const int* c = a.cands + 4 * (int64_t)cand;
     const int b = c[0], d = c[1], mode = c[2], sg = c[3];
     bad = (b < 0 || b >= a.nmat || d < 0 || d >= a.nmat || (mode != 0 && mode != 1) || (sg != 1 && sg != -1));
   }
-  __syncthreads();
+  group_sync<T>();
   if (bad) {
     if (t == 0) {
       const double nan = __builtin_nan("");
@@ -71,7 +89,13 @@ __global__ __launch_bounds__(N * N / 2) void design_search(DesignArgs a) {
   const double* dm = a.mats + (int64_t)c[1] * N * N;
   double* theta = a.theta + (int64_t)cand * NA;
   for (int k = t; k < N * N; k += T) Bs[k] = bm[k];
-  const double d0 = dm[i0 * N + j], d1 = dm[i1 * N + j];
+  double d0[CW], d1[CW];
+#pragma unroll
+  for (int q = 0; q < CW; ++q) {
+    const int j = jg + q * NC;
+    d0[q] = dm[i0 * N + j];
+    d1[q] = dm[i1 * N + j];
+  }
   for (int k = t; k < NA; k += T) {
     th[k] = theta[k];
     mo[k] = 0.0;
@@ -80,55 +104,78 @@ __global__ __launch_bounds__(N * N / 2) void design_search(DesignArgs a) {
   const double alpha = log(100.0) / N;
   const double w0 = exp(-alpha * i0), w1 = exp(-alpha * i1);
   double b1t = 1.0, b2t = 1.0;   // beta1^t, beta2^t
-  __syncthreads();
+  group_sync<T>();
 
   for (int step = 0; step <= a.steps; ++step) {
     const bool last = step == a.steps;
     for (int k = t; k < NA; k += T) sincos(th[k], &cs_s[k], &cs_c[k]);
-    Ms[i0 * N + j] = (i0 == j) ? 1.0 : 0.0;
-    Ms[i1 * N + j] = (i1 == j) ? 1.0 : 0.0;
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      const int j = jg + q * NC;
+      Ms[i0 * N + j] = (i0 == j) ? 1.0 : 0.0;
+      Ms[i1 * N + j] = (i1 == j) ? 1.0 : 0.0;
+    }
+    group_sync<T>();
     // forward: M = G_{N-1} ... G_0 I
     for (int l = 0; l < N; ++l) {
       const int p = (l & 1) + 2 * r;
       if (p + 1 < N) {
         const int k = layer_start<N>(l) + r;
         const double cc = cs_c[k], ss = cs_s[k];
-        const double up = Ms[p * N + j], uq = Ms[(p + 1) * N + j];
-        Ms[p * N + j] = cc * up - ss * uq;
-        Ms[(p + 1) * N + j] = ss * up + cc * uq;
+#pragma unroll
+        for (int q = 0; q < CW; ++q) {
+          const int j = jg + q * NC;
+          const double up = Ms[p * N + j], uq = Ms[(p + 1) * N + j];
+          Ms[p * N + j] = cc * up - ss * uq;
+          Ms[(p + 1) * N + j] = ss * up + cc * uq;
+        }
       }
-      __syncthreads();
+      group_sync<T>();
     }
     // M = G J, J = diag(sigma, 1, ...): kept as G in Ms; the J factor is
-    // applied where M is read (column 0 times sigma)
-    const double js = j == 0 ? sigma : 1.0;
-    // H rows i0, i1 of column j, the error and its adjoint 2 w (H - D)
-    double h0 = 0.0, h1 = 0.0;
-    if (mode == 0) {   // H = B M
+    // applied where M is read (column 0 times sigma).  Per column: H rows
+    // i0, i1, the error and its adjoint 2 w (H - D)
+    double m0[CW], m1[CW], sp = 0.0, er = 0.0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      const int j = jg + q * NC;
+      const double js = j == 0 ? sigma : 1.0;
+      double h0 = 0.0, h1 = 0.0;
+      if (mode == 0) {   // H = B M
 #pragma unroll 8
-      for (int k = 0; k < N; ++k) {
-        const double mk = Ms[k * N + j];
-        h0 += Bs[i0 * N + k] * mk;
-        h1 += Bs[i1 * N + k] * mk;
-      }
-      h0 *= js;
-      h1 *= js;
-    } else {           // H = M B: H[i][j] = sum_k M[i][k] B[k][j], M[i][0] scaled by sigma
+        for (int k = 0; k < N; ++k) {
+          const double mk = Ms[k * N + j];
+          h0 += Bs[i0 * N + k] * mk;
+          h1 += Bs[i1 * N + k] * mk;
+        }
+        h0 *= js;
+        h1 *= js;
+      } else {           // H = M B: H[i][j] = sum_k M[i][k] B[k][j], M[i][0] scaled by sigma
 #pragma unroll 8
-      for (int k = 0; k < N; ++k) {
-        const double bk = Bs[k * N + j];
-        const double sk = k == 0 ? sigma : 1.0;
-        h0 += sk * Ms[i0 * N + k] * bk;
-        h1 += sk * Ms[i1 * N + k] * bk;
+        for (int k = 0; k < N; ++k) {
+          const double bk = Bs[k * N + j];
+          const double sk = k == 0 ? sigma : 1.0;
+          h0 += sk * Ms[i0 * N + k] * bk;
+          h1 += sk * Ms[i1 * N + k] * bk;
+        }
       }
+      const double e0 = h0 - d0[q], e1 = h1 - d1[q];
+      m0[q] = js * Ms[i0 * N + j];   // entries of M = G J
+      m1[q] = js * Ms[i1 * N + j];
+      if (last) {
+        sp += m0[q] * m0[q] / (kSparseEps + fabs(m0[q])) + m1[q] * m1[q] / (kSparseEps + fabs(m1[q]));
+        er += w0 * e0 * e0 + w1 * e1 * e1;
+        if (a.adj) {
+          double* out = a.adj + (int64_t)cand * N * N;
+          out[i0 * N + j] = m0[q];
+          out[i1 * N + j] = m1[q];
+        }
+      }
+      Xs[i0 * N + j] = 2.0 * w0 * e0;
+      Xs[i1 * N + j] = 2.0 * w1 * e1;
     }
-    const double e0 = h0 - d0, e1 = h1 - d1;
-    const double m0 = js * Ms[i0 * N + j], m1 = js * Ms[i1 * N + j];   // entries of M = G J
     if (last) {
       // objective: sparsity of M and weighted error, reduced in a fixed order
-      double sp = m0 * m0 / (kSparseEps + fabs(m0)) + m1 * m1 / (kSparseEps + fabs(m1));
-      double er = w0 * e0 * e0 + w1 * e1 * e1;
 #pragma unroll
       for (int m = 32; m > 0; m >>= 1) {
         if (m < T) {
@@ -140,77 +187,70 @@ __global__ __launch_bounds__(N * N / 2) void design_search(DesignArgs a) {
         red[2 * (t >> 6)] = sp;
         red[2 * (t >> 6) + 1] = er;
       }
-      if (a.adj) {
-        double* out = a.adj + (int64_t)cand * N * N;
-        out[i0 * N + j] = m0;
-        out[i1 * N + j] = m1;
-      }
     }
-    Xs[i0 * N + j] = 2.0 * w0 * e0;
-    Xs[i1 * N + j] = 2.0 * w1 * e1;
-    __syncthreads();
+    group_sync<T>();
     if (last && t == 0) {
-      double sp = 0.0, er = 0.0;
+      double sps = 0.0, ers = 0.0;
       for (int w = 0; w < (T + 63) / 64; ++w) {
-        sp += red[2 * w];
-        er += red[2 * w + 1];
+        sps += red[2 * w];
+        ers += red[2 * w + 1];
       }
-      a.obj[3 * (int64_t)cand] = a.lam * sp + er;
-      a.obj[3 * (int64_t)cand + 1] = sp;
-      a.obj[3 * (int64_t)cand + 2] = er;
+      a.obj[3 * (int64_t)cand] = a.lam * sps + ers;
+      a.obj[3 * (int64_t)cand + 1] = sps;
+      a.obj[3 * (int64_t)cand + 2] = ers;
     }
     // adjoint of M = G J at (i, j): lam phi'(M) + (B^T X or X B^T), then times J
-    double g0, g1;
-    if (mode == 0) {   // dM = B^T X: dM[i][j] = sum_k B[k][i] X[k][j]
-      g0 = 0.0;
-      g1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+      const int j = jg + q * NC;
+      const double js = j == 0 ? sigma : 1.0;
+      double g0 = 0.0, g1 = 0.0;
+      if (mode == 0) {   // dM = B^T X: dM[i][j] = sum_k B[k][i] X[k][j]
 #pragma unroll 8
-      for (int k = 0; k < N; ++k) {
-        const double xk = Xs[k * N + j];
-        g0 += Bs[k * N + i0] * xk;
-        g1 += Bs[k * N + i1] * xk;
-      }
-    } else {           // dM = X B^T: dM[i][j] = sum_k X[i][k] B[j][k]
-      g0 = 0.0;
-      g1 = 0.0;
+        for (int k = 0; k < N; ++k) {
+          const double xk = Xs[k * N + j];
+          g0 += Bs[k * N + i0] * xk;
+          g1 += Bs[k * N + i1] * xk;
+        }
+      } else {           // dM = X B^T: dM[i][j] = sum_k X[i][k] B[j][k]
 #pragma unroll 8
-      for (int k = 0; k < N; ++k) {
-        const double bj = Bs[j * N + k];
-        g0 += Xs[i0 * N + k] * bj;
-        g1 += Xs[i1 * N + k] * bj;
+        for (int k = 0; k < N; ++k) {
+          const double bj = Bs[j * N + k];
+          g0 += Xs[i0 * N + k] * bj;
+          g1 += Xs[i1 * N + k] * bj;
+        }
       }
+      const double a0 = fabs(m0[q]), a1 = fabs(m1[q]);
+      g0 += a.lam * m0[q] * (2.0 * kSparseEps + a0) / ((kSparseEps + a0) * (kSparseEps + a0));
+      g1 += a.lam * m1[q] * (2.0 * kSparseEps + a1) / ((kSparseEps + a1) * (kSparseEps + a1));
+      Gs[i0 * N + j] = js * g0;
+      Gs[i1 * N + j] = js * g1;
     }
-    const double a0 = fabs(m0), a1 = fabs(m1);
-    g0 += a.lam * m0 * (2.0 * kSparseEps + a0) / ((kSparseEps + a0) * (kSparseEps + a0));
-    g1 += a.lam * m1 * (2.0 * kSparseEps + a1) / ((kSparseEps + a1) * (kSparseEps + a1));
-    Gs[i0 * N + j] = js * g0;
-    Gs[i1 * N + j] = js * g1;
-    __syncthreads();
+    group_sync<T>();
     // backward through the layers: angle gradient from each layer's outputs,
     // then step both the activations and the adjoint back through it
     for (int l = N - 1; l >= 0; --l) {
       const int p = (l & 1) + 2 * r;
       const bool valid = p + 1 < N;
+      const int k = layer_start<N>(l) + r;
       double contrib = 0.0;
-      double vp = 0.0, vq = 0.0, gp = 0.0, gq = 0.0;
       if (valid) {
-        vp = Ms[p * N + j];
-        vq = Ms[(p + 1) * N + j];
-        gp = Gs[p * N + j];
-        gq = Gs[(p + 1) * N + j];
-        contrib = -gp * vq + gq * vp;
-      }
-      const double sum = slot_sum<N>(contrib);
-      if (valid) {
-        const int k = layer_start<N>(l) + r;
-        if (j == 0) gr[k] = sum;
         const double cc = cs_c[k], ss = cs_s[k];
-        Ms[p * N + j] = cc * vp + ss * vq;
-        Ms[(p + 1) * N + j] = -ss * vp + cc * vq;
-        Gs[p * N + j] = cc * gp + ss * gq;
-        Gs[(p + 1) * N + j] = -ss * gp + cc * gq;
+#pragma unroll
+        for (int q = 0; q < CW; ++q) {
+          const int j = jg + q * NC;
+          const double vp = Ms[p * N + j], vq = Ms[(p + 1) * N + j];
+          const double gp = Gs[p * N + j], gq = Gs[(p + 1) * N + j];
+          contrib += -gp * vq + gq * vp;
+          Ms[p * N + j] = cc * vp + ss * vq;
+          Ms[(p + 1) * N + j] = -ss * vp + cc * vq;
+          Gs[p * N + j] = cc * gp + ss * gq;
+          Gs[(p + 1) * N + j] = -ss * gp + cc * gq;
+        }
       }
-      __syncthreads();
+      const double sum = slot_sum<NC>(contrib);
+      if (valid && jg == 0) gr[k] = sum;
+      group_sync<T>();
     }
     if (last) break;
     // Adam (Kingma and Ba) with bias correction
@@ -224,7 +264,7 @@ __global__ __launch_bounds__(N * N / 2) void design_search(DesignArgs a) {
       const double vh = ve[k] / (1.0 - b2t);
       th[k] -= a.lr * mh / (sqrt(vh) + a.eps);
     }
-    __syncthreads();
+    group_sync<T>();
   }
   for (int k = t; k < NA; k += T) {
     theta[k] = th[k];
@@ -234,13 +274,14 @@ __global__ __launch_bounds__(N * N / 2) void design_search(DesignArgs a) {
 
 }  // namespace
 
+// threads per workgroup: (n / 2) x (n / CW); n = 16 runs two columns per
+// thread so that one candidate is one wave
 const void* design_kernel(int n, int* threads) {
-  *threads = n * n / 2;
   switch (n) {
-    case 4: return reinterpret_cast<const void*>(&design_search<4>);
-    case 8: return reinterpret_cast<const void*>(&design_search<8>);
-    case 16: return reinterpret_cast<const void*>(&design_search<16>);
-    case 32: return reinterpret_cast<const void*>(&design_search<32>);
+    case 4: *threads = 8; return reinterpret_cast<const void*>(&design_search<4, 1>);
+    case 8: *threads = 32; return reinterpret_cast<const void*>(&design_search<8, 1>);
+    case 16: *threads = 64; return reinterpret_cast<const void*>(&design_search<16, 2>);
+    case 32: *threads = 512; return reinterpret_cast<const void*>(&design_search<32, 1>);
     default: return nullptr;
   }
 }
