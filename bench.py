@@ -367,6 +367,11 @@ def main():
     # the adjusted forward with its dense core on the int8 matrix cores (band on VALU)
     ctx.set_impl(1)
     tfm = _events_mean(lambda i: fwd(x, y, ax), 10)
+    # the direct DST-7 as a dense product on VALU (the comparison the paper's
+    # software measurement makes: full matrix on the same vector units)
+    ctx.set_impl(2)
+    tf7v = _events_mean(lambda i: fwd(x, y, ax7), 10)
+    ti7v = _events_mean(lambda i: inv(y, z, ax7), 10)
     ctx.set_impl(0)
     # plain copy of the same bytes (achievable HBM rate for a 2 B read + 2 B write stream)
     cev = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
@@ -422,6 +427,11 @@ def main():
             "fwd_us": tf7.mean() * 1e6, "inv_us": ti7.mean() * 1e6,
             "adjusted_over_direct": (tf7.mean() + ti7.mean()) / (tf.mean() + ti.mean()),
             "impl": "int8 matrix cores (exact byte-plane split)",
+        },
+        "direct_dst7_valu": {
+            "value": ncoef / (tf7v + ti7v), "unit": "coef/s", "fwd_us": tf7v * 1e6, "inv_us": ti7v * 1e6,
+            "adjusted_over_direct": (tf7v + ti7v) / (tf.mean() + ti.mean()),
+            "impl": "dense integer products on VALU (dot2)",
         },
         "adjusted_fwd_matrix_cores_us": tfm * 1e6,
         "copy_same_bytes": {"us": tcopy * 1e6, "GB/s": bytes_per_launch / tcopy / 1e9},
