@@ -350,12 +350,15 @@ TA_DEV Acc<N> core_direct(const S& src, int shift) {
   return r;
 }
 
-template <int N, int CORE, bool TR, class S>
+// DEEP_INV: the inverse's DCT-2 cores also try the deeper packed levels (the
+// forward's always do: they see residual-sized inputs); worth it for the
+// 32- and 64-point passes of the packed kernels, whose inputs mostly fit
+template <int N, int CORE, bool TR, bool DEEP_INV = false, class S>
 TA_DEV Acc<N> core(const S& src, int shift) {
   constexpr int C = (CORE == C_DST7 || CORE == C_DCT8) ? CORE : (TR ? core_transpose(CORE) : CORE);
-  // the forward's DCT-2 cores see residual-sized inputs: deeper packed levels
-  if constexpr (C == C_DCT2) return core_c2<N, false, false, !TR>(src, shift);
-  else if constexpr (C == C_DST2) return core_c2<N, true, true, !TR>(src, shift);
+  constexpr bool DEEP = !TR || DEEP_INV;
+  if constexpr (C == C_DCT2) return core_c2<N, false, false, DEEP>(src, shift);
+  else if constexpr (C == C_DST2) return core_c2<N, true, true, DEEP>(src, shift);
   else if constexpr (C == C_DCT3) return core_c3<N, false, false>(src, shift);
   else if constexpr (C == C_DST3) return core_c3<N, true, true>(src, shift);
   else return core_direct<N, C, TR>(src, shift);
@@ -420,17 +423,17 @@ struct Axis {
 
 // Run the forward (INV = false) or inverse pass of axis AX on `in`.
 // pf: forward parameters (band taps / Q pairs), pi: transposed parameters.
-template <int N, class AX, bool INV, class S>
+template <int N, class AX, bool INV, bool DEEP_INV = false, class S>
 TA_DEV auto run_pass(const S& in, cparam pf, cparam pi,
                      int s_core, int a) {
   if constexpr (AX::ADJ == ADJ_NONE) {
-    return core<N, AX::CORE, INV>(in, s_core);
+    return core<N, AX::CORE, INV, DEEP_INV>(in, s_core);
   } else if constexpr (AX::ADJ == ADJ_BAND) {
     if constexpr (!INV) {
       const Acc<N> u = band<N, AX::KB, false>(in, pf, a);
       return core<N, AX::CORE, false>(u, s_core);
     } else {
-      const Acc<N> u = core<N, AX::CORE, true>(in, s_core);
+      const Acc<N> u = core<N, AX::CORE, true, DEEP_INV>(in, s_core);
       return band<N, AX::KB, true>(u, pi, a);
     }
   } else {
@@ -450,7 +453,7 @@ TA_DEV auto run_pass(const S& in, cparam pf, cparam pi,
       z.s0 = z.s1 = a;
       post_rows<N, B>(in, pi, a, z.a);
       const Split<N, B, Acc<B>, S> comp{z, in};
-      return core<N, AX::CORE, true>(comp, s_core);
+      return core<N, AX::CORE, true, DEEP_INV>(comp, s_core);
     }
   }
 }
