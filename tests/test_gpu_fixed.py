@@ -88,7 +88,7 @@ def test_adversarial_values(reg, name, kind):
         assert (got == ref).all(), f"inverse={inverse}"
 
 
-@pytest.mark.parametrize("outside", [False, True], ids=["edge_inside", "one_outside"])
+@pytest.mark.parametrize("outside", [False, True, "deep"], ids=["edge_inside", "one_outside", "deep_edge"])
 @pytest.mark.parametrize("name", ["cfg2_dst7_k4", "cfg2_dct8_k4", "dct2_32", "post8_32", "cfg1_dct2_band_16",
                                   "cfg3_post16_64"])
 def test_dct2_butterfly_range_edge(reg, name, outside):
@@ -97,12 +97,17 @@ def test_dct2_butterfly_range_edge(reg, name, outside):
     [-2^14, 2^14).  Inputs drawn from the edges of that range exercise the
     packed level at its limits; one value just outside it in a single block
     sends that block's waves down the int32 path while neighbouring waves
-    stay packed.  Both must give the oracle's result."""
+    stay packed.  Both must give the oracle's result.  "deep": values near
+    +-2^13, so the first level stays packed while the sums feeding the next
+    packed level straddle +-2^14 (the deeper levels' own check)."""
     w, h = CASES[name][:2]
     nb = _ragged(w, h)
     rng = np.random.Generator(np.random.PCG64(77))
-    x = rng.choice(np.array([-16384, -16383, -1, 0, 16382, 16383], np.int16), size=(nb, h, w))
-    if outside:
+    if outside == "deep":
+        x = rng.choice(np.array([-8193, -8192, -1, 0, 8191, 8192], np.int16), size=(nb, h, w))
+    else:
+        x = rng.choice(np.array([-16384, -16383, -1, 0, 16382, 16383], np.int16), size=(nb, h, w))
+    if outside is True:
         x[nb // 2, h // 3, w // 2] = 16384
         x[nb - 1, h - 1, 0] = -16385
     print(f"case {name} outside={outside}", flush=True)
