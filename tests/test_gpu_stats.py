@@ -35,7 +35,7 @@ def _laplace_blocks(nb, h, w, seed, top=3000.0):
     return np.clip(np.rint(y), -32768, 32767).astype(np.int16).reshape(nb, h, w)
 
 
-def _compare(ctx, x, step, offset, exact_summary=True):
+def _compare(ctx, x, step, offset):
     got = ctx.coef_stats(torch.from_numpy(np.ascontiguousarray(x)).cuda(), step, offset)
     g = {k: v.cpu().numpy() for k, v in got.items()}
     ref = S.coef_stats(x, step, offset)
