@@ -258,7 +258,8 @@ def _batched(ctx, ids, res):
     from paper_2505_23618_amd.frames import descriptors as batch_descriptors, register_axes
     register_axes(ctx, ids)
     frames, rows = synth.frames_workload()
-    plan = ta.Plan(ctx, batch_descriptors(rows, frames.shape[1], frames.shape[2]))
+    desc = batch_descriptors(rows, frames.shape[1], frames.shape[2])
+    plan = ta.Plan(ctx, desc)
     X = [torch.from_numpy(frames).cuda() for _ in range(4)]
     Y = [torch.empty_like(X[0]) for _ in range(4)]
     Z = [torch.empty_like(X[0]) for _ in range(4)]
@@ -266,11 +267,17 @@ def _batched(ctx, ids, res):
     nco = int((rows[:, 3].astype(np.int64) * rows[:, 4]).sum())
     tf = _events_mean(lambda i: plan.fwd(X[i % 4], Y[i % 4]), 12)
     ti = _events_mean(lambda i: plan.inv(Y[i % 4], Z[i % 4]), 12)
+    # the same list unplanned: descriptors in device memory, in frame order
+    dev = ctx.blocks_to_device(desc)
+    uf = _events_mean(lambda i: ctx.transform_fwd(dev, X[i % 4], Y[i % 4]), 12)
+    ui = _events_mean(lambda i: ctx.transform_inv(dev, Y[i % 4], Z[i % 4]), 12)
     res["batched_uneven"] = {"value": nco / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
                              "blocks": len(rows), "coefficients": nco, "tiles": info["tiles"], "grid": info["grid"],
                              "GB/s_fwd": (4 * nco + 32 * len(rows)) / tf / 1e9,
+                             "unplanned_value": nco / (uf + ui), "unplanned_fwd_us": uf * 1e6,
+                             "unplanned_inv_us": ui * 1e6,
                              "workload": "8 frames 3840x2160, QT/BT blocks 4..64, per-axis DCT-2 / adj. DST-7 / adj. DCT-8"}
-    del X, Y, Z, plan
+    del X, Y, Z, plan, dev
     torch.cuda.empty_cache()
 
 

@@ -123,6 +123,31 @@ int ta_set_post(ta_ctx* ctx, int param_id, int n, int b,
  * taken from the block; parameter sets must match that size. */
 int ta_set_axis(ta_ctx* ctx, int axis_id, const ta_axis* axis);
 
+/* The same registration with the size and K/B stated (eq. 1: one adjustment
+ * per axis, band A or sub-block C, never both).  log2n = 0 leaves the size to
+ * the block; otherwise, with an adjustment, it must be the parameter set's
+ * size.  k_or_b = 0 takes K (band taps) or B (sub-block side) from the
+ * parameter set; otherwise it must equal it.  An axis without adjustment
+ * takes k_or_b = 0.  Errors: TA_EINVAL (mismatch, null), TA_ENOPARAMS,
+ * TA_EUNSUPPORTED as for ta_set_axis. */
+typedef struct {
+  int32_t base, adj, flip;   /* as in ta_axis */
+  int32_t log2n;             /* 0 or 2..6 */
+  int32_t k_or_b;            /* 0, or K taps (band) / B (sub-block) */
+  int32_t param_id;
+} ta_axis_cfg;
+int ta_set_axis_cfg(ta_ctx* ctx, int axis_id, const ta_axis_cfg* cfg);
+
+/* Register parameter set `param_id` from a layout triple
+ * layout = {adj, size, k_or_b}: TA_ADJ_BAND takes n = size * size dense
+ * entries (ta_set_band with K = k_or_b), TA_ADJ_POST takes n = k_or_b^2
+ * entries of Q (ta_set_post with B = k_or_b).  int_taps at scale 2^a and
+ * f32_params in host memory, copied synchronously.  Errors: TA_EINVAL
+ * (layout kind, n does not match the layout, null), then those of
+ * ta_set_band / ta_set_post. */
+int ta_set_params(ta_ctx* ctx, int param_id, const int16_t* int_taps, const float* f32_params,
+                  const int32_t* layout, int64_t n);
+
 /* Forward / inverse transform of a packed batch of nblocks W x H blocks
  * (W = 2^log2w, H = 2^log2h), horizontal axis axis_h, vertical axis_v.
  * in/out: device pointers to nblocks*W*H elements of dtype. */
@@ -179,6 +204,39 @@ int ta_plan_info(const ta_plan* plan, int64_t* nblocks, int64_t* ntiles, int* gr
 int ta_plan_fwd(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream);
 int ta_plan_inv(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream);
 int ta_plan_autotune(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream, int reps);
+
+/* Unplanned block lists.  ta_transform_fwd / _inv run nblocks descriptors
+ * that are already in device memory (blocks_dev, 8-byte aligned, read as
+ * they are, e.g. written by an earlier kernel) as one persistent launch: the
+ * list is cut into windows of 64 consecutive descriptors, and runs of
+ * consecutive descriptors with the same size and axis ids inside a window
+ * become one tile, so lists sorted by (size, axes) within each window run
+ * fastest; a plan (ta_plan_create) does that grouping on the host once.  The
+ * descriptor rules and transforms are those of the plans (int16, DCT-2 or
+ * DST-3 + 4-tap band axes; axes resolve through the context at launch time,
+ * so a parameter set registered again is seen by the next call).  A
+ * descriptor that breaks a rule the kernel can check (size, offset sign and
+ * alignment, stride, axis id or kind) is skipped and its output untouched.
+ * Extents are the caller's contract: every block must lie inside in and out
+ * and blocks must not overlap in out; ta_validate_blocks checks a list.
+ * in and out: 16-byte aligned device memory, not the same buffer.
+ * Asynchronous on the stream, allocates nothing, capturable in a HIP graph.
+ * Errors: TA_EINVAL (null, negative count, alignment, aliasing, dtype),
+ * TA_EUNSUPPORTED (TA_F32). */
+int ta_transform_fwd(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out,
+                     int dtype, ta_stream_t stream);
+int ta_transform_inv(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out,
+                     int dtype, ta_stream_t stream);
+
+/* Check n device descriptors against the block-list rules and against
+ * buffers of in_elems input and out_elems output elements (a debugging aid:
+ * copies the list to the host and synchronises).  On the first descriptor
+ * that fails, sets *first_bad to its index and returns its error (TA_EINVAL
+ * or TA_EUNSUPPORTED, or TA_ENOPARAMS for an unregistered axis) with the
+ * reason in ta_last_error(); otherwise *first_bad = -1 and TA_OK.  Overlap
+ * of blocks in the output is not checked. */
+int ta_validate_blocks(ta_ctx* ctx, const ta_block* blocks_dev, int64_t n, int64_t in_elems, int64_t out_elems,
+                       int64_t* first_bad);
 
 /* ---- Quantised-coefficient statistics (coding-gain proxy) -------------------
  * A codec-free stand-in for the coding results of the experiments section

@@ -37,7 +37,8 @@ EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis
            "ta_fwd_packed", "ta_inv_packed", "ta_set_impl", "ta_version", "ta_last_error",
            "ta_plan_create", "ta_plan_destroy", "ta_plan_info", "ta_plan_fwd", "ta_plan_inv",
            "ta_plan_autotune", "ta_givens_workspace", "ta_givens_fwd", "ta_givens_bwd",
-           "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats", "ta_design_search")
+           "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats", "ta_design_search",
+           "ta_transform_fwd", "ta_transform_inv", "ta_validate_blocks", "ta_set_axis_cfg", "ta_set_params")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -55,6 +56,11 @@ class TadjError(RuntimeError):
 class _Axis(ctypes.Structure):
     _fields_ = [("base", ctypes.c_int32), ("adj", ctypes.c_int32),
                 ("flip", ctypes.c_int32), ("param_id", ctypes.c_int32)]
+
+
+class _AxisCfg(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_int32), ("adj", ctypes.c_int32), ("flip", ctypes.c_int32),
+                ("log2n", ctypes.c_int32), ("k_or_b", ctypes.c_int32), ("param_id", ctypes.c_int32)]
 
 
 _lib = None
@@ -91,6 +97,11 @@ def lib() -> ctypes.CDLL:
     L.ta_givens_workspace.argtypes = [i64, ctypes.POINTER(i64)]
     L.ta_givens_fwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp]
     L.ta_givens_bwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp, vp, vp, vp]
+    for f in (L.ta_transform_fwd, L.ta_transform_inv):
+        f.argtypes = [vp, vp, i64, vp, vp, i32, vp]
+    L.ta_validate_blocks.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(i64)]
+    L.ta_set_axis_cfg.argtypes = [vp, i32, ctypes.POINTER(_AxisCfg)]
+    L.ta_set_params.argtypes = [vp, i32, vp, vp, vp, i64]
     L.ta_version.restype = ctypes.c_char_p
     L.ta_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -151,6 +162,25 @@ class Context:
         ax = _Axis(base, adj, int(bool(flip)), param)
         _check(lib().ta_set_axis(self._h, aid, ctypes.byref(ax)))
         return aid
+
+    def axis_cfg(self, aid: int, base: int, adj: int = ADJ_NONE, flip: bool = False, log2n: int = 0,
+                 k_or_b: int = 0, param: int = 0) -> int:
+        """ta_set_axis_cfg: as axis(), with the size and K/B stated (checked against the set)."""
+        cfg = _AxisCfg(base, adj, int(bool(flip)), log2n, k_or_b, param)
+        _check(lib().ta_set_axis_cfg(self._h, aid, ctypes.byref(cfg)))
+        return aid
+
+    def set_params(self, pid: int, layout, int_taps: np.ndarray, f32_params: np.ndarray):
+        """ta_set_params with layout = (adj, size, k_or_b)."""
+        int_taps = np.ascontiguousarray(int_taps, dtype=np.int16).ravel()
+        f32_params = np.ascontiguousarray(f32_params, dtype=np.float32).ravel()
+        if int_taps.size != f32_params.size:
+            raise ValueError("int_taps and f32_params differ in size")
+        lay = np.ascontiguousarray(layout, dtype=np.int32)
+        if lay.shape != (3,):
+            raise ValueError("layout is (adj, size, k_or_b)")
+        _check(lib().ta_set_params(self._h, pid, int_taps.ctypes.data, f32_params.ctypes.data, lay.ctypes.data,
+                                   int_taps.size))
 
     def set_impl(self, impl: int):
         """0: matrix-core kernels where built, else VALU; 1: matrix cores only; 2: VALU only."""
@@ -267,6 +297,53 @@ class Context:
         return out
 
     # raw pointer variants (no allocation; for graphs and benchmarks)
+    # -- unplanned block lists ----------------------------------------------------
+    @staticmethod
+    def blocks_to_device(blocks: np.ndarray, device: int = 0):
+        """A ``BLOCK_DTYPE`` array as a uint8 [n, 32] tensor in device memory."""
+        import torch
+        blocks = np.ascontiguousarray(blocks, dtype=BLOCK_DTYPE)
+        raw = torch.from_numpy(blocks.view(np.uint8).reshape(len(blocks), 32).copy())
+        return raw.to(f"cuda:{device}")
+
+    @staticmethod
+    def _nblocks(blocks_dev) -> int:
+        import torch
+        if blocks_dev.dtype != torch.uint8 or blocks_dev.dim() != 2 or blocks_dev.shape[1] != 32:
+            raise ValueError("descriptors are a uint8 [n, 32] device tensor (blocks_to_device)")
+        if not blocks_dev.is_contiguous():
+            raise ValueError("descriptors must be contiguous")
+        return blocks_dev.shape[0]
+
+    def _run_blocks(self, fn, blocks_dev, x, out, stream_handle):
+        import torch
+        n = self._nblocks(blocks_dev)
+        for t in (x, out):
+            if t.dtype != torch.int16 or not t.is_contiguous():
+                raise ValueError("block lists run on contiguous int16 buffers")
+        sh = _stream_handle(None) if stream_handle is None else ctypes.c_void_p(stream_handle)
+        _check(fn(self._h, ctypes.c_void_p(blocks_dev.data_ptr()), n, ctypes.c_void_p(x.data_ptr()),
+                  ctypes.c_void_p(out.data_ptr()), I16, sh))
+        return out
+
+    def transform_fwd(self, blocks_dev, x, out, stream_handle=None):
+        """ta_transform_fwd over descriptors already in device memory."""
+        return self._run_blocks(lib().ta_transform_fwd, blocks_dev, x, out, stream_handle)
+
+    def transform_inv(self, blocks_dev, y, out, stream_handle=None):
+        """ta_transform_inv over descriptors already in device memory."""
+        return self._run_blocks(lib().ta_transform_inv, blocks_dev, y, out, stream_handle)
+
+    def validate_blocks(self, blocks_dev, in_elems: int, out_elems: int):
+        """(-1, "") when every descriptor is valid, else (index of the first bad one, reason)."""
+        n = self._nblocks(blocks_dev)
+        bad = ctypes.c_int64(-1)
+        code = lib().ta_validate_blocks(self._h, ctypes.c_void_p(blocks_dev.data_ptr()), n, in_elems, out_elems,
+                                        ctypes.byref(bad))
+        if code != 0 and bad.value < 0:
+            _check(code)
+        return bad.value, (lib().ta_last_error().decode() if code != 0 else "")
+
     def fwd_ptr(self, axis_h, axis_v, log2w, log2h, nblocks, in_ptr, out_ptr, dtype, stream_handle):
         _check(lib().ta_fwd_packed(self._h, axis_h, axis_v, log2w, log2h, nblocks,
                                    ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr), dtype,

@@ -39,6 +39,7 @@ struct BDesc {
   int32_t in_stride, out_stride;
 };
 constexpr int kMaxTileBlocks = 64;
+static_assert(kMaxTileBlocks == kDescWindow, "a descriptor window is one tile's block buffer");
 static_assert(kBatchLds * 4 <= 20480, "tile LDS above 20 KiB");
 
 template <int W>
@@ -137,45 +138,49 @@ struct Chunk {
   }
 };
 
+// One tile of the forward: rows -> pair-row LDS -> columns -> row-major LDS
+// -> coalesced stores.  Ends with a barrier (LDS free for the next tile).
+TA_DEV void fwd_tile(const BatchArgs& a, const BatchTile& t, uint32_t* lds, BDesc* desc) {
+  uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
+  const int s_row = t.lw + a.bd + a.m - 15, s_col = t.lh + a.m;
+  switch (t.kind_h) {
+    case 0: fwd_rows_w<KC2>(a, t, pch, desc, s_row); break;
+    case 1: fwd_rows_w<KS3>(a, t, pch, desc, s_row); break;
+    default: fwd_rows_w<KC3>(a, t, pch, desc, s_row); break;
+  }
+  __syncthreads();
+  switch (t.kind_v) {
+    case 0: fwd_cols_h<KC2>(a, t, lds, s_col); break;
+    case 1: fwd_cols_h<KS3>(a, t, lds, s_col); break;
+    default: fwd_cols_h<KC3>(a, t, lds, s_col); break;
+  }
+  __syncthreads();
+  // coalesced store of the tile (row-major layout, chunks of 2^lch halfwords)
+  const int lch = t.lw >= 3 ? 3 : 2;
+  const int q = BatchGeo::rm_pitch(t.lh);
+  const int nch = t.count << (t.lw + t.lh - lch);
+  for (int ch = threadIdx.x; ch < nch; ch += 256) {
+    const Chunk k(ch, t.lw, t.lh, lch);
+    const BDesc d = desc[k.b];
+    int16_t* dst = a.out + d.out_off + (int64_t)k.r * d.out_stride + k.c0;
+    const uint16_t* src = pch + k.r * q + (k.b << t.lw) + k.c0;
+    if (lch == 3)
+      *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+    else
+      *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(src);
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_fwd(BatchArgs a) {
   __shared__ __align__(16) uint32_t lds[kBatchLds];
   __shared__ BDesc desc[kMaxTileBlocks];
-  uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
   // this workgroup's XCD list and its stride within that list
   const int xcd = blockIdx.x % kXcds;
   const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
   const int64_t end = a.xstart[xcd + 1];
-  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd) {
-    const BatchTile t = a.tiles[ti];
-    const int s_row = t.lw + a.bd + a.m - 15, s_col = t.lh + a.m;
-    switch (t.kind_h) {
-      case 0: fwd_rows_w<KC2>(a, t, pch, desc, s_row); break;
-      case 1: fwd_rows_w<KS3>(a, t, pch, desc, s_row); break;
-      default: fwd_rows_w<KC3>(a, t, pch, desc, s_row); break;
-    }
-    __syncthreads();
-    switch (t.kind_v) {
-      case 0: fwd_cols_h<KC2>(a, t, lds, s_col); break;
-      case 1: fwd_cols_h<KS3>(a, t, lds, s_col); break;
-      default: fwd_cols_h<KC3>(a, t, lds, s_col); break;
-    }
-    __syncthreads();
-    // coalesced store of the tile (row-major layout, chunks of 2^lch halfwords)
-    const int lch = t.lw >= 3 ? 3 : 2;
-    const int q = BatchGeo::rm_pitch(t.lh);
-    const int nch = t.count << (t.lw + t.lh - lch);
-    for (int ch = threadIdx.x; ch < nch; ch += 256) {
-      const Chunk k(ch, t.lw, t.lh, lch);
-      const BDesc d = desc[k.b];
-      int16_t* dst = a.out + d.out_off + (int64_t)k.r * d.out_stride + k.c0;
-      const uint16_t* src = pch + k.r * q + (k.b << t.lw) + k.c0;
-      if (lch == 3)
-        *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
-      else
-        *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(src);
-    }
-    __syncthreads();
-  }
+  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd)
+    fwd_tile(a, a.tiles[ti], lds, desc);
 }
 
 // ---------------------------------------------------------------- inverse
@@ -258,80 +263,161 @@ TA_DEV void inv_rows_w(const BatchArgs& a, const BatchTile& t, uint16_t* rm, int
   }
 }
 
+// One tile of the inverse: coalesced loads -> pair-row LDS -> columns ->
+// row-major LDS -> rows in place -> coalesced stores.  Ends with a barrier.
+TA_DEV void inv_tile(const BatchArgs& a, const BatchTile& t, uint32_t* lds, BDesc* desc) {
+  uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
+  const int s_col = a.m + 1, s_row = a.m + 14 - a.bd;
+  const int lch = t.lw >= 3 ? 3 : 2;
+  const int nch = t.count << (t.lw + t.lh - lch);
+  if ((int)threadIdx.x < t.count) {
+    const ta_block d = a.blocks[t.first + threadIdx.x];
+    desc[threadIdx.x] = BDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
+  }
+  __syncthreads();
+  // coalesced load of the tile into the pair-row layout
+  {
+    const int p = BatchGeo::pc_pitch(t.lh);
+    for (int ch = threadIdx.x; ch < nch; ch += 256) {
+      const Chunk k(ch, t.lw, t.lh, lch);
+      const BDesc d = desc[k.b];
+      const int16_t* src = a.in + d.in_off + (int64_t)k.r * d.in_stride + k.c0;
+      uint32_t w[4];
+      if (lch == 3) {
+        const uint4 v = *reinterpret_cast<const uint4*>(src);
+        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+      } else {
+        const uint2 v = *reinterpret_cast<const uint2*>(src);
+        w[0] = v.x; w[1] = v.y; w[2] = 0; w[3] = 0;
+      }
+      const int base = ((k.r >> 1) * p + (k.b << t.lw) + k.c0) * 2 + (k.r & 1);
+      for (int j = 0; j < (1 << lch) / 2; ++j) {
+        pch[base + (2 * j) * 2] = (uint16_t)w[j];
+        pch[base + (2 * j + 1) * 2] = (uint16_t)(w[j] >> 16);
+      }
+    }
+  }
+  __syncthreads();
+  switch (t.kind_v) {
+    case 0: inv_cols_h<KC2>(a, t, lds, s_col); break;
+    case 1: inv_cols_h<KS3>(a, t, lds, s_col); break;
+    default: inv_cols_h<KC3>(a, t, lds, s_col); break;
+  }
+  __syncthreads();
+  switch (t.kind_h) {
+    case 0: inv_rows_w<KC2>(a, t, pch, s_row); break;
+    case 1: inv_rows_w<KS3>(a, t, pch, s_row); break;
+    default: inv_rows_w<KC3>(a, t, pch, s_row); break;
+  }
+  __syncthreads();
+  // coalesced store of the tile (row-major layout)
+  {
+    const int q = BatchGeo::rm_pitch(t.lh);
+    for (int ch = threadIdx.x; ch < nch; ch += 256) {
+      const Chunk k(ch, t.lw, t.lh, lch);
+      const BDesc d = desc[k.b];
+      int16_t* dst = a.out + d.out_off + (int64_t)k.r * d.out_stride + k.c0;
+      const uint16_t* src = pch + k.r * q + (k.b << t.lw) + k.c0;
+      if (lch == 3)
+        *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+      else
+        *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(src);
+    }
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_inv(BatchArgs a) {
   __shared__ __align__(16) uint32_t lds[kBatchLds];
   __shared__ BDesc desc[kMaxTileBlocks];
-  uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
   // this workgroup's XCD list and its stride within that list
   const int xcd = blockIdx.x % kXcds;
   const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
   const int64_t end = a.xstart[xcd + 1];
-  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd) {
-    const BatchTile t = a.tiles[ti];
-    const int s_col = a.m + 1, s_row = a.m + 14 - a.bd;
-    const int lch = t.lw >= 3 ? 3 : 2;
-    const int nch = t.count << (t.lw + t.lh - lch);
-    if ((int)threadIdx.x < t.count) {
-      const ta_block d = a.blocks[t.first + threadIdx.x];
-      desc[threadIdx.x] = BDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
-    }
-    __syncthreads();
-    // coalesced load of the tile into the pair-row layout
-    {
-      const int p = BatchGeo::pc_pitch(t.lh);
-      for (int ch = threadIdx.x; ch < nch; ch += 256) {
-        const Chunk k(ch, t.lw, t.lh, lch);
-        const BDesc d = desc[k.b];
-        const int16_t* src = a.in + d.in_off + (int64_t)k.r * d.in_stride + k.c0;
-        uint32_t w[4];
-        if (lch == 3) {
-          const uint4 v = *reinterpret_cast<const uint4*>(src);
-          w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-        } else {
-          const uint2 v = *reinterpret_cast<const uint2*>(src);
-          w[0] = v.x; w[1] = v.y; w[2] = 0; w[3] = 0;
-        }
-        const int base = ((k.r >> 1) * p + (k.b << t.lw) + k.c0) * 2 + (k.r & 1);
-        for (int j = 0; j < (1 << lch) / 2; ++j) {
-          pch[base + (2 * j) * 2] = (uint16_t)w[j];
-          pch[base + (2 * j + 1) * 2] = (uint16_t)(w[j] >> 16);
-        }
+  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd)
+    inv_tile(a, a.tiles[ti], lds, desc);
+}
+
+// ---------------------------------------------------------------- block lists
+// Unplanned: the descriptor list is cut into windows of kMaxTileBlocks
+// consecutive descriptors and the windows into kXcds contiguous ranges, one
+// per XCD (workgroup b runs on XCD b mod kXcds), so that neighbouring blocks
+// of a list in frame order share their L2; within its range a workgroup takes
+// every per_xcd-th window.  Each descriptor's size and axis ids resolve
+// through the context's axis table; runs of consecutive descriptors with the
+// same configuration become tiles of up to BatchGeo::nb_for blocks, processed
+// in order.  A descriptor that the planner would reject (size outside 4..64,
+// negative offset, stride below the width, offsets or strides not multiples
+// of the vector width, an axis with no batched kind at its size) is skipped:
+// its output is left untouched.
+template <bool INV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_desc(BatchArgs a) {
+  __shared__ __align__(16) uint32_t lds[kBatchLds];
+  __shared__ BDesc desc[kMaxTileBlocks];
+  __shared__ int64_t key[kMaxTileBlocks];
+  const int tid = threadIdx.x;
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;   // >= 1: the grid has >= kXcds groups
+  const int64_t nwin = (a.nblocks + kMaxTileBlocks - 1) / kMaxTileBlocks;
+  const int64_t wend = nwin * (xcd + 1) / kXcds;
+  for (int64_t w = nwin * xcd / kXcds + blockIdx.x / kXcds; w < wend; w += per_xcd) {
+    const int64_t w0 = w * kMaxTileBlocks;
+    const int cnt = (int)min<int64_t>(kMaxTileBlocks, a.nblocks - w0);
+    if (tid < cnt) {
+      const ta_block d = a.blocks[w0 + tid];
+      int64_t k = -1;
+      const int ch = d.log2w >= 3 ? 8 : 4;         // elements per vector access
+      if (d.log2w >= 2 && d.log2w <= 6 && d.log2h >= 2 && d.log2h <= 6 && d.in_off >= 0 && d.out_off >= 0 &&
+          d.in_stride >= (1 << d.log2w) && d.out_stride >= (1 << d.log2w) && d.axis_h < kAxisIds &&
+          d.axis_v < kAxisIds && ((d.in_off | d.out_off | (int64_t)d.in_stride | (int64_t)d.out_stride) & (ch - 1)) == 0) {
+        const AxisDev& h = a.axes[d.axis_h * kAxisSizes + d.log2w];
+        const AxisDev& v = a.axes[d.axis_v * kAxisSizes + d.log2h];
+        if (h.kind >= 0 && v.kind >= 0)
+          k = (int64_t)d.log2w | ((int64_t)d.log2h << 3) | ((int64_t)d.axis_h << 6) | ((int64_t)d.axis_v << 22);
       }
+      key[tid] = k;
     }
     __syncthreads();
-    switch (t.kind_v) {
-      case 0: inv_cols_h<KC2>(a, t, lds, s_col); break;
-      case 1: inv_cols_h<KS3>(a, t, lds, s_col); break;
-      default: inv_cols_h<KC3>(a, t, lds, s_col); break;
-    }
-    __syncthreads();
-    switch (t.kind_h) {
-      case 0: inv_rows_w<KC2>(a, t, pch, s_row); break;
-      case 1: inv_rows_w<KS3>(a, t, pch, s_row); break;
-      default: inv_rows_w<KC3>(a, t, pch, s_row); break;
-    }
-    __syncthreads();
-    // coalesced store of the tile (row-major layout)
-    {
-      const int q = BatchGeo::rm_pitch(t.lh);
-      for (int ch = threadIdx.x; ch < nch; ch += 256) {
-        const Chunk k(ch, t.lw, t.lh, lch);
-        const BDesc d = desc[k.b];
-        int16_t* dst = a.out + d.out_off + (int64_t)k.r * d.out_stride + k.c0;
-        const uint16_t* src = pch + k.r * q + (k.b << t.lw) + k.c0;
-        if (lch == 3)
-          *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
-        else
-          *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(src);
+    int j = 0;
+    while (j < cnt) {                 // every thread walks the same runs
+      const int64_t k = key[j];
+      if (k < 0) {
+        ++j;
+        continue;
       }
+      const int lw = (int)(k & 7), lh = (int)((k >> 3) & 7);
+      const int ah = (int)((k >> 6) & 0xffff), av = (int)((k >> 22) & 0xffff);
+      const int cap = BatchGeo::nb_for(lw, lh);
+      int len = 1;
+      while (j + len < cnt && len < cap && key[j + len] == k) ++len;
+      const AxisDev& h = a.axes[ah * kAxisSizes + lw];
+      const AxisDev& v = a.axes[av * kAxisSizes + lh];
+      BatchTile t;
+      t.lw = lw;
+      t.lh = lh;
+      t.kind_h = h.kind;
+      t.kind_v = v.kind;
+      t.first = w0 + j;
+      t.count = len;
+      t.pad = 0;
+      t.ph_f = h.pf;
+      t.ph_i = h.pi;
+      t.pv_f = v.pf;
+      t.pv_i = v.pi;
+      if (INV)
+        inv_tile(a, t, lds, desc);
+      else
+        fwd_tile(a, t, lds, desc);
+      j += len;
     }
-    __syncthreads();
+    __syncthreads();                  // keys of the next window
   }
 }
 
 }  // namespace
 
-const void* batch_kernel(int inv) {
+const void* batch_kernel(int inv, int desc) {
+  if (desc) return inv ? reinterpret_cast<const void*>(&batch_desc<true>) : reinterpret_cast<const void*>(&batch_desc<false>);
   return inv ? reinterpret_cast<const void*>(&batch_inv) : reinterpret_cast<const void*>(&batch_fwd);
 }
 

@@ -80,6 +80,9 @@ struct ta_ctx {
   int impl = 0;   // 0 automatic (matrix cores where built), 1 matrix cores only, 2 VALU only
   ParamSet params[kMaxIds];
   AxisCfg axes[kMaxIds];
+  // device table of the batched kinds of every (axis id, log2 size), read by
+  // the block-list kernels; kind -1 where the axis has no batched kernel
+  ta::AxisDev* axes_dev = nullptr;
   std::vector<void*> allocations;
   std::mutex mu;
 };
@@ -144,6 +147,49 @@ int resolve_axis(ta_ctx* c, int id, int n, int dtype, Resolved* r) {
   return TA_OK;
 }
 
+// kind of a resolved axis in the batched kernel (see batch_kernels.hip)
+int batch_kind(const Resolved& r) {
+  if (r.core == TA_DCT2 && r.adj == TA_ADJ_NONE) return 0;
+  if (r.core == TA_DST3 && r.adj == TA_ADJ_BAND && r.kb == 4) return 1;
+  if (r.core == TA_DCT3 && r.adj == TA_ADJ_BAND && r.kb == 4) return 2;
+  return -1;
+}
+
+// Rewrite the device axis-table row of axis `id`: for each log2 size the
+// batched kind and the band tables, or kind -1.  Sizes the axis does not
+// resolve at are expected (a band is registered for one size), so their
+// messages are not left in the error slot.  Caller holds c->mu.
+int refresh_axis(ta_ctx* c, int id) {
+  ta::AxisDev row[ta::kAxisSizes];
+  const std::string saved = g_err;
+  for (int l = 0; l < ta::kAxisSizes; ++l) {
+    row[l] = ta::AxisDev{-1, 0, nullptr, nullptr};
+    Resolved r;
+    if (l >= 2 && l <= 6 && c->axes[id].set && resolve_axis(c, id, 1 << l, TA_I16, &r) == TA_OK) {
+      row[l].kind = batch_kind(r);
+      row[l].pf = static_cast<const uint32_t*>(r.pf);
+      row[l].pi = static_cast<const uint32_t*>(r.pi);
+      if (row[l].kind < 0) row[l].pf = row[l].pi = nullptr;
+    }
+  }
+  g_err = saved;
+  TA_HIP(hipSetDevice(c->device));
+  TA_HIP(hipMemcpy(c->axes_dev + (size_t)id * ta::kAxisSizes, row, sizeof row, hipMemcpyHostToDevice));
+  return TA_OK;
+}
+
+// After parameter set `pid` changed: refresh every axis that uses it.
+int refresh_param_users(ta_ctx* c, int pid) {
+  for (int id = 0; id < kMaxIds; ++id) {
+    const AxisCfg& ax = c->axes[id];
+    if (ax.set && ax.user.adj != TA_ADJ_NONE && ax.user.param_id == pid) {
+      int e;
+      if ((e = refresh_axis(c, id))) return e;
+    }
+  }
+  return TA_OK;
+}
+
 const ta::KernelEntry* find_kernel(const ta::KernelKey& key, int prefer_mfma, bool mfma_only, bool same) {
   int cnt = 0;
   // Automatic selection uses the matrix-core kernels only where they are the
@@ -165,16 +211,16 @@ const ta::KernelEntry* find_kernel(const ta::KernelKey& key, int prefer_mfma, bo
 
 // Workgroups of kernel k that are resident on device `dev` at once (the grid
 // of a persistent kernel): occupancy per CU times the CU count, cached.
-int resident_groups(const ta::KernelEntry* k, int dev, int* out) {
+int resident_groups(const void* fn, int threads, int dev, int* out) {
   static std::mutex mu;
   static std::map<std::pair<const void*, int>, int> cache;
   std::lock_guard<std::mutex> lk(mu);
-  const auto key = std::make_pair(k->fn, dev);
+  const auto key = std::make_pair(fn, dev);
   auto it = cache.find(key);
   if (it == cache.end()) {
     int per_cu = 0, cus = 0;
     TA_HIP(hipSetDevice(dev));
-    TA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->fn, k->threads, 0));
+    TA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0));
     TA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     if (per_cu < 1 || cus < 1) return fail(TA_EHIP, "kernel occupancy query returned %d x %d", per_cu, cus);
     it = cache.emplace(key, per_cu * cus).first;
@@ -182,6 +228,8 @@ int resident_groups(const ta::KernelEntry* k, int dev, int* out) {
   *out = it->second;
   return TA_OK;
 }
+
+int resident_groups(const ta::KernelEntry* k, int dev, int* out) { return resident_groups(k->fn, k->threads, dev, out); }
 
 int run_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int log2w, int log2h, int64_t nblocks,
                const void* in, void* out, int dtype, ta_stream_t stream) {
@@ -262,6 +310,13 @@ int ta_create(ta_ctx** out, int device, int bit_depth, int m, int a) {
   c->bd = bit_depth;
   c->m = m;
   c->a = a;
+  static_assert(kMaxIds == ta::kAxisIds, "axis table size");
+  std::vector<ta::AxisDev> table((size_t)ta::kAxisIds * ta::kAxisSizes, ta::AxisDev{-1, 0, nullptr, nullptr});
+  int e;
+  if ((e = upload(c.get(), table.data(), table.size() * sizeof(ta::AxisDev), reinterpret_cast<void**>(&c->axes_dev)))) {
+    for (void* p : c->allocations) (void)hipFree(p);
+    return e;
+  }
   *out = c.release();
   return TA_OK;
 }
@@ -340,7 +395,7 @@ int ta_set_band(ta_ctx* c, int id, int n, int k, const int16_t* a_int, const flo
       if ((e = upload(c, packed.data(), packed.size() * 4, &ps.fx[flip][tr]))) return e;
       if ((e = upload(c, fl.data(), fl.size() * 4, &ps.f32[flip][tr]))) return e;
     }
-  return TA_OK;
+  return refresh_param_users(c, id);
 }
 
 int ta_set_post(ta_ctx* c, int id, int n, int b, const int16_t* q_int, const float* q_f32) {
@@ -388,7 +443,7 @@ int ta_set_post(ta_ctx* c, int id, int n, int b, const int16_t* q_int, const flo
     int e;
     if ((e = upload(c, eo.data(), eo.size() * 4, &ps.fx_eo))) return e;
   }
-  return TA_OK;
+  return refresh_param_users(c, id);
 }
 
 int ta_set_axis(ta_ctx* c, int id, const ta_axis* ax) {
@@ -405,7 +460,7 @@ int ta_set_axis(ta_ctx* c, int id, const ta_axis* ax) {
   std::lock_guard<std::mutex> lk(c->mu);
   c->axes[id].set = true;
   c->axes[id].user = *ax;
-  return TA_OK;
+  return refresh_axis(c, id);
 }
 
 int ta_fwd_packed(ta_ctx* c, int axis_h, int axis_v, int log2w, int log2h, int64_t nblocks,
@@ -436,12 +491,31 @@ struct ta_plan {
 
 namespace {
 
-// kind of a resolved axis in the batched kernel (see batch_kernels.hip)
-int batch_kind(const Resolved& r) {
-  if (r.core == TA_DCT2 && r.adj == TA_ADJ_NONE) return 0;
-  if (r.core == TA_DST3 && r.adj == TA_ADJ_BAND && r.kb == 4) return 1;
-  if (r.core == TA_DCT3 && r.adj == TA_ADJ_BAND && r.kb == 4) return 2;
-  return -1;
+// The rules every block-list descriptor meets, shared by the planner and the
+// validator (the unplanned kernels apply the same rules and skip a
+// descriptor that breaks one): sizes 4..64, non-negative offsets, strides of
+// at least the width, offsets and strides multiples of the vector width (8
+// elements, 4 for 4-wide blocks), and axes with a batched kind at the size.
+int check_block(ta_ctx* c, const ta_block& b, int64_t i, Resolved* rh, Resolved* rv, int* kh, int* kv) {
+  if (b.log2w < 2 || b.log2w > 6 || b.log2h < 2 || b.log2h > 6)
+    return fail(TA_EUNSUPPORTED, "block %lld: size %dx%d outside 4..64", (long long)i, 1 << std::min<int>(b.log2w, 30),
+                1 << std::min<int>(b.log2h, 30));
+  const int w = 1 << b.log2w, ch = w >= 8 ? 8 : 4;
+  if (b.in_off < 0 || b.out_off < 0 || b.in_stride < w || b.out_stride < w)
+    return fail(TA_EINVAL, "block %lld: negative offset or stride below the width", (long long)i);
+  if (b.in_off % ch || b.out_off % ch || b.in_stride % ch || b.out_stride % ch)
+    return fail(TA_EUNSUPPORTED, "block %lld: offsets and strides must be multiples of %d elements", (long long)i, ch);
+  int e;
+  if ((e = resolve_axis(c, b.axis_h, w, TA_I16, rh)) || (e = resolve_axis(c, b.axis_v, 1 << b.log2h, TA_I16, rv))) {
+    const std::string m = g_err;
+    return fail(e, "block %lld: %s", (long long)i, m.c_str());
+  }
+  *kh = batch_kind(*rh);
+  *kv = batch_kind(*rv);
+  if (*kh < 0 || *kv < 0)
+    return fail(TA_EUNSUPPORTED, "block %lld: batched kernels take DCT-2, adjusted DST-7 or adjusted DCT-8 "
+                "(DST-3 + 4-tap band) axes", (long long)i);
+  return TA_OK;
 }
 
 int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_stream_t stream, int grid) {
@@ -483,21 +557,10 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
   plan->device = c->device;
   for (int64_t i = 0; i < n; ++i) {
     const ta_block& b = blocks[i];
-    if (b.log2w < 2 || b.log2w > 6 || b.log2h < 2 || b.log2h > 6)
-      return fail(TA_EUNSUPPORTED, "block %lld: size %dx%d outside 4..64", (long long)i, 1 << b.log2w, 1 << b.log2h);
-    const int w = 1 << b.log2w, h = 1 << b.log2h, ch = w >= 8 ? 8 : 4;
-    if (b.in_off < 0 || b.out_off < 0 || b.in_stride < w || b.out_stride < w)
-      return fail(TA_EINVAL, "block %lld: negative offset or stride below the width", (long long)i);
-    if (b.in_off % ch || b.out_off % ch || b.in_stride % ch || b.out_stride % ch)
-      return fail(TA_EUNSUPPORTED, "block %lld: offsets and strides must be multiples of %d elements", (long long)i, ch);
     Resolved rh, rv;
-    int e;
-    if ((e = resolve_axis(c, b.axis_h, w, TA_I16, &rh))) return e;
-    if ((e = resolve_axis(c, b.axis_v, h, TA_I16, &rv))) return e;
-    const int kh = batch_kind(rh), kv = batch_kind(rv);
-    if (kh < 0 || kv < 0)
-      return fail(TA_EUNSUPPORTED, "block %lld: batched kernels take DCT-2, adjusted DST-7 or adjusted DCT-8 "
-                  "(DST-3 + 4-tap band) axes", (long long)i);
+    int kh, kv, e;
+    if ((e = check_block(c, b, i, &rh, &rv, &kh, &kv))) return e;
+    const int w = 1 << b.log2w, h = 1 << b.log2h;
     const Key k{b.in_off / kRegion, b.log2w, b.log2h, kh, kv, rh.pf, rv.pf};
     groups[k].push_back(i);
     res[k] = std::make_tuple(rh, rv);
@@ -583,6 +646,7 @@ int ta_plan_fwd(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t st
   if (!c || !p) return fail(TA_EINVAL, "null argument");
   if (p->ntiles == 0) return TA_OK;
   if (!in || !out) return fail(TA_EINVAL, "null buffer");
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
   return launch_plan(c, p, 0, in, out, stream, p->grid);
 }
 
@@ -590,6 +654,7 @@ int ta_plan_inv(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t st
   if (!c || !p) return fail(TA_EINVAL, "null argument");
   if (p->ntiles == 0) return TA_OK;
   if (!in || !out) return fail(TA_EINVAL, "null buffer");
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
   return launch_plan(c, p, 1, in, out, stream, p->grid);
 }
 
@@ -635,6 +700,133 @@ int ta_plan_autotune(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream
   (void)hipFree(ref);
   if (rc == TA_OK) p->grid = best_grid;
   return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Unplanned block lists: descriptors in device memory, read as they are
+// ---------------------------------------------------------------------------
+namespace {
+
+int run_blocks(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void* in, void* out, int dtype,
+               ta_stream_t stream) {
+  if (!c) return fail(TA_EINVAL, "null context");
+  if (n < 0) return fail(TA_EINVAL, "negative block count");
+  if (dtype != TA_I16 && dtype != TA_F32) return fail(TA_EINVAL, "unknown dtype %d", dtype);
+  if (dtype != TA_I16) return fail(TA_EUNSUPPORTED, "block lists run in fixed point (int16) only");
+  if (n == 0) return TA_OK;
+  if (!blocks || !in || !out) return fail(TA_EINVAL, "null buffer");
+  if (in == out) return fail(TA_EINVAL, "input and output alias");
+  if ((uintptr_t)blocks & 7) return fail(TA_EINVAL, "descriptors must be 8-byte aligned");
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
+  const void* fn = ta::batch_kernel(inv, 1);
+  int resident = 0, e;
+  if ((e = resident_groups(fn, 256, c->device, &resident))) return e;
+  const int64_t windows = (n + ta::kDescWindow - 1) / ta::kDescWindow;
+  // every XCD range needs a workgroup: at least kXcds groups
+  const int64_t g = std::max<int64_t>(ta::kXcds, std::min<int64_t>(windows, resident));
+  ta::BatchArgs args{};
+  args.tiles = nullptr;
+  args.ntiles = 0;
+  args.blocks = blocks;
+  args.in = static_cast<const int16_t*>(in);
+  args.out = static_cast<int16_t*>(out);
+  args.bd = c->bd;
+  args.m = c->m;
+  args.a = c->a;
+  args.axes = c->axes_dev;
+  args.nblocks = n;
+  void* kargs[] = {&args};
+  TA_HIP(hipSetDevice(c->device));
+  TA_HIP(hipLaunchKernel(fn, dim3((unsigned)g), dim3(256), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
+  return TA_OK;
+}
+
+// Last element (exclusive) a block touches at (off, stride), or -1 past `limit`.
+int64_t block_end(int64_t off, int32_t stride, int w, int h, int64_t limit) {
+  if (off > limit) return -1;
+  const int64_t end = off + (int64_t)(h - 1) * stride + w;   // off <= limit < 2^63 - 2^37
+  return end > limit ? -1 : end;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ta_transform_fwd(ta_ctx* c, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out, int dtype,
+                     ta_stream_t stream) {
+  return run_blocks(c, 0, blocks_dev, nblocks, in, out, dtype, stream);
+}
+
+int ta_transform_inv(ta_ctx* c, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out, int dtype,
+                     ta_stream_t stream) {
+  return run_blocks(c, 1, blocks_dev, nblocks, in, out, dtype, stream);
+}
+
+int ta_validate_blocks(ta_ctx* c, const ta_block* blocks_dev, int64_t n, int64_t in_elems, int64_t out_elems,
+                       int64_t* first_bad) {
+  if (!c || !first_bad) return fail(TA_EINVAL, "null argument");
+  *first_bad = -1;
+  if (n < 0 || in_elems < 0 || out_elems < 0) return fail(TA_EINVAL, "negative count");
+  if (n == 0) return TA_OK;
+  if (!blocks_dev) return fail(TA_EINVAL, "null descriptors");
+  if (in_elems > ((int64_t)1 << 62) || out_elems > ((int64_t)1 << 62)) return fail(TA_EINVAL, "buffer size above 2^62");
+  std::vector<ta_block> host((size_t)n);
+  TA_HIP(hipSetDevice(c->device));
+  TA_HIP(hipMemcpy(host.data(), blocks_dev, (size_t)n * sizeof(ta_block), hipMemcpyDeviceToHost));
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (int64_t i = 0; i < n; ++i) {
+    const ta_block& b = host[(size_t)i];
+    Resolved rh, rv;
+    int kh, kv, e;
+    if ((e = check_block(c, b, i, &rh, &rv, &kh, &kv))) {
+      *first_bad = i;
+      return e;
+    }
+    const int w = 1 << b.log2w, h = 1 << b.log2h;
+    if (block_end(b.in_off, b.in_stride, w, h, in_elems) < 0 || block_end(b.out_off, b.out_stride, w, h, out_elems) < 0) {
+      *first_bad = i;
+      return fail(TA_EINVAL, "block %lld: extends past the input (%lld elements) or output (%lld elements)",
+                  (long long)i, (long long)in_elems, (long long)out_elems);
+    }
+  }
+  return TA_OK;
+}
+
+int ta_set_axis_cfg(ta_ctx* c, int axis_id, const ta_axis_cfg* cfg) {
+  if (!c || !cfg) return fail(TA_EINVAL, "null argument");
+  if (cfg->adj == TA_ADJ_NONE) {
+    if (cfg->log2n != 0 && (cfg->log2n < 2 || cfg->log2n > 6)) return fail(TA_EUNSUPPORTED, "log2n %d", cfg->log2n);
+    if (cfg->k_or_b != 0) return fail(TA_EINVAL, "an axis without adjustment has no K or B");
+  } else {
+    if (cfg->param_id < 0 || cfg->param_id >= kMaxIds) return fail(TA_EINVAL, "parameter id %d outside 0..255", cfg->param_id);
+    const ParamSet& ps = c->params[cfg->param_id];
+    if (ps.kind != cfg->adj) return fail(TA_ENOPARAMS, "parameter set %d not registered for this adjustment", cfg->param_id);
+    if (cfg->log2n != 0 && (1 << std::min(std::max(cfg->log2n, 0), 30)) != ps.n)
+      return fail(TA_EINVAL, "log2n %d does not match parameter set %d (size %d)", cfg->log2n, cfg->param_id, ps.n);
+    if (cfg->k_or_b != 0 && cfg->k_or_b != ps.kb)
+      return fail(TA_EINVAL, "K/B %d does not match parameter set %d (%d)", cfg->k_or_b, cfg->param_id, ps.kb);
+  }
+  const ta_axis ax{cfg->base, cfg->adj, cfg->flip, cfg->param_id};
+  return ta_set_axis(c, axis_id, &ax);
+}
+
+int ta_set_params(ta_ctx* c, int param_id, const int16_t* int_taps, const float* f32_params, const int32_t* layout,
+                  int64_t n) {
+  if (!c || !layout) return fail(TA_EINVAL, "null argument");
+  const int adj = layout[0], size = layout[1], kb = layout[2];
+  if (adj == TA_ADJ_BAND) {
+    if (size < 1 || size > 64 || n != (int64_t)size * size)
+      return fail(TA_EINVAL, "band of size %d takes %d x %d entries, got %lld", size, size, size, (long long)n);
+    return ta_set_band(c, param_id, size, kb, int_taps, f32_params);
+  }
+  if (adj == TA_ADJ_POST) {
+    if (kb < 1 || kb > 64 || n != (int64_t)kb * kb)
+      return fail(TA_EINVAL, "sub-block of side %d takes %d x %d entries, got %lld", kb, kb, kb, (long long)n);
+    return ta_set_post(c, param_id, size, kb, int_taps, f32_params);
+  }
+  return fail(TA_EINVAL, "layout kind %d is not a band or sub-block adjustment", adj);
 }
 
 }  // extern "C"

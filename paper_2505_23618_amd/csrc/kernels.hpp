@@ -92,6 +92,20 @@ struct BatchGeo {
   }
 };
 
+// What one axis id means at one block size, for kernels that read block
+// descriptors directly: the batched kind (0 DCT-2, 1 adjusted DST-7,
+// 2 adjusted DCT-8; -1 not usable at this size) and its band taps.
+struct AxisDev {
+  int32_t kind;
+  int32_t pad;
+  const uint32_t* pf;
+  const uint32_t* pi;
+};
+constexpr int kAxisIds = 256;
+constexpr int kAxisSizes = 7;   // indexed by log2 of the size (2..6 used)
+// descriptors per window of the block-list kernels (one workgroup step)
+constexpr int kDescWindow = 64;
+
 struct BatchArgs {
   const BatchTile* tiles;
   int64_t ntiles;
@@ -100,10 +114,15 @@ struct BatchArgs {
   const int16_t* in;
   int16_t* out;
   int bd, m, a;
+  // unplanned block lists (ta_transform_fwd / _inv): descriptors are read as
+  // they are, grouped into tiles on the device
+  const AxisDev* axes;    // kAxisIds x kAxisSizes
+  int64_t nblocks;
 };
 
-// Persistent batched kernels over a planned tile list (batch_kernels.hip).
-const void* batch_kernel(int inv);
+// Persistent batched kernels (batch_kernels.hip): over a planned tile list
+// (desc = 0) or directly over a device array of block descriptors (desc = 1).
+const void* batch_kernel(int inv, int desc = 0);
 
 // Encoder evaluation of the five separable transforms (multi_kernels.hip):
 // out holds 5 consecutive packed batches of nblocks N x N int16 blocks.

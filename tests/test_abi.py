@@ -69,3 +69,21 @@ def test_design_search_argument_checks_without_gpu():
     lib = ta.lib()
     assert lib.ta_design_search(None, 8, 1, None, 1, None, None, 1, 0.01, 1.0, None, None, None,
                                 None) == ta.TA_EINVAL
+
+
+def test_block_list_entry_points_reject_bad_arguments_without_gpu():
+    lib = ta.lib()
+    bad = ctypes.c_int64(7)
+    assert lib.ta_transform_fwd(None, None, 1, None, None, ta.I16, None) == ta.TA_EINVAL
+    assert lib.ta_transform_inv(None, None, 1, None, None, ta.I16, None) == ta.TA_EINVAL
+    assert lib.ta_validate_blocks(None, None, 1, 0, 0, ctypes.byref(bad)) == ta.TA_EINVAL
+    assert lib.ta_set_axis_cfg(None, 0, None) == ta.TA_EINVAL
+    lay = np.array([ta.ADJ_BAND, 8, 4], np.int32)
+    a = np.zeros(64, np.int16)
+    f = np.zeros(64, np.float32)
+    assert lib.ta_set_params(None, 0, a.ctypes.data, f.ctypes.data, lay.ctypes.data, 64) == ta.TA_EINVAL
+
+
+def test_axis_cfg_struct_layout():
+    assert ctypes.sizeof(ta._AxisCfg) == 24
+    assert ctypes.sizeof(ta._Axis) == 16

@@ -1,0 +1,245 @@
+"""GPU parity of the unplanned block-list entry points (ta_transform_fwd /
+_inv over descriptors in device memory) against the oracle, bit-exact; the
+descriptor validator; descriptors the kernel skips; graph replay; and the
+layout-triple registration calls."""
+
+import numpy as np
+import pytest
+
+import synth
+from tests.batchcase import axis_id, descriptors, oracle_frames, register_axes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2505_23618_amd as ta  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def env():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = ta.Context(0)
+    ids = ta.load_params(ctx)
+    register_axes(ctx, ids)
+    return ctx, ids, ta.load_param_file()
+
+
+def small_workload():
+    # 2 frames of 448 x 200 with a ragged CTU row; all 25 block sizes occur
+    return synth.frames_workload(nframes=2, width=448, height=200, seed=30)
+
+
+def run(ctx, d, frames, inverse=False, sentinel=None):
+    x = torch.from_numpy(frames).cuda()
+    y = torch.zeros_like(x) if sentinel is None else torch.full_like(x, sentinel)
+    dev = ctx.blocks_to_device(d)
+    (ctx.transform_inv if inverse else ctx.transform_fwd)(dev, x, y)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+@pytest.mark.parametrize("order", ["frame", "shuffled", "by_size"])
+def test_unplanned_forward_inverse_bit_exact(env, order):
+    ctx, _, params = env
+    frames, rows = small_workload()
+    print(f"{len(rows)} blocks, order {order}", flush=True)
+    if order == "shuffled":
+        rows = rows[np.random.Generator(np.random.PCG64(5)).permutation(len(rows))]
+    elif order == "by_size":
+        rows = rows[np.lexsort((rows[:, 6], rows[:, 5], rows[:, 4], rows[:, 3]))]
+    d = descriptors(rows, frames.shape[1], frames.shape[2])
+    ref = oracle_frames(frames, rows, params)
+    got = run(ctx, d, frames)
+    mism = np.argwhere(got != ref)
+    assert mism.size == 0, f"{len(mism)} mismatches, first {mism[:3].tolist()}"
+    refi = oracle_frames(got, rows, params, inverse=True)
+    assert (run(ctx, d, got, inverse=True) == refi).all()
+
+
+def test_unplanned_equals_plan_on_full_range_values(env):
+    ctx, _, params = env
+    frames, rows = small_workload()
+    full = np.random.Generator(np.random.PCG64(3)).integers(-32768, 32768, size=frames.shape).astype(np.int16)
+    d = descriptors(rows, frames.shape[1], frames.shape[2])
+    plan = ta.Plan(ctx, d)
+    x = torch.from_numpy(full).cuda()
+    yp, zp = torch.zeros_like(x), torch.zeros_like(x)
+    plan.fwd(x, yp)
+    plan.inv(x, zp)
+    torch.cuda.synchronize()
+    assert (run(ctx, d, full) == yp.cpu().numpy()).all()
+    assert (run(ctx, d, full, inverse=True) == zp.cpu().numpy()).all()
+    assert (yp.cpu().numpy() == oracle_frames(full, rows, params)).all()
+
+
+def test_skipped_descriptors_leave_output_untouched(env):
+    ctx, _, params = env
+    frames, rows = small_workload()
+    d = descriptors(rows, frames.shape[1], frames.shape[2])
+    # every defect below is one the kernel checks before touching any buffer
+    planted = {}
+    rng = np.random.Generator(np.random.PCG64(9))
+    picks = rng.choice(len(d), 6, replace=False)
+    defects = ["size", "misaligned", "stride", "axis_range", "unregistered", "negative"]
+    for i, kind in zip(picks, defects):
+        planted[int(i)] = kind
+        if kind == "size":
+            d["log2w"][i] = 7
+        elif kind == "misaligned":
+            d["in_off"][i] += 2
+        elif kind == "stride":
+            d["in_stride"][i] = (1 << int(d["log2w"][i])) - 4
+        elif kind == "axis_range":
+            d["axis_v"][i] = 300
+        elif kind == "unregistered":
+            d["axis_h"][i] = 250
+        elif kind == "negative":
+            d["out_off"][i] = -8
+    got = run(ctx, d, frames, sentinel=12345)
+    ref = oracle_frames(frames, rows, params)
+    for i in range(len(rows)):
+        f, bx, by, w, h = (int(v) for v in rows[i, :5])
+        blk = got[f, by:by + h, bx:bx + w]
+        if i in planted:
+            assert (blk == 12345).all(), f"planted {planted[i]} at {i} was written"
+        else:
+            assert (blk == ref[f, by:by + h, bx:bx + w]).all(), f"block {i}"
+
+
+def test_validate_blocks_names_the_first_bad_descriptor(env):
+    ctx, _, _ = env
+    frames, rows = small_workload()
+    d = descriptors(rows, frames.shape[1], frames.shape[2])
+    total = frames.size
+    assert ctx.validate_blocks(ctx.blocks_to_device(d), total, total) == (-1, "")
+    bad = d.copy()
+    bad["out_off"][41] = total - 8               # rows 1.. fall past the output
+    bad["in_off"][97] += 4 if bad["log2w"][97] >= 3 else 2
+    idx, msg = ctx.validate_blocks(ctx.blocks_to_device(bad), total, total)
+    assert idx == 41 and "past" in msg
+    bad["out_off"][41] = d["out_off"][41]
+    idx, msg = ctx.validate_blocks(ctx.blocks_to_device(bad), total, total)
+    assert idx == 97 and "multiples" in msg
+    bad = d.copy()
+    bad["axis_h"][5] = 250
+    idx, msg = ctx.validate_blocks(ctx.blocks_to_device(bad), total, total)
+    assert idx == 5 and "not registered" in msg
+    assert ctx.validate_blocks(ctx.blocks_to_device(d), total - 1, total)[0] >= 0
+    assert ctx.validate_blocks(ctx.blocks_to_device(d[:0]), 0, 0) == (-1, "")
+
+
+def test_graph_replay(env):
+    ctx, _, params = env
+    frames, rows = small_workload()
+    d = descriptors(rows, frames.shape[1], frames.shape[2])
+    dev = ctx.blocks_to_device(d)
+    x = torch.from_numpy(frames).cuda()
+    y, z = torch.zeros_like(x), torch.zeros_like(x)
+    ctx.transform_fwd(dev, x, y)                 # eager first: occupancy query outside the capture
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            ctx.transform_fwd(dev, x, y, stream_handle=s.cuda_stream)
+            ctx.transform_inv(dev, y, z, stream_handle=s.cuda_stream)
+    ref = oracle_frames(frames, rows, params)
+    refi = oracle_frames(ref.astype(np.int16), rows, params, inverse=True)
+    for rep in range(3):
+        y.fill_(7)
+        z.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert (y.cpu().numpy() == ref).all(), f"replay {rep} forward"
+        assert (z.cpu().numpy() == refi).all(), f"replay {rep} inverse"
+
+
+def test_reregistered_axis_is_seen_by_the_next_call(env):
+    _, ids, params = env
+    ctx = ta.Context(0)
+    ta.load_params(ctx)
+    register_axes(ctx, ids)
+    frames, rows = small_workload()
+    d = descriptors(rows, frames.shape[1], frames.shape[2])
+    assert (run(ctx, d, frames) == oracle_frames(frames, rows, params)).all()
+    # DCT-2 axis ids now name the adjusted DST-7 of their size
+    for n in (4, 8, 16, 32, 64):
+        ctx.axis(axis_id(0, n), ta.DST3, ta.ADJ_BAND, False, ids[f"band_S3_S7_N{n}_K4"])
+    swapped = rows.copy()
+    swapped[:, 5:7][swapped[:, 5:7] == 0] = 1
+    assert (run(ctx, d, frames) == oracle_frames(frames, swapped, params)).all()
+    ctx.close()
+
+
+def test_layout_triple_registration_matches_set_band(env):
+    _, ids, params = env
+    ctx = ta.Context(0)
+    ta.load_params(ctx)
+    register_axes(ctx, ids)
+    frames, rows = small_workload()
+    d = descriptors(rows, frames.shape[1], frames.shape[2])
+    ref = run(ctx, d, frames)
+    # the same bands again, through ta_set_params and ta_set_axis_cfg
+    for n in (4, 8, 16, 32, 64):
+        e = params[f"band_S3_S7_N{n}_K4"]
+        ctx.set_params(200 + int(np.log2(n)), (ta.ADJ_BAND, n, 4), np.asarray(e["a_int"]), np.asarray(e["a_f64"]))
+        ln = int(np.log2(n))
+        for t in (1, 2):
+            ctx.axis_cfg(axis_id(t, n), ta.DST3, ta.ADJ_BAND, t == 2, ln, 4, 200 + ln)
+    assert (run(ctx, d, frames) == ref).all()
+    with pytest.raises(ta.TadjError) as e:
+        ctx.axis_cfg(10, ta.DST3, ta.ADJ_BAND, False, 4, 4, 205)     # set 205 is 32-point
+    assert e.value.code == ta.TA_EINVAL
+    with pytest.raises(ta.TadjError) as e:
+        ctx.axis_cfg(10, ta.DST3, ta.ADJ_BAND, False, 5, 6, 205)     # set 205 has 4 taps
+    assert e.value.code == ta.TA_EINVAL
+    with pytest.raises(ta.TadjError) as e:
+        ctx.set_params(199, (ta.ADJ_BAND, 32, 4), np.zeros(64), np.zeros(64))
+    assert e.value.code == ta.TA_EINVAL
+    ctx.close()
+
+
+def test_call_errors(env):
+    ctx, _, _ = env
+    frames, rows = small_workload()
+    d = descriptors(rows[:8], frames.shape[1], frames.shape[2])
+    dev = ctx.blocks_to_device(d)
+    x = torch.from_numpy(frames).cuda()
+    y = torch.zeros_like(x)
+    L = ta.lib()
+    import ctypes
+    vp = ctypes.c_void_p
+    assert L.ta_transform_fwd(ctx._h, vp(dev.data_ptr()), 8, vp(x.data_ptr()), vp(y.data_ptr()), ta.F32,
+                              None) == ta.TA_EUNSUPPORTED
+    assert L.ta_transform_fwd(ctx._h, vp(dev.data_ptr()), 8, vp(x.data_ptr()), vp(x.data_ptr()), ta.I16,
+                              None) == ta.TA_EINVAL
+    assert L.ta_transform_fwd(ctx._h, vp(dev.data_ptr()), -1, vp(x.data_ptr()), vp(y.data_ptr()), ta.I16,
+                              None) == ta.TA_EINVAL
+    assert L.ta_transform_fwd(ctx._h, vp(dev.data_ptr() + 4), 7, vp(x.data_ptr()), vp(y.data_ptr()), ta.I16,
+                              None) == ta.TA_EINVAL
+    assert L.ta_transform_inv(ctx._h, None, 0, None, None, ta.I16, None) == ta.TA_OK
+
+
+def test_full_workload_sampled(env):
+    """8 frames of 3840 x 2160 in frame order, unplanned; sampled blocks."""
+    ctx, _, params = env
+    frames, rows = synth.frames_workload()
+    print(f"full workload unplanned: {len(rows)} blocks", flush=True)
+    d = descriptors(rows, frames.shape[1], frames.shape[2])
+    dev = ctx.blocks_to_device(d)
+    x = torch.from_numpy(frames).cuda()
+    y, z = torch.zeros_like(x), torch.zeros_like(x)
+    ctx.transform_fwd(dev, x, y)
+    ctx.transform_inv(dev, y, z)
+    torch.cuda.synchronize()
+    sel = np.random.Generator(np.random.PCG64(12)).choice(len(rows), 300, replace=False)
+    ref = oracle_frames(frames, rows, params, select=sel)
+    yc = y.cpu().numpy()
+    refi = oracle_frames(yc, rows, params, inverse=True, select=sel)
+    zc = z.cpu().numpy()
+    for i in sel:
+        f, bx, by, w, h = (int(v) for v in rows[i, :5])
+        assert (yc[f, by:by + h, bx:bx + w] == ref[f, by:by + h, bx:bx + w]).all(), f"block {i}"
+        assert (zc[f, by:by + h, bx:bx + w] == refi[f, by:by + h, bx:bx + w]).all(), f"block {i} inverse"
