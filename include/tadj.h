@@ -207,11 +207,12 @@ int ta_plan_autotune(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_s
 
 /* Unplanned block lists.  ta_transform_fwd / _inv run nblocks descriptors
  * that are already in device memory (blocks_dev, 8-byte aligned, read as
- * they are, e.g. written by an earlier kernel) as one persistent launch: the
- * list is cut into windows of 64 consecutive descriptors, and runs of
- * consecutive descriptors with the same size and axis ids inside a window
- * become one tile, so lists sorted by (size, axes) within each window run
- * fastest; a plan (ta_plan_create) does that grouping on the host once.  The
+ * they are, e.g. written by an earlier kernel) in one launch: the list is cut
+ * into windows of 1024 consecutive descriptors, and the descriptors of equal
+ * size and axis ids inside a window are grouped (in list order) into tiles
+ * of up to 64 blocks.  Throughput grows with the number of equal
+ * configurations per window; a plan (ta_plan_create) groups the whole list
+ * on the host once and runs fastest.  The
  * descriptor rules and transforms are those of the plans (int16, DCT-2 or
  * DST-3 + 4-tap band axes; axes resolve through the context at launch time,
  * so a parameter set registered again is seen by the next call).  A

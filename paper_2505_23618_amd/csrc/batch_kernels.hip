@@ -39,7 +39,6 @@ struct BDesc {
   int32_t in_stride, out_stride;
 };
 constexpr int kMaxTileBlocks = 64;
-static_assert(kMaxTileBlocks == kDescWindow, "a descriptor window is one tile's block buffer");
 static_assert(kBatchLds * 4 <= 20480, "tile LDS above 20 KiB");
 
 template <int W>
@@ -59,11 +58,12 @@ TA_DEV void load_strided_row(const int16_t* __restrict__ src, fx::Packed<W>& x) 
 // ---------------------------------------------------------------- forward
 // row phase of one tile for kind KH at width W (H = 2^lh rows per block)
 template <int W, class KH>
-TA_DEV void fwd_rows(const BatchArgs& a, const BatchTile& t, uint16_t* pch, BDesc* desc, int s_row) {
+TA_DEV void fwd_rows(const BatchArgs& a, const BatchTile& t, const ta_block* blocks, uint16_t* pch, BDesc* desc,
+                      int s_row) {
   const int tid = threadIdx.x;
   if (tid >= (t.count << t.lh)) return;
   const int b = tid >> t.lh, r = tid & ((1 << t.lh) - 1);
-  const ta_block d = a.blocks[t.first + b];
+  const ta_block d = blocks[t.first + b];
   if (r == 0) desc[b] = BDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
   fx::Packed<W> x;
   load_strided_row<W>(a.in + d.in_off + (int64_t)r * d.in_stride, x);
@@ -105,13 +105,14 @@ TA_DEV void fwd_cols(const BatchArgs& a, const BatchTile& t, uint32_t* lds, int 
 }
 
 template <class KH>
-TA_DEV void fwd_rows_w(const BatchArgs& a, const BatchTile& t, uint16_t* pch, BDesc* desc, int s) {
+TA_DEV void fwd_rows_w(const BatchArgs& a, const BatchTile& t, const ta_block* blocks, uint16_t* pch, BDesc* desc,
+                        int s) {
   switch (t.lw) {
-    case 2: fwd_rows<4, KH>(a, t, pch, desc, s); break;
-    case 3: fwd_rows<8, KH>(a, t, pch, desc, s); break;
-    case 4: fwd_rows<16, KH>(a, t, pch, desc, s); break;
-    case 5: fwd_rows<32, KH>(a, t, pch, desc, s); break;
-    default: fwd_rows<64, KH>(a, t, pch, desc, s); break;
+    case 2: fwd_rows<4, KH>(a, t, blocks, pch, desc, s); break;
+    case 3: fwd_rows<8, KH>(a, t, blocks, pch, desc, s); break;
+    case 4: fwd_rows<16, KH>(a, t, blocks, pch, desc, s); break;
+    case 5: fwd_rows<32, KH>(a, t, blocks, pch, desc, s); break;
+    default: fwd_rows<64, KH>(a, t, blocks, pch, desc, s); break;
   }
 }
 
@@ -140,13 +141,13 @@ struct Chunk {
 
 // One tile of the forward: rows -> pair-row LDS -> columns -> row-major LDS
 // -> coalesced stores.  Ends with a barrier (LDS free for the next tile).
-TA_DEV void fwd_tile(const BatchArgs& a, const BatchTile& t, uint32_t* lds, BDesc* desc) {
+TA_DEV void fwd_tile(const BatchArgs& a, const BatchTile& t, const ta_block* blocks, uint32_t* lds, BDesc* desc) {
   uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
   const int s_row = t.lw + a.bd + a.m - 15, s_col = t.lh + a.m;
   switch (t.kind_h) {
-    case 0: fwd_rows_w<KC2>(a, t, pch, desc, s_row); break;
-    case 1: fwd_rows_w<KS3>(a, t, pch, desc, s_row); break;
-    default: fwd_rows_w<KC3>(a, t, pch, desc, s_row); break;
+    case 0: fwd_rows_w<KC2>(a, t, blocks, pch, desc, s_row); break;
+    case 1: fwd_rows_w<KS3>(a, t, blocks, pch, desc, s_row); break;
+    default: fwd_rows_w<KC3>(a, t, blocks, pch, desc, s_row); break;
   }
   __syncthreads();
   switch (t.kind_v) {
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
   const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
   const int64_t end = a.xstart[xcd + 1];
   for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd)
-    fwd_tile(a, a.tiles[ti], lds, desc);
+    fwd_tile(a, a.tiles[ti], a.blocks, lds, desc);
 }
 
 // ---------------------------------------------------------------- inverse
@@ -265,13 +266,13 @@ TA_DEV void inv_rows_w(const BatchArgs& a, const BatchTile& t, uint16_t* rm, int
 
 // One tile of the inverse: coalesced loads -> pair-row LDS -> columns ->
 // row-major LDS -> rows in place -> coalesced stores.  Ends with a barrier.
-TA_DEV void inv_tile(const BatchArgs& a, const BatchTile& t, uint32_t* lds, BDesc* desc) {
+TA_DEV void inv_tile(const BatchArgs& a, const BatchTile& t, const ta_block* blocks, uint32_t* lds, BDesc* desc) {
   uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
   const int s_col = a.m + 1, s_row = a.m + 14 - a.bd;
   const int lch = t.lw >= 3 ? 3 : 2;
   const int nch = t.count << (t.lw + t.lh - lch);
   if ((int)threadIdx.x < t.count) {
-    const ta_block d = a.blocks[t.first + threadIdx.x];
+    const ta_block d = blocks[t.first + threadIdx.x];
     desc[threadIdx.x] = BDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
   }
   __syncthreads();
@@ -335,61 +336,98 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
   const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
   const int64_t end = a.xstart[xcd + 1];
   for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd)
-    inv_tile(a, a.tiles[ti], lds, desc);
+    inv_tile(a, a.tiles[ti], a.blocks, lds, desc);
 }
 
 // ---------------------------------------------------------------- block lists
-// Unplanned: the descriptor list is cut into windows of kMaxTileBlocks
-// consecutive descriptors and the windows into kXcds contiguous ranges, one
-// per XCD (workgroup b runs on XCD b mod kXcds), so that neighbouring blocks
-// of a list in frame order share their L2; within its range a workgroup takes
-// every per_xcd-th window.  Each descriptor's size and axis ids resolve
-// through the context's axis table; runs of consecutive descriptors with the
-// same configuration become tiles of up to BatchGeo::nb_for blocks, processed
-// in order.  A descriptor that the planner would reject (size outside 4..64,
-// negative offset, stride below the width, offsets or strides not multiples
-// of the vector width, an axis with no batched kind at its size) is skipped:
-// its output is left untouched.
+// Unplanned: the descriptor list is cut into sort windows of kSortWin
+// consecutive descriptors, each handled by kSortWin / kDescWindow workgroups
+// ("quarters").  Every quarter sorts the whole window in LDS by
+// (configuration, position) with a bitonic network, which groups the
+// window's descriptors of equal size and axis ids in list order, and then
+// runs its own kDescWindow sorted entries as tiles of up to BatchGeo::nb_for
+// blocks.  The quarters of all windows are split into kXcds contiguous
+// ranges, one per XCD (workgroup b runs on XCD b mod kXcds), so that
+// neighbouring blocks of a list in frame order share their L2.  A descriptor
+// that the planner would reject (size outside 4..64, negative offset, stride
+// below the width, offsets or strides not multiples of the vector width, an
+// axis id outside the table or with no batched kind at its size) sorts last
+// and is skipped: its output is left untouched.
+constexpr int kSortWin = 1024;
+constexpr int kQuarters = kSortQuarters;
+static_assert(kSortWin == kDescWindow * kSortQuarters, "sort window");
+static_assert(kDescWindow == 256 && kSortWin % kDescWindow == 0, "one sorted entry per thread of a quarter");
+static_assert(kAxisIds <= 256, "axis ids take 8 key bits");
+
+// 22-bit configuration key of a descriptor, or -1 when it breaks a rule
+TA_DEV int config_key(const BatchArgs& a, const ta_block& d) {
+  const int ch = d.log2w >= 3 ? 8 : 4;                  // elements per vector access
+  if (d.log2w < 2 || d.log2w > 6 || d.log2h < 2 || d.log2h > 6 || d.in_off < 0 || d.out_off < 0 ||
+      d.in_stride < (1 << d.log2w) || d.out_stride < (1 << d.log2w) || d.axis_h >= kAxisIds ||
+      d.axis_v >= kAxisIds || ((d.in_off | d.out_off | (int64_t)d.in_stride | (int64_t)d.out_stride) & (ch - 1)))
+    return -1;
+  if (a.axes[d.axis_h * kAxisSizes + d.log2w].kind < 0 || a.axes[d.axis_v * kAxisSizes + d.log2h].kind < 0) return -1;
+  return d.log2w | (d.log2h << 3) | (d.axis_h << 6) | (d.axis_v << 14);
+}
+
 template <bool INV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_desc(BatchArgs a) {
   __shared__ __align__(16) uint32_t lds[kBatchLds];
   __shared__ BDesc desc[kMaxTileBlocks];
-  __shared__ int64_t key[kMaxTileBlocks];
+  __shared__ uint32_t skey[kSortWin];            // (configuration << 10 | position), sorted
+  __shared__ ta_block qdesc[kDescWindow];        // this quarter's descriptors, in sorted order
+  constexpr uint32_t kInvalid = ~0u;             // above every valid key (lw <= 6)
   const int tid = threadIdx.x;
   const int xcd = blockIdx.x % kXcds;
   const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;   // >= 1: the grid has >= kXcds groups
-  const int64_t nwin = (a.nblocks + kMaxTileBlocks - 1) / kMaxTileBlocks;
-  const int64_t wend = nwin * (xcd + 1) / kXcds;
-  for (int64_t w = nwin * xcd / kXcds + blockIdx.x / kXcds; w < wend; w += per_xcd) {
-    const int64_t w0 = w * kMaxTileBlocks;
-    const int cnt = (int)min<int64_t>(kMaxTileBlocks, a.nblocks - w0);
-    if (tid < cnt) {
-      const ta_block d = a.blocks[w0 + tid];
-      int64_t k = -1;
-      const int ch = d.log2w >= 3 ? 8 : 4;         // elements per vector access
-      if (d.log2w >= 2 && d.log2w <= 6 && d.log2h >= 2 && d.log2h <= 6 && d.in_off >= 0 && d.out_off >= 0 &&
-          d.in_stride >= (1 << d.log2w) && d.out_stride >= (1 << d.log2w) && d.axis_h < kAxisIds &&
-          d.axis_v < kAxisIds && ((d.in_off | d.out_off | (int64_t)d.in_stride | (int64_t)d.out_stride) & (ch - 1)) == 0) {
-        const AxisDev& h = a.axes[d.axis_h * kAxisSizes + d.log2w];
-        const AxisDev& v = a.axes[d.axis_v * kAxisSizes + d.log2h];
-        if (h.kind >= 0 && v.kind >= 0)
-          k = (int64_t)d.log2w | ((int64_t)d.log2h << 3) | ((int64_t)d.axis_h << 6) | ((int64_t)d.axis_v << 22);
+  const int64_t nunits = (a.nblocks + kSortWin - 1) / kSortWin * kQuarters;
+  const int64_t uend = nunits * (xcd + 1) / kXcds;
+  for (int64_t u = nunits * xcd / kXcds + blockIdx.x / kXcds; u < uend; u += per_xcd) {
+    const int64_t w0 = u / kQuarters * kSortWin;
+    const int q0 = (int)(u % kQuarters) * kDescWindow;
+    const int cnt = (int)min<int64_t>(kSortWin, a.nblocks - w0);
+#pragma unroll
+    for (int r = 0; r < kQuarters; ++r) {
+      const int i = tid + r * 256;
+      uint32_t sk = kInvalid;
+      if (i < cnt) {
+        const int k = config_key(a, a.blocks[w0 + i]);
+        if (k >= 0) sk = ((uint32_t)k << 10) | (uint32_t)i;
       }
-      key[tid] = k;
+      skey[i] = sk;
     }
+    // ascending bitonic sort; the position in the low bits makes every key
+    // distinct, so equal configurations keep list order
+#pragma unroll 1
+    for (int k = 2; k <= kSortWin; k <<= 1)
+#pragma unroll 1
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSortWin / 512; ++r) {
+          const int pr = tid + r * 256;                        // pair index
+          const int lo = ((pr & ~(j - 1)) << 1) | (pr & (j - 1)), hi = lo + j;
+          const uint32_t x = skey[lo], y = skey[hi];
+          if ((x > y) == ((lo & k) == 0)) {
+            skey[lo] = y;
+            skey[hi] = x;
+          }
+        }
+      }
+    __syncthreads();
+    const int qcnt = min(kDescWindow, cnt - q0);
+    if (tid < qcnt && skey[q0 + tid] != kInvalid) qdesc[tid] = a.blocks[w0 + (skey[q0 + tid] & (kSortWin - 1))];
     __syncthreads();
     int j = 0;
-    while (j < cnt) {                 // every thread walks the same runs
-      const int64_t k = key[j];
-      if (k < 0) {
-        ++j;
-        continue;
-      }
+    while (j < qcnt) {                 // every thread walks the same runs
+      const uint32_t s0 = skey[q0 + j];
+      if (s0 == kInvalid) break;       // the rest are invalid too
+      const uint32_t k = s0 >> 10;
       const int lw = (int)(k & 7), lh = (int)((k >> 3) & 7);
-      const int ah = (int)((k >> 6) & 0xffff), av = (int)((k >> 22) & 0xffff);
+      const int ah = (int)((k >> 6) & 0xff), av = (int)((k >> 14) & 0xff);
       const int cap = BatchGeo::nb_for(lw, lh);
       int len = 1;
-      while (j + len < cnt && len < cap && key[j + len] == k) ++len;
+      while (j + len < qcnt && len < cap && (skey[q0 + j + len] >> 10) == k) ++len;
       const AxisDev& h = a.axes[ah * kAxisSizes + lw];
       const AxisDev& v = a.axes[av * kAxisSizes + lh];
       BatchTile t;
@@ -397,7 +435,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
       t.lh = lh;
       t.kind_h = h.kind;
       t.kind_v = v.kind;
-      t.first = w0 + j;
+      t.first = j;
       t.count = len;
       t.pad = 0;
       t.ph_f = h.pf;
@@ -405,12 +443,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
       t.pv_f = v.pf;
       t.pv_i = v.pi;
       if (INV)
-        inv_tile(a, t, lds, desc);
+        inv_tile(a, t, qdesc, lds, desc);
       else
-        fwd_tile(a, t, lds, desc);
+        fwd_tile(a, t, qdesc, lds, desc);
       j += len;
     }
-    __syncthreads();                  // keys of the next window
+    __syncthreads();                   // the window buffers are rewritten next
   }
 }
 

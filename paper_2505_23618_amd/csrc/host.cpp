@@ -721,11 +721,11 @@ int run_blocks(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void
   if ((uintptr_t)blocks & 7) return fail(TA_EINVAL, "descriptors must be 8-byte aligned");
   if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
   const void* fn = ta::batch_kernel(inv, 1);
-  int resident = 0, e;
-  if ((e = resident_groups(fn, 256, c->device, &resident))) return e;
-  const int64_t windows = (n + ta::kDescWindow - 1) / ta::kDescWindow;
-  // every XCD range needs a workgroup: at least kXcds groups
-  const int64_t g = std::max<int64_t>(ta::kXcds, std::min<int64_t>(windows, resident));
+  // one workgroup per quarter of a sort window (the dispatcher balances
+  // quarters of uneven cost), and at least one per XCD range
+  const int64_t sortwin = (int64_t)ta::kDescWindow * ta::kSortQuarters;
+  const int64_t units = (n + sortwin - 1) / sortwin * ta::kSortQuarters;
+  const int64_t g = std::max<int64_t>(ta::kXcds, std::min<int64_t>(units, 0x7fffffff));
   ta::BatchArgs args{};
   args.tiles = nullptr;
   args.ntiles = 0;

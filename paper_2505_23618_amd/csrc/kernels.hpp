@@ -103,8 +103,10 @@ struct AxisDev {
 };
 constexpr int kAxisIds = 256;
 constexpr int kAxisSizes = 7;   // indexed by log2 of the size (2..6 used)
-// descriptors per window of the block-list kernels (one workgroup step)
-constexpr int kDescWindow = 64;
+// descriptors per workgroup of the block-list kernels (one per thread), and
+// descriptors sorted together by kSortQuarters such workgroups
+constexpr int kDescWindow = 256;
+constexpr int kSortQuarters = 4;
 
 struct BatchArgs {
   const BatchTile* tiles;
