@@ -180,8 +180,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
   const int xcd = blockIdx.x % kXcds;
   const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
   const int64_t end = a.xstart[xcd + 1];
-  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd)
-    fwd_tile(a, a.tiles[ti], a.blocks, lds, desc);
+  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd) {
+    const BatchTile t = a.tiles[ti];   // a register copy: a reference would be re-read after every store
+    fwd_tile(a, t, a.blocks, lds, desc);
+  }
 }
 
 // ---------------------------------------------------------------- inverse
@@ -335,8 +337,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
   const int xcd = blockIdx.x % kXcds;
   const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
   const int64_t end = a.xstart[xcd + 1];
-  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd)
-    inv_tile(a, a.tiles[ti], a.blocks, lds, desc);
+  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd) {
+    const BatchTile t = a.tiles[ti];   // a register copy: a reference would be re-read after every store
+    inv_tile(a, t, a.blocks, lds, desc);
+  }
 }
 
 // ---------------------------------------------------------------- block lists
