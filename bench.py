@@ -277,7 +277,24 @@ def _batched(ctx, ids, res):
                              "unplanned_value": nco / (uf + ui), "unplanned_fwd_us": uf * 1e6,
                              "unplanned_inv_us": ui * 1e6,
                              "workload": "8 frames 3840x2160, QT/BT blocks 4..64, per-axis DCT-2 / adj. DST-7 / adj. DCT-8"}
-    del X, Y, Z, plan, dev
+    del X, Y, Z, plan
+    torch.cuda.empty_cache()
+    # the same frames in fp32 (orthonormal transforms), planned and unplanned
+    planf = ta.Plan(ctx, desc, dtype=ta.F32)
+    X = [torch.from_numpy(frames.astype(np.float32)).cuda() for _ in range(4)]
+    Y = [torch.empty_like(X[0]) for _ in range(4)]
+    Z = [torch.empty_like(X[0]) for _ in range(4)]
+    infof = planf.autotune(X[0], Y[0], reps=3)
+    tf = _events_mean(lambda i: planf.fwd(X[i % 4], Y[i % 4]), 12)
+    ti = _events_mean(lambda i: planf.inv(Y[i % 4], Z[i % 4]), 12)
+    uf = _events_mean(lambda i: ctx.transform_fwd(dev, X[i % 4], Y[i % 4]), 12)
+    ui = _events_mean(lambda i: ctx.transform_inv(dev, Y[i % 4], Z[i % 4]), 12)
+    res["batched_uneven_f32"] = {"value": nco / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
+                                 "tiles": infof["tiles"], "grid": infof["grid"],
+                                 "GB/s_fwd": (8 * nco + 32 * len(rows)) / tf / 1e9,
+                                 "unplanned_value": nco / (uf + ui), "unplanned_fwd_us": uf * 1e6,
+                                 "unplanned_inv_us": ui * 1e6}
+    del X, Y, Z, planf, dev
     torch.cuda.empty_cache()
 
 

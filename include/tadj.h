@@ -189,6 +189,9 @@ int ta_fwd_multi(ta_ctx* ctx, int param_id, int log2n, int64_t nblocks, const vo
  * block at (in_off, in_stride) of `in` and writes its coefficients at
  * (out_off, out_stride) of `out`; the inverse reads coefficients at
  * (in_off, in_stride) and writes residuals at (out_off, out_stride).
+ * dtype TA_I16 runs the fixed-point transforms (bit-exact), TA_F32 the
+ * orthonormal fp32 ones (the fp32 parameters of each set); in and out then
+ * hold int16 or float elements.
  * ta_plan_create copies the descriptors to device memory, grouped by
  * (size, kinds) into tiles (synchronous, allocates).  ta_plan_fwd/_inv run
  * the whole plan as one persistent kernel launch on the stream
@@ -213,7 +216,7 @@ int ta_plan_autotune(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_s
  * of up to 64 blocks.  Throughput grows with the number of equal
  * configurations per window; a plan (ta_plan_create) groups the whole list
  * on the host once and runs fastest.  The
- * descriptor rules and transforms are those of the plans (int16, DCT-2 or
+ * descriptor rules, transforms and dtypes are those of the plans (DCT-2 or
  * DST-3 + 4-tap band axes; axes resolve through the context at launch time,
  * so a parameter set registered again is seen by the next call).  A
  * descriptor that breaks a rule the kernel can check (size, offset sign and
@@ -222,8 +225,7 @@ int ta_plan_autotune(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_s
  * and blocks must not overlap in out; ta_validate_blocks checks a list.
  * in and out: 16-byte aligned device memory, not the same buffer.
  * Asynchronous on the stream, allocates nothing, capturable in a HIP graph.
- * Errors: TA_EINVAL (null, negative count, alignment, aliasing, dtype),
- * TA_EUNSUPPORTED (TA_F32). */
+ * Errors: TA_EINVAL (null, negative count, alignment, aliasing, dtype). */
 int ta_transform_fwd(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out,
                      int dtype, ta_stream_t stream);
 int ta_transform_inv(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out,

@@ -318,12 +318,14 @@ class Context:
     def _run_blocks(self, fn, blocks_dev, x, out, stream_handle):
         import torch
         n = self._nblocks(blocks_dev)
-        for t in (x, out):
-            if t.dtype != torch.int16 or not t.is_contiguous():
-                raise ValueError("block lists run on contiguous int16 buffers")
+        if x.dtype != out.dtype or x.dtype not in (torch.int16, torch.float32):
+            raise ValueError("block lists run on int16 (fixed point) or float32 buffers of one dtype")
+        if not (x.is_contiguous() and out.is_contiguous()):
+            raise ValueError("block lists need contiguous buffers")
+        dt = I16 if x.dtype == torch.int16 else F32
         sh = _stream_handle(None) if stream_handle is None else ctypes.c_void_p(stream_handle)
         _check(fn(self._h, ctypes.c_void_p(blocks_dev.data_ptr()), n, ctypes.c_void_p(x.data_ptr()),
-                  ctypes.c_void_p(out.data_ptr()), I16, sh))
+                  ctypes.c_void_p(out.data_ptr()), dt, sh))
         return out
 
     def transform_fwd(self, blocks_dev, x, out, stream_handle=None):

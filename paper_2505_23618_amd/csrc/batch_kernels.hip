@@ -19,6 +19,7 @@
 //
 // Kinds: 0 = DCT-2, 1 = DST-3 + 4-tap band (adjusted DST-7),
 //        2 = DCT-3 + 4-tap band with flipped taps (adjusted DCT-8, eq. 3).
+#include "fp.hpp"
 #include "fx.hpp"
 #include "kernels.hpp"
 
@@ -343,6 +344,195 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
   }
 }
 
+// ---------------------------------------------------------------- fp32 tiles
+// The same phases on fp32 data with the orthonormal fp32 stages (no
+// rounding), in the BatchGeoF32 layout: block b at b * BS, column-major
+// (pitch H + 1) between the row and column phases, row-major (pitch W + 1)
+// for the second phase's output and the coalesced float4 loads and stores.
+constexpr int kBatchLdsF32 = BatchGeoF32::kLds;
+
+TA_DEV const float* fparam(const uint32_t* p) { return reinterpret_cast<const float*>(p); }
+
+template <int W>
+TA_DEV void load_rowf(const float* __restrict__ src, fp::Vec<W>& x) {
+#pragma unroll
+  for (int q = 0; q < W / 4; ++q) {
+    const float4 v = reinterpret_cast<const float4*>(src)[q];
+    x.v[4 * q] = v.x; x.v[4 * q + 1] = v.y; x.v[4 * q + 2] = v.z; x.v[4 * q + 3] = v.w;
+  }
+}
+
+// forward row phase: global row -> transform -> column-major LDS
+template <int W, class KH>
+TA_DEV void fwd_rows_f(const BatchArgs& a, const BatchTile& t, const ta_block* blocks, float* lds, BDesc* desc) {
+  const int tid = threadIdx.x;
+  if (tid >= (t.count << t.lh)) return;
+  const int b = tid >> t.lh, r = tid & ((1 << t.lh) - 1), h1 = (1 << t.lh) + 1;
+  const ta_block d = blocks[t.first + b];
+  if (r == 0) desc[b] = BDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
+  fp::Vec<W> x;
+  load_rowf<W>(reinterpret_cast<const float*>(a.in) + d.in_off + (int64_t)r * d.in_stride, x);
+  const fp::Vec<W> y = fp::run_pass<W, KH, false>(x, fparam(t.ph_f), fparam(t.ph_i));
+  float* blk = lds + b * BatchGeoF32::bs(t.lw, t.lh) + r;
+#pragma unroll
+  for (int c = 0; c < W; ++c) blk[c * h1] = y.v[c];
+}
+
+// column phase (either direction): column-major LDS -> transform -> barrier
+// -> row-major LDS
+template <int H, class KV, bool INV>
+TA_DEV void cols_f(const BatchTile& t, float* lds) {
+  const int tid = threadIdx.x;
+  const bool act = tid < (t.count << t.lw);
+  const int b = tid >> t.lw, c = tid & ((1 << t.lw) - 1), w1 = (1 << t.lw) + 1;
+  float* blk = lds + b * BatchGeoF32::bs(t.lw, t.lh);
+  fp::Vec<H> z;
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < H; ++r) z.v[r] = blk[c * (H + 1) + r];
+    z = fp::run_pass<H, KV, INV>(z, fparam(t.pv_f), fparam(t.pv_i));
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < H; ++r) blk[r * w1 + c] = z.v[r];
+  }
+}
+
+// inverse row phase: row-major LDS row -> transform -> back over the row
+template <int W, class KH>
+TA_DEV void inv_rows_f(const BatchTile& t, float* lds) {
+  const int tid = threadIdx.x;
+  if (tid >= (t.count << t.lh)) return;
+  const int b = tid >> t.lh, r = tid & ((1 << t.lh) - 1);
+  float* row = lds + b * BatchGeoF32::bs(t.lw, t.lh) + r * (W + 1);
+  fp::Vec<W> x;
+#pragma unroll
+  for (int c = 0; c < W; ++c) x.v[c] = row[c];
+  const fp::Vec<W> y = fp::run_pass<W, KH, true>(x, fparam(t.ph_f), fparam(t.ph_i));
+#pragma unroll
+  for (int c = 0; c < W; ++c) row[c] = y.v[c];
+}
+
+template <class KH>
+TA_DEV void fwd_rows_fw(const BatchArgs& a, const BatchTile& t, const ta_block* blocks, float* lds, BDesc* desc) {
+  switch (t.lw) {
+    case 2: fwd_rows_f<4, KH>(a, t, blocks, lds, desc); break;
+    case 3: fwd_rows_f<8, KH>(a, t, blocks, lds, desc); break;
+    case 4: fwd_rows_f<16, KH>(a, t, blocks, lds, desc); break;
+    case 5: fwd_rows_f<32, KH>(a, t, blocks, lds, desc); break;
+    default: fwd_rows_f<64, KH>(a, t, blocks, lds, desc); break;
+  }
+}
+
+template <class KH>
+TA_DEV void inv_rows_fw(const BatchTile& t, float* lds) {
+  switch (t.lw) {
+    case 2: inv_rows_f<4, KH>(t, lds); break;
+    case 3: inv_rows_f<8, KH>(t, lds); break;
+    case 4: inv_rows_f<16, KH>(t, lds); break;
+    case 5: inv_rows_f<32, KH>(t, lds); break;
+    default: inv_rows_f<64, KH>(t, lds); break;
+  }
+}
+
+template <class KV, bool INV>
+TA_DEV void cols_fh(const BatchTile& t, float* lds) {
+  switch (t.lh) {
+    case 2: cols_f<4, KV, INV>(t, lds); break;
+    case 3: cols_f<8, KV, INV>(t, lds); break;
+    case 4: cols_f<16, KV, INV>(t, lds); break;
+    case 5: cols_f<32, KV, INV>(t, lds); break;
+    default: cols_f<64, KV, INV>(t, lds); break;
+  }
+}
+
+template <bool INV>
+TA_DEV void cols_f_kind(const BatchTile& t, float* lds) {
+  switch (t.kind_v) {
+    case 0: cols_fh<KC2, INV>(t, lds); break;
+    case 1: cols_fh<KS3, INV>(t, lds); break;
+    default: cols_fh<KC3, INV>(t, lds); break;
+  }
+}
+
+// Coalesced float4 stores of the tile from the row-major layout.
+TA_DEV void store_tile_f(const BatchArgs& a, const BatchTile& t, const float* lds, const BDesc* desc) {
+  const int lq = t.lw - 2;                       // log2 float4 chunks per row
+  const int nch = t.count << (t.lh + lq), w1 = (1 << t.lw) + 1, bs = BatchGeoF32::bs(t.lw, t.lh);
+  float* out = reinterpret_cast<float*>(a.out);
+  for (int ch = threadIdx.x; ch < nch; ch += 256) {
+    const int b = ch >> (t.lh + lq), r = (ch >> lq) & ((1 << t.lh) - 1), c0 = (ch & ((1 << lq) - 1)) << 2;
+    const BDesc d = desc[b];
+    const float* s = lds + b * bs + r * w1 + c0;
+    *reinterpret_cast<float4*>(out + d.out_off + (int64_t)r * d.out_stride + c0) = make_float4(s[0], s[1], s[2], s[3]);
+  }
+}
+
+// One fp32 tile of the forward.  Ends with a barrier.
+TA_DEV void fwd_tile_f(const BatchArgs& a, const BatchTile& t, const ta_block* blocks, float* lds, BDesc* desc) {
+  switch (t.kind_h) {
+    case 0: fwd_rows_fw<KC2>(a, t, blocks, lds, desc); break;
+    case 1: fwd_rows_fw<KS3>(a, t, blocks, lds, desc); break;
+    default: fwd_rows_fw<KC3>(a, t, blocks, lds, desc); break;
+  }
+  __syncthreads();
+  cols_f_kind<false>(t, lds);
+  __syncthreads();
+  store_tile_f(a, t, lds, desc);
+  __syncthreads();
+}
+
+// One fp32 tile of the inverse: coalesced loads -> column-major LDS ->
+// columns -> row-major LDS -> rows in place -> coalesced stores.  Ends with
+// a barrier.
+TA_DEV void inv_tile_f(const BatchArgs& a, const BatchTile& t, const ta_block* blocks, float* lds, BDesc* desc) {
+  if ((int)threadIdx.x < t.count) {
+    const ta_block d = blocks[t.first + threadIdx.x];
+    desc[threadIdx.x] = BDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
+  }
+  __syncthreads();
+  {
+    const int lq = t.lw - 2;
+    const int nch = t.count << (t.lh + lq), h1 = (1 << t.lh) + 1, bs = BatchGeoF32::bs(t.lw, t.lh);
+    const float* in = reinterpret_cast<const float*>(a.in);
+    for (int ch = threadIdx.x; ch < nch; ch += 256) {
+      const int b = ch >> (t.lh + lq), r = (ch >> lq) & ((1 << t.lh) - 1), c0 = (ch & ((1 << lq) - 1)) << 2;
+      const BDesc d = desc[b];
+      const float4 v = *reinterpret_cast<const float4*>(in + d.in_off + (int64_t)r * d.in_stride + c0);
+      float* dst = lds + b * bs + c0 * h1 + r;
+      dst[0] = v.x; dst[h1] = v.y; dst[2 * h1] = v.z; dst[3 * h1] = v.w;
+    }
+  }
+  __syncthreads();
+  cols_f_kind<true>(t, lds);
+  __syncthreads();
+  switch (t.kind_h) {
+    case 0: inv_rows_fw<KC2>(t, lds); break;
+    case 1: inv_rows_fw<KS3>(t, lds); break;
+    default: inv_rows_fw<KC3>(t, lds); break;
+  }
+  __syncthreads();
+  store_tile_f(a, t, lds, desc);
+  __syncthreads();
+}
+
+template <bool INV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_f32(BatchArgs a) {
+  __shared__ __align__(16) float lds[kBatchLdsF32];
+  __shared__ BDesc desc[kMaxTileBlocks];
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
+  const int64_t end = a.xstart[xcd + 1];
+  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd) {
+    const BatchTile t = a.tiles[ti];
+    if (INV)
+      inv_tile_f(a, t, a.blocks, lds, desc);
+    else
+      fwd_tile_f(a, t, a.blocks, lds, desc);
+  }
+}
+
 // ---------------------------------------------------------------- block lists
 // Unplanned: the descriptor list is cut into sort windows of kSortWin
 // consecutive descriptors, each handled by kSortWin / kDescWindow workgroups
@@ -374,9 +564,10 @@ TA_DEV int config_key(const BatchArgs& a, const ta_block& d) {
   return d.log2w | (d.log2h << 3) | (d.axis_h << 6) | (d.axis_v << 14);
 }
 
-template <bool INV>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_desc(BatchArgs a) {
-  __shared__ __align__(16) uint32_t lds[kBatchLds];
+// (fp32: the larger tile buffer leaves room for three workgroups per CU)
+template <bool INV, bool F32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 3 : 4))) void batch_desc(BatchArgs a) {
+  __shared__ __align__(16) uint32_t lds[F32 ? kBatchLdsF32 : kBatchLds];
   __shared__ BDesc desc[kMaxTileBlocks];
   __shared__ uint32_t skey[kSortWin];            // (configuration << 10 | position), sorted
   __shared__ ta_block qdesc[kDescWindow];        // this quarter's descriptors, in sorted order
@@ -429,7 +620,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
       const uint32_t k = s0 >> 10;
       const int lw = (int)(k & 7), lh = (int)((k >> 3) & 7);
       const int ah = (int)((k >> 6) & 0xff), av = (int)((k >> 14) & 0xff);
-      const int cap = BatchGeo::nb_for(lw, lh);
+      const int cap = F32 ? BatchGeoF32::nb_for(lw, lh) : BatchGeo::nb_for(lw, lh);
       int len = 1;
       while (j + len < qcnt && len < cap && (skey[q0 + j + len] >> 10) == k) ++len;
       const AxisDev& h = a.axes[ah * kAxisSizes + lw];
@@ -442,14 +633,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
       t.first = j;
       t.count = len;
       t.pad = 0;
-      t.ph_f = h.pf;
-      t.ph_i = h.pi;
-      t.pv_f = v.pf;
-      t.pv_i = v.pi;
-      if (INV)
-        inv_tile(a, t, qdesc, lds, desc);
-      else
-        fwd_tile(a, t, qdesc, lds, desc);
+      if (F32) {
+        t.ph_f = reinterpret_cast<const uint32_t*>(h.ff);
+        t.ph_i = reinterpret_cast<const uint32_t*>(h.fi);
+        t.pv_f = reinterpret_cast<const uint32_t*>(v.ff);
+        t.pv_i = reinterpret_cast<const uint32_t*>(v.fi);
+        float* fl = reinterpret_cast<float*>(lds);
+        if (INV)
+          inv_tile_f(a, t, qdesc, fl, desc);
+        else
+          fwd_tile_f(a, t, qdesc, fl, desc);
+      } else {
+        t.ph_f = h.pf;
+        t.ph_i = h.pi;
+        t.pv_f = v.pf;
+        t.pv_i = v.pi;
+        if (INV)
+          inv_tile(a, t, qdesc, lds, desc);
+        else
+          fwd_tile(a, t, qdesc, lds, desc);
+      }
       j += len;
     }
     __syncthreads();                   // the window buffers are rewritten next
@@ -458,8 +661,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
 
 }  // namespace
 
-const void* batch_kernel(int inv, int desc) {
-  if (desc) return inv ? reinterpret_cast<const void*>(&batch_desc<true>) : reinterpret_cast<const void*>(&batch_desc<false>);
+const void* batch_kernel(int inv, int desc, int f32) {
+  if (desc && f32)
+    return inv ? reinterpret_cast<const void*>(&batch_desc<true, true>)
+               : reinterpret_cast<const void*>(&batch_desc<false, true>);
+  if (desc)
+    return inv ? reinterpret_cast<const void*>(&batch_desc<true, false>)
+               : reinterpret_cast<const void*>(&batch_desc<false, false>);
+  if (f32) return inv ? reinterpret_cast<const void*>(&batch_f32<true>) : reinterpret_cast<const void*>(&batch_f32<false>);
   return inv ? reinterpret_cast<const void*>(&batch_inv) : reinterpret_cast<const void*>(&batch_fwd);
 }
 

@@ -163,13 +163,15 @@ int refresh_axis(ta_ctx* c, int id) {
   ta::AxisDev row[ta::kAxisSizes];
   const std::string saved = g_err;
   for (int l = 0; l < ta::kAxisSizes; ++l) {
-    row[l] = ta::AxisDev{-1, 0, nullptr, nullptr};
-    Resolved r;
-    if (l >= 2 && l <= 6 && c->axes[id].set && resolve_axis(c, id, 1 << l, TA_I16, &r) == TA_OK) {
+    row[l] = ta::AxisDev{-1, 0, nullptr, nullptr, nullptr, nullptr};
+    Resolved r, rf;
+    if (l >= 2 && l <= 6 && c->axes[id].set && resolve_axis(c, id, 1 << l, TA_I16, &r) == TA_OK &&
+        resolve_axis(c, id, 1 << l, TA_F32, &rf) == TA_OK && batch_kind(r) >= 0) {
       row[l].kind = batch_kind(r);
       row[l].pf = static_cast<const uint32_t*>(r.pf);
       row[l].pi = static_cast<const uint32_t*>(r.pi);
-      if (row[l].kind < 0) row[l].pf = row[l].pi = nullptr;
+      row[l].ff = static_cast<const float*>(rf.pf);
+      row[l].fi = static_cast<const float*>(rf.pi);
     }
   }
   g_err = saved;
@@ -311,7 +313,7 @@ int ta_create(ta_ctx** out, int device, int bit_depth, int m, int a) {
   c->m = m;
   c->a = a;
   static_assert(kMaxIds == ta::kAxisIds, "axis table size");
-  std::vector<ta::AxisDev> table((size_t)ta::kAxisIds * ta::kAxisSizes, ta::AxisDev{-1, 0, nullptr, nullptr});
+  std::vector<ta::AxisDev> table((size_t)ta::kAxisIds * ta::kAxisSizes, ta::AxisDev{-1, 0, nullptr, nullptr, nullptr, nullptr});
   int e;
   if ((e = upload(c.get(), table.data(), table.size() * sizeof(ta::AxisDev), reinterpret_cast<void**>(&c->axes_dev)))) {
     for (void* p : c->allocations) (void)hipFree(p);
@@ -481,6 +483,7 @@ int ta_inv_packed(ta_ctx* c, int axis_h, int axis_v, int log2w, int log2h, int64
 
 struct ta_plan {
   int device = 0;
+  int dtype = TA_I16;
   int64_t nblocks = 0, ntiles = 0;
   int grid = 2048;                 // persistent workgroups (autotuned)
   ta_block* blocks_dev = nullptr;  // block descriptors in plan order
@@ -496,7 +499,7 @@ namespace {
 // descriptor that breaks one): sizes 4..64, non-negative offsets, strides of
 // at least the width, offsets and strides multiples of the vector width (8
 // elements, 4 for 4-wide blocks), and axes with a batched kind at the size.
-int check_block(ta_ctx* c, const ta_block& b, int64_t i, Resolved* rh, Resolved* rv, int* kh, int* kv) {
+int check_block(ta_ctx* c, const ta_block& b, int64_t i, int dtype, Resolved* rh, Resolved* rv, int* kh, int* kv) {
   if (b.log2w < 2 || b.log2w > 6 || b.log2h < 2 || b.log2h > 6)
     return fail(TA_EUNSUPPORTED, "block %lld: size %dx%d outside 4..64", (long long)i, 1 << std::min<int>(b.log2w, 30),
                 1 << std::min<int>(b.log2h, 30));
@@ -506,7 +509,7 @@ int check_block(ta_ctx* c, const ta_block& b, int64_t i, Resolved* rh, Resolved*
   if (b.in_off % ch || b.out_off % ch || b.in_stride % ch || b.out_stride % ch)
     return fail(TA_EUNSUPPORTED, "block %lld: offsets and strides must be multiples of %d elements", (long long)i, ch);
   int e;
-  if ((e = resolve_axis(c, b.axis_h, w, TA_I16, rh)) || (e = resolve_axis(c, b.axis_v, 1 << b.log2h, TA_I16, rv))) {
+  if ((e = resolve_axis(c, b.axis_h, w, dtype, rh)) || (e = resolve_axis(c, b.axis_v, 1 << b.log2h, dtype, rv))) {
     const std::string m = g_err;
     return fail(e, "block %lld: %s", (long long)i, m.c_str());
   }
@@ -533,7 +536,7 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
   // at least one workgroup per XCD list
   const int64_t g = std::max<int64_t>(ta::kXcds, std::min<int64_t>(grid, std::max<int64_t>(1, p->ntiles)));
   TA_HIP(hipSetDevice(c->device));
-  TA_HIP(hipLaunchKernel(ta::batch_kernel(inv), dim3((unsigned)g), dim3(256), kargs, 0,
+  TA_HIP(hipLaunchKernel(ta::batch_kernel(inv, 0, p->dtype == TA_F32), dim3((unsigned)g), dim3(256), kargs, 0,
                          reinterpret_cast<hipStream_t>(stream)));
   return TA_OK;
 }
@@ -546,7 +549,7 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
   if (!c || !out || (n > 0 && !blocks)) return fail(TA_EINVAL, "null argument");
   *out = nullptr;
   if (n < 0) return fail(TA_EINVAL, "negative block count");
-  if (dtype != TA_I16) return fail(TA_EUNSUPPORTED, "batched plans are built for int16 (fixed point) only");
+  if (dtype != TA_I16 && dtype != TA_F32) return fail(TA_EINVAL, "unknown dtype %d", dtype);
   // group blocks by (region, size, kinds, parameter tables); a region is a
   // window of kRegion input elements (about 4 CTU rows of a 3840-wide frame)
   constexpr int64_t kRegion = int64_t(1) << 20;
@@ -555,11 +558,12 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
   std::map<Key, std::tuple<Resolved, Resolved>> res;
   auto plan = std::make_unique<ta_plan>();
   plan->device = c->device;
+  plan->dtype = dtype;
   for (int64_t i = 0; i < n; ++i) {
     const ta_block& b = blocks[i];
     Resolved rh, rv;
     int kh, kv, e;
-    if ((e = check_block(c, b, i, &rh, &rv, &kh, &kv))) return e;
+    if ((e = check_block(c, b, i, dtype, &rh, &rv, &kh, &kv))) return e;
     const int w = 1 << b.log2w, h = 1 << b.log2h;
     const Key k{b.in_off / kRegion, b.log2w, b.log2h, kh, kv, rh.pf, rv.pf};
     groups[k].push_back(i);
@@ -586,7 +590,7 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
       region_xcd[region] = next;
     }
     const int lw = std::get<1>(k), lh = std::get<2>(k);
-    const int nb = ta::BatchGeo::nb_for(lw, lh);
+    const int nb = dtype == TA_F32 ? ta::BatchGeoF32::nb_for(lw, lh) : ta::BatchGeo::nb_for(lw, lh);
     const Resolved& rh = std::get<0>(res[k]);
     const Resolved& rv = std::get<1>(res[k]);
     const auto& idx = groups[k];
@@ -666,7 +670,7 @@ int ta_plan_autotune(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   TA_HIP(hipSetDevice(c->device));
   // reference output of the first candidate, to check every candidate bitwise
-  const size_t bytes = (size_t)p->max_out_elem * sizeof(int16_t);
+  const size_t bytes = (size_t)p->max_out_elem * (p->dtype == TA_F32 ? sizeof(float) : sizeof(int16_t));
   void* ref = nullptr;
   TA_HIP(hipMalloc(&ref, bytes));
   std::vector<char> ha(bytes), hb(bytes);
@@ -714,13 +718,12 @@ int run_blocks(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void
   if (!c) return fail(TA_EINVAL, "null context");
   if (n < 0) return fail(TA_EINVAL, "negative block count");
   if (dtype != TA_I16 && dtype != TA_F32) return fail(TA_EINVAL, "unknown dtype %d", dtype);
-  if (dtype != TA_I16) return fail(TA_EUNSUPPORTED, "block lists run in fixed point (int16) only");
   if (n == 0) return TA_OK;
   if (!blocks || !in || !out) return fail(TA_EINVAL, "null buffer");
   if (in == out) return fail(TA_EINVAL, "input and output alias");
   if ((uintptr_t)blocks & 7) return fail(TA_EINVAL, "descriptors must be 8-byte aligned");
   if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
-  const void* fn = ta::batch_kernel(inv, 1);
+  const void* fn = ta::batch_kernel(inv, 1, dtype == TA_F32);
   // one workgroup per quarter of a sort window (the dispatcher balances
   // quarters of uneven cost), and at least one per XCD range
   const int64_t sortwin = (int64_t)ta::kDescWindow * ta::kSortQuarters;
@@ -780,7 +783,7 @@ int ta_validate_blocks(ta_ctx* c, const ta_block* blocks_dev, int64_t n, int64_t
     const ta_block& b = host[(size_t)i];
     Resolved rh, rv;
     int kh, kv, e;
-    if ((e = check_block(c, b, i, &rh, &rv, &kh, &kv))) {
+    if ((e = check_block(c, b, i, TA_I16, &rh, &rv, &kh, &kv))) {
       *first_bad = i;
       return e;
     }

@@ -92,14 +92,35 @@ struct BatchGeo {
   }
 };
 
+// FP32 tiles: block b of the tile holds BS(W, H) floats at b * BS, laid
+// out column-major (pitch H + 1) for the column phase and row-major (pitch
+// W + 1) for the row phase and the coalesced stores; odd pitches keep the
+// per-element accesses of a wave in distinct banks.  NB = 256 / max(W, H),
+// capped so that the tile fits kLds floats (34 KiB: four workgroups per CU).
+struct BatchGeoF32 {
+  static constexpr int kLds = 8704;
+  static constexpr int bs(int lw, int lh) {
+    const int w = 1 << lw, h = 1 << lh, cm = w * (h + 1), rm = h * (w + 1);
+    return cm > rm ? cm : rm;
+  }
+  static constexpr int nb_for(int lw, int lh) {
+    const int nb = 256 >> (lw > lh ? lw : lh);
+    const int cap = kLds / bs(lw, lh);
+    return nb < cap ? nb : cap;
+  }
+};
+
 // What one axis id means at one block size, for kernels that read block
 // descriptors directly: the batched kind (0 DCT-2, 1 adjusted DST-7,
-// 2 adjusted DCT-8; -1 not usable at this size) and its band taps.
+// 2 adjusted DCT-8; -1 not usable at this size) and its band taps, as
+// packed int16 pairs (pf, pi) and as fp32 (ff, fi).
 struct AxisDev {
   int32_t kind;
   int32_t pad;
   const uint32_t* pf;
   const uint32_t* pi;
+  const float* ff;
+  const float* fi;
 };
 constexpr int kAxisIds = 256;
 constexpr int kAxisSizes = 7;   // indexed by log2 of the size (2..6 used)
@@ -113,7 +134,7 @@ struct BatchArgs {
   int64_t ntiles;
   int64_t xstart[kXcds + 1];
   const ta_block* blocks;
-  const int16_t* in;
+  const int16_t* in;      // int16 data; the fp32 kernels read these as float*
   int16_t* out;
   int bd, m, a;
   // unplanned block lists (ta_transform_fwd / _inv): descriptors are read as
@@ -123,8 +144,9 @@ struct BatchArgs {
 };
 
 // Persistent batched kernels (batch_kernels.hip): over a planned tile list
-// (desc = 0) or directly over a device array of block descriptors (desc = 1).
-const void* batch_kernel(int inv, int desc = 0);
+// (desc = 0) or directly over a device array of block descriptors (desc = 1);
+// int16 fixed point, or fp32 with f32 = 1.
+const void* batch_kernel(int inv, int desc = 0, int f32 = 0);
 
 // Encoder evaluation of the five separable transforms (multi_kernels.hip):
 // out holds 5 consecutive packed batches of nblocks N x N int16 blocks.

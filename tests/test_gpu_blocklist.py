@@ -211,8 +211,8 @@ def test_call_errors(env):
     L = ta.lib()
     import ctypes
     vp = ctypes.c_void_p
-    assert L.ta_transform_fwd(ctx._h, vp(dev.data_ptr()), 8, vp(x.data_ptr()), vp(y.data_ptr()), ta.F32,
-                              None) == ta.TA_EUNSUPPORTED
+    assert L.ta_transform_fwd(ctx._h, vp(dev.data_ptr()), 8, vp(x.data_ptr()), vp(y.data_ptr()), 7,
+                              None) == ta.TA_EINVAL
     assert L.ta_transform_fwd(ctx._h, vp(dev.data_ptr()), 8, vp(x.data_ptr()), vp(x.data_ptr()), ta.I16,
                               None) == ta.TA_EINVAL
     assert L.ta_transform_fwd(ctx._h, vp(dev.data_ptr()), -1, vp(x.data_ptr()), vp(y.data_ptr()), ta.I16,
