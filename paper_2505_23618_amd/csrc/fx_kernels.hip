@@ -31,7 +31,15 @@ struct Tile {
   // whether every thread owns a row (a column) of the tile
   static constexpr bool ROWS_ALL = NB * H == 256, COLS_ALL = NB * W == 256;
   static constexpr int PP = W + 1;
-  static constexpr int PCB = (H / 2) * PP;                 // dwords per block, PC
+  // XCOL (64-wide tiles of 4 blocks): in the column pass wave w takes
+  // columns [16w, 16w + 16) of all 4 blocks instead of all columns of one
+  // block.  The large values of a block's rows sit in its first few columns,
+  // so only wave 0 then leaves the packed int16 butterfly (the wave-uniform
+  // range check fails for a whole wave when any of its lanes is out of
+  // range).  Its PC block pitch is padded to 16 mod 64 dwords so that the 4
+  // blocks a wave reads fall in distinct banks.
+  static constexpr bool XCOL = W == 64 && NB == 4;
+  static constexpr int PCB = (H / 2) * PP + (XCOL ? 48 : 0);   // dwords per block, PC
   // RM row pitch: the inverse reads whole rows with ds_read_b128 and pads each
   // row by 16 bytes; the forward reads consecutive 16-byte chunks and needs no
   // row padding.  Each block is padded by 64 bytes so that the two blocks a
@@ -107,19 +115,19 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
   // column pass (vertical transform of every column); PC is dead once every
   // thread has read its column, then the same LDS holds RM
   uint32_t o[H / 2];
+  const int cb = T::XCOL ? (tid >> 4) & 3 : tid / W;                  // column thread -> block
+  const int cc = T::XCOL ? ((tid >> 6) << 4) | (tid & 15) : tid % W;  // and column
   if (T::COLS_ALL || tid < NB * W) {
-    const int b = tid / W, c = tid % W;
     PV z;
 #pragma unroll
-    for (int i = 0; i < H / 2; ++i) z.p[i] = pc[b * T::PCB + i * T::PP + c];
+    for (int i = 0; i < H / 2; ++i) z.p[i] = pc[cb * T::PCB + i * T::PP + cc];
     const auto y = fx::run_pass<H, AV, false>(z, pv_f, pv_i, p.s_col, p.a);
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
   }
   __syncthreads();
   if (T::COLS_ALL || tid < NB * W) {
-    const int b = tid / W, c = tid % W;
-    const int base = b * T::RMBF + c;
+    const int base = cb * T::RMBF + cc;
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) {
       rm[base + (2 * i) * T::RPF] = (uint16_t)o[i];
