@@ -310,6 +310,7 @@ def _batched(ctx, ids, res):
     ui = _events_mean(lambda i: ctx.transform_inv(dev, Y[i % 4], Z[i % 4]), 12)
     res["batched_uneven"] = {"value": nco / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
                              "blocks": len(rows), "coefficients": nco, "tiles": info["tiles"], "grid": info["grid"],
+                             "region_log2": info["region_log2"],
                              "GB/s_fwd": (4 * nco + 32 * len(rows)) / tf / 1e9,
                              "unplanned_value": nco / (uf + ui), "unplanned_fwd_us": uf * 1e6,
                              "unplanned_inv_us": ui * 1e6,
@@ -327,7 +328,7 @@ def _batched(ctx, ids, res):
     uf = _events_mean(lambda i: ctx.transform_fwd(dev, X[i % 4], Y[i % 4]), 12)
     ui = _events_mean(lambda i: ctx.transform_inv(dev, Y[i % 4], Z[i % 4]), 12)
     res["batched_uneven_f32"] = {"value": nco / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
-                                 "tiles": infof["tiles"], "grid": infof["grid"],
+                                 "tiles": infof["tiles"], "grid": infof["grid"], "region_log2": infof["region_log2"],
                                  "GB/s_fwd": (8 * nco + 32 * len(rows)) / tf / 1e9,
                                  "unplanned_value": nco / (uf + ui), "unplanned_fwd_us": uf * 1e6,
                                  "unplanned_inv_us": ui * 1e6}

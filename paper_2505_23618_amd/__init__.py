@@ -38,7 +38,8 @@ EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis
            "ta_plan_create", "ta_plan_destroy", "ta_plan_info", "ta_plan_fwd", "ta_plan_inv",
            "ta_plan_autotune", "ta_givens_workspace", "ta_givens_fwd", "ta_givens_bwd",
            "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats", "ta_design_search",
-           "ta_transform_fwd", "ta_transform_inv", "ta_validate_blocks", "ta_set_axis_cfg", "ta_set_params")
+           "ta_transform_fwd", "ta_transform_inv", "ta_validate_blocks", "ta_set_axis_cfg", "ta_set_params",
+           "ta_plan_tuning")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -94,6 +95,7 @@ def lib() -> ctypes.CDLL:
     L.ta_plan_fwd.argtypes = [vp, vp, vp, vp, vp]
     L.ta_plan_inv.argtypes = [vp, vp, vp, vp, vp]
     L.ta_plan_autotune.argtypes = [vp, vp, vp, vp, vp, i32]
+    L.ta_plan_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.ta_givens_workspace.argtypes = [i64, ctypes.POINTER(i64)]
     L.ta_givens_fwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp]
     L.ta_givens_bwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -378,9 +380,10 @@ class Plan:
             pass
 
     def info(self):
-        nb, nt, g = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+        nb, nt, g, r = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
         _check(lib().ta_plan_info(self._h, ctypes.byref(nb), ctypes.byref(nt), ctypes.byref(g)))
-        return {"blocks": nb.value, "tiles": nt.value, "grid": g.value}
+        _check(lib().ta_plan_tuning(self._h, ctypes.byref(g), ctypes.byref(r)))
+        return {"blocks": nb.value, "tiles": nt.value, "grid": g.value, "region_log2": r.value}
 
     def fwd(self, x, out, stream_handle=None):
         sh = _stream_handle(None) if stream_handle is None else ctypes.c_void_p(stream_handle)

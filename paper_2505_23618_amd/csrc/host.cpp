@@ -484,6 +484,13 @@ int ta_inv_packed(ta_ctx* c, int axis_h, int axis_v, int log2w, int log2h, int64
 struct ta_plan {
   int device = 0;
   int dtype = TA_I16;
+  int region_log2 = 20;            // frame-region size of the tile lists (autotuned)
+  // the validated descriptors and, per block, its class: the axes as resolved
+  // when the plan was built (kinds and parameter tables), kept for re-planning
+  std::vector<ta_block> host;
+  std::vector<uint32_t> cls;
+  struct Class { int kh, kv; const void *phf, *phi, *pvf, *pvi; };
+  std::vector<Class> classes;
   int64_t nblocks = 0, ntiles = 0;
   int grid = 2048;                 // persistent workgroups (autotuned)
   ta_block* blocks_dev = nullptr;  // block descriptors in plan order
@@ -541,6 +548,74 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
   return TA_OK;
 }
 
+// Group the plan's blocks by (frame region of 2^region_log2 input elements,
+// size, class) and cut the groups into tiles; regions go round-robin to the
+// XCD lists, and within a region larger blocks come first.  Replaces the
+// plan's device descriptor and tile arrays (synchronous, allocates).
+int build_tiles(ta_plan* plan, int region_log2) {
+  typedef std::tuple<int64_t, int, int, uint32_t> Key;   // region, log2w, log2h, class
+  std::map<Key, std::vector<int64_t>> groups;
+  const int64_t n = plan->nblocks;
+  for (int64_t i = 0; i < n; ++i) {
+    const ta_block& b = plan->host[(size_t)i];
+    groups[Key{b.in_off >> region_log2, b.log2w, b.log2h, plan->cls[(size_t)i]}].push_back(i);
+  }
+  std::vector<Key> keys;
+  for (auto& kv : groups) keys.push_back(kv.first);
+  std::stable_sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
+    if (std::get<0>(x) != std::get<0>(y)) return std::get<0>(x) < std::get<0>(y);
+    return std::get<1>(x) + std::get<2>(x) > std::get<1>(y) + std::get<2>(y);
+  });
+  std::vector<ta_block> ordered;
+  std::vector<ta::BatchTile> lists[ta::kXcds];
+  ordered.reserve((size_t)n);
+  std::map<int64_t, int> region_xcd;
+  for (const Key& k : keys) {
+    const int64_t region = std::get<0>(k);
+    if (!region_xcd.count(region)) {
+      const int next = (int)region_xcd.size() % ta::kXcds;
+      region_xcd[region] = next;
+    }
+    const int lw = std::get<1>(k), lh = std::get<2>(k);
+    const int nb = plan->dtype == TA_F32 ? ta::BatchGeoF32::nb_for(lw, lh) : ta::BatchGeo::nb_for(lw, lh);
+    const ta_plan::Class& cl = plan->classes[std::get<3>(k)];
+    const auto& idx = groups[k];
+    for (size_t s = 0; s < idx.size(); s += nb) {
+      ta::BatchTile t{};
+      t.lw = lw;
+      t.lh = lh;
+      t.kind_h = cl.kh;
+      t.kind_v = cl.kv;
+      t.first = (int64_t)ordered.size();
+      t.count = (int32_t)std::min<size_t>(nb, idx.size() - s);
+      t.ph_f = static_cast<const uint32_t*>(cl.phf);
+      t.ph_i = static_cast<const uint32_t*>(cl.phi);
+      t.pv_f = static_cast<const uint32_t*>(cl.pvf);
+      t.pv_i = static_cast<const uint32_t*>(cl.pvi);
+      lists[region_xcd[region]].push_back(t);
+      for (size_t j = s; j < s + t.count; ++j) ordered.push_back(plan->host[(size_t)idx[j]]);
+    }
+  }
+  std::vector<ta::BatchTile> tiles;
+  for (int x = 0; x < ta::kXcds; ++x) {
+    plan->xstart[x] = (int64_t)tiles.size();
+    tiles.insert(tiles.end(), lists[x].begin(), lists[x].end());
+  }
+  plan->xstart[ta::kXcds] = (int64_t)tiles.size();
+  plan->ntiles = (int64_t)tiles.size();
+  plan->region_log2 = region_log2;
+  TA_HIP(hipSetDevice(plan->device));
+  if (n > 0) {
+    // allocated once, at their largest (a tile holds at least one block), so
+    // that re-planning never moves them
+    if (!plan->blocks_dev) TA_HIP(hipMalloc(&plan->blocks_dev, (size_t)n * sizeof(ta_block)));
+    if (!plan->tiles_dev) TA_HIP(hipMalloc(&plan->tiles_dev, (size_t)n * sizeof(ta::BatchTile)));
+    TA_HIP(hipMemcpy(plan->blocks_dev, ordered.data(), ordered.size() * sizeof(ta_block), hipMemcpyHostToDevice));
+    TA_HIP(hipMemcpy(plan->tiles_dev, tiles.data(), tiles.size() * sizeof(ta::BatchTile), hipMemcpyHostToDevice));
+  }
+  return TA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -550,81 +625,31 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
   *out = nullptr;
   if (n < 0) return fail(TA_EINVAL, "negative block count");
   if (dtype != TA_I16 && dtype != TA_F32) return fail(TA_EINVAL, "unknown dtype %d", dtype);
-  // group blocks by (region, size, kinds, parameter tables); a region is a
-  // window of kRegion input elements (about 4 CTU rows of a 3840-wide frame)
-  constexpr int64_t kRegion = int64_t(1) << 20;
-  typedef std::tuple<int64_t, int, int, int, int, const void*, const void*> Key;
-  std::map<Key, std::vector<int64_t>> groups;
-  std::map<Key, std::tuple<Resolved, Resolved>> res;
   auto plan = std::make_unique<ta_plan>();
   plan->device = c->device;
   plan->dtype = dtype;
+  plan->host.assign(blocks, blocks + n);
+  plan->cls.resize((size_t)n);
+  std::map<std::tuple<int, int, const void*, const void*, const void*, const void*>, uint32_t> class_of;
   for (int64_t i = 0; i < n; ++i) {
     const ta_block& b = blocks[i];
     Resolved rh, rv;
     int kh, kv, e;
     if ((e = check_block(c, b, i, dtype, &rh, &rv, &kh, &kv))) return e;
+    const auto key = std::make_tuple(kh, kv, rh.pf, rh.pi, rv.pf, rv.pi);
+    auto it = class_of.find(key);
+    if (it == class_of.end()) {
+      it = class_of.emplace(key, (uint32_t)plan->classes.size()).first;
+      plan->classes.push_back(ta_plan::Class{kh, kv, rh.pf, rh.pi, rv.pf, rv.pi});
+    }
+    plan->cls[(size_t)i] = it->second;
     const int w = 1 << b.log2w, h = 1 << b.log2h;
-    const Key k{b.in_off / kRegion, b.log2w, b.log2h, kh, kv, rh.pf, rv.pf};
-    groups[k].push_back(i);
-    res[k] = std::make_tuple(rh, rv);
     plan->max_in_elem = std::max<int64_t>(plan->max_in_elem, b.in_off + (int64_t)(h - 1) * b.in_stride + w);
     plan->max_out_elem = std::max<int64_t>(plan->max_out_elem, b.out_off + (int64_t)(h - 1) * b.out_stride + w);
   }
-  // tiles: regions go round-robin to the XCD lists; within a region, larger
-  // blocks first
-  std::vector<Key> keys;
-  for (auto& kv : groups) keys.push_back(kv.first);
-  std::stable_sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
-    if (std::get<0>(x) != std::get<0>(y)) return std::get<0>(x) < std::get<0>(y);
-    return std::get<1>(x) + std::get<2>(x) > std::get<1>(y) + std::get<2>(y);
-  });
-  std::vector<ta_block> ordered;
-  std::vector<ta::BatchTile> lists[ta::kXcds];
-  ordered.reserve(n);
-  std::map<int64_t, int> region_xcd;
-  for (const Key& k : keys) {
-    const int64_t region = std::get<0>(k);
-    if (!region_xcd.count(region)) {
-      const int next = (int)region_xcd.size() % ta::kXcds;
-      region_xcd[region] = next;
-    }
-    const int lw = std::get<1>(k), lh = std::get<2>(k);
-    const int nb = dtype == TA_F32 ? ta::BatchGeoF32::nb_for(lw, lh) : ta::BatchGeo::nb_for(lw, lh);
-    const Resolved& rh = std::get<0>(res[k]);
-    const Resolved& rv = std::get<1>(res[k]);
-    const auto& idx = groups[k];
-    for (size_t s = 0; s < idx.size(); s += nb) {
-      ta::BatchTile t{};
-      t.lw = lw;
-      t.lh = lh;
-      t.kind_h = std::get<3>(k);
-      t.kind_v = std::get<4>(k);
-      t.first = (int64_t)ordered.size();
-      t.count = (int32_t)std::min<size_t>(nb, idx.size() - s);
-      t.ph_f = static_cast<const uint32_t*>(rh.pf);
-      t.ph_i = static_cast<const uint32_t*>(rh.pi);
-      t.pv_f = static_cast<const uint32_t*>(rv.pf);
-      t.pv_i = static_cast<const uint32_t*>(rv.pi);
-      lists[region_xcd[region]].push_back(t);
-      for (size_t j = s; j < s + t.count; ++j) ordered.push_back(blocks[idx[j]]);
-    }
-  }
-  std::vector<ta::BatchTile> tiles;
-  for (int x = 0; x < ta::kXcds; ++x) {
-    plan->xstart[x] = (int64_t)tiles.size();
-    tiles.insert(tiles.end(), lists[x].begin(), lists[x].end());
-  }
-  plan->xstart[ta::kXcds] = (int64_t)tiles.size();
   plan->nblocks = n;
-  plan->ntiles = (int64_t)tiles.size();
-  TA_HIP(hipSetDevice(c->device));
-  if (n > 0) {
-    TA_HIP(hipMalloc(&plan->blocks_dev, ordered.size() * sizeof(ta_block)));
-    TA_HIP(hipMemcpy(plan->blocks_dev, ordered.data(), ordered.size() * sizeof(ta_block), hipMemcpyHostToDevice));
-    TA_HIP(hipMalloc(&plan->tiles_dev, tiles.size() * sizeof(ta::BatchTile)));
-    TA_HIP(hipMemcpy(plan->tiles_dev, tiles.data(), tiles.size() * sizeof(ta::BatchTile), hipMemcpyHostToDevice));
-  }
+  int e;
+  if ((e = build_tiles(plan.get(), plan->region_log2))) return e;
   *out = plan.release();
   return TA_OK;
 }
@@ -643,6 +668,13 @@ int ta_plan_info(const ta_plan* p, int64_t* nblocks, int64_t* ntiles, int* grid)
   if (nblocks) *nblocks = p->nblocks;
   if (ntiles) *ntiles = p->ntiles;
   if (grid) *grid = p->grid;
+  return TA_OK;
+}
+
+int ta_plan_tuning(const ta_plan* p, int* grid, int* region_log2) {
+  if (!p) return fail(TA_EINVAL, "null plan");
+  if (grid) *grid = p->grid;
+  if (region_log2) *region_log2 = p->region_log2;
   return TA_OK;
 }
 
@@ -666,44 +698,54 @@ int ta_plan_autotune(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream
   if (!c || !p) return fail(TA_EINVAL, "null argument");
   if (p->ntiles == 0) return TA_OK;
   if (!in || !out) return fail(TA_EINVAL, "null buffer");
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
   if (reps < 1) reps = 3;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   TA_HIP(hipSetDevice(c->device));
-  // reference output of the first candidate, to check every candidate bitwise
+  // every candidate's output is checked bitwise against the first one's
   const size_t bytes = (size_t)p->max_out_elem * (p->dtype == TA_F32 ? sizeof(float) : sizeof(int16_t));
-  void* ref = nullptr;
-  TA_HIP(hipMalloc(&ref, bytes));
-  std::vector<char> ha(bytes), hb(bytes);
-  const int cands[] = {256, 512, 1024, 2048, 4096, 8192};
+  std::vector<char> ref(bytes), got(bytes);
+  const int regions[] = {18, 19, 20, 21, 22};     // tile mapping: frame-region size of the XCD lists
+  const int grids[] = {256, 512, 1024, 2048, 4096, 8192};
   hipEvent_t e0, e1;
   TA_HIP(hipEventCreate(&e0));
   TA_HIP(hipEventCreate(&e1));
   float best = 1e30f;
-  int best_grid = p->grid;
+  const int orig_region = p->region_log2;
+  int best_grid = p->grid, best_region = orig_region;
   int rc = TA_OK;
-  for (size_t ci = 0; ci < sizeof(cands) / sizeof(cands[0]) && rc == TA_OK; ++ci) {
-    const int g = cands[ci];
-    if ((rc = launch_plan(c, p, 0, in, out, stream, g))) break;
-    (void)hipEventRecord(e0, s);
-    for (int r = 0; r < reps && rc == TA_OK; ++r) rc = launch_plan(c, p, 0, in, out, stream, g);
-    (void)hipEventRecord(e1, s);
-    if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(TA_EHIP, "autotune sync failed"); break; }
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ci == 0) {
-      if (hipMemcpy(ref, out, bytes, hipMemcpyDeviceToDevice) != hipSuccess) { rc = fail(TA_EHIP, "copy"); break; }
-    } else {
-      if (hipMemcpy(ha.data(), ref, bytes, hipMemcpyDeviceToHost) != hipSuccess ||
-          hipMemcpy(hb.data(), out, bytes, hipMemcpyDeviceToHost) != hipSuccess) { rc = fail(TA_EHIP, "copy"); break; }
-      if (memcmp(ha.data(), hb.data(), bytes) != 0) { rc = fail(TA_EHIP, "autotune candidate %d disagrees", g); break; }
+  bool have_ref = false;
+  for (int region : regions) {
+    if (rc != TA_OK) break;
+    if ((rc = build_tiles(p, region))) break;
+    for (int g : grids) {
+      if ((rc = launch_plan(c, p, 0, in, out, stream, g))) break;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps && rc == TA_OK; ++r) rc = launch_plan(c, p, 0, in, out, stream, g);
+      (void)hipEventRecord(e1, s);
+      if (rc != TA_OK) break;
+      if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(TA_EHIP, "autotune sync failed"); break; }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (hipMemcpy(have_ref ? got.data() : ref.data(), out, bytes, hipMemcpyDeviceToHost) != hipSuccess) {
+        rc = fail(TA_EHIP, "autotune copy failed");
+        break;
+      }
+      if (have_ref && memcmp(ref.data(), got.data(), bytes) != 0) {
+        rc = fail(TA_EHIP, "autotune candidate (region 2^%d, grid %d) disagrees", region, g);
+        break;
+      }
+      have_ref = true;
+      if (ms < best) { best = ms; best_grid = g; best_region = region; }
     }
-    if (ms < best) { best = ms; best_grid = g; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipFree(ref);
-  if (rc == TA_OK) p->grid = best_grid;
-  return rc;
+  // keep the fastest mapping (rebuilt also when a candidate failed, so the
+  // plan stays consistent)
+  const int rc2 = build_tiles(p, rc == TA_OK ? best_region : orig_region);
+  if (rc == TA_OK && rc2 == TA_OK) p->grid = best_grid;
+  return rc != TA_OK ? rc : rc2;
 }
 
 }  // extern "C"

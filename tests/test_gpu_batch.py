@@ -72,6 +72,7 @@ def test_autotune_and_graph_replay(env):
     y = torch.zeros_like(x)
     info = plan.autotune(x, y, reps=2)
     assert info["grid"] in (256, 512, 1024, 2048, 4096, 8192)
+    assert 18 <= info["region_log2"] <= 22
     ref = oracle_frames(frames, rows, params)
     # capture forward + inverse in a graph; replay with eager work in between
     z = torch.zeros_like(x)

@@ -89,6 +89,7 @@ def test_f32_plan_autotune_and_graph_replay(env):
     y, z = torch.zeros_like(x), torch.zeros_like(x)
     info = plan.autotune(x, y, reps=2)
     assert info["grid"] in (256, 512, 1024, 2048, 4096, 8192)
+    assert 18 <= info["region_log2"] <= 22
     dev = ctx.blocks_to_device(d)
     y2 = torch.zeros_like(x)
     ctx.transform_fwd(dev, x, y2)
