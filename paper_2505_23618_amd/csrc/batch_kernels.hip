@@ -19,6 +19,10 @@
 //
 // Kinds: 0 = DCT-2, 1 = DST-3 + 4-tap band (adjusted DST-7),
 //        2 = DCT-3 + 4-tap band with flipped taps (adjusted DCT-8, eq. 3).
+//
+// The same tile walk runs on fp32 data with the orthonormal fp32 stages
+// (batch_f32, BatchGeoF32 layout), and both data types also run unplanned,
+// straight from a device array of descriptors (batch_desc).
 #include "fp.hpp"
 #include "fx.hpp"
 #include "kernels.hpp"
