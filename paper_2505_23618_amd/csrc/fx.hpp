@@ -9,6 +9,8 @@
 // and lets the consumer choose the pairing it needs for its own dot2 operands.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace ta {
@@ -43,6 +45,19 @@ struct Acc {
   TA_DEV int value(int i) const { return a[i] >> (i < SPLIT ? s0 : s1); }
   TA_DEV uint32_t pair(int i, int j) const {
     return satpk(i >= 0 ? value(i) : 0, j >= 0 ? value(j) : 0);
+  }
+};
+
+// Stage result scaled so that its shift is 16: the rounded value is the high
+// half of each sum, and a pair packs with one byte permute instead of two
+// shifts and a saturating pack.  Only for stages whose sums provably stay
+// below 2^31 and whose rounded values provably fit int16 (no clamp here).
+template <int N>
+struct AccHi {
+  int a[N];
+  TA_DEV int value(int i) const { return a[i] >> 16; }
+  TA_DEV uint32_t pair(int i, int j) const {
+    return perm(j >= 0 ? (uint32_t)a[j] : 0u, i >= 0 ? (uint32_t)a[i] : 0u, 0x07060302u);
   }
 };
 
@@ -110,24 +125,25 @@ TA_DEV Acc<N> band(const S& src, cparam taps, int shift) {
 // Even part: the N/2-point DCT-3 of w[0], w[2], ...; odd part:
 // O[n] = sum_j C2_N[2j+1][n] w[2j+1]; z[n] = E[n] + O[n], z[N-1-n] = E[n] - O[n].
 // ---------------------------------------------------------------------------
-template <int N, int M, bool OFF, class W>
+// SC scales every table entry by 2^SC (see core_c3).
+template <int N, int M, bool OFF, int SC, class W>
 TA_DEV void c3_even(const W& w, int (&e)[M], int off) {
-  constexpr int ST = N / M;
+  constexpr int ST = N / M, F = 1 << SC;
   if constexpr (M == 2) {
     const uint32_t p = w.pair(0, ST);
-    const uint32_t c0 = pk2(c2i<2>(0, 0), c2i<2>(1, 0)), c1 = pk2(c2i<2>(0, 1), c2i<2>(1, 1));
+    const uint32_t c0 = pk2(F * c2i<2>(0, 0), F * c2i<2>(1, 0)), c1 = pk2(F * c2i<2>(0, 1), F * c2i<2>(1, 1));
     e[0] = OFF ? dot2h(p, c0, off) : dot2h0(p, c0);
     e[1] = OFF ? dot2h(p, c1, off) : dot2h0(p, c1);
   } else {
     int ee[M / 2];
-    c3_even<N, M / 2, OFF>(w, ee, off);
+    c3_even<N, M / 2, OFF, SC>(w, ee, off);
 #pragma unroll
     for (int n = 0; n < M / 2; ++n) {
       int o = 0;
 #pragma unroll
       for (int i = 0; i < M / 4; ++i) {
         const int k1 = 4 * i + 1, k2 = 4 * i + 3;
-        const uint32_t pr = w.pair(k1 * ST, k2 * ST), cf = pk2(c2i<M>(k1, n), c2i<M>(k2, n));
+        const uint32_t pr = w.pair(k1 * ST, k2 * ST), cf = pk2(F * c2i<M>(k1, n), F * c2i<M>(k2, n));
         o = i == 0 ? dot2h0(pr, cf) : dot2(pr, cf, o);
       }
       e[n] = ee[n] + o;
@@ -138,17 +154,21 @@ TA_DEV void c3_even(const W& w, int (&e)[M], int off) {
 
 // OSIGN applies S to the output before rounding (DST-3 = S DCT-3 R);
 // IREV reverses the input.  The rounding offset enters once per output.
-template <int N, bool IREV, bool OSIGN, class S>
-TA_DEV Acc<N> core_c3(const S& src, int shift) {
+// SC > 0 (with shift + SC = 16) scales the table by 2^SC and returns an
+// AccHi: RS(2^SC v, 16) = RS(v, shift) exactly.  The caller guarantees the
+// bounds: |2^SC v| < 2^31 and |RS(v, shift)| < 2^15 for its inputs.
+template <int N, bool IREV, bool OSIGN, int SC = 0, class S>
+TA_DEV auto core_c3(const S& src, int shift) {
+  constexpr int F = 1 << SC;
   const Rev<N, IREV, S> w{src};
-  const int off = 1 << (shift - 1);
-  Acc<N> r;
-  r.s0 = r.s1 = shift;
+  const int off = 1 << (shift + SC - 1);
+  std::conditional_t<(SC > 0), AccHi<N>, Acc<N>> r;
+  if constexpr (SC == 0) r.s0 = r.s1 = shift;
   int ee[N / 2];
-  c3_even<N, N / 2, !OSIGN>(w, ee, off);
+  c3_even<N, N / 2, !OSIGN, SC>(w, ee, off);
 #pragma unroll
   for (int n = 0; n < N / 2; ++n) {
-    const int sg = (OSIGN && (n & 1)) ? -1 : 1;
+    const int sg = (OSIGN && (n & 1)) ? -F : F;
     int o = 0;
 #pragma unroll
     for (int i = 0; i < N / 4; ++i) {
@@ -353,14 +373,16 @@ TA_DEV Acc<N> core_direct(const S& src, int shift) {
 // DEEP_INV: the inverse's DCT-2 cores also try the deeper packed levels (the
 // forward's always do: they see residual-sized inputs); worth it for the
 // 32- and 64-point passes of the packed kernels, whose inputs mostly fit
-template <int N, int CORE, bool TR, bool DEEP_INV = false, class S>
-TA_DEV Acc<N> core(const S& src, int shift) {
+// SC: see core_c3 (DCT-3 / DST-3 cores only).
+template <int N, int CORE, bool TR, bool DEEP_INV = false, int SC = 0, class S>
+TA_DEV auto core(const S& src, int shift) {
   constexpr int C = (CORE == C_DST7 || CORE == C_DCT8) ? CORE : (TR ? core_transpose(CORE) : CORE);
   constexpr bool DEEP = !TR || DEEP_INV;
+  static_assert(SC == 0 || C == C_DCT3 || C == C_DST3, "scaled results are built for the DCT-3 butterfly only");
   if constexpr (C == C_DCT2) return core_c2<N, false, false, DEEP>(src, shift);
   else if constexpr (C == C_DST2) return core_c2<N, true, true, DEEP>(src, shift);
-  else if constexpr (C == C_DCT3) return core_c3<N, false, false>(src, shift);
-  else if constexpr (C == C_DST3) return core_c3<N, true, true>(src, shift);
+  else if constexpr (C == C_DCT3) return core_c3<N, false, false, SC>(src, shift);
+  else if constexpr (C == C_DST3) return core_c3<N, true, true, SC>(src, shift);
   else return core_direct<N, C, TR>(src, shift);
 }
 
@@ -423,15 +445,18 @@ struct Axis {
 
 // Run the forward (INV = false) or inverse pass of axis AX on `in`.
 // pf: forward parameters (band taps / Q pairs), pi: transposed parameters.
-template <int N, class AX, bool INV, bool DEEP_INV = false, class S>
+// SC (forward passes whose core is a DCT-3 or DST-3): the core's result is
+// scaled to a shift of 16 (see core_c3); 0 leaves it as is.
+template <int N, class AX, bool INV, bool DEEP_INV = false, int SC = 0, class S>
 TA_DEV auto run_pass(const S& in, cparam pf, cparam pi,
                      int s_core, int a) {
+  static_assert(SC == 0 || (!INV && AX::ADJ != ADJ_POST), "scaled results: forward band or plain passes only");
   if constexpr (AX::ADJ == ADJ_NONE) {
-    return core<N, AX::CORE, INV, DEEP_INV>(in, s_core);
+    return core<N, AX::CORE, INV, DEEP_INV, SC>(in, s_core);
   } else if constexpr (AX::ADJ == ADJ_BAND) {
     if constexpr (!INV) {
       const Acc<N> u = band<N, AX::KB, false>(in, pf, a);
-      return core<N, AX::CORE, false>(u, s_core);
+      return core<N, AX::CORE, false, false, SC>(u, s_core);
     } else {
       const Acc<N> u = core<N, AX::CORE, true, DEEP_INV>(in, s_core);
       return band<N, AX::KB, true>(u, pi, a);

@@ -114,6 +114,14 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
 
   // column pass (vertical transform of every column); PC is dead once every
   // thread has read its column, then the same LDS holds RM
+  // The column pass ends the forward.  With a DCT-3 / DST-3 core (band or no
+  // adjustment) its table is scaled by 2^(8 - LH), so that its shift
+  // s_col = LH + m becomes 16 (the contexts fix m = 8) and each output pair
+  // packs with one permute: for every int16 input the scaled sums stay below
+  // 2^31 and the results inside int16, because a column of the integer DCT-2
+  // has an L1 norm below H * 2^8 (7449 < 8192 at H = 32).
+  constexpr bool SCALED = (AV::CORE == C_DCT3 || AV::CORE == C_DST3) && AV::ADJ != ADJ_POST;
+  constexpr int SCV = SCALED ? 8 - LH : 0;
   uint32_t o[H / 2];
   const int cb = T::XCOL ? (tid >> 4) & 3 : tid / W;                  // column thread -> block
   const int cc = T::XCOL ? ((tid >> 6) << 4) | (tid & 15) : tid % W;  // and column
@@ -121,7 +129,7 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
     PV z;
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) z.p[i] = pc[cb * T::PCB + i * T::PP + cc];
-    const auto y = fx::run_pass<H, AV, false>(z, pv_f, pv_i, p.s_col, p.a);
+    const auto y = fx::run_pass<H, AV, false, false, SCV>(z, pv_f, pv_i, p.s_col, p.a);
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
   }
