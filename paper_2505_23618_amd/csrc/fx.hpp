@@ -199,11 +199,13 @@ TA_DEV auto core_c3(const S& src, int shift) {
 // N/2-point and smaller levels on int32 partial sums (|v| < 2^21) with 24-bit
 // multiply-adds.  With NEG_ODD the transform input is u[n] = -v[n] for odd n
 // (the sign is folded into the first level's additions and coefficients).
-template <int M, bool NEG_ODD = false>
+// SC scales every table entry by 2^SC (see core_c2).
+template <int M, bool NEG_ODD = false, int SC = 0>
 TA_DEV void c2_int(const int (&v)[M], int (&z)[M], int off) {
+  constexpr int F = 1 << SC;
   if constexpr (M == 2) {
-    z[0] = ((NEG_ODD ? v[0] - v[1] : v[0] + v[1]) << 8) + off;     // row 0 = 2^8
-    z[1] = ((NEG_ODD ? v[0] + v[1] : v[0] - v[1]) << 8) + off;     // 2-point row 1 = (+2^8, -2^8)
+    z[0] = ((NEG_ODD ? v[0] - v[1] : v[0] + v[1]) << (8 + SC)) + off;     // row 0 = 2^8
+    z[1] = ((NEG_ODD ? v[0] + v[1] : v[0] - v[1]) << (8 + SC)) + off;     // 2-point row 1 = (+2^8, -2^8)
   } else {
     int e[M / 2], o[M / 2];
 #pragma unroll
@@ -224,11 +226,11 @@ TA_DEV void c2_int(const int (&v)[M], int (&z)[M], int off) {
       int acc = off;
 #pragma unroll
       for (int n = 0; n < M / 2; ++n)
-        acc = mad24(o[n], (NEG_ODD && (n & 1)) ? -c2i<M>(k, n) : c2i<M>(k, n), acc);
+        acc = mad24(o[n], (NEG_ODD && (n & 1)) ? -F * c2i<M>(k, n) : F * c2i<M>(k, n), acc);
       z[k] = acc;
     }
     int ze[M / 2];
-    c2_int<M / 2>(e, ze, off);
+    c2_int<M / 2, false, SC>(e, ze, off);
 #pragma unroll
     for (int k = 0; k < M / 2; ++k) z[2 * k] = ze[k];
   }
@@ -254,9 +256,9 @@ TA_DEV void unpack_pairs(const uint32_t (&p)[M / 2], int (&v)[M]) {
 // way while the wave's e values stay within +-2^14 (forward passes, whose
 // inputs are residual-sized); otherwise, and below 4 points, it continues
 // on int32 with 24-bit multiply-adds.  z[k] gets the exact sum plus off.
-template <int M, bool NEG, bool DEEP>
+template <int M, bool NEG, bool DEEP, int SC = 0>
 TA_DEV void c2_packed(const uint32_t (&x)[M / 2], int (&z)[M], int off) {
-  constexpr int SG = NEG ? -1 : 1;
+  constexpr int SG = NEG ? -1 : 1, F = 1 << SC;
   uint32_t dp[M / 4], ep[M / 4];
 #pragma unroll
   for (int s = 0; s < M / 4; ++s) {
@@ -269,7 +271,7 @@ TA_DEV void c2_packed(const uint32_t (&x)[M / 2], int (&z)[M], int off) {
     int acc = off;
 #pragma unroll
     for (int s = 0; s < M / 4; ++s) {
-      const uint32_t cf = pk2(c2i<M>(k, 2 * s), SG * c2i<M>(k, 2 * s + 1));
+      const uint32_t cf = pk2(F * c2i<M>(k, 2 * s), SG * F * c2i<M>(k, 2 * s + 1));
       acc = s == 0 ? dot2h(dp[s], cf, off) : dot2(dp[s], cf, acc);
     }
     z[k] = acc;
@@ -278,14 +280,14 @@ TA_DEV void c2_packed(const uint32_t (&x)[M / 2], int (&z)[M], int off) {
   bool packed = false;
   if constexpr (DEEP && M / 2 >= 4) {
     if (wave_all(lanes_within_14(ep))) {
-      c2_packed<M / 2, NEG, DEEP>(ep, ze, off);
+      c2_packed<M / 2, NEG, DEEP, SC>(ep, ze, off);
       packed = true;
     }
   }
   if (!packed) {
     int e[M / 2];
     unpack_pairs<M / 2>(ep, e);
-    c2_int<M / 2, NEG>(e, ze, off);
+    c2_int<M / 2, NEG, SC>(e, ze, off);
   }
 #pragma unroll
   for (int k = 0; k < M / 2; ++k) z[2 * k] = ze[k];
@@ -298,11 +300,14 @@ TA_DEV void c2_packed(const uint32_t (&x)[M / 2], int (&z)[M], int off) {
 // DEEP, deeper levels) in int16; otherwise the odd rows are taken as
 // full-length dot products of the input pairs and e is formed in int32.
 // Both give the same exact integer sums.
-template <int N, bool ISIGN, bool OREV, bool DEEP, class S>
-TA_DEV Acc<N> core_c2(const S& src, int shift) {
-  const int off = 1 << (shift - 1);
-  Acc<N> r;
-  r.s0 = r.s1 = shift;
+// SC > 0 (with shift + SC = 16) scales the table by 2^SC and returns an
+// AccHi, under the same caller guarantees as core_c3.
+template <int N, bool ISIGN, bool OREV, bool DEEP, int SC = 0, class S>
+TA_DEV auto core_c2(const S& src, int shift) {
+  constexpr int F = 1 << SC;
+  const int off = 1 << (shift + SC - 1);
+  std::conditional_t<(SC > 0), AccHi<N>, Acc<N>> r;
+  if constexpr (SC == 0) r.s0 = r.s1 = shift;
   uint32_t x[N / 2];
 #pragma unroll
   for (int s = 0; s < N / 2; ++s) x[s] = src.pair(2 * s, 2 * s + 1);
@@ -311,14 +316,14 @@ TA_DEV Acc<N> core_c2(const S& src, int shift) {
   constexpr int SG = ISIGN ? -1 : 1;
   int z[N];
   if (wave_all(lanes_within_14(x))) {
-    c2_packed<N, ISIGN, DEEP>(x, z, off);
+    c2_packed<N, ISIGN, DEEP, SC>(x, z, off);
   } else {
 #pragma unroll
     for (int k = 1; k < N; k += 2) {
       int acc = off;
 #pragma unroll
       for (int s = 0; s < N / 2; ++s) {
-        const uint32_t cf = pk2(c2i<N>(k, 2 * s), SG * c2i<N>(k, 2 * s + 1));
+        const uint32_t cf = pk2(F * c2i<N>(k, 2 * s), SG * F * c2i<N>(k, 2 * s + 1));
         acc = s == 0 ? dot2h(x[s], cf, off) : dot2(x[s], cf, acc);
       }
       z[k] = acc;
@@ -332,7 +337,7 @@ TA_DEV Acc<N> core_c2(const S& src, int shift) {
       e[n] = ISIGN ? a - b : a + b;
     }
     int ze[N / 2];
-    c2_int<N / 2, ISIGN>(e, ze, off);
+    c2_int<N / 2, ISIGN, SC>(e, ze, off);
 #pragma unroll
     for (int k = 0; k < N / 2; ++k) z[2 * k] = ze[k];
   }
@@ -373,14 +378,15 @@ TA_DEV Acc<N> core_direct(const S& src, int shift) {
 // DEEP_INV: the inverse's DCT-2 cores also try the deeper packed levels (the
 // forward's always do: they see residual-sized inputs); worth it for the
 // 32- and 64-point passes of the packed kernels, whose inputs mostly fit
-// SC: see core_c3 (DCT-3 / DST-3 cores only).
+// SC: see core_c3 and core_c2 (butterfly cores only).
 template <int N, int CORE, bool TR, bool DEEP_INV = false, int SC = 0, class S>
 TA_DEV auto core(const S& src, int shift) {
   constexpr int C = (CORE == C_DST7 || CORE == C_DCT8) ? CORE : (TR ? core_transpose(CORE) : CORE);
   constexpr bool DEEP = !TR || DEEP_INV;
-  static_assert(SC == 0 || C == C_DCT3 || C == C_DST3, "scaled results are built for the DCT-3 butterfly only");
-  if constexpr (C == C_DCT2) return core_c2<N, false, false, DEEP>(src, shift);
-  else if constexpr (C == C_DST2) return core_c2<N, true, true, DEEP>(src, shift);
+  static_assert(SC == 0 || C == C_DCT2 || C == C_DST2 || C == C_DCT3 || C == C_DST3,
+                "scaled results are built for the butterfly cores only");
+  if constexpr (C == C_DCT2) return core_c2<N, false, false, DEEP, SC>(src, shift);
+  else if constexpr (C == C_DST2) return core_c2<N, true, true, DEEP, SC>(src, shift);
   else if constexpr (C == C_DCT3) return core_c3<N, false, false, SC>(src, shift);
   else if constexpr (C == C_DST3) return core_c3<N, true, true, SC>(src, shift);
   else return core_direct<N, C, TR>(src, shift);
@@ -445,12 +451,13 @@ struct Axis {
 
 // Run the forward (INV = false) or inverse pass of axis AX on `in`.
 // pf: forward parameters (band taps / Q pairs), pi: transposed parameters.
-// SC (forward passes whose core is a DCT-3 or DST-3): the core's result is
-// scaled to a shift of 16 (see core_c3); 0 leaves it as is.
+// SC (band or plain passes with a butterfly core): the core's result is
+// scaled to a shift of 16 (see core_c3, core_c2); 0 leaves it as is.  The
+// caller guarantees s_core + SC = 16 and the bounds for its inputs.
 template <int N, class AX, bool INV, bool DEEP_INV = false, int SC = 0, class S>
 TA_DEV auto run_pass(const S& in, cparam pf, cparam pi,
                      int s_core, int a) {
-  static_assert(SC == 0 || (!INV && AX::ADJ != ADJ_POST), "scaled results: forward band or plain passes only");
+  static_assert(SC == 0 || AX::ADJ != ADJ_POST, "scaled results: band or plain passes only");
   if constexpr (AX::ADJ == ADJ_NONE) {
     return core<N, AX::CORE, INV, DEEP_INV, SC>(in, s_core);
   } else if constexpr (AX::ADJ == ADJ_BAND) {
@@ -458,7 +465,7 @@ TA_DEV auto run_pass(const S& in, cparam pf, cparam pi,
       const Acc<N> u = band<N, AX::KB, false>(in, pf, a);
       return core<N, AX::CORE, false, false, SC>(u, s_core);
     } else {
-      const Acc<N> u = core<N, AX::CORE, true, DEEP_INV>(in, s_core);
+      const auto u = core<N, AX::CORE, true, DEEP_INV, SC>(in, s_core);
       return band<N, AX::KB, true>(u, pi, a);
     }
   } else {

@@ -231,7 +231,15 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   __syncthreads();
 
   // row pass (inverse horizontal transform); the rows go back to RM and
-  // leave the tile with coalesced 16-byte stores
+  // leave the tile with coalesced 16-byte stores.  At bit depth 8 the row
+  // shift m + 14 - bd is 14 (the contexts fix m = 8): a butterfly core of
+  // up to 32 points then runs with its table scaled by 4 (shift 16, see
+  // core_c2 / core_c3): the sums stay within 4 * W * 2^8 * 2^15 <= 2^30 and
+  // the results within W * 2^8 * 2^15 / 2^14 <= 2^14 for every int16 input.
+  constexpr bool ROW_SC = W <= 32 && AH::ADJ != ADJ_POST &&
+                          (AH::CORE == C_DCT2 || AH::CORE == C_DST2 || AH::CORE == C_DCT3 || AH::CORE == C_DST3);
+  auto row_pass = [&](auto sc) {
+  constexpr int SC = decltype(sc)::value;
   if (T::ROWS_ALL || tid < NB * H) {
     const int b = tid / H, r = tid % H;
     PH x;
@@ -246,7 +254,7 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
       const uint2 v = *reinterpret_cast<const uint2*>(s);
       x.p[0] = v.x; x.p[1] = v.y;
     }
-    const auto y = fx::run_pass<W, AH, true, (W >= 32)>(x, ph_f, ph_i, p.s_row, p.a);
+    const auto y = fx::run_pass<W, AH, true, (W >= 32), SC>(x, ph_f, ph_i, p.s_row, p.a);
     // the result goes back over this thread's own row of RM
     uint16_t* d = rm + b * T::RMBI + r * T::RPI;
     uint32_t o2[W / 2];
@@ -259,6 +267,15 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
     } else {
       *reinterpret_cast<uint2*>(d) = make_uint2(o2[0], o2[1]);
     }
+  }
+  };
+  if constexpr (ROW_SC) {
+    if (p.s_row == 14)
+      row_pass(std::integral_constant<int, 2>{});
+    else
+      row_pass(std::integral_constant<int, 0>{});
+  } else {
+    row_pass(std::integral_constant<int, 0>{});
   }
   __syncthreads();
   // coalesced store of the tile from RM: chunk tid + 256 k

@@ -61,8 +61,8 @@ ALL_CASES = {**CASES, **F32_ONLY}
 class Registered:
     """A context with every frozen parameter set and every case's axes."""
 
-    def __init__(self, device=0):
-        self.ctx = ta.Context(device)
+    def __init__(self, device=0, bit_depth=8):
+        self.ctx = ta.Context(device, bit_depth=bit_depth)
         self.ids = ta.load_params(self.ctx)
         self.params = ta.load_param_file()
         self.axes = {}
