@@ -198,12 +198,15 @@ int ta_fwd_multi(ta_ctx* ctx, int param_id, int log2n, int64_t nblocks, const vo
  * (asynchronous, no allocation, capturable in a HIP graph).
  * ta_plan_autotune times the tile mappings (frame regions of 2^18 .. 2^22
  * input elements per XCD tile list) times the persistent grid sizes (256 ..
- * 8192 workgroups) on the given buffers, checks that every candidate's
- * output is bitwise identical, and keeps the fastest (synchronous, host
- * scratch; runs the forward).  It rewrites the plan's device tile list in
- * place: launches captured in a HIP graph before it must be captured again.
- * ta_plan_tuning reports the chosen grid and region (log2 elements).  Blocks
- * must not overlap in `out`. */
+ * 8192 workgroups) on the given buffers, each launch after a 512 MiB cache
+ * flush (a batch streams through HBM once per call), checks that every
+ * candidate's output is bitwise identical, and keeps the fastest
+ * (synchronous; allocates 512 MiB of scratch while it runs; runs the
+ * forward).  ta_plan_set_tuning applies a known grid (>= 8) and region
+ * (log2 input elements, 12..40) without timing (synchronous).  Both rewrite
+ * the plan's device tile list in place: launches captured in a HIP graph
+ * before must be captured again.  ta_plan_tuning reports the grid and
+ * region in use.  Blocks must not overlap in `out`. */
 typedef struct ta_plan ta_plan;
 int ta_plan_create(ta_ctx* ctx, const ta_block* blocks_host, int64_t n, int dtype, ta_plan** out);
 int ta_plan_destroy(ta_plan* plan);
@@ -212,6 +215,7 @@ int ta_plan_fwd(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream
 int ta_plan_inv(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream);
 int ta_plan_autotune(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream, int reps);
 int ta_plan_tuning(const ta_plan* plan, int* grid, int* region_log2);
+int ta_plan_set_tuning(ta_plan* plan, int grid, int region_log2);
 
 /* Unplanned block lists.  ta_transform_fwd / _inv run nblocks descriptors
  * that are already in device memory (blocks_dev, 8-byte aligned, read as

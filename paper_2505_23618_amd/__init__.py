@@ -39,7 +39,7 @@ EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis
            "ta_plan_autotune", "ta_givens_workspace", "ta_givens_fwd", "ta_givens_bwd",
            "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats", "ta_design_search",
            "ta_transform_fwd", "ta_transform_inv", "ta_validate_blocks", "ta_set_axis_cfg", "ta_set_params",
-           "ta_plan_tuning")
+           "ta_plan_tuning", "ta_plan_set_tuning")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -96,6 +96,7 @@ def lib() -> ctypes.CDLL:
     L.ta_plan_inv.argtypes = [vp, vp, vp, vp, vp]
     L.ta_plan_autotune.argtypes = [vp, vp, vp, vp, vp, i32]
     L.ta_plan_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.ta_plan_set_tuning.argtypes = [vp, i32, i32]
     L.ta_givens_workspace.argtypes = [i64, ctypes.POINTER(i64)]
     L.ta_givens_fwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp]
     L.ta_givens_bwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -396,6 +397,10 @@ class Plan:
         _check(lib().ta_plan_inv(self.ctx._h, self._h, ctypes.c_void_p(y.data_ptr()),
                                  ctypes.c_void_p(out.data_ptr()), sh))
         return out
+
+    def set_tuning(self, grid: int, region_log2: int):
+        _check(lib().ta_plan_set_tuning(self._h, grid, region_log2))
+        return self.info()
 
     def autotune(self, x, out, reps: int = 3):
         _check(lib().ta_plan_autotune(self.ctx._h, self._h, ctypes.c_void_p(x.data_ptr()),

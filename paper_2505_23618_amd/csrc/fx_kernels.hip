@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
     PV z;
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) z.p[i] = pc[cb * T::PCB + i * T::PP + cc];
-    const auto y = fx::run_pass<H, AV, false, false, SCV>(z, pv_f, pv_i, p.s_col, p.a);
+    const auto y = fx::run_pass_sc<H, AV, false, false, SCV>(z, pv_f, pv_i, p.s_col, p.a);
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
   }
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
       const uint2 v = *reinterpret_cast<const uint2*>(s);
       x.p[0] = v.x; x.p[1] = v.y;
     }
-    const auto y = fx::run_pass<W, AH, true, (W >= 32), SC>(x, ph_f, ph_i, p.s_row, p.a);
+    const auto y = fx::run_pass_sc<W, AH, true, (W >= 32), SC>(x, ph_f, ph_i, p.s_row, p.a);
     // the result goes back over this thread's own row of RM
     uint16_t* d = rm + b * T::RMBI + r * T::RPI;
     uint32_t o2[W / 2];
