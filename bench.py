@@ -351,7 +351,11 @@ def _refit(ctx, res):
         loss.backward()
 
     t = _events_mean(step, 20, warm=3)
-    res["refit_step"] = {"us": t * 1e6, "vectors": 131072, "angles": 31,
+    # the same step captured once in a HIP graph and replayed
+    th2 = torch.zeros(31, dtype=torch.float32, device="cuda", requires_grad=True)
+    graphed = RF.GraphedRefitStep(xv, th2, ctx)
+    tg = _events_mean(lambda i: graphed.replay(), 20, warm=3)
+    res["refit_step"] = {"us": t * 1e6, "graph_replay_us": tg * 1e6, "vectors": 131072, "angles": 31,
                          "what": "fp32 forward (data + basis) + loss + backward (adjoint and angle gradients)"}
 
 

@@ -71,14 +71,60 @@ def dst7_rows(n: int, device) -> torch.Tensor:
     return d.to(device=device, dtype=torch.float32)
 
 
+_CONSTS = {}
+
+
+def _consts(n: int, device):
+    """The identity and the exact DST-7 rows of size n on `device`, built once
+    (a step then launches no host-to-device copy)."""
+    key = (n, str(device))
+    if key not in _CONSTS:
+        _CONSTS[key] = (torch.eye(n, device=device, dtype=torch.float32), dst7_rows(n, device))
+    return _CONSTS[key]
+
+
 def refit_loss(x, theta, tctx, base=DCT2, taps=4, p=8, lam=1.0):
     """Basis term + lam * energy-compaction term (see the module docstring)."""
     n = x.shape[1]
-    eye = torch.eye(n, device=x.device, dtype=torch.float32)
+    eye, d = _consts(n, x.device)
     ht = adjusted(eye, theta, tctx, base, taps)          # row j = H e_j = column j of H
     h = ht.t()
-    d = dst7_rows(n, x.device)
     basis = ((h[:p] - d[:p]) ** 2).sum()
     y = adjusted(x, theta, tctx, base, taps)
     energy = lam * (1.0 - (y[:, :p] ** 2).sum() / (x ** 2).sum())
     return basis + energy, basis, energy
+
+
+class GraphedRefitStep:
+    """One refit step (refit_loss forward and backward) captured once in a HIP
+    graph and replayed: replay() recomputes the loss terms and theta.grad for
+    the current contents of x and theta, which must stay the same tensors
+    (update them in place, and leave theta.grad in place: the graph writes
+    that tensor).  Launch overhead is what dominates an eager step on a
+    cache-resident batch; the replay issues the same kernels as one graph."""
+
+    def __init__(self, x, theta, tctx, base=DCT2, taps=4, p=8, lam=1.0, warmup=2):
+        self.x, self.theta = x, theta
+        args = (tctx, base, taps, p, lam)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                theta.grad = None
+                # no reference to the warm-up's loss terms survives the loop, so
+                # the capture does not find their autograd graph (and the
+                # angles' gradient accumulator made on this stream) alive
+                refit_loss(x, theta, *args)[0].backward()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        theta.grad = None
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.loss, self.basis, self.energy = refit_loss(x, theta, *args)
+            self.loss.backward()
+        self.grad = theta.grad
+
+    def replay(self):
+        self.graph.replay()
+        return self.loss
+

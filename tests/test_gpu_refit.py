@@ -103,3 +103,27 @@ def test_refit_lowers_the_loss(tctx):
     lt = R.loss(th.detach().cpu().numpy().astype(np.float64), x.cpu().numpy().astype(np.float64))
     loss, _, _ = RF.refit_loss(x, th, tctx)
     assert abs(loss.item() - lt) <= 1e-5 * max(1.0, abs(lt))
+
+
+def test_graphed_step_matches_eager_on_every_replay(tctx):
+    """The captured step, replayed with the angles updated in place between
+    replays (and eager work in between), gives the eager loss and gradient
+    each time, and the oracle's within the fp32 tolerances."""
+    xh = _vectors(131072)
+    x = torch.tensor(xh, dtype=torch.float32, device="cuda")
+    th = torch.tensor(np.linspace(-0.2, 0.25, 31), dtype=torch.float32, device="cuda", requires_grad=True)
+    step = RF.GraphedRefitStep(x, th, tctx)
+    for rep in range(4):
+        with torch.no_grad():
+            th.add_(0.01 * (rep + 1))                   # new angles, same tensor
+        loss = step.replay().item()
+        g = th.grad.clone()
+        t = th.detach().clone().requires_grad_(True)      # eager reference at the same angles
+        le, _, _ = RF.refit_loss(x, t, tctx)
+        le.backward()
+        torch.cuda.synchronize()
+        assert abs(loss - le.item()) <= 1e-6 * max(1.0, abs(le.item())), f"replay {rep} loss"
+        assert torch.allclose(g, t.grad, rtol=1e-6, atol=1e-7 * t.grad.abs().max().item()), f"replay {rep} grad"
+        thn = th.detach().cpu().numpy().astype(np.float64)
+        gref = R.grad(thn, xh)
+        assert np.abs(g.cpu().numpy() - gref).max() <= 1e-4 * np.abs(gref).max(), f"replay {rep} vs oracle"
