@@ -372,8 +372,9 @@ def main():
                     help="also launch one plain copy per step (counter calibration runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(blocks are independent; see DESIGN.md for how the batch would shard)", file=sys.stderr)
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported "
+              "(blocks are independent: a batch would shard into contiguous, coefficient-balanced block "
+              "ranges, one per GPU, with no exchange between them)", file=sys.stderr)
         sys.exit(2)
 
     import torch
