@@ -133,3 +133,26 @@ def test_full_workload_sampled(env):
         f, bx, by, w, h = (int(v) for v in rows[i, :5])
         assert (yc[f, by:by + h, bx:bx + w] == ref[f, by:by + h, bx:bx + w]).all(), f"block {i}"
         assert (zc[f, by:by + h, bx:bx + w] == refi[f, by:by + h, bx:bx + w]).all(), f"block {i} inverse"
+
+
+def test_set_tuning_keeps_outputs_bitwise(env):
+    ctx, params = env
+    frames, rows = small_workload()
+    plan = ta.Plan(ctx, descriptors(rows, frames.shape[1], frames.shape[2]))
+    x = torch.from_numpy(frames).cuda()
+    y0, z0 = torch.zeros_like(x), torch.zeros_like(x)
+    plan.fwd(x, y0)
+    plan.inv(y0, z0)
+    for grid, region in ((8, 12), (256, 18), (1024, 20), (8192, 22), (4096, 30)):
+        info = plan.set_tuning(grid, region)
+        assert info["grid"] == grid and info["region_log2"] == region
+        y, z = torch.full_like(x, 5), torch.full_like(x, -5)
+        plan.fwd(x, y)
+        plan.inv(y0, z)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y0) and torch.equal(z, z0), f"grid {grid} region {region}"
+    assert (y0.cpu().numpy() == oracle_frames(frames, rows, params)).all()
+    for grid, region in ((4, 20), (1024, 11), (1024, 41)):
+        with pytest.raises(ta.TadjError) as e:
+            plan.set_tuning(grid, region)
+        assert e.value.code == ta.TA_EINVAL
