@@ -11,6 +11,7 @@
 #include <tuple>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -30,6 +31,19 @@ int fail(int code, const char* fmt, ...) {
   va_end(ap);
   g_err = buf;
   return code;
+}
+
+// Host allocations sized by the caller (descriptor copies, plan state,
+// comparison buffers) must not let an exception cross the C ABI.
+template <class F>
+int guard(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(TA_EINVAL, "host memory allocation failed (sizes too large?)");
+  } catch (...) {
+    return fail(TA_EHIP, "unexpected host exception");
+  }
 }
 
 #define TA_HIP(call)                                                                   \
@@ -621,37 +635,39 @@ int build_tiles(ta_plan* plan, int region_log2) {
 extern "C" {
 
 int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_plan** out) {
-  if (!c || !out || (n > 0 && !blocks)) return fail(TA_EINVAL, "null argument");
-  *out = nullptr;
-  if (n < 0) return fail(TA_EINVAL, "negative block count");
-  if (dtype != TA_I16 && dtype != TA_F32) return fail(TA_EINVAL, "unknown dtype %d", dtype);
-  auto plan = std::make_unique<ta_plan>();
-  plan->device = c->device;
-  plan->dtype = dtype;
-  plan->host.assign(blocks, blocks + n);
-  plan->cls.resize((size_t)n);
-  std::map<std::tuple<int, int, const void*, const void*, const void*, const void*>, uint32_t> class_of;
-  for (int64_t i = 0; i < n; ++i) {
-    const ta_block& b = blocks[i];
-    Resolved rh, rv;
-    int kh, kv, e;
-    if ((e = check_block(c, b, i, dtype, &rh, &rv, &kh, &kv))) return e;
-    const auto key = std::make_tuple(kh, kv, rh.pf, rh.pi, rv.pf, rv.pi);
-    auto it = class_of.find(key);
-    if (it == class_of.end()) {
-      it = class_of.emplace(key, (uint32_t)plan->classes.size()).first;
-      plan->classes.push_back(ta_plan::Class{kh, kv, rh.pf, rh.pi, rv.pf, rv.pi});
+  return guard([&]() -> int {
+    if (!c || !out || (n > 0 && !blocks)) return fail(TA_EINVAL, "null argument");
+    *out = nullptr;
+    if (n < 0) return fail(TA_EINVAL, "negative block count");
+    if (dtype != TA_I16 && dtype != TA_F32) return fail(TA_EINVAL, "unknown dtype %d", dtype);
+    auto plan = std::make_unique<ta_plan>();
+    plan->device = c->device;
+    plan->dtype = dtype;
+    plan->host.assign(blocks, blocks + n);
+    plan->cls.resize((size_t)n);
+    std::map<std::tuple<int, int, const void*, const void*, const void*, const void*>, uint32_t> class_of;
+    for (int64_t i = 0; i < n; ++i) {
+      const ta_block& b = blocks[i];
+      Resolved rh, rv;
+      int kh, kv, e;
+      if ((e = check_block(c, b, i, dtype, &rh, &rv, &kh, &kv))) return e;
+      const auto key = std::make_tuple(kh, kv, rh.pf, rh.pi, rv.pf, rv.pi);
+      auto it = class_of.find(key);
+      if (it == class_of.end()) {
+        it = class_of.emplace(key, (uint32_t)plan->classes.size()).first;
+        plan->classes.push_back(ta_plan::Class{kh, kv, rh.pf, rh.pi, rv.pf, rv.pi});
+      }
+      plan->cls[(size_t)i] = it->second;
+      const int w = 1 << b.log2w, h = 1 << b.log2h;
+      plan->max_in_elem = std::max<int64_t>(plan->max_in_elem, b.in_off + (int64_t)(h - 1) * b.in_stride + w);
+      plan->max_out_elem = std::max<int64_t>(plan->max_out_elem, b.out_off + (int64_t)(h - 1) * b.out_stride + w);
     }
-    plan->cls[(size_t)i] = it->second;
-    const int w = 1 << b.log2w, h = 1 << b.log2h;
-    plan->max_in_elem = std::max<int64_t>(plan->max_in_elem, b.in_off + (int64_t)(h - 1) * b.in_stride + w);
-    plan->max_out_elem = std::max<int64_t>(plan->max_out_elem, b.out_off + (int64_t)(h - 1) * b.out_stride + w);
-  }
-  plan->nblocks = n;
-  int e;
-  if ((e = build_tiles(plan.get(), plan->region_log2))) return e;
-  *out = plan.release();
-  return TA_OK;
+    plan->nblocks = n;
+    int e;
+    if ((e = build_tiles(plan.get(), plan->region_log2))) return e;
+    *out = plan.release();
+    return TA_OK;
+  });
 }
 
 int ta_plan_destroy(ta_plan* p) {
@@ -695,79 +711,83 @@ int ta_plan_inv(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t st
 }
 
 int ta_plan_autotune(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t stream, int reps) {
-  if (!c || !p) return fail(TA_EINVAL, "null argument");
-  if (p->ntiles == 0) return TA_OK;
-  if (!in || !out) return fail(TA_EINVAL, "null buffer");
-  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
-  if (reps < 1) reps = 3;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  TA_HIP(hipSetDevice(c->device));
-  // every candidate's output is checked bitwise against the first one's
-  const size_t bytes = (size_t)p->max_out_elem * (p->dtype == TA_F32 ? sizeof(float) : sizeof(int16_t));
-  std::vector<char> ref(bytes), got(bytes);
-  // A frame batch streams through HBM once per call, so each timed launch
-  // starts from cold caches: a 512 MiB write (more than the L2s and the
-  // Infinity Cache hold) runs before it.
-  constexpr size_t kFlush = size_t(512) << 20;
-  void* flush = nullptr;
-  TA_HIP(hipMalloc(&flush, kFlush));
-  const int regions[] = {18, 19, 20, 21, 22};     // tile mapping: frame-region size of the XCD lists
-  const int grids[] = {256, 512, 1024, 2048, 4096, 8192};
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  int rc = TA_OK;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(TA_EHIP, "event create failed");
-  float best = 1e30f;
-  const int orig_region = p->region_log2;
-  int best_grid = p->grid, best_region = orig_region;
-  bool have_ref = false;
-  for (int region : regions) {
-    if (rc != TA_OK) break;
-    if ((rc = build_tiles(p, region))) break;
-    for (int g : grids) {
-      if ((rc = launch_plan(c, p, 0, in, out, stream, g))) break;
-      float total = 0.0f;
-      for (int r = 0; r < reps && rc == TA_OK; ++r) {
-        if (hipMemsetAsync(flush, r & 0xff, kFlush, s) != hipSuccess) { rc = fail(TA_EHIP, "autotune flush failed"); break; }
-        (void)hipEventRecord(e0, s);
-        if ((rc = launch_plan(c, p, 0, in, out, stream, g))) break;
-        (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(TA_EHIP, "autotune sync failed"); break; }
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        total += ms;
-      }
+  return guard([&]() -> int {
+    if (!c || !p) return fail(TA_EINVAL, "null argument");
+    if (p->ntiles == 0) return TA_OK;
+    if (!in || !out) return fail(TA_EINVAL, "null buffer");
+    if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
+    if (reps < 1) reps = 3;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    TA_HIP(hipSetDevice(c->device));
+    // every candidate's output is checked bitwise against the first one's
+    const size_t bytes = (size_t)p->max_out_elem * (p->dtype == TA_F32 ? sizeof(float) : sizeof(int16_t));
+    std::vector<char> ref(bytes), got(bytes);
+    // A frame batch streams through HBM once per call, so each timed launch
+    // starts from cold caches: a 512 MiB write (more than the L2s and the
+    // Infinity Cache hold) runs before it.
+    constexpr size_t kFlush = size_t(512) << 20;
+    void* flush = nullptr;
+    TA_HIP(hipMalloc(&flush, kFlush));
+    const int regions[] = {18, 19, 20, 21, 22};     // tile mapping: frame-region size of the XCD lists
+    const int grids[] = {256, 512, 1024, 2048, 4096, 8192};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = TA_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(TA_EHIP, "event create failed");
+    float best = 1e30f;
+    const int orig_region = p->region_log2;
+    int best_grid = p->grid, best_region = orig_region;
+    bool have_ref = false;
+    for (int region : regions) {
       if (rc != TA_OK) break;
-      if (hipMemcpy(have_ref ? got.data() : ref.data(), out, bytes, hipMemcpyDeviceToHost) != hipSuccess) {
-        rc = fail(TA_EHIP, "autotune copy failed");
-        break;
+      if ((rc = build_tiles(p, region))) break;
+      for (int g : grids) {
+        if ((rc = launch_plan(c, p, 0, in, out, stream, g))) break;
+        float total = 0.0f;
+        for (int r = 0; r < reps && rc == TA_OK; ++r) {
+          if (hipMemsetAsync(flush, r & 0xff, kFlush, s) != hipSuccess) { rc = fail(TA_EHIP, "autotune flush failed"); break; }
+          (void)hipEventRecord(e0, s);
+          if ((rc = launch_plan(c, p, 0, in, out, stream, g))) break;
+          (void)hipEventRecord(e1, s);
+          if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(TA_EHIP, "autotune sync failed"); break; }
+          float ms = 0.0f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          total += ms;
+        }
+        if (rc != TA_OK) break;
+        if (hipMemcpy(have_ref ? got.data() : ref.data(), out, bytes, hipMemcpyDeviceToHost) != hipSuccess) {
+          rc = fail(TA_EHIP, "autotune copy failed");
+          break;
+        }
+        if (have_ref && memcmp(ref.data(), got.data(), bytes) != 0) {
+          rc = fail(TA_EHIP, "autotune candidate (region 2^%d, grid %d) disagrees", region, g);
+          break;
+        }
+        have_ref = true;
+        if (total < best) { best = total; best_grid = g; best_region = region; }
       }
-      if (have_ref && memcmp(ref.data(), got.data(), bytes) != 0) {
-        rc = fail(TA_EHIP, "autotune candidate (region 2^%d, grid %d) disagrees", region, g);
-        break;
-      }
-      have_ref = true;
-      if (total < best) { best = total; best_grid = g; best_region = region; }
     }
-  }
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
-  (void)hipStreamSynchronize(s);
-  (void)hipFree(flush);
-  // keep the fastest mapping (rebuilt also when a candidate failed, so the
-  // plan stays consistent)
-  const int rc2 = build_tiles(p, rc == TA_OK ? best_region : orig_region);
-  if (rc == TA_OK && rc2 == TA_OK) p->grid = best_grid;
-  return rc != TA_OK ? rc : rc2;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(flush);
+    // keep the fastest mapping (rebuilt also when a candidate failed, so the
+    // plan stays consistent)
+    const int rc2 = build_tiles(p, rc == TA_OK ? best_region : orig_region);
+    if (rc == TA_OK && rc2 == TA_OK) p->grid = best_grid;
+    return rc != TA_OK ? rc : rc2;
+  });
 }
 
 int ta_plan_set_tuning(ta_plan* p, int grid, int region_log2) {
-  if (!p) return fail(TA_EINVAL, "null plan");
-  if (grid < ta::kXcds || grid > (1 << 20)) return fail(TA_EINVAL, "grid %d outside %d..2^20", grid, ta::kXcds);
-  if (region_log2 < 12 || region_log2 > 40) return fail(TA_EINVAL, "region 2^%d outside 2^12..2^40", region_log2);
-  int e;
-  if (region_log2 != p->region_log2 && (e = build_tiles(p, region_log2))) return e;
-  p->grid = grid;
-  return TA_OK;
+  return guard([&]() -> int {
+    if (!p) return fail(TA_EINVAL, "null plan");
+    if (grid < ta::kXcds || grid > (1 << 20)) return fail(TA_EINVAL, "grid %d outside %d..2^20", grid, ta::kXcds);
+    if (region_log2 < 12 || region_log2 > 40) return fail(TA_EINVAL, "region 2^%d outside 2^12..2^40", region_log2);
+    int e;
+    if (region_log2 != p->region_log2 && (e = build_tiles(p, region_log2))) return e;
+    p->grid = grid;
+    return TA_OK;
+  });
 }
 
 }  // extern "C"
@@ -833,32 +853,34 @@ int ta_transform_inv(ta_ctx* c, const ta_block* blocks_dev, int64_t nblocks, con
 
 int ta_validate_blocks(ta_ctx* c, const ta_block* blocks_dev, int64_t n, int64_t in_elems, int64_t out_elems,
                        int64_t* first_bad) {
-  if (!c || !first_bad) return fail(TA_EINVAL, "null argument");
-  *first_bad = -1;
-  if (n < 0 || in_elems < 0 || out_elems < 0) return fail(TA_EINVAL, "negative count");
-  if (n == 0) return TA_OK;
-  if (!blocks_dev) return fail(TA_EINVAL, "null descriptors");
-  if (in_elems > ((int64_t)1 << 62) || out_elems > ((int64_t)1 << 62)) return fail(TA_EINVAL, "buffer size above 2^62");
-  std::vector<ta_block> host((size_t)n);
-  TA_HIP(hipSetDevice(c->device));
-  TA_HIP(hipMemcpy(host.data(), blocks_dev, (size_t)n * sizeof(ta_block), hipMemcpyDeviceToHost));
-  std::lock_guard<std::mutex> lk(c->mu);
-  for (int64_t i = 0; i < n; ++i) {
-    const ta_block& b = host[(size_t)i];
-    Resolved rh, rv;
-    int kh, kv, e;
-    if ((e = check_block(c, b, i, TA_I16, &rh, &rv, &kh, &kv))) {
-      *first_bad = i;
-      return e;
+  return guard([&]() -> int {
+    if (!c || !first_bad) return fail(TA_EINVAL, "null argument");
+    *first_bad = -1;
+    if (n < 0 || in_elems < 0 || out_elems < 0) return fail(TA_EINVAL, "negative count");
+    if (n == 0) return TA_OK;
+    if (!blocks_dev) return fail(TA_EINVAL, "null descriptors");
+    if (in_elems > ((int64_t)1 << 62) || out_elems > ((int64_t)1 << 62)) return fail(TA_EINVAL, "buffer size above 2^62");
+    std::vector<ta_block> host((size_t)n);
+    TA_HIP(hipSetDevice(c->device));
+    TA_HIP(hipMemcpy(host.data(), blocks_dev, (size_t)n * sizeof(ta_block), hipMemcpyDeviceToHost));
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (int64_t i = 0; i < n; ++i) {
+      const ta_block& b = host[(size_t)i];
+      Resolved rh, rv;
+      int kh, kv, e;
+      if ((e = check_block(c, b, i, TA_I16, &rh, &rv, &kh, &kv))) {
+        *first_bad = i;
+        return e;
+      }
+      const int w = 1 << b.log2w, h = 1 << b.log2h;
+      if (block_end(b.in_off, b.in_stride, w, h, in_elems) < 0 || block_end(b.out_off, b.out_stride, w, h, out_elems) < 0) {
+        *first_bad = i;
+        return fail(TA_EINVAL, "block %lld: extends past the input (%lld elements) or output (%lld elements)",
+                    (long long)i, (long long)in_elems, (long long)out_elems);
+      }
     }
-    const int w = 1 << b.log2w, h = 1 << b.log2h;
-    if (block_end(b.in_off, b.in_stride, w, h, in_elems) < 0 || block_end(b.out_off, b.out_stride, w, h, out_elems) < 0) {
-      *first_bad = i;
-      return fail(TA_EINVAL, "block %lld: extends past the input (%lld elements) or output (%lld elements)",
-                  (long long)i, (long long)in_elems, (long long)out_elems);
-    }
-  }
-  return TA_OK;
+    return TA_OK;
+  });
 }
 
 int ta_set_axis_cfg(ta_ctx* c, int axis_id, const ta_axis_cfg* cfg) {
