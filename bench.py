@@ -136,7 +136,7 @@ def _events_mean(fn, reps, warm=2):
     return float(np.mean([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)])) * 1e-3
 
 
-EXTRAS = ("multiple", "proxy", "subblock", "batched", "refit", "design")
+EXTRAS = ("multiple", "proxy", "subblock", "batched", "refit", "design", "table1")
 
 
 def secondary(ctx, ids, x32, only=EXTRAS):
@@ -180,10 +180,54 @@ def secondary(ctx, ids, x32, only=EXTRAS):
         _refit(ctx, res)
     if "design" in only:
         _design(ctx, res)
+    if "table1" in only:
+        _table1(ctx, ids, x32, res)
     return res
 
 
-FP64_PEAK_TFLOPS = 78.6
+def _table1(ctx, ids, x32, res):
+    """The paper's Table 1 on this GPU: throughput of each adjusted transform
+    over the full-matrix DST-7 of the same size and direction, per direction.
+    The paper compares software on the same vector units, so the ratios are
+    taken against the direct DST-7 as dense products on VALU (set_impl(2));
+    the direct DST-7 on the int8 matrix cores (the fastest here) is beside.
+    Adjusted and direct launches alternate in rounds and each time is the
+    median over the rounds, so that clock drift during the run cancels."""
+    import torch
+    import synth
+    import paper_2505_23618_amd as ta
+    x64 = torch.from_numpy(synth.workload_blocks("cfg3_64x64")).cuda()
+    rows = {
+        "band_4tap_32": (x32, ta.DST3, ta.ADJ_BAND, "band_S3_S7_N32_K4"),
+        "band_6tap_32": (x32, ta.DST3, ta.ADJ_BAND, "band_S3_S7_N32_K6"),
+        "subblock_8x8_32": (x32, ta.DCT2, ta.ADJ_POST, "post_C2_S7_N32_B8"),
+        "subblock_16x16_64": (x64, ta.DCT2, ta.ADJ_POST, "post_C2_S7_N64_B16"),
+    }
+    s7 = ctx.axis(40, ta.DST7)
+    out = {}
+    for k, (x, base, adj, pname) in rows.items():
+        ax = ctx.axis(41, base, adj, False, ids[pname])
+        y, z = torch.empty_like(x), torch.empty_like(x)
+        cases = {"adj": (ax, 2), "valu": (s7, 2), "mfma": (s7, 0)}   # axis, impl
+        t = {(c, d): [] for c in cases for d in ("fwd", "inv")}
+        for _ in range(3):
+            for c, (a, impl) in cases.items():
+                ctx.set_impl(impl)
+                t[(c, "fwd")].append(_events_mean(lambda i: ctx.fwd(x, a, a, out=y), 5))
+                t[(c, "inv")].append(_events_mean(lambda i: ctx.inv(y, a, a, out=z), 5))
+        ctx.set_impl(0)
+        m = {kk: float(np.median(v)) for kk, v in t.items()}
+        out[k] = {"fwd_us": m[("adj", "fwd")] * 1e6, "inv_us": m[("adj", "inv")] * 1e6,
+                  "direct_valu_us": [m[("valu", "fwd")] * 1e6, m[("valu", "inv")] * 1e6],
+                  "direct_mfma_us": [m[("mfma", "fwd")] * 1e6, m[("mfma", "inv")] * 1e6],
+                  "ratio_fwd_vs_valu_direct": m[("valu", "fwd")] / m[("adj", "fwd")],
+                  "ratio_inv_vs_valu_direct": m[("valu", "inv")] / m[("adj", "inv")],
+                  "ratio_fwd_vs_mfma_direct": m[("mfma", "fwd")] / m[("adj", "fwd")],
+                  "ratio_inv_vs_mfma_direct": m[("mfma", "inv")] / m[("adj", "inv")]}
+        del y, z
+    res["table1_ratios"] = out
+    del x64
+    torch.cuda.empty_cache()
 
 
 def _design(ctx, res):
