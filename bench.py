@@ -230,6 +230,9 @@ def _table1(ctx, ids, x32, res):
     torch.cuda.empty_cache()
 
 
+FP64_PEAK_TFLOPS = 78.6
+
+
 def _design(ctx, res):
     """The Fig. 1 design study: every (target DST, base, pre/post) with
     random restarts, Adam on the sparsity objective, all in one launch."""

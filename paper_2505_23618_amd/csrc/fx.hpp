@@ -480,22 +480,6 @@ struct AccHi {
   }
 };
 
-// A forward sub-block pass over a scaled core: elements below B are the
-// sub-block's sums (shift s0, saturating pack), the others the core's scaled
-// sums (high halves, one permute per pair).  B is even, so a natural pair
-// never mixes the two.
-template <int N, int B>
-struct AccSplitHi {
-  int a[N];
-  int s0;
-  TA_DEV int value(int i) const { return i < B ? a[i] >> s0 : a[i] >> 16; }
-  TA_DEV uint32_t pair(int i, int j) const {
-    if ((i < 0 || i >= B) && (j < 0 || j >= B))
-      return perm(j >= 0 ? (uint32_t)a[j] : 0u, i >= 0 ? (uint32_t)a[i] : 0u, 0x07060302u);
-    return satpk(i >= 0 ? value(i) : 0, j >= 0 ? value(j) : 0);
-  }
-};
-
 // SC scales every table entry by 2^SC (see core_c3_sc).
 template <int N, int M, bool OFF, int SC, class W>
 TA_DEV void c3_even_sc(const W& w, int (&e)[M], int off) {
@@ -701,7 +685,7 @@ TA_DEV auto core_sc(const S& src, int shift) {
 template <int N, class AX, bool INV, bool DEEP_INV = false, int SC = 0, class S>
 TA_DEV auto run_pass_sc(const S& in, cparam pf, cparam pi,
                      int s_core, int a) {
-  static_assert(SC == 0 || AX::ADJ != ADJ_POST || !INV, "scaled results: not in an inverse sub-block pass");
+  static_assert(SC == 0 || AX::ADJ != ADJ_POST, "scaled results: band or plain passes only");
   if constexpr (AX::ADJ == ADJ_NONE) {
     return core_sc<N, AX::CORE, INV, DEEP_INV, SC>(in, s_core);
   } else if constexpr (AX::ADJ == ADJ_BAND) {
@@ -714,18 +698,7 @@ TA_DEV auto run_pass_sc(const S& in, cparam pf, cparam pi,
     }
   } else {
     constexpr int B = AX::KB;
-    if constexpr (!INV && SC > 0) {
-      // scaled core: the sub-block reads its inputs as permuted high halves,
-      // the other outputs leave as they are
-      const auto y = core_sc<N, AX::CORE, false, false, SC>(in, s_core);
-      AccSplitHi<N, B> r;
-      r.s0 = a;
-      int z[B];
-      post_rows<N, B>(y, pf, a, z);
-#pragma unroll
-      for (int i = 0; i < N; ++i) r.a[i] = i < B ? z[i] : y.a[i];
-      return r;
-    } else if constexpr (!INV) {
+    if constexpr (!INV) {
       const Acc<N> y = core_sc<N, AX::CORE, false>(in, s_core);
       Acc<N, B> r;
       r.s0 = a;

@@ -120,12 +120,10 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
   // packs with one permute: for every int16 input the scaled sums stay below
   // 2^31 and the results inside int16, because a column of the integer DCT-2
   // has an L1 norm below H * 2^8 (7449 < 8192 at H = 32).
-  // A DCT-2 core feeding a sub-block (32 and 64 points) is scaled the same
-  // way: a row of the integer DCT-2 has an L1 norm of at most H * 2^8 (the
-  // DC row), so the scaled sums lie in [-2^31, 2^31 - 2^16] and the results
-  // in [-2^15, 2^15 - 1] for every int16 input.
-  constexpr bool SCALED = ((AV::CORE == C_DCT3 || AV::CORE == C_DST3) && AV::ADJ != ADJ_POST) ||
-                          (AV::CORE == C_DCT2 && AV::ADJ == ADJ_POST && H >= 32);
+  // (A DCT-2 core cannot be scaled so: its rows reach an L1 norm of H * 2^8,
+  // and with inputs of matching signs at +32767 / -32768 the scaled sum
+  // reaches 2^31.)
+  constexpr bool SCALED = (AV::CORE == C_DCT3 || AV::CORE == C_DST3) && AV::ADJ != ADJ_POST;
   constexpr int SCV = SCALED ? 8 - LH : 0;
   uint32_t o[H / 2];
   const int cb = T::XCOL ? (tid >> 4) & 3 : tid / W;                  // column thread -> block
