@@ -10,10 +10,10 @@ from tests.cfgs import type_axis
 from paper_2505_23618_amd.frames import SIZES, axis_id, descriptors, register_axes  # noqa: F401
 
 
-def oracle_frames(frames, rows, params, inverse=False, select=None):
+def oracle_frames(frames, rows, params, inverse=False, select=None, bd=8):
     """Expected output frames (forward or inverse) for the blocks in `rows`
     (or only the indices in `select`), computed by the oracle per group of
-    equal (w, h, type_h, type_v)."""
+    equal (w, h, type_h, type_v), at bit depth `bd`."""
     out = np.zeros_like(frames, dtype=np.int64)
     sel = np.arange(len(rows)) if select is None else np.asarray(select)
     keys = {}
@@ -23,7 +23,7 @@ def oracle_frames(frames, rows, params, inverse=False, select=None):
     for (w, h, th, tv), idx in keys.items():
         stack = np.stack([frames[rows[i, 0], rows[i, 2]:rows[i, 2] + h, rows[i, 1]:rows[i, 1] + w] for i in idx])
         ah, av = type_axis(params, th, w), type_axis(params, tv, h)
-        res = F.inv2d(stack, ah, av) if inverse else F.fwd2d(stack, ah, av)
+        res = F.inv2d(stack, ah, av, bd=bd) if inverse else F.fwd2d(stack, ah, av, bd=bd)
         for j, i in enumerate(idx):
             out[rows[i, 0], rows[i, 2]:rows[i, 2] + h, rows[i, 1]:rows[i, 1] + w] = res[j]
     return out
