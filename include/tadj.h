@@ -336,9 +336,10 @@ int ta_givens_bwd(ta_ctx* ctx, int base, int n, int taps, const float* theta, in
                   ta_stream_t stream);
 
 /* Select the kernels used for packed batches: 0 = automatic (the matrix-core
- * kernels where one is built for the configuration, otherwise the VALU
- * butterfly kernels), 1 = matrix-core kernels only (TA_EUNSUPPORTED when
- * none is built), 2 = VALU kernels only.  Both give identical results. */
+ * kernels for int16 transforms without a band adjustment, where one is built;
+ * otherwise the VALU butterfly kernels, which are faster with a band), 1 =
+ * matrix-core kernels only (TA_EUNSUPPORTED when none is built), 2 = VALU
+ * kernels only.  Both give identical results. */
 int ta_set_impl(ta_ctx* ctx, int impl);
 
 /* Library version string. */

@@ -186,7 +186,8 @@ class Context:
                                    int_taps.size))
 
     def set_impl(self, impl: int):
-        """0: matrix-core kernels where built, else VALU; 1: matrix cores only; 2: VALU only."""
+        """0: matrix-core kernels for int16 transforms without a band adjustment
+        where built, else VALU; 1: matrix cores only; 2: VALU only."""
         _check(lib().ta_set_impl(self._h, impl))
 
     # -- transforms -------------------------------------------------------------
