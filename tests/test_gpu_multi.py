@@ -22,8 +22,9 @@ ORDER = [("C2", "C2"), ("S7", "S7"), ("S7", "C8"), ("C8", "S7"), ("C8", "C8")]
 
 
 class Setup:
-    def __init__(self):
-        self.ctx = ta.Context(0)
+    def __init__(self, bd=8):
+        self.bd = bd
+        self.ctx = ta.Context(0, bit_depth=bd)
         self.ids = ta.load_params(self.ctx)
         self.params = ta.load_param_file()
         self.axes = {}
@@ -49,7 +50,7 @@ def _check_all(st, n, pname, x):
     for k, (v, h) in enumerate(ORDER):
         ah, oh = st.axes[(n, h)]
         av, ov = st.axes[(n, v)]
-        ref = F.fwd2d(x, oh, ov)
+        ref = F.fwd2d(x, oh, ov, bd=st.bd)
         mism = np.argwhere(got[k] != ref)
         assert mism.size == 0, f"output {k} ({v}, {h}): {len(mism)} mismatches, first {mism[:3].tolist()}"
         try:
@@ -74,6 +75,25 @@ def test_five_transforms_adversarial(st, n, b, pname, kind):
     print(f"case multi {n} {kind}", flush=True)
     x = synth.adversarial_blocks(n, n, kind, seed=8, n=2 * (256 // n) + 1)
     _check_all(st, n, pname, x)
+
+
+@pytest.mark.parametrize("bd", [6, 10, 12])
+def test_five_transforms_at_bit_depth(bd):
+    """The row and column shifts follow bd; residuals of that bit depth and
+    full-range int16 values."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = Setup(bd)
+    try:
+        rng = np.random.Generator(np.random.PCG64(3000 + bd))
+        lim = (1 << bd) - 1
+        for n, b, pname in SIZES:
+            nb = 2 * (256 // n) + 3
+            print(f"case multi {n} B={b} bd {bd}", flush=True)
+            for x in (rng.integers(-lim, lim + 1, size=(nb, n, n)), rng.integers(-32768, 32768, size=(nb, n, n))):
+                _check_all(s, n, pname, x.astype(np.int16))
+    finally:
+        s.ctx.close()
 
 
 def test_single_block_and_empty(st):
