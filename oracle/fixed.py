@@ -32,7 +32,14 @@ nesting of even rows, DC row exactly 2^m, derived DST-2/DST-3 tables equal to
 their directly rounded formulas, DCT-8 table equal to S DST-7_int R); the 2-D
 result equals the un-rounded rational product of the integer stages within the
 propagated rounding bound, and is unbiased; constant blocks through the DCT-2
-give the closed-form DC value; inverse(forward(x)) returns x within a few LSB.
+give the closed-form DC value; a DC-only coefficient block through the
+inverse DCT-2 gives the hand-derived chain RS(256 RS(256 c, m + 1), m + 14 - bd)
+at bit depths 8 and 10, which pins each inverse shift on its own (moving one
+bit between the two stages changes the result); the 2-D result lies within
+the rounding bound of the rational product of the stages as written out in
+the test itself (tables rounded from the FP64 formulas, the stage order of
+every axis kind with and without the flip, the four core shifts), forward
+and inverse, unbiased; inverse(forward(x)) returns x within a few LSB.
 """
 
 from __future__ import annotations

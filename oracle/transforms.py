@@ -32,7 +32,12 @@ orthonormal DCT/DST types 2 and 3; DST-7 rows equal the eigenvectors of the
 second-difference matrix tridiag(-1, 2, -1) with last diagonal entry 1
 (a textbook characterisation); the recursive even/odd DCT-2 below equals the
 dense product; DST-1 and DST-4 equal scipy.fft's orthonormal types 1 and 4;
-DST-6 is the transpose of DST-7; every matrix is orthogonal.
+DST-6 is the transpose of DST-7; DST-5 and DST-8 rows equal the eigenvectors
+of the second-difference matrix with their boundary rows (DST-5: last diagonal
+entry 3; DST-8: first diagonal 3 and the last off-diagonal pair -sqrt2, the
+symmetric form of its half-sample boundary), with eigenvalues 2 - 2 cos w at
+the closed-form frequencies, plus hand-evaluated N = 4 entries; every matrix
+is orthogonal.
 """
 
 from __future__ import annotations

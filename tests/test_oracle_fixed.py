@@ -165,3 +165,137 @@ def test_single_pass_headroom_holds_for_all_int16():
         for kind in ("C2", "C3", "S7"):
             t = F.int_table(kind, n)
             assert int(np.abs(t).sum(axis=1).max()) * 32768 < (1 << 31)
+
+
+def _rs(v, s):
+    return (v + (1 << (s - 1))) >> s if s > 0 else v
+
+
+@pytest.mark.parametrize("bd", [8, 10])
+@pytest.mark.parametrize("lw,lh", [(2, 2), (3, 5), (5, 5), (6, 6), (6, 3)])
+def test_dc_only_inverse_dct2_closed_form(bd, lw, lh):
+    """A block whose only non-zero coefficient is the DC value c, through the
+    plain inverse 2-D DCT-2, worked out by hand.  Every entry of the integer
+    DC row is 2^m = 256, so the column pass (inverse first, shift m + 1 = 9)
+    turns column 0 into the constant RS(256 c, 9) and leaves the other columns
+    zero; the row pass (shift m + 14 - bd) then spreads that value over the
+    row: every residual equals RS(256 RS(256 c, 9), 22 - bd).  The two
+    shifts are pinned one by one: the same chain with one bit moved from
+    one stage to the other differs from it for some c in the range."""
+    w, h = 1 << lw, 1 << lh
+    cs = np.arange(-4000, 4001, 7)
+    y = np.zeros((len(cs), h, w), np.int64)
+    y[:, 0, 0] = cs
+    ax = cfgs.plain_axis("C2")
+    x = F.inv2d(y, ax, ax, bd=bd)
+    chain = [_rs(256 * _rs(256 * int(c), 9), 22 - bd) for c in cs]
+    assert (x == np.asarray(chain)[:, None, None]).all()
+    for s_col, s_row in ((10, 21 - bd), (8, 23 - bd)):
+        moved = [_rs(256 * _rs(256 * int(c), s_col), s_row) for c in cs]
+        assert moved != chain, (s_col, s_row)
+
+
+@pytest.mark.parametrize("bd", [8, 10])
+def test_dc_only_forward_then_inverse_chain(bd):
+    """Constant residual blocks c: the forward DC (rows shift log2 W + bd - 7,
+    columns log2 H + 8) followed by the inverse chain above, all by hand."""
+    lw, lh = 4, 3
+    w, h = 1 << lw, 1 << lh
+    cs = np.arange(-255, 256, 3)
+    x = np.broadcast_to(cs[:, None, None], (len(cs), h, w)).astype(np.int64)
+    ax = cfgs.plain_axis("C2")
+    y = F.fwd2d(x, ax, ax, bd=bd)
+    dc = [_rs(h * 256 * _rs(w * 256 * int(c), lw + bd - 7), lh + 8) for c in cs]
+    assert (y[:, 0, 0] == np.asarray(dc)).all()
+    xr = F.inv2d(np.where(np.arange(h * w).reshape(1, h, w) == 0, y, 0), ax, ax, bd=bd)
+    back = [_rs(256 * _rs(256 * d, 9), 22 - bd) for d in dc]
+    assert (xr == np.asarray(back)[:, None, None]).all()
+
+
+# ---------------------------------------------------------------------------
+# The same fixed-point reading written out here, independently of
+# oracle.fixed's stage and shift helpers: integer tables rounded directly from
+# the FP64 formulas, the stage order of each axis kind, and the core shifts.
+# ---------------------------------------------------------------------------
+def _int_mat(kind, n, m=8):
+    return round_half_away((2.0 ** m) * np.sqrt(n) * T.matrix(kind, n)).astype(np.float64)
+
+
+def _stages_written_out(ax, n, a, m=8):
+    """Forward stages of one axis as (matrix, 'core' | 'adj'): with f the DCT-8
+    flip, none = [S^f B R^f]; band = [A R^f (a), S^f B (core)];
+    post = [S^f B R^f (core), blkdiag(S^f Q S^f, 2^a I) (a)]."""
+    b = _int_mat(ax.base, n, m)
+    idx = np.arange(n)
+    rev = np.eye(n)[::-1] if ax.flip else np.eye(n)
+    sgn = np.diag((-1.0) ** idx) if ax.flip else np.eye(n)
+    if ax.adj == "none":
+        return [(sgn @ b @ rev, "core")]
+    if ax.adj == "band":
+        return [(np.asarray(ax.a_int, np.float64) @ rev, "adj"), (sgn @ b, "core")]
+    q = np.asarray(ax.q_int, np.float64)
+    bb = q.shape[0]
+    sq = np.diag((-1.0) ** np.arange(bb)) if ax.flip else np.eye(bb)
+    c = (2.0 ** a) * np.eye(n)
+    c[:bb, :bb] = sq @ q @ sq
+    return [(sgn @ b @ rev, "core"), (c, "adj")]
+
+
+def _rational_written_out(x, ax_h, ax_v, bd, a, inverse):
+    nb, h, w = x.shape
+    lw, lh, m = int(np.log2(w)), int(np.log2(h)), 8
+    fwd_row, fwd_col = lw + bd + m - 15, lh + m           # forward: rows first
+    inv_col, inv_row = m + 1, m + 14 - bd                  # inverse: columns first
+    sh, sv = _stages_written_out(ax_h, w, a), _stages_written_out(ax_v, h, a)
+    if inverse:
+        seq = [("v", st.T, inv_col if r == "core" else a) for st, r in reversed(sv)] + \
+              [("h", st.T, inv_row if r == "core" else a) for st, r in reversed(sh)]
+    else:
+        seq = [("h", st, fwd_row if r == "core" else a) for st, r in sh] + \
+              [("v", st, fwd_col if r == "core" else a) for st, r in sv]
+    v = x.astype(np.float64)
+    err = 0.0
+    for axis, mat, s in seq:
+        mf = mat / (2.0 ** s)
+        v = v @ mf.T if axis == "h" else np.einsum("kj,bji->bki", mf, v)
+        err = np.abs(mf).sum(axis=1).max() * err + 0.5
+    return v, err
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2", "cfg2_flip", "cfg3", "post8", "s2_c8", "s7direct"])
+@pytest.mark.parametrize("bd", [8, 10])
+def test_fixed_within_bound_of_reading_written_out(params, which, bd):
+    """The oracle's integers lie within the propagated rounding bound of the
+    exact rational product of the stages as the reading states them (written
+    out above, not taken from oracle.fixed), forward and inverse, with a
+    tight bias check; so a stage in the wrong order, a missing flip or a
+    shift off by one in any stage fails here."""
+    if which == "cfg1":
+        ax_h, ax_v = cfgs.cfg1(params); w = h = 16
+    elif which == "cfg2":
+        ax_h, ax_v = cfgs.cfg2(params); w = h = 32
+    elif which == "cfg2_flip":
+        ax_h = cfgs.band_axis(params, "S3", 32, 4, flip=True)
+        ax_v = cfgs.band_axis(params, "S3", 16, 6)
+        w, h = 32, 16
+    elif which == "cfg3":
+        ax_h, ax_v = cfgs.cfg3(params); w = h = 64
+    elif which == "post8":
+        ax_h, ax_v = cfgs.post_axis(params, 32, 8, flip=True), cfgs.post_axis(params, 16, 8); w, h = 32, 16
+    elif which == "s2_c8":
+        ax_h, ax_v = cfgs.plain_axis("S2"), cfgs.plain_axis("S7", flip=True); w, h = 8, 16
+    else:
+        ax_h = ax_v = cfgs.plain_axis("S7"); w = h = 16
+    x = synth.ar1_blocks(24, h, w, 0.95, 16.0, seed=17)
+    if bd == 10:
+        x = x * 4
+    y = F.fwd2d(x, ax_h, ax_v, bd=bd)
+    ref, bound = _rational_written_out(x, ax_h, ax_v, bd, 10, inverse=False)
+    assert np.abs(ref).max() < 32767
+    d = y - ref
+    assert np.abs(d).max() <= bound + 1e-9
+    assert abs(d.mean()) < 0.1
+    xi = F.inv2d(y, ax_h, ax_v, bd=bd)
+    ref, bound = _rational_written_out(y, ax_h, ax_v, bd, 10, inverse=True)
+    assert np.abs(xi - ref).max() <= bound + 1e-9
+    assert abs((xi - ref).mean()) < 0.1
