@@ -206,11 +206,18 @@ int ta_fwd_multi(ta_ctx* ctx, int param_id, int log2n, int64_t nblocks, const vo
  * (log2 input elements, 12..40) without timing (synchronous).  Both rewrite
  * the plan's device tile list in place: launches captured in a HIP graph
  * before must be captured again.  ta_plan_tuning reports the grid and
- * region in use.  Blocks must not overlap in `out`. */
+ * region in use.  Blocks must not overlap in `out`.  A plan runs only with
+ * the context that created it (TA_EINVAL otherwise) and must be destroyed
+ * before that context: its tiles point into the context's parameter
+ * tables. */
 typedef struct ta_plan ta_plan;
 int ta_plan_create(ta_ctx* ctx, const ta_block* blocks_host, int64_t n, int dtype, ta_plan** out);
 int ta_plan_destroy(ta_plan* plan);
 int ta_plan_info(const ta_plan* plan, int64_t* nblocks, int64_t* ntiles, int* grid);
+/* The plan's dtype and the smallest input / output buffers (in elements)
+ * that hold every block it addresses; ta_plan_fwd/_inv cannot check their
+ * buffers (they take none of these sizes), so the caller checks them here. */
+int ta_plan_extents(const ta_plan* plan, int* dtype, int64_t* in_elems, int64_t* out_elems);
 int ta_plan_fwd(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream);
 int ta_plan_inv(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream);
 int ta_plan_autotune(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream, int reps);

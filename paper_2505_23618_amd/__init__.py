@@ -39,7 +39,7 @@ EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis
            "ta_plan_autotune", "ta_givens_workspace", "ta_givens_fwd", "ta_givens_bwd",
            "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats", "ta_design_search",
            "ta_transform_fwd", "ta_transform_inv", "ta_validate_blocks", "ta_set_axis_cfg", "ta_set_params",
-           "ta_plan_tuning", "ta_plan_set_tuning")
+           "ta_plan_tuning", "ta_plan_set_tuning", "ta_plan_extents")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
     L.ta_plan_autotune.argtypes = [vp, vp, vp, vp, vp, i32]
     L.ta_plan_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.ta_plan_set_tuning.argtypes = [vp, i32, i32]
+    L.ta_plan_extents.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.ta_givens_workspace.argtypes = [i64, ctypes.POINTER(i64)]
     L.ta_givens_fwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp]
     L.ta_givens_bwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -122,6 +123,22 @@ STATS_SYMBOLS = 65      # levels -31..31 and the two escapes
 def _check(code: int):
     if code != 0:
         raise TadjError(code, lib().ta_last_error().decode())
+
+
+def _check_side(n: int):
+    if n < 4 or n > 64 or n & (n - 1):
+        raise ValueError(f"block side {n}: sides are powers of two in 4..64")
+
+
+def _check_out(out, shape, dtype, device):
+    """A caller-supplied output must be exactly what the kernel writes: the
+    C ABI receives only its pointer, so a smaller or differently typed tensor
+    would be written past its end."""
+    if tuple(out.shape) != tuple(shape) or out.dtype != dtype or out.device != device:
+        raise ValueError(f"out must be {dtype} {tuple(shape)} on {device}, got {out.dtype} "
+                         f"{tuple(out.shape)} on {out.device}")
+    if not out.is_contiguous():
+        raise ValueError("out must be contiguous")
 
 
 def _stream_handle(stream):
@@ -196,6 +213,8 @@ class Context:
         if x.dim() != 3:
             raise ValueError("expected [nblocks, H, W]")
         nb, h, w = x.shape
+        _check_side(h)
+        _check_side(w)
         lw, lh = w.bit_length() - 1, h.bit_length() - 1
         dt = {torch.int16: I16, torch.float32: F32}.get(x.dtype)
         if dt is None:
@@ -205,6 +224,8 @@ class Context:
         x = x.contiguous()
         if out is None:
             out = torch.empty_like(x)
+        else:
+            _check_out(out, x.shape, x.dtype, x.device)
         _check(fn(self._h, axis_h, axis_v, lw, lh, nb, ctypes.c_void_p(x.data_ptr()),
                   ctypes.c_void_p(out.data_ptr()), dt, _stream_handle(None)))
         return out
@@ -227,8 +248,11 @@ class Context:
             raise ValueError("expected a GPU int16 tensor [nblocks, N, N]")
         x = x.contiguous()
         nb, n = x.shape[0], x.shape[1]
+        _check_side(n)
         if out is None:
             out = torch.empty((5, nb, n, n), dtype=torch.int16, device=x.device)
+        else:
+            _check_out(out, (5, nb, n, n), torch.int16, x.device)
         _check(lib().ta_fwd_multi(self._h, param_id, n.bit_length() - 1, nb, ctypes.c_void_p(x.data_ptr()),
                                   ctypes.c_void_p(out.data_ptr()), _stream_handle(None)))
         return out
@@ -369,6 +393,26 @@ class Plan:
         self.ctx = ctx
         self._h = ctypes.c_void_p()
         _check(lib().ta_plan_create(ctx._h, blocks.ctypes.data, len(blocks), dtype, ctypes.byref(self._h)))
+        dt, ie, oe = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().ta_plan_extents(self._h, ctypes.byref(dt), ctypes.byref(ie), ctypes.byref(oe)))
+        self.dtype, self.in_elems, self.out_elems = dt.value, ie.value, oe.value
+
+    def _check_buffers(self, x, out):
+        """The kernels read and write every block the plan addresses: the
+        buffers must hold them, in the plan's dtype, contiguous, on its GPU."""
+        import torch
+        want = torch.int16 if self.dtype == I16 else torch.float32
+        for name, t, need in (("input", x, self.in_elems), ("output", out, self.out_elems)):
+            if t.dtype != want:
+                raise ValueError(f"{name} must be {want} for this plan, got {t.dtype}")
+            if not t.is_cuda or t.device.index != self.ctx.device:
+                raise ValueError(f"{name} must be on cuda:{self.ctx.device}")
+            if not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+            if t.numel() < need:
+                raise ValueError(f"{name} holds {t.numel()} elements, the plan addresses {need}")
+        if x.data_ptr() == out.data_ptr():
+            raise ValueError("input and output must be different buffers")
 
     def close(self):
         if self._h:
@@ -388,12 +432,14 @@ class Plan:
         return {"blocks": nb.value, "tiles": nt.value, "grid": g.value, "region_log2": r.value}
 
     def fwd(self, x, out, stream_handle=None):
+        self._check_buffers(x, out)
         sh = _stream_handle(None) if stream_handle is None else ctypes.c_void_p(stream_handle)
         _check(lib().ta_plan_fwd(self.ctx._h, self._h, ctypes.c_void_p(x.data_ptr()),
                                  ctypes.c_void_p(out.data_ptr()), sh))
         return out
 
     def inv(self, y, out, stream_handle=None):
+        self._check_buffers(y, out)
         sh = _stream_handle(None) if stream_handle is None else ctypes.c_void_p(stream_handle)
         _check(lib().ta_plan_inv(self.ctx._h, self._h, ctypes.c_void_p(y.data_ptr()),
                                  ctypes.c_void_p(out.data_ptr()), sh))
@@ -404,6 +450,7 @@ class Plan:
         return self.info()
 
     def autotune(self, x, out, reps: int = 3):
+        self._check_buffers(x, out)
         _check(lib().ta_plan_autotune(self.ctx._h, self._h, ctypes.c_void_p(x.data_ptr()),
                                       ctypes.c_void_p(out.data_ptr()), _stream_handle(None), reps))
         return self.info()

@@ -52,6 +52,36 @@ int guard(F&& f) {
     if (e_ != hipSuccess) return fail(TA_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
+// Makes `dev` the calling thread's current device for the guard's lifetime
+// and restores the caller's device afterwards: library calls never change
+// which device the caller's thread has current.
+class DeviceGuard {
+ public:
+  DeviceGuard() = default;
+  DeviceGuard(const DeviceGuard&) = delete;
+  DeviceGuard& operator=(const DeviceGuard&) = delete;
+  hipError_t enter(int dev) {
+    hipError_t e = hipGetDevice(&prev_);
+    if (e != hipSuccess) return e;
+    if (prev_ == dev) return hipSuccess;
+    e = hipSetDevice(dev);
+    if (e == hipSuccess) switched_ = true;
+    return e;
+  }
+  ~DeviceGuard() {
+    if (switched_) (void)hipSetDevice(prev_);
+  }
+
+ private:
+  int prev_ = -1;
+  bool switched_ = false;
+};
+
+// Run the rest of the enclosing scope on device `dev` (see DeviceGuard).
+#define TA_ON_DEVICE(dev)          \
+  DeviceGuard device_guard_;       \
+  TA_HIP(device_guard_.enter(dev))
+
 constexpr int kMaxIds = 256;
 
 // Device copies of one parameter set in the four orientations the kernels
@@ -105,7 +135,7 @@ namespace {
 
 int upload(ta_ctx* c, const void* host, size_t bytes, void** dev) {
   void* p = nullptr;
-  TA_HIP(hipSetDevice(c->device));
+  TA_ON_DEVICE(c->device);
   TA_HIP(hipMalloc(&p, bytes));
   c->allocations.push_back(p);
   TA_HIP(hipMemcpy(p, host, bytes, hipMemcpyHostToDevice));
@@ -189,7 +219,7 @@ int refresh_axis(ta_ctx* c, int id) {
     }
   }
   g_err = saved;
-  TA_HIP(hipSetDevice(c->device));
+  TA_ON_DEVICE(c->device);
   TA_HIP(hipMemcpy(c->axes_dev + (size_t)id * ta::kAxisSizes, row, sizeof row, hipMemcpyHostToDevice));
   return TA_OK;
 }
@@ -235,7 +265,7 @@ int resident_groups(const void* fn, int threads, int dev, int* out) {
   auto it = cache.find(key);
   if (it == cache.end()) {
     int per_cu = 0, cus = 0;
-    TA_HIP(hipSetDevice(dev));
+    TA_ON_DEVICE(dev);
     TA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0));
     TA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     if (per_cu < 1 || cus < 1) return fail(TA_EHIP, "kernel occupancy query returned %d x %d", per_cu, cus);
@@ -298,7 +328,7 @@ int run_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int log2w, int log2h,
   if (cap > 0 && groups > cap) groups = cap;
   if (groups > 0x7fffffff) return fail(TA_EUNSUPPORTED, "batch too large for one launch");
   void* kargs[] = {&args};
-  TA_HIP(hipSetDevice(c->device));
+  TA_ON_DEVICE(c->device);
   TA_HIP(hipLaunchKernel(k->fn, dim3((unsigned)groups), dim3(k->threads), kargs, 0,
                          reinterpret_cast<hipStream_t>(stream)));
   return TA_OK;
@@ -339,7 +369,8 @@ int ta_create(ta_ctx** out, int device, int bit_depth, int m, int a) {
 
 int ta_destroy(ta_ctx* c) {
   if (!c) return fail(TA_EINVAL, "null context");
-  (void)hipSetDevice(c->device);
+  DeviceGuard device_guard_;
+  (void)device_guard_.enter(c->device);
   for (void* p : c->allocations) (void)hipFree(p);
   delete c;
   return TA_OK;
@@ -365,8 +396,9 @@ int ta_set_band(ta_ctx* c, int id, int n, int k, const int16_t* a_int, const flo
         return fail(TA_EUNSUPPORTED, "band entry (%d,%d) outside the %d-tap Givens band", i, j, k);
     }
   std::lock_guard<std::mutex> lk(c->mu);
-  ParamSet& ps = c->params[id];
-  ps = ParamSet{};
+  // the new tables are built aside and replace the registered set only once
+  // every upload has succeeded (a failure keeps the previous set)
+  ParamSet ps;
   ps.kind = TA_ADJ_BAND;
   ps.n = n;
   ps.kb = k;
@@ -411,6 +443,7 @@ int ta_set_band(ta_ctx* c, int id, int n, int k, const int16_t* a_int, const flo
       if ((e = upload(c, packed.data(), packed.size() * 4, &ps.fx[flip][tr]))) return e;
       if ((e = upload(c, fl.data(), fl.size() * 4, &ps.f32[flip][tr]))) return e;
     }
+  c->params[id] = ps;
   return refresh_param_users(c, id);
 }
 
@@ -420,8 +453,7 @@ int ta_set_post(ta_ctx* c, int id, int n, int b, const int16_t* q_int, const flo
   if (log2_exact(n) < 2 || n > 64) return fail(TA_EUNSUPPORTED, "post size %d", n);
   if (b < 2 || b > n || (b & 1)) return fail(TA_EUNSUPPORTED, "sub-block %d for size %d", b, n);
   std::lock_guard<std::mutex> lk(c->mu);
-  ParamSet& ps = c->params[id];
-  ps = ParamSet{};
+  ParamSet ps;   // replaces the registered set once every upload succeeded
   ps.kind = TA_ADJ_POST;
   ps.n = n;
   ps.kb = b;
@@ -459,6 +491,7 @@ int ta_set_post(ta_ctx* c, int id, int n, int b, const int16_t* q_int, const flo
     int e;
     if ((e = upload(c, eo.data(), eo.size() * 4, &ps.fx_eo))) return e;
   }
+  c->params[id] = ps;
   return refresh_param_users(c, id);
 }
 
@@ -496,6 +529,7 @@ int ta_inv_packed(ta_ctx* c, int axis_h, int axis_v, int log2w, int log2h, int64
 // ---------------------------------------------------------------------------
 
 struct ta_plan {
+  const ta_ctx* ctx = nullptr;     // the context whose parameter tables the tiles point into
   int device = 0;
   int dtype = TA_I16;
   int region_log2 = 20;            // frame-region size of the tile lists (autotuned)
@@ -556,7 +590,7 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
   void* kargs[] = {&args};
   // at least one workgroup per XCD list
   const int64_t g = std::max<int64_t>(ta::kXcds, std::min<int64_t>(grid, std::max<int64_t>(1, p->ntiles)));
-  TA_HIP(hipSetDevice(c->device));
+  TA_ON_DEVICE(c->device);
   TA_HIP(hipLaunchKernel(ta::batch_kernel(inv, 0, p->dtype == TA_F32), dim3((unsigned)g), dim3(256), kargs, 0,
                          reinterpret_cast<hipStream_t>(stream)));
   return TA_OK;
@@ -618,7 +652,7 @@ int build_tiles(ta_plan* plan, int region_log2) {
   plan->xstart[ta::kXcds] = (int64_t)tiles.size();
   plan->ntiles = (int64_t)tiles.size();
   plan->region_log2 = region_log2;
-  TA_HIP(hipSetDevice(plan->device));
+  TA_ON_DEVICE(plan->device);
   if (n > 0) {
     // allocated once, at their largest (a tile holds at least one block), so
     // that re-planning never moves them
@@ -641,6 +675,7 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
     if (n < 0) return fail(TA_EINVAL, "negative block count");
     if (dtype != TA_I16 && dtype != TA_F32) return fail(TA_EINVAL, "unknown dtype %d", dtype);
     auto plan = std::make_unique<ta_plan>();
+    plan->ctx = c;
     plan->device = c->device;
     plan->dtype = dtype;
     plan->host.assign(blocks, blocks + n);
@@ -672,7 +707,8 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
 
 int ta_plan_destroy(ta_plan* p) {
   if (!p) return fail(TA_EINVAL, "null plan");
-  (void)hipSetDevice(p->device);
+  DeviceGuard device_guard_;
+  (void)device_guard_.enter(p->device);
   if (p->blocks_dev) (void)hipFree(p->blocks_dev);
   if (p->tiles_dev) (void)hipFree(p->tiles_dev);
   delete p;
@@ -687,6 +723,14 @@ int ta_plan_info(const ta_plan* p, int64_t* nblocks, int64_t* ntiles, int* grid)
   return TA_OK;
 }
 
+int ta_plan_extents(const ta_plan* p, int* dtype, int64_t* in_elems, int64_t* out_elems) {
+  if (!p) return fail(TA_EINVAL, "null plan");
+  if (dtype) *dtype = p->dtype;
+  if (in_elems) *in_elems = p->max_in_elem;
+  if (out_elems) *out_elems = p->max_out_elem;
+  return TA_OK;
+}
+
 int ta_plan_tuning(const ta_plan* p, int* grid, int* region_log2) {
   if (!p) return fail(TA_EINVAL, "null plan");
   if (grid) *grid = p->grid;
@@ -696,6 +740,7 @@ int ta_plan_tuning(const ta_plan* p, int* grid, int* region_log2) {
 
 int ta_plan_fwd(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t stream) {
   if (!c || !p) return fail(TA_EINVAL, "null argument");
+  if (p->ctx != c) return fail(TA_EINVAL, "plan was created with another context");
   if (p->ntiles == 0) return TA_OK;
   if (!in || !out) return fail(TA_EINVAL, "null buffer");
   if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
@@ -704,6 +749,7 @@ int ta_plan_fwd(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t st
 
 int ta_plan_inv(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t stream) {
   if (!c || !p) return fail(TA_EINVAL, "null argument");
+  if (p->ctx != c) return fail(TA_EINVAL, "plan was created with another context");
   if (p->ntiles == 0) return TA_OK;
   if (!in || !out) return fail(TA_EINVAL, "null buffer");
   if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
@@ -713,12 +759,13 @@ int ta_plan_inv(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t st
 int ta_plan_autotune(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream_t stream, int reps) {
   return guard([&]() -> int {
     if (!c || !p) return fail(TA_EINVAL, "null argument");
+    if (p->ctx != c) return fail(TA_EINVAL, "plan was created with another context");
     if (p->ntiles == 0) return TA_OK;
     if (!in || !out) return fail(TA_EINVAL, "null buffer");
     if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
     if (reps < 1) reps = 3;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    TA_HIP(hipSetDevice(c->device));
+    TA_ON_DEVICE(c->device);
     // every candidate's output is checked bitwise against the first one's
     const size_t bytes = (size_t)p->max_out_elem * (p->dtype == TA_F32 ? sizeof(float) : sizeof(int16_t));
     std::vector<char> ref(bytes), got(bytes);
@@ -825,7 +872,7 @@ int run_blocks(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void
   args.axes = c->axes_dev;
   args.nblocks = n;
   void* kargs[] = {&args};
-  TA_HIP(hipSetDevice(c->device));
+  TA_ON_DEVICE(c->device);
   TA_HIP(hipLaunchKernel(fn, dim3((unsigned)g), dim3(256), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
   return TA_OK;
 }
@@ -861,7 +908,7 @@ int ta_validate_blocks(ta_ctx* c, const ta_block* blocks_dev, int64_t n, int64_t
     if (!blocks_dev) return fail(TA_EINVAL, "null descriptors");
     if (in_elems > ((int64_t)1 << 62) || out_elems > ((int64_t)1 << 62)) return fail(TA_EINVAL, "buffer size above 2^62");
     std::vector<ta_block> host((size_t)n);
-    TA_HIP(hipSetDevice(c->device));
+    TA_ON_DEVICE(c->device);
     TA_HIP(hipMemcpy(host.data(), blocks_dev, (size_t)n * sizeof(ta_block), hipMemcpyDeviceToHost));
     std::lock_guard<std::mutex> lk(c->mu);
     for (int64_t i = 0; i < n; ++i) {
@@ -958,7 +1005,7 @@ int ta_fwd_multi(ta_ctx* c, int param_id, int log2n, int64_t nblocks, const void
   const int64_t groups = (nblocks + per_wg - 1) / per_wg;
   if (groups > 0x7fffffff) return fail(TA_EUNSUPPORTED, "batch too large for one launch");
   void* kargs[] = {&a};
-  TA_HIP(hipSetDevice(c->device));
+  TA_ON_DEVICE(c->device);
   TA_HIP(hipLaunchKernel(fn, dim3((unsigned)groups), dim3(threads), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
   return TA_OK;
 }
@@ -977,7 +1024,7 @@ int ta_givens_fwd(ta_ctx* c, int base, int n, int taps, const float* theta, int6
   if (!x || !y) return fail(TA_EINVAL, "null buffer");
   ta::GivensArgs a{theta, x, nullptr, y, nullptr, nullptr, nvec};
   void* kargs[] = {&a};
-  TA_HIP(hipSetDevice(c->device));
+  TA_ON_DEVICE(c->device);
   TA_HIP(hipLaunchKernel(ta::givens_kernel(0, n, taps / 2, base), dim3((unsigned)((nvec + 255) / 256)), dim3(256),
                          kargs, 0, reinterpret_cast<hipStream_t>(stream)));
   return TA_OK;
@@ -991,7 +1038,7 @@ int ta_givens_bwd(ta_ctx* c, int base, int n, int taps, const float* theta, int6
   if (nvec > 0 && (!x || !gy || !gx || !workspace)) return fail(TA_EINVAL, "null buffer");
   const int64_t groups = (nvec + 255) / 256;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  TA_HIP(hipSetDevice(c->device));
+  TA_ON_DEVICE(c->device);
   if (groups > 0) {
     ta::GivensArgs a{theta, x, gy, nullptr, gx, static_cast<float*>(workspace), nvec};
     void* kargs[] = {&a};
@@ -1107,7 +1154,7 @@ int ta_coef_stats(ta_ctx* c, const int16_t* coef, int64_t nblocks, int log2h, in
   a.part_b = a.part_d + slots;
   a.log_energy = reinterpret_cast<double*>(a.part_b + slots);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  TA_HIP(hipSetDevice(c->device));
+  TA_ON_DEVICE(c->device);
   void* kargs[] = {&a};
   if (a.steps > 0) {
     TA_HIP(hipLaunchKernel(ta::stats_kernel(1), dim3((unsigned)(a.ranges * a.slabs)), dim3(256), kargs, 0, s));
@@ -1159,7 +1206,7 @@ int ta_design_search(ta_ctx* c, int n, int nmat, const double* mats, int64_t nca
     return fail(TA_EINVAL, "misaligned buffer");
   ta::DesignArgs a{mats, nmat, cands, theta, steps, lr, lam, 0.9, 0.999, 1e-8, grad, obj, adj};
   void* kargs[] = {&a};
-  TA_HIP(hipSetDevice(c->device));
+  TA_ON_DEVICE(c->device);
   TA_HIP(hipLaunchKernel(fn, dim3((unsigned)ncand), dim3(threads), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
   return TA_OK;
 }

@@ -37,6 +37,7 @@ CASES = {
                      (ta.DST3, ta.ADJ_BAND, False, "band_S3_S7_N32_K6")),
     "direct_dst7_32": (32, 32, (ta.DST7, ta.ADJ_NONE, False, None), (ta.DST7, ta.ADJ_NONE, False, None)),
     "dct2_32": (32, 32, (ta.DCT2, ta.ADJ_NONE, False, None), (ta.DCT2, ta.ADJ_NONE, False, None)),
+    "direct_dct8_32": (32, 32, (ta.DCT8, ta.ADJ_NONE, False, None), (ta.DCT8, ta.ADJ_NONE, False, None)),
     "post8_32": (32, 32, (ta.DCT2, ta.ADJ_POST, False, "post_C2_S7_N32_B8"),
                  (ta.DCT2, ta.ADJ_POST, True, "post_C2_S7_N32_B8")),
     "cfg1_dct2_band_16": (16, 16, (ta.DCT2, ta.ADJ_BAND, False, "band_C2_S7_N16_K4"),

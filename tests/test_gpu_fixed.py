@@ -10,7 +10,9 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import adjust as OA
 from oracle import fixed as F
+from oracle.fixed import Axis
 from tests.libcases import CASES, Registered
 
 torch = pytest.importorskip("torch")
@@ -27,9 +29,9 @@ def reg():
 
 
 # forward cases that also have a matrix-core (int8 MFMA) kernel
-MFMA_FWD = ["cfg2_dst7_k4", "cfg2_dct8_k4", "cfg2_dst7_k6", "direct_dst7_32", "dct2_32"]
+MFMA_FWD = ["cfg2_dst7_k4", "cfg2_dct8_k4", "cfg2_dst7_k6", "direct_dst7_32", "dct2_32", "direct_dct8_32"]
 # inverse cases with a matrix-core kernel
-MFMA_INV = ["direct_dst7_32", "dct2_32"]
+MFMA_INV = ["direct_dst7_32", "dct2_32", "direct_dct8_32"]
 
 
 @pytest.fixture
@@ -229,3 +231,113 @@ def test_matrix_core_inverse_bit_exact(reg, name, impl):
         ref = F.inv2d(x, oh, ov)
         mism = np.argwhere(got != ref)
         assert mism.size == 0, f"{len(mism)} mismatches, first {mism[:3].tolist()}"
+
+
+@pytest.mark.parametrize("impl", [1], indirect=True, ids=["matrix"])
+@pytest.mark.parametrize("name", MFMA_INV)
+def test_matrix_core_inverse_full_size_sampled(reg, name, impl):
+    """The persistent matrix-core inverse at the benchmark's size (262,144
+    blocks, every wave walks many blocks with its next block prefetched),
+    on the coefficients of the AR(1) workload and on full-range int16
+    coefficients; the oracle checks sampled blocks, including the first and
+    the last."""
+    x = synth.workload_blocks("cfg2_32x32")
+    ah, av = reg.axes[name]
+    oh, ov = reg.oracle_axes(name)
+    print(f"full-size matrix-core inverse {name}", flush=True)
+    rng = np.random.Generator(np.random.PCG64(79))
+    idx = np.concatenate([np.sort(rng.choice(x.shape[0], size=48, replace=False)), [0, 1, x.shape[0] - 1]])
+    ti = torch.from_numpy(idx).cuda()
+    y = reg.ctx.fwd(_gpu(x), ah, av)
+    z = reg.ctx.inv(y, ah, av)
+    torch.cuda.synchronize()
+    ys = y[ti].cpu().numpy()
+    assert (ys == F.fwd2d(x[idx], oh, ov)).all()
+    assert (z[ti].cpu().numpy() == F.inv2d(ys, oh, ov)).all()
+    del y, z
+    c = torch.randint(-32768, 32768, x.shape, dtype=torch.int16, generator=torch.Generator().manual_seed(80))
+    z = reg.ctx.inv(c.cuda(), ah, av)
+    torch.cuda.synchronize()
+    assert (z[ti].cpu().numpy() == F.inv2d(c.numpy()[idx], oh, ov)).all()
+
+
+def _random_band(n, taps, seed):
+    """A K-tap band from random Givens angles (a valid parameter set that
+    differs from the frozen one), integer version at scale 2^10."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    theta = rng.uniform(-0.6, 0.6, OA.n_angles(n, taps // 2))
+    a_f = OA.band_matrix(n, taps // 2, theta)
+    return OA.round_half_away(a_f * 1024.0), a_f
+
+
+@pytest.mark.parametrize("impl", [1, 2], indirect=True, ids=["matrix", "valu"])
+@pytest.mark.parametrize("taps", [4, 6])
+@pytest.mark.parametrize("flip", [False, True], ids=["dst7", "dct8"])
+def test_two_band_sets(reg, taps, flip, impl):
+    """Rows and columns with different band parameter sets of the same size
+    and kind: the matrix-core forward then keeps one set of tap registers per
+    axis.  Checked in both directions on AR(1) and full-range inputs, with
+    the frozen set on one axis and a random one on the other, both ways."""
+    if flip and taps == 6:
+        pytest.skip("no DCT-3 + 6-tap kernel pair in the packed table")
+    ctx = reg.ctx
+    a_int, a_f = _random_band(32, taps, seed=90 + taps)
+    pid = 200 + taps
+    ctx.set_band(pid, a_int, a_f, taps)
+    frozen = reg.params[f"band_S3_S7_N32_K{taps}"]
+    ax_r = ctx.axis(240 + taps + int(flip), ta.DST3, ta.ADJ_BAND, flip, pid)
+    ax_f = ctx.axis(230 + taps + int(flip), ta.DST3, ta.ADJ_BAND, flip, reg.ids[f"band_S3_S7_N32_K{taps}"])
+    o_r = Axis(base="S3", adj="band", flip=flip, a_int=a_int, a_f=a_f)
+    o_f = Axis(base="S3", adj="band", flip=flip, a_int=np.asarray(frozen["a_int"], np.int64),
+               a_f=np.asarray(frozen["a_f64"]))
+    sets = [synth.ar1_blocks(61, 32, 32, 0.95, 16.0, seed=204),
+            synth.adversarial_blocks(32, 32, "full16", seed=8, n=7),
+            synth.adversarial_blocks(32, 32, "extreme16", seed=8, n=7)]
+    print(f"impl {impl} two band sets K={taps} flip={flip}", flush=True)
+    for (ah, av, oh, ov) in ((ax_f, ax_r, o_f, o_r), (ax_r, ax_f, o_r, o_f)):
+        for x in sets:
+            ctx.set_impl(impl)
+            y = ctx.fwd(_gpu(x), ah, av).cpu().numpy()
+            yr = F.fwd2d(x, oh, ov)
+            assert (y == yr).all(), "forward"
+            ctx.set_impl(2)          # the band inverse runs on VALU only
+            z = ctx.inv(_gpu(yr), ah, av).cpu().numpy()
+            assert (z == F.inv2d(yr, oh, ov)).all(), "inverse"
+
+
+@pytest.mark.parametrize("impl", [1], indirect=True, ids=["matrix"])
+def test_two_band_sets_full_size_sampled(reg, impl):
+    """The persistent matrix-core forward with two band sets at the
+    benchmark's size, on sampled blocks."""
+    ctx = reg.ctx
+    a_int, a_f = _random_band(32, 4, seed=94)
+    ctx.set_band(210, a_int, a_f, 4)
+    ah = ctx.axis(250, ta.DST3, ta.ADJ_BAND, False, reg.ids["band_S3_S7_N32_K4"])
+    av = ctx.axis(251, ta.DST3, ta.ADJ_BAND, False, 210)
+    frozen = reg.params["band_S3_S7_N32_K4"]
+    oh = Axis(base="S3", adj="band", a_int=np.asarray(frozen["a_int"], np.int64), a_f=np.asarray(frozen["a_f64"]))
+    ov = Axis(base="S3", adj="band", a_int=a_int, a_f=a_f)
+    x = synth.workload_blocks("cfg2_32x32")
+    y = ctx.fwd(_gpu(x), ah, av)
+    torch.cuda.synchronize()
+    rng = np.random.Generator(np.random.PCG64(81))
+    idx = np.concatenate([np.sort(rng.choice(x.shape[0], size=48, replace=False)), [0, x.shape[0] - 1]])
+    assert (y[torch.from_numpy(idx).cuda()].cpu().numpy() == F.fwd2d(x[idx], oh, ov)).all()
+
+
+def test_binding_rejects_bad_outputs(reg):
+    """The C ABI receives only pointers, so the binding checks a caller's
+    output tensor before the call: shape, dtype, contiguity, and block sides
+    that are powers of two in 4..64."""
+    ah, av = reg.axes["cfg2_dst7_k4"]
+    x = torch.zeros((4, 32, 32), dtype=torch.int16, device="cuda")
+    for bad in (torch.empty((3, 32, 32), dtype=torch.int16, device="cuda"),
+                torch.empty((4, 32, 32), dtype=torch.float32, device="cuda"),
+                torch.empty((4, 32, 64), dtype=torch.int16, device="cuda")[:, :, ::2]):
+        with pytest.raises(ValueError):
+            reg.ctx.fwd(x, ah, av, out=bad)
+    with pytest.raises(ValueError):
+        reg.ctx.fwd(torch.zeros((4, 48, 48), dtype=torch.int16, device="cuda"), ah, av)
+    pid = reg.ids["post_C2_S7_N32_B8"]
+    with pytest.raises(ValueError):
+        reg.ctx.fwd_multi(x, pid, out=torch.empty((4, 4, 32, 32), dtype=torch.int16, device="cuda"))
