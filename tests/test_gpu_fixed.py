@@ -298,7 +298,7 @@ def test_two_band_sets(reg, taps, flip, impl):
         for x in sets:
             ctx.set_impl(impl)
             y = ctx.fwd(_gpu(x), ah, av).cpu().numpy()
-            yr = F.fwd2d(x, oh, ov)
+            yr = F.fwd2d(x, oh, ov).astype(np.int16)
             assert (y == yr).all(), "forward"
             ctx.set_impl(2)          # the band inverse runs on VALU only
             z = ctx.inv(_gpu(yr), ah, av).cpu().numpy()
