@@ -342,6 +342,19 @@ int ta_givens_bwd(ta_ctx* ctx, int base, int n, int taps, const float* theta, in
                   const float* x, const float* gy, float* gx, float* gtheta, void* workspace,
                   ta_stream_t stream);
 
+/* ta_givens_bwd for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the same
+ * backward, with the per-workgroup partial rows of the angle gradient in a
+ * static device array of the library (1.5 MiB per device, held until the
+ * process ends) instead of a caller's workspace; allocates nothing.
+ * nvec <= 1,048,576 (4,096 workgroups of 256 vectors), else TA_EINVAL.  The
+ * array needs no clearing (every row a call reads is written by that call),
+ * and every call on one device shares it: calls that overlap on one device
+ * (other streams, other contexts or threads) race and must be ordered by the
+ * caller.  Results are bitwise identical to ta_givens_bwd's. */
+int ta_givens_bwd_noalloc(ta_ctx* ctx, int base, int n, int taps, const float* theta, int64_t nvec,
+                          const float* x, const float* gy, float* gx, float* gtheta, ta_stream_t stream);
+
 /* Select the kernels used for packed batches: 0 = automatic (the matrix-core
  * kernels for int16 transforms without a band adjustment, where one is built;
  * otherwise the VALU butterfly kernels, which are faster with a band), 1 =

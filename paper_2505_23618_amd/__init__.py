@@ -39,7 +39,7 @@ EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis
            "ta_plan_autotune", "ta_givens_workspace", "ta_givens_fwd", "ta_givens_bwd",
            "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats", "ta_design_search",
            "ta_transform_fwd", "ta_transform_inv", "ta_validate_blocks", "ta_set_axis_cfg", "ta_set_params",
-           "ta_plan_tuning", "ta_plan_set_tuning", "ta_plan_extents")
+           "ta_plan_tuning", "ta_plan_set_tuning", "ta_plan_extents", "ta_givens_bwd_noalloc")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
     L.ta_givens_workspace.argtypes = [i64, ctypes.POINTER(i64)]
     L.ta_givens_fwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp]
     L.ta_givens_bwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp, vp, vp, vp]
+    L.ta_givens_bwd_noalloc.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp, vp, vp]
     for f in (L.ta_transform_fwd, L.ta_transform_inv):
         f.argtypes = [vp, vp, i64, vp, vp, i32, vp]
     L.ta_validate_blocks.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(i64)]

@@ -12,6 +12,7 @@
 // reduced across the workgroup with wave shuffles and LDS in a fixed order
 // into one partial row per workgroup, and the partial rows are summed in a
 // fixed order by a second kernel: the result is bitwise reproducible.
+#include <mutex>
 #include <type_traits>
 
 #include "fp.hpp"
@@ -216,5 +217,34 @@ const void* givens_kernel(int bwd, int n, int layers, int base) {
 }
 
 const void* givens_reduce_kernel() { return reinterpret_cast<const void*>(&givens_reduce); }
+
+// Scratch of the allocation-free backward: the per-workgroup partial rows of
+// the angle gradient (kMaxAng floats each) for up to kNoAllocGroups
+// workgroups.  Every device the library runs on holds its own copy until the
+// process ends; every call on a device shares it.
+static __device__ __align__(256) float scratch[kNoAllocGroups * kMaxAng];
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (the array's name in host code is only a stand-in for
+// the symbol, never a device address).
+int givens_scratch(int device, float** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static float* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return -1;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[device]) {
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) return -2;
+    if (prev != device && hipSetDevice(device) != hipSuccess) return -2;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !p) return -2;
+    addr[device] = static_cast<float*>(p);
+  }
+  *ptr = addr[device];
+  return 0;
+}
 
 }  // namespace ta

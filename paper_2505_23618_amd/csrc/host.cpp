@@ -127,6 +127,8 @@ struct ta_ctx {
   // device table of the batched kinds of every (axis id, log2 size), read by
   // the block-list kernels; kind -1 where the axis has no batched kernel
   ta::AxisDev* axes_dev = nullptr;
+  // this device's static scratch (ta_givens_bwd_noalloc), looked up at create
+  float* scratch = nullptr;
   std::vector<void*> allocations;
   std::mutex mu;
 };
@@ -362,6 +364,14 @@ int ta_create(ta_ctx** out, int device, int bit_depth, int m, int a) {
   if ((e = upload(c.get(), table.data(), table.size() * sizeof(ta::AxisDev), reinterpret_cast<void**>(&c->axes_dev)))) {
     for (void* p : c->allocations) (void)hipFree(p);
     return e;
+  }
+  {
+    // the static scratch's address on this device, looked up once per device
+    TA_ON_DEVICE(device);
+    if (ta::givens_scratch(device, &c->scratch) != 0) {
+      for (void* p : c->allocations) (void)hipFree(p);
+      return fail(TA_EHIP, "static scratch address lookup failed on device %d", device);
+    }
   }
   *out = c.release();
   return TA_OK;
@@ -1030,27 +1040,56 @@ int ta_givens_fwd(ta_ctx* c, int base, int n, int taps, const float* theta, int6
   return TA_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The backward's two launches with the partial rows in `part` (the caller's
+// workspace, or the static scratch of the allocation-free entry point).
+int givens_bwd_launch(ta_ctx* c, int base, int n, int taps, const float* theta, int64_t nvec, const float* x,
+                      const float* gy, float* gx, float* gtheta, float* part, ta_stream_t stream) {
+  const int64_t groups = (nvec + 255) / 256;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TA_ON_DEVICE(c->device);
+  if (groups > 0) {
+    ta::GivensArgs a{theta, x, gy, nullptr, gx, part, nvec};
+    void* kargs[] = {&a};
+    TA_HIP(hipLaunchKernel(ta::givens_kernel(1, n, taps / 2, base), dim3((unsigned)groups), dim3(256), kargs, 0, s));
+  }
+  int na = 0;
+  for (int l = 0; l < taps / 2; ++l) na += (n - 2 - (l & 1)) / 2 + 1;
+  const float* cpart = part;
+  int64_t g64 = groups;
+  void* rargs[] = {&cpart, &g64, &na, &gtheta};
+  TA_HIP(hipLaunchKernel(ta::givens_reduce_kernel(), dim3((unsigned)na), dim3(256), rargs, 0, s));
+  return TA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int ta_givens_bwd(ta_ctx* c, int base, int n, int taps, const float* theta, int64_t nvec, const float* x,
                   const float* gy, float* gx, float* gtheta, void* workspace, ta_stream_t stream) {
   int e;
   if ((e = givens_check(c, base, n, taps, theta, nvec))) return e;
   if (!gtheta) return fail(TA_EINVAL, "null gradient buffer");
   if (nvec > 0 && (!x || !gy || !gx || !workspace)) return fail(TA_EINVAL, "null buffer");
-  const int64_t groups = (nvec + 255) / 256;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  TA_ON_DEVICE(c->device);
-  if (groups > 0) {
-    ta::GivensArgs a{theta, x, gy, nullptr, gx, static_cast<float*>(workspace), nvec};
-    void* kargs[] = {&a};
-    TA_HIP(hipLaunchKernel(ta::givens_kernel(1, n, taps / 2, base), dim3((unsigned)groups), dim3(256), kargs, 0, s));
-  }
-  int na = 0;
-  for (int l = 0; l < taps / 2; ++l) na += (n - 2 - (l & 1)) / 2 + 1;
-  const float* part = static_cast<const float*>(workspace);
-  int64_t g64 = groups;
-  void* rargs[] = {&part, &g64, &na, &gtheta};
-  TA_HIP(hipLaunchKernel(ta::givens_reduce_kernel(), dim3((unsigned)na), dim3(256), rargs, 0, s));
-  return TA_OK;
+  return givens_bwd_launch(c, base, n, taps, theta, nvec, x, gy, gx, gtheta, static_cast<float*>(workspace),
+                           stream);
+}
+
+int ta_givens_bwd_noalloc(ta_ctx* c, int base, int n, int taps, const float* theta, int64_t nvec, const float* x,
+                          const float* gy, float* gx, float* gtheta, ta_stream_t stream) {
+  int e;
+  if ((e = givens_check(c, base, n, taps, theta, nvec))) return e;
+  if (!gtheta) return fail(TA_EINVAL, "null gradient buffer");
+  if (nvec > 0 && (!x || !gy || !gx)) return fail(TA_EINVAL, "null buffer");
+  if (nvec > ta::kNoAllocGroups * 256)
+    return fail(TA_EINVAL, "%lld vectors: the allocation-free backward takes at most %lld", (long long)nvec,
+                (long long)(ta::kNoAllocGroups * 256));
+  if (!c->scratch) return fail(TA_EHIP, "static scratch of device %d not available", c->device);
+  return givens_bwd_launch(c, base, n, taps, theta, nvec, x, gy, gx, gtheta, c->scratch, stream);
 }
 
 }  // extern "C"

@@ -219,6 +219,12 @@ struct GivensArgs {
 };
 const void* givens_kernel(int bwd, int n, int layers, int base);
 const void* givens_reduce_kernel();
+// Static scratch of the allocation-free backward (givens_kernels.hip): room
+// for the partial rows of kNoAllocGroups workgroups of 256 vectors.
+constexpr int64_t kNoAllocGroups = 4096;
+// Device address of the scratch on `device` (looked up once per device):
+// 0, or -1 for a device index out of range, -2 for a HIP failure.
+int givens_scratch(int device, float** ptr);
 
 // Tables of compiled kernels (defined in the kernel translation units).
 const KernelEntry* fx_kernels(int* count);
