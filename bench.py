@@ -122,6 +122,21 @@ def cpu_blas_context(x: np.ndarray, nsample: int = 65536):
             "sample": f"first {m} of the 262,144 blocks, {dt:.2f} s wall"}
 
 
+def _settle(fn, seconds=1.5):
+    """Run `fn` back to back for `seconds` of wall time (untimed): the GPU's
+    clocks ramp up under sustained load, and a few warm-up launches (a few
+    milliseconds) leave the first timed ones slower than the steady state."""
+    import torch
+    t0 = time.perf_counter()
+    i = 0
+    while time.perf_counter() - t0 < seconds:
+        fn(i)
+        i += 1
+        if i % 16 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+
+
 def _events_mean(fn, reps, warm=2):
     import torch
     st = torch.cuda.current_stream()
@@ -209,6 +224,8 @@ def _table1(ctx, ids, x32, res):
         ax = ctx.axis(41, base, adj, False, ids[pname])
         y, z = torch.empty_like(x), torch.empty_like(x)
         cases = {"adj": (ax, 2), "valu": (s7, 2), "mfma": (s7, 0)}   # axis, impl
+        ctx.set_impl(2)
+        _settle(lambda i: (ctx.fwd(x, ax, ax, out=y), ctx.inv(y, ax, ax, out=z)), 1.0)
         t = {(c, d): [] for c in cases for d in ("fwd", "inv")}
         for _ in range(3):
             for c, (a, impl) in cases.items():
@@ -318,6 +335,7 @@ def _subblock(ctx, ids, res):
     x64 = torch.from_numpy(synth.workload_blocks("cfg3_64x64")).cuda()
     n64 = x64.numel()
     y64, z64 = torch.empty_like(x64), torch.empty_like(x64)
+    _settle(lambda i: (ctx.fwd(x64, ph, pv, out=y64), ctx.inv(y64, ph, pv, out=z64)), 1.0)
     tf = _events_mean(lambda i: ctx.fwd(x64, ph, pv, out=y64), 10)
     ti = _events_mean(lambda i: ctx.inv(y64, ph, pv, out=z64), 10)
     res["subblock_64x64_i16"] = {"value": n64 / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
@@ -452,6 +470,7 @@ def main():
         ctx.inv_ptr(a, a, 5, 5, nb, src.data_ptr(), dst.data_ptr(), ta.I16, sh)
 
     def timed(a, steps, warmup, with_copy=False):
+        _settle(lambda i: (fwd(x, y, a), inv(y, z, a)))
         for _ in range(warmup):
             fwd(x, y, a)
             inv(y, z, a)
@@ -536,6 +555,10 @@ def main():
         },
         "fwd_us": tf.mean() * 1e6,
         "inv_us": ti.mean() * 1e6,
+        "per_launch_us": {"fwd_median": float(np.median(tf)) * 1e6, "fwd_min": tf.min() * 1e6,
+                          "fwd_max": tf.max() * 1e6, "inv_median": float(np.median(ti)) * 1e6,
+                          "inv_min": ti.min() * 1e6, "inv_max": ti.max() * 1e6,
+                          "clock_settling": "1.5 s of the same launches before the warm-up steps"},
         "direct_dst7": {
             "value": ncoef / (tf7.mean() + ti7.mean()), "unit": "coef/s",
             "fwd_us": tf7.mean() * 1e6, "inv_us": ti7.mean() * 1e6,

@@ -150,7 +150,14 @@ int ta_set_params(ta_ctx* ctx, int param_id, const int16_t* int_taps, const floa
 
 /* Forward / inverse transform of a packed batch of nblocks W x H blocks
  * (W = 2^log2w, H = 2^log2h), horizontal axis axis_h, vertical axis_v.
- * in/out: device pointers to nblocks*W*H elements of dtype. */
+ * in/out: device pointers to nblocks*W*H elements of dtype, 16-byte aligned,
+ * not overlapping.  Every registered axis kind runs at every size 4..64 (a
+ * parameter set serves the size it was registered for): common pairs have
+ * specialised kernels (and the matrix-core ones, see ta_set_impl), the
+ * others run on the general kernel, which applies each axis as its stages
+ * (eq. 1: band A then base, or base then sub-block C; the inverse transposed
+ * in reverse order) with the same integer results.  TA_EUNSUPPORTED only
+ * when ta_set_impl(1) requires a matrix-core kernel that is not built. */
 int ta_fwd_packed(ta_ctx* ctx, int axis_h, int axis_v, int log2w, int log2h,
                   int64_t nblocks, const void* in, void* out, int dtype, ta_stream_t stream);
 int ta_inv_packed(ta_ctx* ctx, int axis_h, int axis_v, int log2w, int log2h,
@@ -181,10 +188,14 @@ int ta_fwd_multi(ta_ctx* ctx, int param_id, int log2n, int64_t nblocks, const vo
 
 /* ---- Batched uneven blocks (block lists) ----------------------------------
  * A plan takes a host array of n ta_block descriptors (block sizes 4..64 per
- * side, any mix) whose axes resolve to DCT-2, or to a DST-3 + 4-tap band
- * (adjusted DST-7, or with flip = 1 adjusted DCT-8): each axis id names the
- * parameter set of its size, so a workload registers one axis id per
- * (type, size).  Offsets and row strides are in elements and must be
+ * side, any mix) whose axes are any registered kind (base DCT-2, DCT-3,
+ * DST-2, DST-3, direct DST-7 / DCT-8; band or sub-block adjustment of any
+ * registered K / B; flipped or not): an axis with an adjustment names the
+ * parameter set of one size, so a workload registers one axis id per
+ * (type, size).  A plan whose axes are all DCT-2, DST-3 + 4-tap band or its
+ * flip (the adjusted DST-7 / DCT-8) runs on the fast batched kernel; any
+ * other kind moves the whole plan to the general kernel (the same results,
+ * each axis applied as its stages).  Offsets and row strides are in elements and must be
  * multiples of 8 (4 for 4-wide blocks); the forward reads the residual
  * block at (in_off, in_stride) of `in` and writes its coefficients at
  * (out_off, out_stride) of `out`; the inverse reads coefficients at
@@ -232,11 +243,15 @@ int ta_plan_set_tuning(ta_plan* plan, int grid, int region_log2);
  * of up to 64 blocks.  Throughput grows with the number of equal
  * configurations per window; a plan (ta_plan_create) groups the whole list
  * on the host once and runs fastest.  The
- * descriptor rules, transforms and dtypes are those of the plans (DCT-2 or
- * DST-3 + 4-tap band axes; axes resolve through the context at launch time,
- * so a parameter set registered again is seen by the next call).  A
- * descriptor that breaks a rule the kernel can check (size, offset sign and
- * alignment, stride, axis id or kind) is skipped and its output untouched.
+ * descriptor rules, transforms and dtypes are those of the plans (axes
+ * resolve through the context at launch time, so a parameter set registered
+ * again is seen by the next call).  While every axis registered with the
+ * context resolves to a fast kind at each size it resolves at, the fast
+ * kernel runs the list; once any registered axis has another kind, the
+ * general kernel runs every list of the context.  A descriptor that breaks a
+ * rule the kernel can check (size, offset sign and alignment, stride, axis
+ * id, an axis that does not resolve at the block's size) is skipped and its
+ * output untouched.
  * Extents are the caller's contract: every block must lie inside in and out
  * and blocks must not overlap in out; ta_validate_blocks checks a list.
  * in and out: 16-byte aligned device memory, not the same buffer.

@@ -26,6 +26,7 @@
 #include "fp.hpp"
 #include "fx.hpp"
 #include "kernels.hpp"
+#include "window_sort.hpp"
 
 namespace ta {
 namespace {
@@ -595,24 +596,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 3 : 4
       }
       skey[i] = sk;
     }
-    // ascending bitonic sort; the position in the low bits makes every key
+    // ascending sort; the position in the low bits makes every key
     // distinct, so equal configurations keep list order
-#pragma unroll 1
-    for (int k = 2; k <= kSortWin; k <<= 1)
-#pragma unroll 1
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kSortWin / 512; ++r) {
-          const int pr = tid + r * 256;                        // pair index
-          const int lo = ((pr & ~(j - 1)) << 1) | (pr & (j - 1)), hi = lo + j;
-          const uint32_t x = skey[lo], y = skey[hi];
-          if ((x > y) == ((lo & k) == 0)) {
-            skey[lo] = y;
-            skey[hi] = x;
-          }
-        }
-      }
+    bitonic_sort_window<kSortWin>(skey, tid);
     __syncthreads();
     const int qcnt = min(kDescWindow, cnt - q0);
     if (tid < qcnt && skey[q0 + tid] != kInvalid) qdesc[tid] = a.blocks[w0 + (skey[q0 + tid] & (kSortWin - 1))];

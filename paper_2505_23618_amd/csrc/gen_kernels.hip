@@ -1,0 +1,437 @@
+// General block transforms: every axis kind of the library, in block lists
+// (planned or unplanned) and in packed batches without a specialised kernel.
+//
+// An axis is a program of at most two 1-D stages (GenProg, built by the host
+// from the registered axis: the core kind after the DCT-8 flip, the band or
+// sub-block tables in the orientation of the direction).  A tile holds NB
+// blocks of one size W x H; one kernel serves both directions:
+//   load   coalesced 16-byte (int16) or float4 (fp32) chunks of every block
+//          into LDS, row-major, row pitch RP (GenGeo)
+//   pass 1 forward: every row by the horizontal program; inverse: every
+//          column by the vertical program (one vector per thread, updated in
+//          place)
+//   pass 2 the other axis
+//   store  coalesced chunks back out.
+// Stages are wave-uniform runtime choices (the tile's program); each is a
+// compile-time body per vector length, and the two passes share one call
+// site per length.  The stages are those of the specialised kernels
+// (fx.hpp, fp.hpp): the butterfly cores, the K-tap band and the B x B
+// sub-block, plus a dense N x N product for the direct DST-7 / DCT-8 and for
+// sub-blocks of a side without a compiled stage.  Fixed point is exact (the
+// same integers as every other kernel); fp32 has no rounding.
+#include "fp.hpp"
+#include "fx.hpp"
+#include "kernels.hpp"
+#include "window_sort.hpp"
+
+namespace ta {
+namespace {
+
+// Offsets and strides of the blocks of the current tile (in LDS).
+struct GDesc {
+  int64_t in_off, out_off;
+  int32_t in_stride, out_stride;
+};
+constexpr int kGenMaxBlocks = 64;
+
+// A stage's parameters live in the constant address space: they are
+// wave-uniform and arrive by scalar loads.
+TA_DEV GenStage load_stage(const GenProg* pr, int i) {
+  typedef const __attribute__((address_space(4))) int32_t* cint;
+  typedef const __attribute__((address_space(4))) uint64_t* cu64;
+  const cint w = (cint)&pr->st[i];
+  GenStage s;
+  s.op = w[0];
+  s.arg = w[1];
+  s.tr = w[2];
+  s.adj = w[3];
+  s.p = reinterpret_cast<const void*>(*(cu64)&pr->st[i].p);
+  return s;
+}
+TA_DEV int load_nst(const GenProg* pr) {
+  typedef const __attribute__((address_space(4))) int32_t* cint;
+  return *(cint)&pr->nst;
+}
+
+// ---------------------------------------------------------------- int16 stages
+template <int N, class A>
+TA_DEV void pack_into(const A& acc, fx::Packed<N>& x) {
+#pragma unroll
+  for (int s = 0; s < N / 2; ++s) x.p[s] = acc.pair(2 * s, 2 * s + 1);
+}
+
+// z = M x for a dense N x N integer matrix, row k of m holding the packed
+// pairs (M[k][2j], M[k][2j+1]).
+template <int N, class S>
+TA_DEV fx::Acc<N> dense(const S& src, cparam m, int shift) {
+  fx::Acc<N> r;
+  r.s0 = r.s1 = shift;
+  const int off = 1 << (shift - 1);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    int acc = off;
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) acc = dot2(src.p[j], m[k * (N / 2) + j], acc);
+    r.a[k] = acc;
+  }
+  return r;
+}
+
+template <int N, int K>
+TA_DEV void band_fx(fx::Packed<N>& x, cparam taps, int tr, int shift) {
+  if (tr)
+    pack_into<N>(fx::band<N, K, true>(x, taps, shift), x);
+  else
+    pack_into<N>(fx::band<N, K, false>(x, taps, shift), x);
+}
+
+// First B entries become RS(Q x_{<B}, a), the rest pass through.
+template <int N, int B>
+TA_DEV void post_fx(fx::Packed<N>& x, cparam q, int a) {
+  if constexpr (B <= N) {
+    int z[B];
+    fx::post_rows<N, B>(x, q, a, z);
+#pragma unroll
+    for (int s = 0; s < B / 2; ++s) x.p[s] = satpk(z[2 * s] >> a, z[2 * s + 1] >> a);
+  }
+}
+
+template <int N>
+TA_DEV void apply_fx(const GenStage& st, fx::Packed<N>& x, int s_core, int a) {
+  const int sh = st.adj ? a : s_core;
+  const cparam p = as_cparam(st.p);
+  switch (st.op) {
+    case GS_C2: pack_into<N>(fx::core_c2<N, false, false, false>(x, sh), x); break;
+    case GS_S2: pack_into<N>(fx::core_c2<N, true, true, false>(x, sh), x); break;
+    case GS_C3: pack_into<N>(fx::core_c3<N, false, false>(x, sh), x); break;
+    case GS_S3: pack_into<N>(fx::core_c3<N, true, true>(x, sh), x); break;
+    case GS_DENSE: pack_into<N>(dense<N>(x, p, sh), x); break;
+    case GS_BAND:
+      switch (st.arg) {
+        case 2: band_fx<N, 2>(x, p, st.tr, sh); break;
+        case 4: band_fx<N, 4>(x, p, st.tr, sh); break;
+        case 6: band_fx<N, 6>(x, p, st.tr, sh); break;
+        default: band_fx<N, 8>(x, p, st.tr, sh); break;
+      }
+      break;
+    default:   // GS_POST
+      switch (st.arg) {
+        case 4: post_fx<N, 4>(x, p, sh); break;
+        case 8: post_fx<N, 8>(x, p, sh); break;
+        default: post_fx<N, 16>(x, p, sh); break;
+      }
+      break;
+  }
+}
+
+// One vector of a tile in LDS: N int16 at base + i * stride halfwords (a row
+// when stride == 1: dword-aligned, read and written as dwords; a column
+// otherwise).  Runs the program's stages and writes the result in place.
+template <int N>
+TA_DEV void vec_fx(uint16_t* lds, int base, int stride, const GenProg* pr, int s_core, int a) {
+  fx::Packed<N> x;
+  if (stride == 1) {
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(lds + base);
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) x.p[j] = s[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j)
+      x.p[j] = (uint32_t)lds[base + 2 * j * stride] | ((uint32_t)lds[base + (2 * j + 1) * stride] << 16);
+  }
+  const int nst = load_nst(pr);
+#pragma unroll 1
+  for (int i = 0; i < nst; ++i) apply_fx<N>(load_stage(pr, i), x, s_core, a);
+  if (stride == 1) {
+    uint32_t* d = reinterpret_cast<uint32_t*>(lds + base);
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) d[j] = x.p[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < N / 2; ++j) {
+      lds[base + 2 * j * stride] = (uint16_t)x.p[j];
+      lds[base + (2 * j + 1) * stride] = (uint16_t)(x.p[j] >> 16);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- fp32 stages
+template <int N>
+TA_DEV fp::Vec<N> dense_f(const fp::Vec<N>& x, const float* __restrict__ m) {
+  typedef const __attribute__((address_space(4))) float* cfl;
+  const cfl c = (cfl)m;
+  fp::Vec<N> z;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int n = 0; n < N; ++n) acc = __builtin_fmaf(c[k * N + n], x.v[n], acc);
+    z.v[k] = acc;
+  }
+  return z;
+}
+
+template <int N, int K>
+TA_DEV void band_f(fp::Vec<N>& x, const float* taps, int tr) {
+  x = tr ? fp::band<N, K, true>(x, taps) : fp::band<N, K, false>(x, taps);
+}
+
+template <int N, int B>
+TA_DEV void post_f(fp::Vec<N>& x, const float* q) {
+  if constexpr (B <= N) x = fp::post<N, B>(x, q);
+}
+
+template <int N>
+TA_DEV void apply_f(const GenStage& st, fp::Vec<N>& x) {
+  const float* p = static_cast<const float*>(st.p);
+  switch (st.op) {
+    case GS_C2: x = fp::core_c2<N, false, false>(x); break;
+    case GS_S2: x = fp::core_c2<N, true, true>(x); break;
+    case GS_C3: x = fp::core_c3<N, false, false>(x); break;
+    case GS_S3: x = fp::core_c3<N, true, true>(x); break;
+    case GS_DENSE: x = dense_f<N>(x, p); break;
+    case GS_BAND:
+      switch (st.arg) {
+        case 2: band_f<N, 2>(x, p, st.tr); break;
+        case 4: band_f<N, 4>(x, p, st.tr); break;
+        case 6: band_f<N, 6>(x, p, st.tr); break;
+        default: band_f<N, 8>(x, p, st.tr); break;
+      }
+      break;
+    default:   // GS_POST
+      switch (st.arg) {
+        case 4: post_f<N, 4>(x, p); break;
+        case 8: post_f<N, 8>(x, p); break;
+        default: post_f<N, 16>(x, p); break;
+      }
+      break;
+  }
+}
+
+template <int N>
+TA_DEV void vec_f(float* lds, int base, int stride, const GenProg* pr) {
+  fp::Vec<N> x;
+#pragma unroll
+  for (int i = 0; i < N; ++i) x.v[i] = lds[base + i * stride];
+  const int nst = load_nst(pr);
+#pragma unroll 1
+  for (int i = 0; i < nst; ++i) apply_f<N>(load_stage(pr, i), x);
+#pragma unroll
+  for (int i = 0; i < N; ++i) lds[base + i * stride] = x.v[i];
+}
+
+// ---------------------------------------------------------------- one tile
+// Where the blocks of a tile are: descriptors (first + b), or a packed batch
+// (block first + b at (first + b) * W * H, row stride W).
+TA_DEV GDesc tile_desc(const ta_block* blocks, int64_t idx, int lw, int lh) {
+  if (blocks) {
+    const ta_block d = blocks[idx];
+    return GDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
+  }
+  const int64_t off = idx << (lw + lh);
+  return GDesc{off, off, 1 << lw, 1 << lw};
+}
+
+// One tile: NB blocks of 2^lw x 2^lh at descriptors first..first+count-1,
+// programs ph (rows) and pv (columns) of the launch direction.  Ends with a
+// barrier (LDS free for the next tile).
+template <bool F32>
+TA_DEV void gen_tile(const GenArgs& a, const ta_block* blocks, int64_t first, int lw, int lh, int count,
+                     const GenProg* ph, const GenProg* pv, void* lds_raw, GDesc* desc) {
+  const int tid = threadIdx.x;
+  const int w = 1 << lw;
+  const int rp = GenGeo::rp(lw, F32), bs = GenGeo::bs(lw, lh, F32);
+  if (tid < count) desc[tid] = tile_desc(blocks, first + tid, lw, lh);
+  __syncthreads();
+  // coalesced load: chunks of 8 halfwords / 4 floats (4 halfwords for 4-wide int16 rows)
+  const int lch = F32 ? 2 : (lw >= 3 ? 3 : 2);
+  const int lq = lw - lch;                             // log2 chunks per row
+  const int nch = count << (lh + lq);
+  for (int ch = tid; ch < nch; ch += 256) {
+    const int b = ch >> (lh + lq), r = (ch >> lq) & ((1 << lh) - 1), c0 = (ch & ((1 << lq) - 1)) << lch;
+    const GDesc d = desc[b];
+    if constexpr (F32) {
+      const float4 v = *reinterpret_cast<const float4*>(static_cast<const float*>(a.in) + d.in_off +
+                                                        (int64_t)r * d.in_stride + c0);
+      float* dst = static_cast<float*>(lds_raw) + b * bs + r * rp + c0;
+      dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
+    } else {
+      const int16_t* src = static_cast<const int16_t*>(a.in) + d.in_off + (int64_t)r * d.in_stride + c0;
+      uint32_t* dst = reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(lds_raw) + b * bs + r * rp + c0);
+      if (lch == 3) {
+        const uint4 v = *reinterpret_cast<const uint4*>(src);
+        dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
+      } else {
+        const uint2 v = *reinterpret_cast<const uint2*>(src);
+        dst[0] = v.x; dst[1] = v.y;
+      }
+    }
+  }
+  __syncthreads();
+  // two passes: forward rows then columns, inverse columns then rows
+  const int s_row = a.inv ? a.m + 14 - a.bd : lw + a.bd + a.m - 15;
+  const int s_col = a.inv ? a.m + 1 : lh + a.m;
+#pragma unroll 1
+  for (int ps = 0; ps < 2; ++ps) {
+    const bool rows = (ps == 0) == (a.inv == 0);
+    const int nlog = rows ? lw : lh;
+    const int nvec = count << (rows ? lh : lw);
+    if (tid < nvec) {
+      const int b = tid >> (rows ? lh : lw), i = tid & ((1 << (rows ? lh : lw)) - 1);
+      const int base = b * bs + (rows ? i * rp : i);
+      const int stride = rows ? 1 : rp;
+      const GenProg* pr = rows ? ph : pv;
+      const int sc = rows ? s_row : s_col;
+      if constexpr (F32) {
+        float* l = static_cast<float*>(lds_raw);
+        switch (nlog) {
+          case 2: vec_f<4>(l, base, stride, pr); break;
+          case 3: vec_f<8>(l, base, stride, pr); break;
+          case 4: vec_f<16>(l, base, stride, pr); break;
+          case 5: vec_f<32>(l, base, stride, pr); break;
+          default: vec_f<64>(l, base, stride, pr); break;
+        }
+      } else {
+        uint16_t* l = static_cast<uint16_t*>(lds_raw);
+        switch (nlog) {
+          case 2: vec_fx<4>(l, base, stride, pr, sc, a.a); break;
+          case 3: vec_fx<8>(l, base, stride, pr, sc, a.a); break;
+          case 4: vec_fx<16>(l, base, stride, pr, sc, a.a); break;
+          case 5: vec_fx<32>(l, base, stride, pr, sc, a.a); break;
+          default: vec_fx<64>(l, base, stride, pr, sc, a.a); break;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // coalesced store
+  for (int ch = tid; ch < nch; ch += 256) {
+    const int b = ch >> (lh + lq), r = (ch >> lq) & ((1 << lh) - 1), c0 = (ch & ((1 << lq) - 1)) << lch;
+    const GDesc d = desc[b];
+    if constexpr (F32) {
+      const float* s = static_cast<const float*>(lds_raw) + b * bs + r * rp + c0;
+      *reinterpret_cast<float4*>(static_cast<float*>(a.out) + d.out_off + (int64_t)r * d.out_stride + c0) =
+          make_float4(s[0], s[1], s[2], s[3]);
+    } else {
+      const uint32_t* s = reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(lds_raw) + b * bs + r * rp + c0);
+      int16_t* dst = static_cast<int16_t*>(a.out) + d.out_off + (int64_t)r * d.out_stride + c0;
+      if (lch == 3)
+        *reinterpret_cast<uint4*>(dst) = make_uint4(s[0], s[1], s[2], s[3]);
+      else
+        *reinterpret_cast<uint2*>(dst) = make_uint2(s[0], s[1]);
+    }
+  }
+  __syncthreads();
+}
+
+constexpr int lds_dwords(bool f32) { return f32 ? kGenLdsF32 : kGenLdsI16 / 2; }
+
+// Planned tile lists (one per XCD, walked with a grid stride by the
+// workgroups of that XCD), or a packed batch (tiles == null): tile t holds
+// blocks t * NB .. t * NB + NB - 1, walked with a grid stride.
+template <bool F32>
+__global__ __launch_bounds__(256) void gen_plan(GenArgs a) {
+  __shared__ __align__(16) uint32_t lds[lds_dwords(F32)];
+  __shared__ GDesc desc[kGenMaxBlocks];
+  if (a.tiles) {
+    const int xcd = blockIdx.x % kXcds;
+    const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
+    const int64_t end = a.xstart[xcd + 1];
+    for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd) {
+      const BatchTile t = a.tiles[ti];
+      const GenProg* ph = reinterpret_cast<const GenProg*>(a.inv ? t.ph_i : t.ph_f);
+      const GenProg* pv = reinterpret_cast<const GenProg*>(a.inv ? t.pv_i : t.pv_f);
+      gen_tile<F32>(a, a.blocks, t.first, t.lw, t.lh, t.count, ph, pv, lds, desc);
+    }
+  } else {
+    const int nb = GenGeo::nb_for(a.lw, a.lh, F32);
+    const int64_t ntiles = (a.nblocks + nb - 1) / nb;
+    for (int64_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+      const int64_t first = ti * nb;
+      const int count = (int)min<int64_t>(nb, a.nblocks - first);
+      gen_tile<F32>(a, nullptr, first, a.lw, a.lh, count, a.ph, a.pv, lds, desc);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- block lists
+// Unplanned descriptors, grouped on the device as in the fast block-list
+// kernel (batch_kernels.hip): windows of kSortWin descriptors, each shared by
+// kSortQuarters workgroups that sort the whole window by (configuration,
+// position) and run their own quarter of it as tiles of equal size and axis
+// ids.  A descriptor that breaks a rule the kernel can check (size, offset
+// sign and alignment, stride, axis id, no program for the axis at its size)
+// sorts last and is skipped.
+constexpr int kSortWin = kDescWindow * kSortQuarters;
+
+TA_DEV const GenProg* axis_prog(const GenArgs& a, int axis, int lsize, int inv) {
+  return a.progs + ((size_t)axis * kAxisSizes + lsize) * 2 + inv;
+}
+
+TA_DEV int gen_key(const GenArgs& a, const ta_block& d) {
+  const int ch = d.log2w >= 3 ? 8 : 4;
+  if (d.log2w < 2 || d.log2w > 6 || d.log2h < 2 || d.log2h > 6 || d.in_off < 0 || d.out_off < 0 ||
+      d.in_stride < (1 << d.log2w) || d.out_stride < (1 << d.log2w) || d.axis_h >= kAxisIds ||
+      d.axis_v >= kAxisIds || ((d.in_off | d.out_off | (int64_t)d.in_stride | (int64_t)d.out_stride) & (ch - 1)))
+    return -1;
+  if (axis_prog(a, d.axis_h, d.log2w, a.inv)->nst <= 0 || axis_prog(a, d.axis_v, d.log2h, a.inv)->nst <= 0) return -1;
+  return d.log2w | (d.log2h << 3) | (d.axis_h << 6) | (d.axis_v << 14);
+}
+
+template <bool F32>
+__global__ __launch_bounds__(256) void gen_desc(GenArgs a) {
+  __shared__ __align__(16) uint32_t lds[lds_dwords(F32)];
+  __shared__ GDesc desc[kGenMaxBlocks];
+  __shared__ uint32_t skey[kSortWin];
+  __shared__ ta_block qdesc[kDescWindow];
+  constexpr uint32_t kInvalid = ~0u;
+  const int tid = threadIdx.x;
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
+  const int64_t nunits = (a.nblocks + kSortWin - 1) / kSortWin * kSortQuarters;
+  const int64_t uend = nunits * (xcd + 1) / kXcds;
+  for (int64_t u = nunits * xcd / kXcds + blockIdx.x / kXcds; u < uend; u += per_xcd) {
+    const int64_t w0 = u / kSortQuarters * kSortWin;
+    const int q0 = (int)(u % kSortQuarters) * kDescWindow;
+    const int cnt = (int)min<int64_t>(kSortWin, a.nblocks - w0);
+#pragma unroll
+    for (int r = 0; r < kSortQuarters; ++r) {
+      const int i = tid + r * 256;
+      uint32_t sk = kInvalid;
+      if (i < cnt) {
+        const int k = gen_key(a, a.blocks[w0 + i]);
+        if (k >= 0) sk = ((uint32_t)k << 10) | (uint32_t)i;
+      }
+      skey[i] = sk;
+    }
+    bitonic_sort_window<kSortWin>(skey, tid);
+    __syncthreads();
+    const int qcnt = min(kDescWindow, cnt - q0);
+    if (tid < qcnt && skey[q0 + tid] != kInvalid) qdesc[tid] = a.blocks[w0 + (skey[q0 + tid] & (kSortWin - 1))];
+    __syncthreads();
+    int j = 0;
+    while (j < qcnt) {
+      const uint32_t s0 = skey[q0 + j];
+      if (s0 == kInvalid) break;
+      const uint32_t k = s0 >> 10;
+      const int lw = (int)(k & 7), lh = (int)((k >> 3) & 7);
+      const int ah = (int)((k >> 6) & 0xff), av = (int)((k >> 14) & 0xff);
+      const int cap = GenGeo::nb_for(lw, lh, F32);
+      int len = 1;
+      while (j + len < qcnt && len < cap && (skey[q0 + j + len] >> 10) == k) ++len;
+      gen_tile<F32>(a, qdesc, j, lw, lh, len, axis_prog(a, ah, lw, a.inv), axis_prog(a, av, lh, a.inv), lds, desc);
+      j += len;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+const void* gen_kernel(int desc, int f32) {
+  if (desc)
+    return f32 ? reinterpret_cast<const void*>(&gen_desc<true>) : reinterpret_cast<const void*>(&gen_desc<false>);
+  return f32 ? reinterpret_cast<const void*>(&gen_plan<true>) : reinterpret_cast<const void*>(&gen_plan<false>);
+}
+
+}  // namespace ta

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <tuple>
+#include <utility>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -17,6 +18,7 @@
 
 #include "../../include/tadj.h"
 #include "kernels.hpp"
+#include "tables_gen.h"
 
 namespace {
 
@@ -95,6 +97,11 @@ struct ParamSet {
   // sub-block sets: Q (forward, unflipped) as even/odd column pairs, for the
   // simultaneous DST-7 / DCT-8 adjustment
   void* fx_eo = nullptr;
+  // sub-block sets of a side without a compiled general stage (B not in
+  // {4, 8, 16}): C = blkdiag(Q, 2^a I) (fixed point) and blkdiag(Q, I)
+  // (fp32) as dense n x n matrices, [flip][transposed]
+  void* dense_fx[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  void* dense_f32[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 };
 
 struct AxisCfg {
@@ -129,6 +136,15 @@ struct ta_ctx {
   ta::AxisDev* axes_dev = nullptr;
   // this device's static scratch (ta_givens_bwd_noalloc), looked up at create
   float* scratch = nullptr;
+  // general kernels: the direct DST-7 / DCT-8 integer (packed pairs) and
+  // fp32 matrices of every size, [dtype][kind: 0 DST-7, 1 DCT-8][transposed][log2 n]
+  const void* direct[2][2][2][ta::kAxisSizes] = {};
+  // stage programs of every (axis id, log2 size, direction), one device
+  // table per dtype (kAxisIds x kAxisSizes x 2; nst = 0 where the axis does
+  // not resolve), and which entries have no fast batched kind
+  ta::GenProg* gprogs_dev[2] = {nullptr, nullptr};
+  bool general[kMaxIds][ta::kAxisSizes] = {};
+  int ngeneral = 0;
   std::vector<void*> allocations;
   std::mutex mu;
 };
@@ -170,6 +186,11 @@ struct Resolved {
   int core, adj, kb;
   const void* pf;  // forward-orientation parameters
   const void* pi;  // transposed parameters
+  const void* pdf; // sub-block as a dense n x n matrix (sides without a compiled general stage)
+  const void* pdi;
+  bool operator<(const Resolved& o) const {
+    return std::tie(core, adj, kb, pf, pi, pdf, pdi) < std::tie(o.core, o.adj, o.kb, o.pf, o.pi, o.pdf, o.pdi);
+  }
 };
 
 // Turn a user axis into the kernel's (core, adjustment, K/B, parameters).
@@ -180,7 +201,7 @@ int resolve_axis(ta_ctx* c, int id, int n, int dtype, Resolved* r) {
   r->core = core;
   r->adj = u.adj;
   r->kb = 0;
-  r->pf = r->pi = nullptr;
+  r->pf = r->pi = r->pdf = r->pdi = nullptr;
   if (u.adj == TA_ADJ_NONE) return TA_OK;
   const ParamSet& ps = c->params[u.param_id];
   if (ps.kind != u.adj) return fail(TA_ENOPARAMS, "axis %d: parameter set %d missing or of another kind", id, u.param_id);
@@ -190,7 +211,72 @@ int resolve_axis(ta_ctx* c, int id, int n, int dtype, Resolved* r) {
   const int f = u.flip ? 1 : 0;
   r->pf = dtype == TA_I16 ? ps.fx[f][0] : ps.f32[f][0];
   r->pi = dtype == TA_I16 ? ps.fx[f][1] : ps.f32[f][1];
+  r->pdf = dtype == TA_I16 ? ps.dense_fx[f][0] : ps.dense_f32[f][0];
+  r->pdi = dtype == TA_I16 ? ps.dense_fx[f][1] : ps.dense_f32[f][1];
   return TA_OK;
+}
+
+// Sub-block sides with a compiled stage in the general kernels.
+bool gen_post_side(int b) { return b == 4 || b == 8 || b == 16; }
+
+// The stage program of a resolved axis at size 2^l (section 2.2, eq. 1):
+// forward [A, B] for a band, [B, C] for a sub-block, [B] without adjustment;
+// the inverse runs the transposed stages in reverse order.  Butterfly cores
+// transpose by kind (DCT-2 <-> DCT-3, DST-2 <-> DST-3); the direct DST-7 /
+// DCT-8 run as dense matrices.
+ta::GenProg gen_prog(const ta_ctx* c, const Resolved& r, int l, int dtype, int inv) {
+  auto butterfly = [](int core) {
+    switch (core) {
+      case TA_DCT2: return (int)ta::GS_C2;
+      case TA_DST2: return (int)ta::GS_S2;
+      case TA_DCT3: return (int)ta::GS_C3;
+      case TA_DST3: return (int)ta::GS_S3;
+    }
+    return -1;
+  };
+  auto transposed = [](int core) {
+    switch (core) {
+      case TA_DCT2: return (int)TA_DCT3;
+      case TA_DCT3: return (int)TA_DCT2;
+      case TA_DST2: return (int)TA_DST3;
+      case TA_DST3: return (int)TA_DST2;
+    }
+    return core;
+  };
+  ta::GenStage core{};
+  const int bop = butterfly(inv ? transposed(r.core) : r.core);
+  if (bop >= 0) {
+    core.op = bop;
+  } else {
+    core.op = ta::GS_DENSE;
+    core.p = c->direct[dtype == TA_F32][r.core == TA_DCT8][inv][l];
+  }
+  ta::GenProg pr{};
+  if (r.adj == TA_ADJ_NONE) {
+    pr.nst = 1;
+    pr.st[0] = core;
+    return pr;
+  }
+  ta::GenStage adj{};
+  adj.adj = 1;
+  if (r.adj == TA_ADJ_BAND) {
+    adj.op = ta::GS_BAND;
+    adj.arg = r.kb;
+    adj.tr = inv;
+    adj.p = inv ? r.pi : r.pf;
+  } else if (gen_post_side(r.kb)) {
+    adj.op = ta::GS_POST;
+    adj.arg = r.kb;
+    adj.p = inv ? r.pi : r.pf;
+  } else {
+    adj.op = ta::GS_DENSE;
+    adj.p = inv ? r.pdi : r.pdf;
+  }
+  const bool adj_first = (r.adj == TA_ADJ_BAND) != (inv != 0);
+  pr.nst = 2;
+  pr.st[0] = adj_first ? adj : core;
+  pr.st[1] = adj_first ? core : adj;
+  return pr;
 }
 
 // kind of a resolved axis in the batched kernel (see batch_kernels.hip)
@@ -207,22 +293,35 @@ int batch_kind(const Resolved& r) {
 // messages are not left in the error slot.  Caller holds c->mu.
 int refresh_axis(ta_ctx* c, int id) {
   ta::AxisDev row[ta::kAxisSizes];
+  ta::GenProg progs[2][ta::kAxisSizes][2] = {};   // [dtype][log2 size][direction]
   const std::string saved = g_err;
   for (int l = 0; l < ta::kAxisSizes; ++l) {
     row[l] = ta::AxisDev{-1, 0, nullptr, nullptr, nullptr, nullptr};
     Resolved r, rf;
-    if (l >= 2 && l <= 6 && c->axes[id].set && resolve_axis(c, id, 1 << l, TA_I16, &r) == TA_OK &&
-        resolve_axis(c, id, 1 << l, TA_F32, &rf) == TA_OK && batch_kind(r) >= 0) {
+    const bool ok = l >= 2 && l <= 6 && c->axes[id].set && resolve_axis(c, id, 1 << l, TA_I16, &r) == TA_OK &&
+                    resolve_axis(c, id, 1 << l, TA_F32, &rf) == TA_OK;
+    if (ok && batch_kind(r) >= 0) {
       row[l].kind = batch_kind(r);
       row[l].pf = static_cast<const uint32_t*>(r.pf);
       row[l].pi = static_cast<const uint32_t*>(r.pi);
       row[l].ff = static_cast<const float*>(rf.pf);
       row[l].fi = static_cast<const float*>(rf.pi);
     }
+    if (ok)
+      for (int inv = 0; inv < 2; ++inv) {
+        progs[0][l][inv] = gen_prog(c, r, l, TA_I16, inv);
+        progs[1][l][inv] = gen_prog(c, rf, l, TA_F32, inv);
+      }
+    const bool gen = ok && batch_kind(r) < 0;
+    c->ngeneral += (int)gen - (int)c->general[id][l];
+    c->general[id][l] = gen;
   }
   g_err = saved;
   TA_ON_DEVICE(c->device);
   TA_HIP(hipMemcpy(c->axes_dev + (size_t)id * ta::kAxisSizes, row, sizeof row, hipMemcpyHostToDevice));
+  for (int dt = 0; dt < 2; ++dt)
+    TA_HIP(hipMemcpy(c->gprogs_dev[dt] + (size_t)id * ta::kAxisSizes * 2, progs[dt], sizeof progs[dt],
+                     hipMemcpyHostToDevice));
   return TA_OK;
 }
 
@@ -234,6 +333,59 @@ int refresh_param_users(ta_ctx* c, int pid) {
       int e;
       if ((e = refresh_axis(c, id))) return e;
     }
+  }
+  return TA_OK;
+}
+
+// Direct DST-7 (kind 0) or DCT-8 (kind 1) integer entry of size n, row k,
+// column j, transposed when tr: DCT-8[k][j] = (-1)^k DST-7[k][n-1-j] (eq. 3).
+template <class T7>
+int direct_entry(const T7& s7, int n, int kind, int tr, int k, int j) {
+  if (tr) std::swap(k, j);
+  if (kind == 0) return s7[k][j];
+  return (k & 1) ? -s7[k][n - 1 - j] : s7[k][n - 1 - j];
+}
+
+template <int N>
+int upload_direct(ta_ctx* c, const short (&s7)[N][N], const double (&s7f)[N][N], int l) {
+  for (int kind = 0; kind < 2; ++kind)
+    for (int tr = 0; tr < 2; ++tr) {
+      std::vector<uint32_t> fx((size_t)N * N / 2);
+      std::vector<float> f32((size_t)N * N);
+      for (int k = 0; k < N; ++k) {
+        for (int j = 0; j < N / 2; ++j)
+          fx[(size_t)k * (N / 2) + j] = pack2(direct_entry(s7, N, kind, tr, k, 2 * j),
+                                              direct_entry(s7, N, kind, tr, k, 2 * j + 1));
+        for (int j = 0; j < N; ++j) {
+          int kk = k, jj = j;
+          if (tr) std::swap(kk, jj);
+          const double v = kind == 0 ? s7f[kk][jj] : ((kk & 1) ? -s7f[kk][N - 1 - jj] : s7f[kk][N - 1 - jj]);
+          f32[(size_t)k * N + j] = (float)v;
+        }
+      }
+      void* p = nullptr;
+      int e;
+      if ((e = upload(c, fx.data(), fx.size() * 4, &p))) return e;
+      c->direct[0][kind][tr][l] = p;
+      if ((e = upload(c, f32.data(), f32.size() * 4, &p))) return e;
+      c->direct[1][kind][tr][l] = p;
+    }
+  return TA_OK;
+}
+
+// The general kernels' context tables: direct matrices of every size and the
+// (empty) program tables.
+int upload_general_tables(ta_ctx* c) {
+  int e;
+  if ((e = upload_direct<4>(c, ta_s7_4, ta_s7f_4, 2)) || (e = upload_direct<8>(c, ta_s7_8, ta_s7f_8, 3)) ||
+      (e = upload_direct<16>(c, ta_s7_16, ta_s7f_16, 4)) || (e = upload_direct<32>(c, ta_s7_32, ta_s7f_32, 5)) ||
+      (e = upload_direct<64>(c, ta_s7_64, ta_s7f_64, 6)))
+    return e;
+  std::vector<ta::GenProg> empty((size_t)ta::kAxisIds * ta::kAxisSizes * 2, ta::GenProg{});
+  for (int dt = 0; dt < 2; ++dt) {
+    void* p = nullptr;
+    if ((e = upload(c, empty.data(), empty.size() * sizeof(ta::GenProg), &p))) return e;
+    c->gprogs_dev[dt] = static_cast<ta::GenProg*>(p);
   }
   return TA_OK;
 }
@@ -279,6 +431,38 @@ int resident_groups(const void* fn, int threads, int dev, int* out) {
 
 int resident_groups(const ta::KernelEntry* k, int dev, int* out) { return resident_groups(k->fn, k->threads, dev, out); }
 
+// A packed batch without a specialised kernel: the general kernel, with the
+// axes' stage programs from the context table, as a persistent grid over
+// tiles of GenGeo::nb_for blocks.
+int launch_general_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int lw, int lh, int64_t nblocks,
+                          const void* in, void* out, int dtype, ta_stream_t stream) {
+  const bool f32 = dtype == TA_F32;
+  ta::GenArgs g{};
+  g.in = in;
+  g.out = out;
+  g.inv = inv;
+  g.bd = c->bd;
+  g.m = c->m;
+  g.a = c->a;
+  g.lw = lw;
+  g.lh = lh;
+  g.nblocks = nblocks;
+  const ta::GenProg* t = c->gprogs_dev[f32];
+  g.ph = t + ((size_t)axis_h * ta::kAxisSizes + lw) * 2 + inv;
+  g.pv = t + ((size_t)axis_v * ta::kAxisSizes + lh) * 2 + inv;
+  g.progs = t;
+  const void* fn = ta::gen_kernel(0, f32);
+  const int nb = ta::GenGeo::nb_for(lw, lh, f32);
+  const int64_t tiles = (nblocks + nb - 1) / nb;
+  int cap = 0, e;
+  if ((e = resident_groups(fn, 256, c->device, &cap))) return e;
+  const int64_t grid = std::min<int64_t>(tiles, cap);
+  void* kargs[] = {&g};
+  TA_ON_DEVICE(c->device);
+  TA_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(256), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
+  return TA_OK;
+}
+
 int run_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int log2w, int log2h, int64_t nblocks,
                const void* in, void* out, int dtype, ta_stream_t stream) {
   if (!c) return fail(TA_EINVAL, "null context");
@@ -303,11 +487,7 @@ int run_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int log2w, int log2h,
   const bool same = rh.pf == rv.pf && rh.pi == rv.pi && rh.kb == rv.kb;
   const ta::KernelEntry* k = find_kernel(key, prefer_mfma, c->impl == 1, same);
   if (!k && c->impl == 1) return fail(TA_EUNSUPPORTED, "no matrix-core kernel for this transform");
-  if (!k)
-    return fail(TA_EUNSUPPORTED,
-                "no kernel for %s %s %dx%d axes (core %d adj %d k/b %d) x (core %d adj %d k/b %d)",
-                inv ? "inverse" : "forward", dtype == TA_I16 ? "int16" : "fp32", 1 << log2w, 1 << log2h,
-                rh.core, rh.adj, rh.kb, rv.core, rv.adj, rv.kb);
+  if (!k) return launch_general_packed(c, inv, axis_h, axis_v, log2w, log2h, nblocks, in, out, dtype, stream);
   ta::PackedArgs args;
   args.in = in;
   args.out = out;
@@ -361,7 +541,9 @@ int ta_create(ta_ctx** out, int device, int bit_depth, int m, int a) {
   static_assert(kMaxIds == ta::kAxisIds, "axis table size");
   std::vector<ta::AxisDev> table((size_t)ta::kAxisIds * ta::kAxisSizes, ta::AxisDev{-1, 0, nullptr, nullptr, nullptr, nullptr});
   int e;
-  if ((e = upload(c.get(), table.data(), table.size() * sizeof(ta::AxisDev), reinterpret_cast<void**>(&c->axes_dev)))) {
+  if ((e = guard([&] { return upload(c.get(), table.data(), table.size() * sizeof(ta::AxisDev),
+                                     reinterpret_cast<void**>(&c->axes_dev)); })) ||
+      (e = guard([&] { return upload_general_tables(c.get()); }))) {
     for (void* p : c->allocations) (void)hipFree(p);
     return e;
   }
@@ -489,6 +671,19 @@ int ta_set_post(ta_ctx* c, int id, int n, int b, const int16_t* q_int, const flo
       int e;
       if ((e = upload(c, packed.data(), packed.size() * 4, &ps.fx[flip][tr]))) return e;
       if ((e = upload(c, fl.data(), fl.size() * 4, &ps.f32[flip][tr]))) return e;
+      if (!gen_post_side(b)) {
+        // blkdiag(M, 2^a I) at shift a leaves the entries >= b exactly as
+        // they are: RS(2^a y, a) = y
+        std::vector<uint32_t> dfx((size_t)n * n / 2);
+        std::vector<float> df((size_t)n * n, 0.0f);
+        auto dent = [&](int i, int j) { return (i < b && j < b) ? at(i, j) : (i == j ? (1 << c->a) : 0); };
+        for (int i = 0; i < n; ++i) {
+          for (int j = 0; j < n / 2; ++j) dfx[(size_t)i * (n / 2) + j] = pack2(dent(i, 2 * j), dent(i, 2 * j + 1));
+          for (int j = 0; j < n; ++j) df[(size_t)i * n + j] = (i < b && j < b) ? atf(i, j) : (i == j ? 1.0f : 0.0f);
+        }
+        if ((e = upload(c, dfx.data(), dfx.size() * 4, &ps.dense_fx[flip][tr]))) return e;
+        if ((e = upload(c, df.data(), df.size() * 4, &ps.dense_f32[flip][tr]))) return e;
+      }
     }
   if (b % 4 == 0) {
     // row i: (Q[i][4t], Q[i][4t+2]) for t < b/4, then (Q[i][4t+1], Q[i][4t+3])
@@ -547,8 +742,24 @@ struct ta_plan {
   // when the plan was built (kinds and parameter tables), kept for re-planning
   std::vector<ta_block> host;
   std::vector<uint32_t> cls;
-  struct Class { int kh, kv; const void *phf, *phi, *pvf, *pvi; };
+  struct Class { int lw, lh, kh, kv; Resolved rh, rv; };
   std::vector<Class> classes;
+  // a plan with an axis kind outside the fast batched kernel's runs on the
+  // general kernel: per class the stage programs h forward, h inverse,
+  // v forward, v inverse
+  bool general = false;
+  ta::GenProg* progs_dev = nullptr;
+  ta_plan() = default;
+  ta_plan(const ta_plan&) = delete;
+  ta_plan& operator=(const ta_plan&) = delete;
+  ~ta_plan() {
+    if (!blocks_dev && !tiles_dev && !progs_dev) return;
+    DeviceGuard device_guard_;
+    (void)device_guard_.enter(device);
+    if (blocks_dev) (void)hipFree(blocks_dev);
+    if (tiles_dev) (void)hipFree(tiles_dev);
+    if (progs_dev) (void)hipFree(progs_dev);
+  }
   int64_t nblocks = 0, ntiles = 0;
   int grid = 2048;                 // persistent workgroups (autotuned)
   ta_block* blocks_dev = nullptr;  // block descriptors in plan order
@@ -578,15 +789,32 @@ int check_block(ta_ctx* c, const ta_block& b, int64_t i, int dtype, Resolved* rh
     const std::string m = g_err;
     return fail(e, "block %lld: %s", (long long)i, m.c_str());
   }
+  // -1: no fast batched kind, the block runs on the general kernel
   *kh = batch_kind(*rh);
   *kv = batch_kind(*rv);
-  if (*kh < 0 || *kv < 0)
-    return fail(TA_EUNSUPPORTED, "block %lld: batched kernels take DCT-2, adjusted DST-7 or adjusted DCT-8 "
-                "(DST-3 + 4-tap band) axes", (long long)i);
   return TA_OK;
 }
 
 int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_stream_t stream, int grid) {
+  // at least one workgroup per XCD list
+  const int64_t g = std::max<int64_t>(ta::kXcds, std::min<int64_t>(grid, std::max<int64_t>(1, p->ntiles)));
+  if (p->general) {
+    ta::GenArgs ga{};
+    ga.tiles = p->tiles_dev;
+    for (int x = 0; x <= ta::kXcds; ++x) ga.xstart[x] = p->xstart[x];
+    ga.blocks = p->blocks_dev;
+    ga.in = in;
+    ga.out = out;
+    ga.inv = inv;
+    ga.bd = c->bd;
+    ga.m = c->m;
+    ga.a = c->a;
+    void* kargs[] = {&ga};
+    TA_ON_DEVICE(c->device);
+    TA_HIP(hipLaunchKernel(ta::gen_kernel(0, p->dtype == TA_F32), dim3((unsigned)g), dim3(256), kargs, 0,
+                           reinterpret_cast<hipStream_t>(stream)));
+    return TA_OK;
+  }
   ta::BatchArgs args;
   args.tiles = p->tiles_dev;
   args.ntiles = p->ntiles;
@@ -598,8 +826,6 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
   args.m = c->m;
   args.a = c->a;
   void* kargs[] = {&args};
-  // at least one workgroup per XCD list
-  const int64_t g = std::max<int64_t>(ta::kXcds, std::min<int64_t>(grid, std::max<int64_t>(1, p->ntiles)));
   TA_ON_DEVICE(c->device);
   TA_HIP(hipLaunchKernel(ta::batch_kernel(inv, 0, p->dtype == TA_F32), dim3((unsigned)g), dim3(256), kargs, 0,
                          reinterpret_cast<hipStream_t>(stream)));
@@ -635,8 +861,11 @@ int build_tiles(ta_plan* plan, int region_log2) {
       region_xcd[region] = next;
     }
     const int lw = std::get<1>(k), lh = std::get<2>(k);
-    const int nb = plan->dtype == TA_F32 ? ta::BatchGeoF32::nb_for(lw, lh) : ta::BatchGeo::nb_for(lw, lh);
-    const ta_plan::Class& cl = plan->classes[std::get<3>(k)];
+    const bool f32 = plan->dtype == TA_F32;
+    const int nb = plan->general ? ta::GenGeo::nb_for(lw, lh, f32)
+                                 : f32 ? ta::BatchGeoF32::nb_for(lw, lh) : ta::BatchGeo::nb_for(lw, lh);
+    const uint32_t ci = std::get<3>(k);
+    const ta_plan::Class& cl = plan->classes[ci];
     const auto& idx = groups[k];
     for (size_t s = 0; s < idx.size(); s += nb) {
       ta::BatchTile t{};
@@ -646,10 +875,19 @@ int build_tiles(ta_plan* plan, int region_log2) {
       t.kind_v = cl.kv;
       t.first = (int64_t)ordered.size();
       t.count = (int32_t)std::min<size_t>(nb, idx.size() - s);
-      t.ph_f = static_cast<const uint32_t*>(cl.phf);
-      t.ph_i = static_cast<const uint32_t*>(cl.phi);
-      t.pv_f = static_cast<const uint32_t*>(cl.pvf);
-      t.pv_i = static_cast<const uint32_t*>(cl.pvi);
+      if (plan->general) {
+        // the class's stage programs (forward / inverse of each axis)
+        const ta::GenProg* pr = plan->progs_dev + 4 * (size_t)ci;
+        t.ph_f = reinterpret_cast<const uint32_t*>(pr + 0);
+        t.ph_i = reinterpret_cast<const uint32_t*>(pr + 1);
+        t.pv_f = reinterpret_cast<const uint32_t*>(pr + 2);
+        t.pv_i = reinterpret_cast<const uint32_t*>(pr + 3);
+      } else {
+        t.ph_f = static_cast<const uint32_t*>(cl.rh.pf);
+        t.ph_i = static_cast<const uint32_t*>(cl.rh.pi);
+        t.pv_f = static_cast<const uint32_t*>(cl.rv.pf);
+        t.pv_i = static_cast<const uint32_t*>(cl.rv.pi);
+      }
       lists[region_xcd[region]].push_back(t);
       for (size_t j = s; j < s + t.count; ++j) ordered.push_back(plan->host[(size_t)idx[j]]);
     }
@@ -690,17 +928,20 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
     plan->dtype = dtype;
     plan->host.assign(blocks, blocks + n);
     plan->cls.resize((size_t)n);
-    std::map<std::tuple<int, int, const void*, const void*, const void*, const void*>, uint32_t> class_of;
+    // a class is one (size, kinds, resolved axes): the general kernel's
+    // programs depend on the size also for axes without parameters
+    std::map<std::tuple<int, int, int, int, Resolved, Resolved>, uint32_t> class_of;
     for (int64_t i = 0; i < n; ++i) {
       const ta_block& b = blocks[i];
       Resolved rh, rv;
       int kh, kv, e;
       if ((e = check_block(c, b, i, dtype, &rh, &rv, &kh, &kv))) return e;
-      const auto key = std::make_tuple(kh, kv, rh.pf, rh.pi, rv.pf, rv.pi);
+      const auto key = std::make_tuple((int)b.log2w, (int)b.log2h, kh, kv, rh, rv);
       auto it = class_of.find(key);
       if (it == class_of.end()) {
         it = class_of.emplace(key, (uint32_t)plan->classes.size()).first;
-        plan->classes.push_back(ta_plan::Class{kh, kv, rh.pf, rh.pi, rv.pf, rv.pi});
+        plan->classes.push_back(ta_plan::Class{b.log2w, b.log2h, kh, kv, rh, rv});
+        if (kh < 0 || kv < 0) plan->general = true;
       }
       plan->cls[(size_t)i] = it->second;
       const int w = 1 << b.log2w, h = 1 << b.log2h;
@@ -709,6 +950,19 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
     }
     plan->nblocks = n;
     int e;
+    if (plan->general && !plan->classes.empty()) {
+      // stage programs of every class
+      std::vector<ta::GenProg> progs(4 * plan->classes.size());
+      for (size_t k = 0; k < plan->classes.size(); ++k)
+        for (int inv = 0; inv < 2; ++inv) {
+          const ta_plan::Class& cl = plan->classes[k];
+          progs[4 * k + inv] = gen_prog(c, cl.rh, cl.lw, dtype, inv);
+          progs[4 * k + 2 + inv] = gen_prog(c, cl.rv, cl.lh, dtype, inv);
+        }
+      TA_ON_DEVICE(c->device);
+      TA_HIP(hipMalloc(&plan->progs_dev, progs.size() * sizeof(ta::GenProg)));
+      TA_HIP(hipMemcpy(plan->progs_dev, progs.data(), progs.size() * sizeof(ta::GenProg), hipMemcpyHostToDevice));
+    }
     if ((e = build_tiles(plan.get(), plan->region_log2))) return e;
     *out = plan.release();
     return TA_OK;
@@ -717,11 +971,7 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
 
 int ta_plan_destroy(ta_plan* p) {
   if (!p) return fail(TA_EINVAL, "null plan");
-  DeviceGuard device_guard_;
-  (void)device_guard_.enter(p->device);
-  if (p->blocks_dev) (void)hipFree(p->blocks_dev);
-  if (p->tiles_dev) (void)hipFree(p->tiles_dev);
-  delete p;
+  delete p;   // frees the plan's device arrays
   return TA_OK;
 }
 
@@ -864,12 +1114,31 @@ int run_blocks(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void
   if (in == out) return fail(TA_EINVAL, "input and output alias");
   if ((uintptr_t)blocks & 7) return fail(TA_EINVAL, "descriptors must be 8-byte aligned");
   if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
-  const void* fn = ta::batch_kernel(inv, 1, dtype == TA_F32);
   // one workgroup per quarter of a sort window (the dispatcher balances
   // quarters of uneven cost), and at least one per XCD range
   const int64_t sortwin = (int64_t)ta::kDescWindow * ta::kSortQuarters;
   const int64_t units = (n + sortwin - 1) / sortwin * ta::kSortQuarters;
   const int64_t g = std::max<int64_t>(ta::kXcds, std::min<int64_t>(units, 0x7fffffff));
+  if (c->ngeneral > 0) {
+    // some registered axis has a kind outside the fast kernel's: the general
+    // kernel runs the list (every kind, through the axes' stage programs)
+    ta::GenArgs ga{};
+    ga.blocks = blocks;
+    ga.in = in;
+    ga.out = out;
+    ga.inv = inv;
+    ga.bd = c->bd;
+    ga.m = c->m;
+    ga.a = c->a;
+    ga.nblocks = n;
+    ga.progs = c->gprogs_dev[dtype == TA_F32];
+    void* kargs[] = {&ga};
+    TA_ON_DEVICE(c->device);
+    TA_HIP(hipLaunchKernel(ta::gen_kernel(1, dtype == TA_F32), dim3((unsigned)g), dim3(256), kargs, 0,
+                           reinterpret_cast<hipStream_t>(stream)));
+    return TA_OK;
+  }
+  const void* fn = ta::batch_kernel(inv, 1, dtype == TA_F32);
   ta::BatchArgs args{};
   args.tiles = nullptr;
   args.ntiles = 0;

@@ -226,6 +226,70 @@ constexpr int64_t kNoAllocGroups = 4096;
 // 0, or -1 for a device index out of range, -2 for a HIP failure.
 int givens_scratch(int device, float** ptr);
 
+// ---- General block transforms (gen_kernels.hip) ---------------------------
+// Every axis kind runs as a program of at most two 1-D stages (eq. 1: the
+// adjustment A before the base or C after it, never both; the DCT-8 flip is
+// folded into the core kind and the parameter tables by the host):
+//   forward  none [core], band [A, core], sub-block [core, C]
+//   inverse  the transposed stages in reverse order.
+// Each stage ends with clip16(RS(sum, shift)) in fixed point, the core stage
+// shifting by the pass's core shift and the adjustment by a.
+enum GenOp : int32_t {
+  GS_C2 = 0,     // DCT-2 butterfly
+  GS_S2 = 1,     // DST-2 = R DCT-2 S
+  GS_C3 = 2,     // DCT-3 butterfly
+  GS_S3 = 3,     // DST-3 = S DCT-3 R
+  GS_DENSE = 4,  // N x N matrix from p (direct DST-7 / DCT-8 and their transposes,
+                 // sub-blocks of a side without a compiled stage, as blkdiag(C, 2^a I))
+  GS_BAND = 5,   // K-tap band from p, K = arg, transposed window when tr
+  GS_POST = 6    // B x B sub-block from p on the first B entries, B = arg in {4, 8, 16}
+};
+struct GenStage {
+  int32_t op, arg, tr;
+  int32_t adj;        // 1: shift by the adjustment precision a; 0: by the core shift
+  const void* p;      // int16 pairs (fixed point) or floats (fp32), by the launch dtype
+};
+struct GenProg {
+  int32_t nst, pad;   // stages in use (1 or 2)
+  GenStage st[2];
+};
+constexpr int kGenLdsI16 = 16896;   // halfwords of a general int16 tile (64 x 64: 4 blocks of 64 rows of 66; 33 KiB)
+constexpr int kGenLdsF32 = 8704;    // floats of a general fp32 tile (34 KiB)
+// Tile geometry of the general kernels: NB blocks of W x H side by side,
+// block b at b * BS elements, row r of a block at r * RP (int16: RP = W + 2
+// halfwords, an odd number of dwords; fp32: RP = W + 1 floats).
+struct GenGeo {
+  static constexpr int rp(int lw, bool f32) { return (1 << lw) + (f32 ? 1 : 2); }
+  static constexpr int bs(int lw, int lh, bool f32) { return (1 << lh) * rp(lw, f32); }
+  static constexpr int nb_for(int lw, int lh, bool f32) {
+    const int nb = 256 >> (lw > lh ? lw : lh);
+    const int cap = (f32 ? kGenLdsF32 : kGenLdsI16) / bs(lw, lh, f32);
+    return nb < cap ? nb : cap;
+  }
+};
+struct GenArgs {
+  // planned tiles (ph_f / ph_i / pv_f / pv_i hold GenProg pointers of the
+  // forward and inverse programs) in per-XCD lists, or null for a packed batch
+  const BatchTile* tiles;
+  int64_t xstart[kXcds + 1];
+  const ta_block* blocks;   // descriptors (planned order, or the caller's list)
+  const void* in;
+  void* out;
+  int inv, bd, m, a;
+  // packed batch (tiles == null, blocks == null): nblocks blocks of
+  // 2^lw x 2^lh with the programs ph, pv of the launch direction;
+  // unplanned list (tiles == null, blocks != null): nblocks descriptors
+  int lw, lh;
+  int64_t nblocks;
+  const GenProg* ph;
+  const GenProg* pv;
+  // unplanned: programs per (axis id, log2 size, direction) for this dtype
+  // (kAxisIds x kAxisSizes x 2; nst = 0 where the axis has none)
+  const GenProg* progs;
+};
+// 0 = planned or packed, 1 = unplanned descriptors; fp32 with f32 = 1
+const void* gen_kernel(int desc, int f32);
+
 // Tables of compiled kernels (defined in the kernel translation units).
 const KernelEntry* fx_kernels(int* count);
 const KernelEntry* f32_kernels(int* count);

@@ -156,11 +156,19 @@ def test_errors(reg):
     with pytest.raises(ta.TadjError) as e:
         reg.ctx.fwd(x, ah, av, out=x)
     assert e.value.code == ta.TA_EINVAL
-    # a combination without a compiled kernel
+    # a combination without a specialised kernel runs on the general kernel
     s7 = reg.axes["direct_dst7_32"][0]
-    with pytest.raises(ta.TadjError) as e:
-        reg.ctx.fwd(x, ah, s7)
-    assert e.value.code == ta.TA_EUNSUPPORTED
+    xs = synth.ar1_blocks(4, 32, 32, 0.95, 16.0, seed=12)
+    oh, ov = reg.oracle_axes("cfg2_dst7_k4")[0], reg.oracle_axes("direct_dst7_32")[1]
+    assert (reg.ctx.fwd(_gpu(xs), ah, s7).cpu().numpy() == F.fwd2d(xs, oh, ov)).all()
+    # ... but not when the matrix-core kernels are required
+    reg.ctx.set_impl(1)
+    try:
+        with pytest.raises(ta.TadjError) as e:
+            reg.ctx.fwd(x, ah, s7)
+        assert e.value.code == ta.TA_EUNSUPPORTED
+    finally:
+        reg.ctx.set_impl(0)
 
 
 @pytest.mark.parametrize("name,wl", [("cfg2_dst7_k4", "cfg2_32x32"), ("cfg3_post16_64", "cfg3_64x64")])
