@@ -356,8 +356,12 @@ def _batched(ctx, ids, res):
     import torch
     import synth
     import paper_2505_23618_amd as ta
-    # batched uneven frames: 8 x 3840x2160, 4 buffer sets rotated (> infinity cache)
+    # batched uneven frames: 8 x 3840x2160, 4 buffer sets rotated (> infinity cache),
+    # in a context of their own that registers the workload's three axis
+    # types only (as a codec would)
     from paper_2505_23618_amd.frames import descriptors as batch_descriptors, register_axes
+    ctx = ta.Context(0)
+    ids = ta.load_params(ctx)
     register_axes(ctx, ids)
     frames, rows = synth.frames_workload()
     desc = batch_descriptors(rows, frames.shape[1], frames.shape[2])

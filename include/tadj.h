@@ -245,10 +245,11 @@ int ta_plan_set_tuning(ta_plan* plan, int grid, int region_log2);
  * on the host once and runs fastest.  The
  * descriptor rules, transforms and dtypes are those of the plans (axes
  * resolve through the context at launch time, so a parameter set registered
- * again is seen by the next call).  While every axis registered with the
- * context resolves to a fast kind at each size it resolves at, the fast
- * kernel runs the list; once any registered axis has another kind, the
- * general kernel runs every list of the context.  A descriptor that breaks a
+ * again is seen by the next call).  The fast batched kernel runs the
+ * descriptors whose axes are DCT-2 or the DST-3 + 4-tap band (plain or
+ * flipped); once any axis registered with the context has another kind, a
+ * second launch on the same stream runs the other descriptors on the
+ * general kernel.  A descriptor that breaks a
  * rule the kernel can check (size, offset sign and alignment, stride, axis
  * id, an axis that does not resolve at the block's size) is skipped and its
  * output untouched.

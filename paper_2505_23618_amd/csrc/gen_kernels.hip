@@ -361,7 +361,8 @@ __global__ __launch_bounds__(256) void gen_plan(GenArgs a) {
 // position) and run their own quarter of it as tiles of equal size and axis
 // ids.  A descriptor that breaks a rule the kernel can check (size, offset
 // sign and alignment, stride, axis id, no program for the axis at its size)
-// sorts last and is skipped.
+// sorts last and is skipped, and so is one that the fast block-list kernel
+// runs in the same call (both axes of a fast kind, when `fast` is set).
 constexpr int kSortWin = kDescWindow * kSortQuarters;
 
 TA_DEV const GenProg* axis_prog(const GenArgs& a, int axis, int lsize, int inv) {
@@ -375,6 +376,8 @@ TA_DEV int gen_key(const GenArgs& a, const ta_block& d) {
       d.axis_v >= kAxisIds || ((d.in_off | d.out_off | (int64_t)d.in_stride | (int64_t)d.out_stride) & (ch - 1)))
     return -1;
   if (axis_prog(a, d.axis_h, d.log2w, a.inv)->nst <= 0 || axis_prog(a, d.axis_v, d.log2h, a.inv)->nst <= 0) return -1;
+  if (a.fast && a.fast[d.axis_h * kAxisSizes + d.log2w].kind >= 0 && a.fast[d.axis_v * kAxisSizes + d.log2h].kind >= 0)
+    return -1;   // the fast block-list kernel runs this one
   return d.log2w | (d.log2h << 3) | (d.axis_h << 6) | (d.axis_v << 14);
 }
 

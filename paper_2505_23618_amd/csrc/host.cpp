@@ -1119,25 +1119,6 @@ int run_blocks(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void
   const int64_t sortwin = (int64_t)ta::kDescWindow * ta::kSortQuarters;
   const int64_t units = (n + sortwin - 1) / sortwin * ta::kSortQuarters;
   const int64_t g = std::max<int64_t>(ta::kXcds, std::min<int64_t>(units, 0x7fffffff));
-  if (c->ngeneral > 0) {
-    // some registered axis has a kind outside the fast kernel's: the general
-    // kernel runs the list (every kind, through the axes' stage programs)
-    ta::GenArgs ga{};
-    ga.blocks = blocks;
-    ga.in = in;
-    ga.out = out;
-    ga.inv = inv;
-    ga.bd = c->bd;
-    ga.m = c->m;
-    ga.a = c->a;
-    ga.nblocks = n;
-    ga.progs = c->gprogs_dev[dtype == TA_F32];
-    void* kargs[] = {&ga};
-    TA_ON_DEVICE(c->device);
-    TA_HIP(hipLaunchKernel(ta::gen_kernel(1, dtype == TA_F32), dim3((unsigned)g), dim3(256), kargs, 0,
-                           reinterpret_cast<hipStream_t>(stream)));
-    return TA_OK;
-  }
   const void* fn = ta::batch_kernel(inv, 1, dtype == TA_F32);
   ta::BatchArgs args{};
   args.tiles = nullptr;
@@ -1153,6 +1134,25 @@ int run_blocks(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void
   void* kargs[] = {&args};
   TA_ON_DEVICE(c->device);
   TA_HIP(hipLaunchKernel(fn, dim3((unsigned)g), dim3(256), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
+  if (c->ngeneral > 0) {
+    // some registered axis has a kind outside the fast kernel's: a second
+    // launch runs the descriptors with such an axis through the general
+    // kernel (the fast kernel skips them, the general one skips the rest)
+    ta::GenArgs ga{};
+    ga.blocks = blocks;
+    ga.in = in;
+    ga.out = out;
+    ga.inv = inv;
+    ga.bd = c->bd;
+    ga.m = c->m;
+    ga.a = c->a;
+    ga.nblocks = n;
+    ga.progs = c->gprogs_dev[dtype == TA_F32];
+    ga.fast = c->axes_dev;
+    void* gargs[] = {&ga};
+    TA_HIP(hipLaunchKernel(ta::gen_kernel(1, dtype == TA_F32), dim3((unsigned)g), dim3(256), gargs, 0,
+                           reinterpret_cast<hipStream_t>(stream)));
+  }
   return TA_OK;
 }
 

@@ -286,6 +286,9 @@ struct GenArgs {
   // unplanned: programs per (axis id, log2 size, direction) for this dtype
   // (kAxisIds x kAxisSizes x 2; nst = 0 where the axis has none)
   const GenProg* progs;
+  // unplanned, beside the fast block-list kernel: the fast kinds' table; a
+  // descriptor whose two axes both have a fast kind is left to that kernel
+  const AxisDev* fast;
 };
 // 0 = planned or packed, 1 = unplanned descriptors; fp32 with f32 = 1
 const void* gen_kernel(int desc, int f32);
