@@ -94,9 +94,23 @@ typedef struct {
 } ta_block;
 
 /* Create a context on HIP device `device`.  bit_depth (bd) in 6..16 sets the
- * fixed-point shifts; m (integer-matrix precision) must be 8; a (adjustment
- * precision) in 6..14 is the scale 2^a of integer adjustment parameters. */
+ * fixed-point shifts; m (integer-matrix precision) in 6..9 sets the integer
+ * base tables round_half_away(2^m sqrt(N) T) (m = 6 is the scaling of the
+ * video-codec integer transforms the paper integrates into; m above 9 could
+ * overflow the int32 sums of 64-point stages), with bd + m >= 14 so that
+ * every core shift is at least 1; a (adjustment precision) in 6..14 is the
+ * scale 2^a of integer adjustment parameters.  The specialised and
+ * matrix-core fixed-point kernels hold the m = 8 tables: at another m every
+ * fixed-point transform runs on the general kernel (the same definition),
+ * ta_set_impl(1) finds no kernel and ta_fwd_multi is unsupported. */
 int ta_create(ta_ctx** out, int device, int bit_depth, int m, int a);
+
+/* The n x n integer base table of kind TA_DCT2 .. TA_DCT8 at precision m
+ * (6..9), row-major (rows = basis vectors), as every kernel of a context
+ * with that m uses it (section 2.1: DCT-3 = DCT-2^T, DST-2 = R DCT-2 S,
+ * DST-3 = S DCT-3 R, each exact in integers).  Host memory; needs no
+ * device.  Errors: TA_EINVAL (kind, null), TA_EUNSUPPORTED (n, m). */
+int ta_int_table(int kind, int n, int m, int16_t* out);
 int ta_destroy(ta_ctx* ctx);
 
 /* Register a K-tap band pre-adjustment A (section 2.2 item 1, Fig. 2a) for

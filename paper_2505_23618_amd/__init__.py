@@ -39,7 +39,8 @@ EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis
            "ta_plan_autotune", "ta_givens_workspace", "ta_givens_fwd", "ta_givens_bwd",
            "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats", "ta_design_search",
            "ta_transform_fwd", "ta_transform_inv", "ta_validate_blocks", "ta_set_axis_cfg", "ta_set_params",
-           "ta_plan_tuning", "ta_plan_set_tuning", "ta_plan_extents", "ta_givens_bwd_noalloc")
+           "ta_plan_tuning", "ta_plan_set_tuning", "ta_plan_extents", "ta_givens_bwd_noalloc",
+           "ta_int_table")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -102,6 +103,7 @@ def lib() -> ctypes.CDLL:
     L.ta_givens_fwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp]
     L.ta_givens_bwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp, vp, vp, vp]
     L.ta_givens_bwd_noalloc.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp, vp, vp]
+    L.ta_int_table.argtypes = [i32, i32, i32, vp]
     for f in (L.ta_transform_fwd, L.ta_transform_inv):
         f.argtypes = [vp, vp, i64, vp, vp, i32, vp]
     L.ta_validate_blocks.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(i64)]
@@ -455,6 +457,13 @@ class Plan:
         _check(lib().ta_plan_autotune(self.ctx._h, self._h, ctypes.c_void_p(x.data_ptr()),
                                       ctypes.c_void_p(out.data_ptr()), _stream_handle(None), reps))
         return self.info()
+
+
+def int_table(kind: int, n: int, m: int = 8) -> np.ndarray:
+    """The library's integer base table (ta_int_table; no GPU needed)."""
+    out = np.zeros((n, n), dtype=np.int16)
+    _check(lib().ta_int_table(kind, n, m, out.ctypes.data))
+    return out
 
 
 def load_param_file(path: Path = PARAMS_PATH) -> dict:

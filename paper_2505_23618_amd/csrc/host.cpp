@@ -136,9 +136,11 @@ struct ta_ctx {
   ta::AxisDev* axes_dev = nullptr;
   // this device's static scratch (ta_givens_bwd_noalloc), looked up at create
   float* scratch = nullptr;
-  // general kernels: the direct DST-7 / DCT-8 integer (packed pairs) and
-  // fp32 matrices of every size, [dtype][kind: 0 DST-7, 1 DCT-8][transposed][log2 n]
-  const void* direct[2][2][2][ta::kAxisSizes] = {};
+  // general kernels: integer base tables of precision m as dense matrices
+  // (packed pairs), [TA_DCT2..TA_DCT8][transposed][log2 n], and the fp32
+  // direct DST-7 / DCT-8, [0 DST-7, 1 DCT-8][transposed][log2 n]
+  const void* dense_core[6][2][ta::kAxisSizes] = {};
+  const void* direct_f32[2][2][ta::kAxisSizes] = {};
   // stage programs of every (axis id, log2 size, direction), one device
   // table per dtype (kAxisIds x kAxisSizes x 2; nst = 0 where the axis does
   // not resolve), and which entries have no fast batched kind
@@ -245,11 +247,11 @@ ta::GenProg gen_prog(const ta_ctx* c, const Resolved& r, int l, int dtype, int i
   };
   ta::GenStage core{};
   const int bop = butterfly(inv ? transposed(r.core) : r.core);
-  if (bop >= 0) {
-    core.op = bop;
+  if (bop >= 0 && (dtype == TA_F32 || c->m == 8)) {
+    core.op = bop;                 // the butterflies hold the m = 8 tables
   } else {
     core.op = ta::GS_DENSE;
-    core.p = c->direct[dtype == TA_F32][r.core == TA_DCT8][inv][l];
+    core.p = dtype == TA_F32 ? c->direct_f32[r.core == TA_DCT8][inv][l] : c->dense_core[r.core][inv][l];
   }
   ta::GenProg pr{};
   if (r.adj == TA_ADJ_NONE) {
@@ -279,8 +281,10 @@ ta::GenProg gen_prog(const ta_ctx* c, const Resolved& r, int l, int dtype, int i
   return pr;
 }
 
-// kind of a resolved axis in the batched kernel (see batch_kernels.hip)
-int batch_kind(const Resolved& r) {
+// kind of a resolved axis in the batched kernel (see batch_kernels.hip),
+// whose butterflies hold the m = 8 tables; -1: the general kernel runs it
+int batch_kind(const ta_ctx* c, const Resolved& r) {
+  if (c->m != 8) return -1;
   if (r.core == TA_DCT2 && r.adj == TA_ADJ_NONE) return 0;
   if (r.core == TA_DST3 && r.adj == TA_ADJ_BAND && r.kb == 4) return 1;
   if (r.core == TA_DCT3 && r.adj == TA_ADJ_BAND && r.kb == 4) return 2;
@@ -300,8 +304,8 @@ int refresh_axis(ta_ctx* c, int id) {
     Resolved r, rf;
     const bool ok = l >= 2 && l <= 6 && c->axes[id].set && resolve_axis(c, id, 1 << l, TA_I16, &r) == TA_OK &&
                     resolve_axis(c, id, 1 << l, TA_F32, &rf) == TA_OK;
-    if (ok && batch_kind(r) >= 0) {
-      row[l].kind = batch_kind(r);
+    if (ok && batch_kind(c, r) >= 0) {
+      row[l].kind = batch_kind(c, r);
       row[l].pf = static_cast<const uint32_t*>(r.pf);
       row[l].pi = static_cast<const uint32_t*>(r.pi);
       row[l].ff = static_cast<const float*>(rf.pf);
@@ -312,7 +316,7 @@ int refresh_axis(ta_ctx* c, int id) {
         progs[0][l][inv] = gen_prog(c, r, l, TA_I16, inv);
         progs[1][l][inv] = gen_prog(c, rf, l, TA_F32, inv);
       }
-    const bool gen = ok && batch_kind(r) < 0;
+    const bool gen = ok && batch_kind(c, r) < 0;
     c->ngeneral += (int)gen - (int)c->general[id][l];
     c->general[id][l] = gen;
   }
@@ -337,50 +341,64 @@ int refresh_param_users(ta_ctx* c, int pid) {
   return TA_OK;
 }
 
-// Direct DST-7 (kind 0) or DCT-8 (kind 1) integer entry of size n, row k,
-// column j, transposed when tr: DCT-8[k][j] = (-1)^k DST-7[k][n-1-j] (eq. 3).
-template <class T7>
-int direct_entry(const T7& s7, int n, int kind, int tr, int k, int j) {
-  if (tr) std::swap(k, j);
-  if (kind == 0) return s7[k][j];
-  return (k & 1) ? -s7[k][n - 1 - j] : s7[k][n - 1 - j];
+// Round half away from zero (the sign-symmetric rule of the integer tables).
+int round_half_away(double v) { return v < 0 ? -(int)std::floor(-v + 0.5) : (int)std::floor(v + 0.5); }
+
+// Orthonormal base matrices (rows = basis vectors, section 2.1): DCT-2 with
+// e_0 = 1/sqrt 2, DST-7 and DCT-8 with sqrt(4 / (2N + 1)).
+double base_entry(int kind, int n, int k, int j) {
+  const double pi = 3.14159265358979323846;
+  switch (kind) {
+    case TA_DCT2: return std::sqrt(2.0 / n) * (k == 0 ? std::sqrt(0.5) : 1.0) * std::cos(pi * k * (2 * j + 1) / (2.0 * n));
+    case TA_DST7: return std::sqrt(4.0 / (2 * n + 1)) * std::sin(pi * (2 * k + 1) * (j + 1) / (2.0 * n + 1));
+    default: return std::sqrt(4.0 / (2 * n + 1)) * std::cos(pi * (2 * k + 1) * (2 * j + 1) / (4.0 * n + 2));
+  }
 }
 
-template <int N>
-int upload_direct(ta_ctx* c, const short (&s7)[N][N], const double (&s7f)[N][N], int l) {
-  for (int kind = 0; kind < 2; ++kind)
-    for (int tr = 0; tr < 2; ++tr) {
-      std::vector<uint32_t> fx((size_t)N * N / 2);
-      std::vector<float> f32((size_t)N * N);
-      for (int k = 0; k < N; ++k) {
-        for (int j = 0; j < N / 2; ++j)
-          fx[(size_t)k * (N / 2) + j] = pack2(direct_entry(s7, N, kind, tr, k, 2 * j),
-                                              direct_entry(s7, N, kind, tr, k, 2 * j + 1));
-        for (int j = 0; j < N; ++j) {
-          int kk = k, jj = j;
-          if (tr) std::swap(kk, jj);
-          const double v = kind == 0 ? s7f[kk][jj] : ((kk & 1) ? -s7f[kk][N - 1 - jj] : s7f[kk][N - 1 - jj]);
-          f32[(size_t)k * N + j] = (float)v;
-        }
-      }
-      void* p = nullptr;
-      int e;
-      if ((e = upload(c, fx.data(), fx.size() * 4, &p))) return e;
-      c->direct[0][kind][tr][l] = p;
-      if ((e = upload(c, f32.data(), f32.size() * 4, &p))) return e;
-      c->direct[1][kind][tr][l] = p;
-    }
-  return TA_OK;
+// Integer base table of precision m (row-major n x n): round_half_away(2^m
+// sqrt(n) T) for the DCT-2, DST-7 and DCT-8; DCT-3 = DCT-2^T, DST-2 = R DCT-2 S
+// and DST-3 = S DCT-2^T R (section 2.1), exact in integers.
+int int_table_entry(int kind, int n, int m, int k, int j) {
+  auto c2 = [&](int kk, int jj) { return round_half_away(std::ldexp(std::sqrt((double)n), m) * base_entry(TA_DCT2, n, kk, jj)); };
+  switch (kind) {
+    case TA_DCT2: return c2(k, j);
+    case TA_DCT3: return c2(j, k);
+    case TA_DST2: return ((j & 1) ? -1 : 1) * c2(n - 1 - k, j);
+    case TA_DST3: return ((k & 1) ? -1 : 1) * c2(n - 1 - j, k);
+    default: return round_half_away(std::ldexp(std::sqrt((double)n), m) * base_entry(kind, n, k, j));
+  }
 }
 
-// The general kernels' context tables: direct matrices of every size and the
-// (empty) program tables.
+// The general kernels' context tables: every base kind of every size as a
+// dense matrix in both orientations (the direct DST-7 / DCT-8 always run
+// dense; the butterfly kinds run dense in fixed point when m != 8, whose
+// tables are not compiled into the butterflies), fp32 direct matrices, and
+// the (empty) program tables.
 int upload_general_tables(ta_ctx* c) {
   int e;
-  if ((e = upload_direct<4>(c, ta_s7_4, ta_s7f_4, 2)) || (e = upload_direct<8>(c, ta_s7_8, ta_s7f_8, 3)) ||
-      (e = upload_direct<16>(c, ta_s7_16, ta_s7f_16, 4)) || (e = upload_direct<32>(c, ta_s7_32, ta_s7f_32, 5)) ||
-      (e = upload_direct<64>(c, ta_s7_64, ta_s7f_64, 6)))
-    return e;
+  for (int l = 2; l <= 6; ++l) {
+    const int n = 1 << l;
+    for (int kind = TA_DCT2; kind <= TA_DCT8; ++kind)
+      for (int tr = 0; tr < 2; ++tr) {
+        std::vector<uint32_t> fx((size_t)n * n / 2);
+        for (int k = 0; k < n; ++k)
+          for (int j = 0; j < n / 2; ++j) {
+            const int r = tr ? 2 * j : k, c0 = tr ? k : 2 * j;
+            const int r1 = tr ? 2 * j + 1 : k, c1 = tr ? k : 2 * j + 1;
+            fx[(size_t)k * (n / 2) + j] = pack2(int_table_entry(kind, n, c->m, r, c0), int_table_entry(kind, n, c->m, r1, c1));
+          }
+        void* p = nullptr;
+        if ((e = upload(c, fx.data(), fx.size() * 4, &p))) return e;
+        c->dense_core[kind][tr][l] = p;
+        if (kind >= TA_DST7) {
+          std::vector<float> f32((size_t)n * n);
+          for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j) f32[(size_t)k * n + j] = (float)(tr ? base_entry(kind, n, j, k) : base_entry(kind, n, k, j));
+          if ((e = upload(c, f32.data(), f32.size() * 4, &p))) return e;
+          c->direct_f32[kind == TA_DCT8][tr][l] = p;
+        }
+      }
+  }
   std::vector<ta::GenProg> empty((size_t)ta::kAxisIds * ta::kAxisSizes * 2, ta::GenProg{});
   for (int dt = 0; dt < 2; ++dt) {
     void* p = nullptr;
@@ -485,7 +503,8 @@ int run_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int log2w, int log2h,
   const ta::KernelKey key{inv, dtype, log2w, log2h, rh.core, rh.adj, rh.kb, rv.core, rv.adj, rv.kb};
   const int prefer_mfma = c->impl != 2;
   const bool same = rh.pf == rv.pf && rh.pi == rv.pi && rh.kb == rv.kb;
-  const ta::KernelEntry* k = find_kernel(key, prefer_mfma, c->impl == 1, same);
+  // the specialised fixed-point kernels hold the m = 8 tables
+  const ta::KernelEntry* k = (dtype == TA_I16 && c->m != 8) ? nullptr : find_kernel(key, prefer_mfma, c->impl == 1, same);
   if (!k && c->impl == 1) return fail(TA_EUNSUPPORTED, "no matrix-core kernel for this transform");
   if (!k) return launch_general_packed(c, inv, axis_h, axis_v, log2w, log2h, nblocks, in, out, dtype, stream);
   ta::PackedArgs args;
@@ -520,15 +539,28 @@ int run_packed(ta_ctx* c, int inv, int axis_h, int axis_v, int log2w, int log2h,
 
 extern "C" {
 
-const char* ta_version(void) { return "tadj 0.1 (gfx950)"; }
+const char* ta_version(void) { return "tadj 0.2 (gfx950)"; }
+
+int ta_int_table(int kind, int n, int m, int16_t* out) {
+  if (!out) return fail(TA_EINVAL, "null output");
+  if (kind < TA_DCT2 || kind > TA_DCT8) return fail(TA_EINVAL, "kind %d", kind);
+  if (log2_exact(n) < 2 || n > 64) return fail(TA_EUNSUPPORTED, "size %d", n);
+  if (m < 6 || m > 9) return fail(TA_EUNSUPPORTED, "m=%d outside 6..9", m);
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j) out[k * n + j] = (int16_t)int_table_entry(kind, n, m, k, j);
+  return TA_OK;
+}
 
 const char* ta_last_error(void) { return g_err.c_str(); }
 
 int ta_create(ta_ctx** out, int device, int bit_depth, int m, int a) {
   if (!out) return fail(TA_EINVAL, "null output pointer");
   *out = nullptr;
-  if (m != 8) return fail(TA_EUNSUPPORTED, "integer-matrix precision m=%d: only 8 is built", m);
+  if (m < 6 || m > 9) return fail(TA_EUNSUPPORTED, "integer-matrix precision m=%d outside 6..9", m);
   if (bit_depth < 6 || bit_depth > 16) return fail(TA_EUNSUPPORTED, "bit depth %d outside 6..16", bit_depth);
+  if (bit_depth + m < 14)
+    return fail(TA_EUNSUPPORTED, "bit depth %d with m=%d: the 4-point forward row shift log2 4 + bd + m - 15 would be below 1",
+                bit_depth, m);
   if (a < 6 || a > 14) return fail(TA_EUNSUPPORTED, "adjustment precision %d outside 6..14", a);
   int ndev = 0;
   TA_HIP(hipGetDeviceCount(&ndev));
@@ -790,8 +822,8 @@ int check_block(ta_ctx* c, const ta_block& b, int64_t i, int dtype, Resolved* rh
     return fail(e, "block %lld: %s", (long long)i, m.c_str());
   }
   // -1: no fast batched kind, the block runs on the general kernel
-  *kh = batch_kind(*rh);
-  *kv = batch_kind(*rv);
+  *kh = batch_kind(c, *rh);
+  *kv = batch_kind(c, *rv);
   return TA_OK;
 }
 
@@ -1133,7 +1165,9 @@ int run_blocks(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void
   args.nblocks = n;
   void* kargs[] = {&args};
   TA_ON_DEVICE(c->device);
-  TA_HIP(hipLaunchKernel(fn, dim3((unsigned)g), dim3(256), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
+  // (with m != 8 no axis has a fast kind: the general launch runs them all)
+  if (c->m == 8)
+    TA_HIP(hipLaunchKernel(fn, dim3((unsigned)g), dim3(256), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
   if (c->ngeneral > 0) {
     // some registered axis has a kind outside the fast kernel's: a second
     // launch runs the descriptors with such an axis through the general
@@ -1269,6 +1303,7 @@ int ta_fwd_multi(ta_ctx* c, int param_id, int log2n, int64_t nblocks, const void
   const ParamSet& ps = c->params[param_id];
   if (ps.kind != TA_ADJ_POST || !ps.fx_eo) return fail(TA_ENOPARAMS, "parameter set %d is not a sub-block set", param_id);
   if (ps.n != (1 << log2n)) return fail(TA_EINVAL, "parameter set %d is for size %d, not %d", param_id, ps.n, 1 << log2n);
+  if (c->m != 8) return fail(TA_EUNSUPPORTED, "simultaneous evaluation is built for m = 8");
   int threads = 0, per_wg = 0;
   const void* fn = ta::multi_kernel(log2n, ps.kb, &threads, &per_wg);
   if (!fn) return fail(TA_EUNSUPPORTED, "simultaneous evaluation is built for 32x32 with B = 8 and 64x64 with B = 16");

@@ -36,8 +36,11 @@ def test_create_rejects_bad_arguments_without_gpu():
     lib = ta.lib()
     h = ctypes.c_void_p()
     assert lib.ta_create(None, 0, 8, 8, 10) == ta.TA_EINVAL
-    assert lib.ta_create(ctypes.byref(h), 0, 8, 6, 10) == ta.TA_EUNSUPPORTED
-    assert b"precision" in lib.ta_last_error()
+    for m in (5, 10):
+        assert lib.ta_create(ctypes.byref(h), 0, 8, m, 10) == ta.TA_EUNSUPPORTED
+        assert b"precision" in lib.ta_last_error()
+    assert lib.ta_create(ctypes.byref(h), 0, 7, 6, 10) == ta.TA_EUNSUPPORTED   # bd + m < 14
+    assert b"shift" in lib.ta_last_error()
     assert lib.ta_create(ctypes.byref(h), 0, 30, 8, 10) == ta.TA_EUNSUPPORTED
     assert lib.ta_create(ctypes.byref(h), 0, 8, 8, 20) == ta.TA_EUNSUPPORTED
 
