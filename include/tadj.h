@@ -385,6 +385,44 @@ int ta_givens_bwd(ta_ctx* ctx, int base, int n, int taps, const float* theta, in
 int ta_givens_bwd_noalloc(ta_ctx* ctx, int base, int n, int taps, const float* theta, int64_t nvec,
                           const float* x, const float* gy, float* gx, float* gtheta, ta_stream_t stream);
 
+/* ---- Backward of the block-list transform (fp32) ---------------------------
+ * Adjustments parametrised by angles (section 2: orthogonality through
+ * sequential sets of parallel Givens rotations; eq. 2 is minimised over
+ * them).  ta_set_band_angles registers band set `param_id` as
+ * A(theta) = G_{L-1} ... G_0, L = taps / 2 layers, layer l rotating the
+ * adjacent pairs that start at l mod 2, rotation (p, p+1) by t:
+ * v_p = cos t u_p - sin t u_p+1, v_p+1 = sin t u_p + cos t u_p+1; theta
+ * (host, double) holds the angles layer by layer, pairs in order.
+ * ta_set_post_angles registers sub-block set `param_id` (B in {4, 8, 16},
+ * B <= n) as Q = Q0 R(phi), R(phi) the rotations over the pairs (p, q),
+ * p < q in lexicographic order, each applied after the previous ones; q0 is
+ * a B x B row-major orthogonal matrix (host, double) or null for the
+ * identity.  Both store the integer (round half away of 2^a M) and fp32
+ * tables exactly as ta_set_band / ta_set_post do (so the set serves every
+ * transform), and keep the angles for ta_transform_bwd.  Synchronous,
+ * allocate; errors as ta_set_band / ta_set_post. */
+int ta_set_band_angles(ta_ctx* ctx, int param_id, int n, int taps, const double* theta);
+int ta_set_post_angles(ta_ctx* ctx, int param_id, int n, int b, const double* q0, const double* phi);
+
+/* Backward of the fp32 forward ta_transform_fwd over a block list (eq. 1,
+ * section 2.2: Y = H_v X H_h^T per block): given dL/dY in gy_dev (each
+ * block at out_off, out_stride, like the forward's output), writes
+ * dL/dX = H_v^T (dL/dY) H_h into gx_dev (at in_off, in_stride, like the
+ * forward's input) and dL/dangles of set param_id into gtheta_dev (its
+ * angle count, float), summed over every block axis that uses the set,
+ * plain or flipped (DCT-8 from the DST-7 design, eq. 3 / eq. 5); x_dev holds
+ * the forward's input (at in_off, in_stride).  All pointers are device
+ * memory; gx_dev must not alias x_dev or gy_dev; blocks must not overlap in
+ * gx_dev.  The set must have been registered by its angles (else
+ * TA_ENOPARAMS).  Descriptors the transforms skip are skipped (their gx left
+ * untouched).  The angle gradient is reduced in a fixed order (bitwise
+ * repeatable) through a workspace the set owns: calls for one set must not
+ * overlap (one stream, or ordered by the caller).  Asynchronous on the
+ * stream, allocates nothing.  Errors: TA_EINVAL (null, alignment, aliasing,
+ * negative count), TA_ENOPARAMS. */
+int ta_transform_bwd(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, const float* x_dev,
+                     const float* gy_dev, float* gx_dev, float* gtheta_dev, int param_id, ta_stream_t stream);
+
 /* Select the kernels used for packed batches: 0 = automatic (the matrix-core
  * kernels for int16 transforms without a band adjustment, where one is built;
  * otherwise the VALU butterfly kernels, which are faster with a band), 1 =

@@ -40,7 +40,7 @@ EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis
            "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats", "ta_design_search",
            "ta_transform_fwd", "ta_transform_inv", "ta_validate_blocks", "ta_set_axis_cfg", "ta_set_params",
            "ta_plan_tuning", "ta_plan_set_tuning", "ta_plan_extents", "ta_givens_bwd_noalloc",
-           "ta_int_table")
+           "ta_int_table", "ta_set_band_angles", "ta_set_post_angles", "ta_transform_bwd")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -104,6 +104,9 @@ def lib() -> ctypes.CDLL:
     L.ta_givens_bwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp, vp, vp, vp]
     L.ta_givens_bwd_noalloc.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp, vp, vp]
     L.ta_int_table.argtypes = [i32, i32, i32, vp]
+    L.ta_set_band_angles.argtypes = [vp, i32, i32, i32, vp]
+    L.ta_set_post_angles.argtypes = [vp, i32, i32, i32, vp, vp]
+    L.ta_transform_bwd.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, vp]
     for f in (L.ta_transform_fwd, L.ta_transform_inv):
         f.argtypes = [vp, vp, i64, vp, vp, i32, vp]
     L.ta_validate_blocks.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(i64)]
@@ -362,6 +365,30 @@ class Context:
     def transform_fwd(self, blocks_dev, x, out, stream_handle=None):
         """ta_transform_fwd over descriptors already in device memory."""
         return self._run_blocks(lib().ta_transform_fwd, blocks_dev, x, out, stream_handle)
+
+    def set_band_angles(self, pid: int, n: int, taps: int, theta):
+        """ta_set_band_angles: band set `pid` as A(theta) (layers of Givens rotations)."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        _check(lib().ta_set_band_angles(self._h, pid, n, taps, th.ctypes.data))
+
+    def set_post_angles(self, pid: int, n: int, b: int, phi, q0=None):
+        """ta_set_post_angles: sub-block set `pid` as Q0 R(phi)."""
+        ph = np.ascontiguousarray(phi, dtype=np.float64)
+        q = None if q0 is None else np.ascontiguousarray(q0, dtype=np.float64)
+        _check(lib().ta_set_post_angles(self._h, pid, n, b, None if q is None else q.ctypes.data, ph.ctypes.data))
+
+    def transform_bwd(self, blocks_dev, x, gy, gx, gtheta, pid: int, stream_handle=None):
+        """ta_transform_bwd over descriptors in device memory (fp32 buffers)."""
+        import torch
+        n = self._nblocks(blocks_dev)
+        for t in (x, gy, gx, gtheta):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("the backward takes contiguous float32 GPU tensors")
+        sh = _stream_handle(None) if stream_handle is None else ctypes.c_void_p(stream_handle)
+        _check(lib().ta_transform_bwd(self._h, ctypes.c_void_p(blocks_dev.data_ptr()), n, ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(gy.data_ptr()), ctypes.c_void_p(gx.data_ptr()),
+                                      ctypes.c_void_p(gtheta.data_ptr()), pid, sh))
+        return gx, gtheta
 
     def transform_inv(self, blocks_dev, y, out, stream_handle=None):
         """ta_transform_inv over descriptors already in device memory."""

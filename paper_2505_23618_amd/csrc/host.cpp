@@ -102,6 +102,14 @@ struct ParamSet {
   // (fp32) as dense n x n matrices, [flip][transposed]
   void* dense_fx[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   void* dense_f32[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  // sets registered by their angles (ta_set_band_angles / ta_set_post_angles),
+  // for ta_transform_bwd: the angles and Q0 (device, fp64) and the workspace
+  // of per-workgroup partial matrix gradients
+  int nang = 0;
+  double* ang_dev = nullptr;
+  double* q0_dev = nullptr;
+  float* part_dev = nullptr;
+  int part_groups = 0;
 };
 
 struct AxisCfg {
@@ -147,6 +155,9 @@ struct ta_ctx {
   ta::GenProg* gprogs_dev[2] = {nullptr, nullptr};
   bool general[kMaxIds][ta::kAxisSizes] = {};
   int ngeneral = 0;
+  // per axis id: its parameter set, flip and adjustment (param id | flip << 8
+  // | adjustment << 9), or -1 without an adjustment (read by the backward)
+  int32_t* axis_use_dev = nullptr;
   std::vector<void*> allocations;
   std::mutex mu;
 };
@@ -326,6 +337,9 @@ int refresh_axis(ta_ctx* c, int id) {
   for (int dt = 0; dt < 2; ++dt)
     TA_HIP(hipMemcpy(c->gprogs_dev[dt] + (size_t)id * ta::kAxisSizes * 2, progs[dt], sizeof progs[dt],
                      hipMemcpyHostToDevice));
+  const ta_axis& u = c->axes[id].user;
+  const int32_t use = (c->axes[id].set && u.adj != TA_ADJ_NONE) ? (u.param_id | (u.flip << 8) | (u.adj << 9)) : -1;
+  TA_HIP(hipMemcpy(c->axis_use_dev + id, &use, sizeof use, hipMemcpyHostToDevice));
   return TA_OK;
 }
 
@@ -405,6 +419,10 @@ int upload_general_tables(ta_ctx* c) {
     if ((e = upload(c, empty.data(), empty.size() * sizeof(ta::GenProg), &p))) return e;
     c->gprogs_dev[dt] = static_cast<ta::GenProg*>(p);
   }
+  std::vector<int32_t> unused(ta::kAxisIds, -1);
+  void* p = nullptr;
+  if ((e = upload(c, unused.data(), unused.size() * sizeof(int32_t), &p))) return e;
+  c->axis_use_dev = static_cast<int32_t*>(p);
   return TA_OK;
 }
 
@@ -1551,6 +1569,156 @@ int ta_design_search(ta_ctx* c, int n, int nmat, const double* mats, int64_t nca
   void* kargs[] = {&a};
   TA_ON_DEVICE(c->device);
   TA_HIP(hipLaunchKernel(fn, dim3((unsigned)ncand), dim3(threads), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
+  return TA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Angle-parametrised parameter sets and the backward of the block-list
+// transform
+// ---------------------------------------------------------------------------
+namespace {
+
+// Rotation (p, q) by t applied from the left to the rows of a row-major
+// n x n matrix: v_p = c u_p - s u_q, v_q = s u_p + c u_q.
+void rotate_rows(std::vector<double>& m, int n, int p, int q, double t) {
+  const double c = std::cos(t), s = std::sin(t);
+  for (int j = 0; j < n; ++j) {
+    const double a = m[(size_t)p * n + j], b = m[(size_t)q * n + j];
+    m[(size_t)p * n + j] = c * a - s * b;
+    m[(size_t)q * n + j] = s * a + c * b;
+  }
+}
+
+int band_angle_count(int n, int taps) {
+  int c = 0;
+  for (int l = 0; l < taps / 2; ++l) c += (n - 2 - (l & 1)) / 2 + 1;
+  return c;
+}
+
+// After a set was registered from its angles: keep the angles (and Q0) on
+// the device and size the backward's workspace for the resident grid.
+int attach_angles(ta_ctx* c, int id, const std::vector<double>& ang, const std::vector<double>* q0, int ne) {
+  ParamSet& ps = c->params[id];
+  int e, groups = 0;
+  if ((e = resident_groups(ta::bwd_kernel(0), 256, c->device, &groups))) return e;
+  void* p = nullptr;
+  if ((e = upload(c, ang.data(), ang.size() * sizeof(double), &p))) return e;
+  ps.ang_dev = static_cast<double*>(p);
+  if (q0) {
+    if ((e = upload(c, q0->data(), q0->size() * sizeof(double), &p))) return e;
+    ps.q0_dev = static_cast<double*>(p);
+  }
+  std::vector<float> zero((size_t)groups * ne, 0.0f);
+  if ((e = upload(c, zero.data(), zero.size() * sizeof(float), &p))) return e;
+  ps.part_dev = static_cast<float*>(p);
+  ps.part_groups = groups;
+  ps.nang = (int)ang.size();
+  return TA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ta_set_band_angles(ta_ctx* c, int id, int n, int taps, const double* theta) {
+  return guard([&]() -> int {
+    if (!c || !theta) return fail(TA_EINVAL, "null argument");
+    if (id < 0 || id >= kMaxIds) return fail(TA_EINVAL, "parameter id %d outside 0..255", id);
+    if (log2_exact(n) < 2 || n > 64) return fail(TA_EUNSUPPORTED, "band size %d", n);
+    if (taps != 2 && taps != 4 && taps != 6 && taps != 8) return fail(TA_EUNSUPPORTED, "band taps %d", taps);
+    const int na = band_angle_count(n, taps);
+    std::vector<double> ang(theta, theta + na);
+    // A = G_{L-1} ... G_0: layer l applied after the layers before it
+    std::vector<double> a((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) a[(size_t)i * n + i] = 1.0;
+    int r = 0;
+    for (int l = 0; l < taps / 2; ++l)
+      for (int p = (l & 1); p + 1 < n; p += 2) rotate_rows(a, n, p, p + 1, ang[r++]);
+    std::vector<int16_t> ai((size_t)n * n);
+    std::vector<float> af((size_t)n * n);
+    for (size_t k = 0; k < a.size(); ++k) {
+      ai[k] = (int16_t)round_half_away(std::ldexp(a[k], c->a));
+      af[k] = (float)a[k];
+    }
+    int e;
+    if ((e = ta_set_band(c, id, n, taps, ai.data(), af.data()))) return e;
+    std::lock_guard<std::mutex> lk(c->mu);
+    return attach_angles(c, id, ang, nullptr, n * taps);
+  });
+}
+
+int ta_set_post_angles(ta_ctx* c, int id, int n, int b, const double* q0, const double* phi) {
+  return guard([&]() -> int {
+    if (!c || !phi) return fail(TA_EINVAL, "null argument");
+    if (id < 0 || id >= kMaxIds) return fail(TA_EINVAL, "parameter id %d outside 0..255", id);
+    if (log2_exact(n) < 2 || n > 64) return fail(TA_EUNSUPPORTED, "post size %d", n);
+    if ((b != 4 && b != 8 && b != 16) || b > n)
+      return fail(TA_EUNSUPPORTED, "angle-parametrised sub-blocks take B in {4, 8, 16} (B <= n), got %d", b);
+    const int na = b * (b - 1) / 2;
+    std::vector<double> ang(phi, phi + na);
+    std::vector<double> q0v((size_t)b * b, 0.0);
+    for (int i = 0; i < b; ++i)
+      for (int j = 0; j < b; ++j) q0v[(size_t)i * b + j] = q0 ? q0[i * b + j] : (i == j ? 1.0 : 0.0);
+    // R(phi): the rotations over the pairs (p, q), p < q in lexicographic
+    // order, each applied after the previous ones; Q = Q0 R
+    std::vector<double> rm((size_t)b * b, 0.0);
+    for (int i = 0; i < b; ++i) rm[(size_t)i * b + i] = 1.0;
+    int r = 0;
+    for (int p = 0; p < b; ++p)
+      for (int q = p + 1; q < b; ++q) rotate_rows(rm, b, p, q, ang[r++]);
+    std::vector<int16_t> qi((size_t)b * b);
+    std::vector<float> qf((size_t)b * b);
+    for (int i = 0; i < b; ++i)
+      for (int j = 0; j < b; ++j) {
+        double v = 0.0;
+        for (int k = 0; k < b; ++k) v += q0v[(size_t)i * b + k] * rm[(size_t)k * b + j];
+        qi[(size_t)i * b + j] = (int16_t)round_half_away(std::ldexp(v, c->a));
+        qf[(size_t)i * b + j] = (float)v;
+      }
+    int e;
+    if ((e = ta_set_post(c, id, n, b, qi.data(), qf.data()))) return e;
+    std::lock_guard<std::mutex> lk(c->mu);
+    return attach_angles(c, id, ang, q0 ? &q0v : nullptr, b * b);
+  });
+}
+
+int ta_transform_bwd(ta_ctx* c, const ta_block* blocks_dev, int64_t nblocks, const float* x_dev, const float* gy_dev,
+                     float* gx_dev, float* gtheta_dev, int param_id, ta_stream_t stream) {
+  if (!c) return fail(TA_EINVAL, "null context");
+  if (nblocks < 0) return fail(TA_EINVAL, "negative block count");
+  if (param_id < 0 || param_id >= kMaxIds) return fail(TA_EINVAL, "parameter id %d outside 0..255", param_id);
+  const ParamSet& ps = c->params[param_id];
+  if (!ps.ang_dev || !ps.part_dev)
+    return fail(TA_ENOPARAMS, "parameter set %d was not registered by its angles", param_id);
+  if (!gtheta_dev) return fail(TA_EINVAL, "null gradient buffer");
+  if (nblocks > 0 && (!blocks_dev || !x_dev || !gy_dev || !gx_dev)) return fail(TA_EINVAL, "null buffer");
+  if ((uintptr_t)blocks_dev & 7) return fail(TA_EINVAL, "descriptors must be 8-byte aligned");
+  if (gx_dev && (gx_dev == x_dev || gx_dev == gy_dev)) return fail(TA_EINVAL, "gx must not alias x or gy");
+  const int ne = ps.kind == TA_ADJ_BAND ? ps.n * ps.kb : ps.kb * ps.kb;
+  const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nblocks, ps.part_groups));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TA_ON_DEVICE(c->device);
+  ta::BwdArgs a{};
+  a.blocks = blocks_dev;
+  a.nblocks = nblocks;
+  a.x = x_dev;
+  a.gy = gy_dev;
+  a.gx = gx_dev;
+  a.progs = c->gprogs_dev[1];
+  a.axis_use = c->axis_use_dev;
+  a.pid = param_id;
+  a.kind = ps.kind;
+  a.n = ps.n;
+  a.k_or_b = ps.kb;
+  a.ne = ne;
+  a.part = ps.part_dev;
+  void* kargs[] = {&a};
+  TA_HIP(hipLaunchKernel(ta::bwd_kernel(0), dim3((unsigned)grid), dim3(256), kargs, 0, s));
+  ta::BwdChainArgs ch{ps.part_dev, grid, ne, ps.kind, ps.n, ps.kb, ps.nang, ps.ang_dev, ps.q0_dev, gtheta_dev};
+  void* cargs[] = {&ch};
+  TA_HIP(hipLaunchKernel(ta::bwd_kernel(1), dim3(1), dim3(256), cargs, 0, s));
   return TA_OK;
 }
 

@@ -293,6 +293,32 @@ struct GenArgs {
 // 0 = planned or packed, 1 = unplanned descriptors; fp32 with f32 = 1
 const void* gen_kernel(int desc, int f32);
 
+// ---- Backward of the fp32 block-list transform (bwd_kernels.hip) ----------
+constexpr int kBwdMaxEntries = 512;   // matrix-gradient entries: 64 x 8 band support, 16 x 16 sub-block
+constexpr int kBwdMaxAngles = 128;    // 126 for a 64-point 8-tap band, 120 for a 16 x 16 sub-block
+struct BwdArgs {
+  const ta_block* blocks;
+  int64_t nblocks;
+  const float* x;             // forward inputs (at in_off, in_stride)
+  const float* gy;            // dL/dY (at out_off, out_stride)
+  float* gx;                  // dL/dX (at in_off, in_stride)
+  const GenProg* progs;       // fp32 stage programs [axis id][log2 size][direction]
+  const int32_t* axis_use;    // per axis id: param id | flip << 8 | adjustment << 9, or -1
+  int pid, kind, n, k_or_b;   // the angle set: id, TA_ADJ_BAND / TA_ADJ_POST, size, K or B
+  int ne;                     // matrix-gradient entries: n * K (band support) or B * B
+  float* part;                // [grid][ne] per-workgroup partial sums
+};
+struct BwdChainArgs {
+  const float* part;
+  int64_t groups;             // partial rows to sum
+  int ne, kind, n, k_or_b, nang;
+  const double* angles;       // the set's angles (band theta, sub-block phi)
+  const double* q0;           // sub-block Q0 (B x B), null for the identity
+  float* gtheta;
+};
+// 0 = per-block gradients (persistent over the list), 1 = chain rule (one workgroup)
+const void* bwd_kernel(int which);
+
 // Tables of compiled kernels (defined in the kernel translation units).
 const KernelEntry* fx_kernels(int* count);
 const KernelEntry* f32_kernels(int* count);
