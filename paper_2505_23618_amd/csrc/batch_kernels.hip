@@ -47,6 +47,20 @@ struct BDesc {
 constexpr int kMaxTileBlocks = 64;
 static_assert(kBatchLds * 4 <= 20480, "tile LDS above 20 KiB");
 
+// The tile loads issue all of a thread's chunks at once: at most 4 chunks
+// (8 halfwords, 4 for 4-wide blocks) per thread for int16 tiles and 8 float4
+// per thread for fp32 tiles.
+constexpr bool tile_chunks_fit() {
+  for (int lw = 2; lw <= 6; ++lw)
+    for (int lh = 2; lh <= 6; ++lh) {
+      const int elems = BatchGeo::nb_for(lw, lh) << (lw + lh);
+      if (elems / (lw >= 3 ? 8 : 4) > 4 * 256) return false;
+      if ((BatchGeoF32::nb_for(lw, lh) << (lw + lh)) / 4 > 8 * 256) return false;
+    }
+  return true;
+}
+static_assert(tile_chunks_fit(), "a tile has more chunks than the loads issue");
+
 template <int W>
 TA_DEV void load_strided_row(const int16_t* __restrict__ src, fx::Packed<W>& x) {
   if constexpr (W >= 8) {
@@ -284,25 +298,39 @@ TA_DEV void inv_tile(const BatchArgs& a, const BatchTile& t, const ta_block* blo
     desc[threadIdx.x] = BDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
   }
   __syncthreads();
-  // coalesced load of the tile into the pair-row layout
+  // coalesced load of the tile into the pair-row layout: a tile holds at
+  // most 1024 chunks, so each thread's (at most 4) loads are issued together
+  // before any is written to LDS (a load followed by its own scatter would
+  // wait for each in turn)
   {
     const int p = BatchGeo::pc_pitch(t.lh);
-    for (int ch = threadIdx.x; ch < nch; ch += 256) {
-      const Chunk k(ch, t.lw, t.lh, lch);
-      const BDesc d = desc[k.b];
-      const int16_t* src = a.in + d.in_off + (int64_t)k.r * d.in_stride + k.c0;
-      uint32_t w[4];
-      if (lch == 3) {
-        const uint4 v = *reinterpret_cast<const uint4*>(src);
-        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-      } else {
-        const uint2 v = *reinterpret_cast<const uint2*>(src);
-        w[0] = v.x; w[1] = v.y; w[2] = 0; w[3] = 0;
+    uint4 v[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int ch = threadIdx.x + 256 * g;
+      if (ch < nch) {
+        const Chunk k(ch, t.lw, t.lh, lch);
+        const BDesc d = desc[k.b];
+        const int16_t* src = a.in + d.in_off + (int64_t)k.r * d.in_stride + k.c0;
+        if (lch == 3) {
+          v[g] = *reinterpret_cast<const uint4*>(src);
+        } else {
+          const uint2 h = *reinterpret_cast<const uint2*>(src);
+          v[g] = make_uint4(h.x, h.y, 0, 0);
+        }
       }
-      const int base = ((k.r >> 1) * p + (k.b << t.lw) + k.c0) * 2 + (k.r & 1);
-      for (int j = 0; j < (1 << lch) / 2; ++j) {
-        pch[base + (2 * j) * 2] = (uint16_t)w[j];
-        pch[base + (2 * j + 1) * 2] = (uint16_t)(w[j] >> 16);
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int ch = threadIdx.x + 256 * g;
+      if (ch < nch) {
+        const Chunk k(ch, t.lw, t.lh, lch);
+        const uint32_t w[4] = {v[g].x, v[g].y, v[g].z, v[g].w};
+        const int base = ((k.r >> 1) * p + (k.b << t.lw) + k.c0) * 2 + (k.r & 1);
+        for (int j = 0; j < (1 << lch) / 2; ++j) {
+          pch[base + (2 * j) * 2] = (uint16_t)w[j];
+          pch[base + (2 * j + 1) * 2] = (uint16_t)(w[j] >> 16);
+        }
       }
     }
   }
@@ -498,15 +526,33 @@ TA_DEV void inv_tile_f(const BatchArgs& a, const BatchTile& t, const ta_block* b
   }
   __syncthreads();
   {
+    // at most 2048 float4 chunks per tile: two rounds of (at most) 4 loads
+    // per thread, each round's loads issued together before any is written
+    // to LDS
     const int lq = t.lw - 2;
     const int nch = t.count << (t.lh + lq), h1 = (1 << t.lh) + 1, bs = BatchGeoF32::bs(t.lw, t.lh);
     const float* in = reinterpret_cast<const float*>(a.in);
-    for (int ch = threadIdx.x; ch < nch; ch += 256) {
-      const int b = ch >> (t.lh + lq), r = (ch >> lq) & ((1 << t.lh) - 1), c0 = (ch & ((1 << lq) - 1)) << 2;
-      const BDesc d = desc[b];
-      const float4 v = *reinterpret_cast<const float4*>(in + d.in_off + (int64_t)r * d.in_stride + c0);
-      float* dst = lds + b * bs + c0 * h1 + r;
-      dst[0] = v.x; dst[h1] = v.y; dst[2 * h1] = v.z; dst[3 * h1] = v.w;
+#pragma unroll
+    for (int k0 = 0; k0 < 8; k0 += 4) {
+      float4 v[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int ch = threadIdx.x + 256 * (k0 + g);
+        if (ch < nch) {
+          const int b = ch >> (t.lh + lq), r = (ch >> lq) & ((1 << t.lh) - 1), c0 = (ch & ((1 << lq) - 1)) << 2;
+          const BDesc d = desc[b];
+          v[g] = *reinterpret_cast<const float4*>(in + d.in_off + (int64_t)r * d.in_stride + c0);
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int ch = threadIdx.x + 256 * (k0 + g);
+        if (ch < nch) {
+          const int b = ch >> (t.lh + lq), r = (ch >> lq) & ((1 << t.lh) - 1), c0 = (ch & ((1 << lq) - 1)) << 2;
+          float* dst = lds + b * bs + c0 * h1 + r;
+          dst[0] = v[g].x; dst[h1] = v[g].y; dst[2 * h1] = v[g].z; dst[3 * h1] = v[g].w;
+        }
+      }
     }
   }
   __syncthreads();

@@ -108,17 +108,28 @@ __global__ __launch_bounds__(256) void f32_inv(PackedArgs p) {
   const float* pv_f = static_cast<const float*>(p.pv_f);
   const float* pv_i = static_cast<const float*>(p.pv_i);
 
-  // coalesced float4 loads into the column-major layout
+  // coalesced float4 loads into the column-major layout, in groups of G
+  // chunks per thread whose loads are all issued before any is written to
+  // LDS (a load followed by its own scatter would wait for each in turn)
   const int nch = nbh * T::Q4;
+  constexpr int G = T::CPT < 8 ? T::CPT : 8;
 #pragma unroll
-  for (int k = 0; k < T::CPT; ++k) {
-    const int c = tid + 256 * k;
-    if (c < nch) {
-      const int b = c / T::Q4, q = c % T::Q4;
-      const int r = q / (W / 4), c0 = (q % (W / 4)) * 4;
-      const float4 v = reinterpret_cast<const float4*>(in)[c];
-      float* d = lds + b * T::BS + c0 * (H + 1) + r;
-      d[0] = v.x; d[H + 1] = v.y; d[2 * (H + 1)] = v.z; d[3 * (H + 1)] = v.w;
+  for (int k0 = 0; k0 < T::CPT; k0 += G) {
+    float4 v[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int c = tid + 256 * (k0 + g);
+      if (c < nch) v[g] = reinterpret_cast<const float4*>(in)[c];
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int c = tid + 256 * (k0 + g);
+      if (c < nch) {
+        const int b = c / T::Q4, q = c % T::Q4;
+        const int r = q / (W / 4), c0 = (q % (W / 4)) * 4;
+        float* d = lds + b * T::BS + c0 * (H + 1) + r;
+        d[0] = v[g].x; d[H + 1] = v[g].y; d[2 * (H + 1)] = v[g].z; d[3 * (H + 1)] = v[g].w;
+      }
     }
   }
   __syncthreads();

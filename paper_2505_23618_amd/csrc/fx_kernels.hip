@@ -184,27 +184,36 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
   using PH = fx::Packed<W>;
 
   // coalesced load of the tile into the pair-column layout: chunk
-  // tid + 256 k, k < CPT
+  // tid + 256 k, k < CPT.  All of a thread's loads are issued before any of
+  // them is written to LDS, so they are in flight together (a load followed
+  // by its own scatter would wait for each load in turn).
   const int nch = nbh * T::CPB;
+  uint32_t w[T::CPT][T::CH / 2];
 #pragma unroll
   for (int k = 0; k < T::CPT; ++k) {
     const int c = tid + 256 * k;
-    if (c >= nch) break;
-    const int b = c / T::CPB, q = c % T::CPB;
-    const int r = q / (W / T::CH), c0 = (q % (W / T::CH)) * T::CH;
-    uint32_t w[T::CH / 2];
-    if constexpr (T::CH == 8) {
-      const uint4 v = reinterpret_cast<const uint4*>(in)[c];
-      w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-    } else {
-      const uint2 v = reinterpret_cast<const uint2*>(in)[c];
-      w[0] = v.x; w[1] = v.y;
+    if (c < nch) {
+      if constexpr (T::CH == 8) {
+        const uint4 v = reinterpret_cast<const uint4*>(in)[c];
+        w[k][0] = v.x; w[k][1] = v.y; w[k][2] = v.z; w[k][3] = v.w;
+      } else {
+        const uint2 v = reinterpret_cast<const uint2*>(in)[c];
+        w[k][0] = v.x; w[k][1] = v.y;
+      }
     }
-    const int base = (b * T::PCB + (r >> 1) * T::PP + c0) * 2 + (r & 1);
+  }
 #pragma unroll
-    for (int k = 0; k < T::CH / 2; ++k) {
-      pch[base + (2 * k) * 2] = (uint16_t)w[k];
-      pch[base + (2 * k + 1) * 2] = (uint16_t)(w[k] >> 16);
+  for (int k = 0; k < T::CPT; ++k) {
+    const int c = tid + 256 * k;
+    if (c < nch) {
+      const int b = c / T::CPB, q = c % T::CPB;
+      const int r = q / (W / T::CH), c0 = (q % (W / T::CH)) * T::CH;
+      const int base = (b * T::PCB + (r >> 1) * T::PP + c0) * 2 + (r & 1);
+#pragma unroll
+      for (int j = 0; j < T::CH / 2; ++j) {
+        pch[base + (2 * j) * 2] = (uint16_t)w[k][j];
+        pch[base + (2 * j + 1) * 2] = (uint16_t)(w[k][j] >> 16);
+      }
     }
   }
   __syncthreads();
@@ -281,13 +290,22 @@ __global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
     row_pass(std::integral_constant<int, 0>{});
   }
   __syncthreads();
-  // coalesced store of the tile from RM: chunk tid + 256 k
+  // coalesced store of the tile from RM: the chunks tid + 256 k, with the
+  // lanes of a wave permuted inside their 64 consecutive chunks (the same
+  // 1 KiB of the output per store instruction) so that 8 consecutive lanes
+  // read the same column chunk of 8 consecutive rows: with the row pitch of
+  // RPI / 2 = 4 mod 8 dwords their 16-byte reads then fall in distinct banks
+  // (in row order, 4 chunks of one row and 4 of the next collide once).
+  constexpr int CR = W / T::CH;                       // chunks per row
+  constexpr int RW = CR < 64 ? 64 / CR : 1;           // rows per 64 chunks
+  const int lane = tid & 63;
+  const int tperm = (tid & ~63) | (CR < 64 ? (lane % RW) * CR + lane / RW : lane);
 #pragma unroll
   for (int k = 0; k < T::CPT; ++k) {
-    const int c = tid + 256 * k;
+    const int c = tperm + 256 * k;
     if (c < nch) {
       const int b = c / T::CPB, q = c % T::CPB;
-      const int r = q / (W / T::CH), c0 = (q % (W / T::CH)) * T::CH;
+      const int r = q / CR, c0 = (q % CR) * T::CH;
       const uint16_t* s = rm + b * T::RMBI + r * T::RPI + c0;
       if constexpr (T::CH == 8)
         reinterpret_cast<uint4*>(out)[c] = *reinterpret_cast<const uint4*>(s);

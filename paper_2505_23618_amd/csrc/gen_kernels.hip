@@ -62,23 +62,45 @@ TA_DEV void gen_tile(const GenArgs& a, const ta_block* blocks, int64_t first, in
   const int lch = F32 ? 2 : (lw >= 3 ? 3 : 2);
   const int lq = lw - lch;                             // log2 chunks per row
   const int nch = count << (lh + lq);
-  for (int ch = tid; ch < nch; ch += 256) {
-    const int b = ch >> (lh + lq), r = (ch >> lq) & ((1 << lh) - 1), c0 = (ch & ((1 << lq) - 1)) << lch;
-    const GDesc d = desc[b];
-    if constexpr (F32) {
-      const float4 v = *reinterpret_cast<const float4*>(static_cast<const float*>(a.in) + d.in_off +
-                                                        (int64_t)r * d.in_stride + c0);
-      float* dst = static_cast<float*>(lds_raw) + b * bs + r * rp + c0;
-      dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
-    } else {
-      const int16_t* src = static_cast<const int16_t*>(a.in) + d.in_off + (int64_t)r * d.in_stride + c0;
-      uint32_t* dst = reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(lds_raw) + b * bs + r * rp + c0);
-      if (lch == 3) {
-        const uint4 v = *reinterpret_cast<const uint4*>(src);
-        dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
-      } else {
-        const uint2 v = *reinterpret_cast<const uint2*>(src);
-        dst[0] = v.x; dst[1] = v.y;
+  // groups of 4 chunks per thread: the group's loads are issued together
+  // before any is written to LDS
+  for (int ch0 = tid; ch0 < nch; ch0 += 1024) {
+    uint4 v[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int ch = ch0 + 256 * g;
+      if (ch < nch) {
+        const int b = ch >> (lh + lq), r = (ch >> lq) & ((1 << lh) - 1), c0 = (ch & ((1 << lq) - 1)) << lch;
+        const GDesc d = desc[b];
+        if constexpr (F32) {
+          const float4 f = *reinterpret_cast<const float4*>(static_cast<const float*>(a.in) + d.in_off +
+                                                            (int64_t)r * d.in_stride + c0);
+          v[g] = make_uint4(__float_as_uint(f.x), __float_as_uint(f.y), __float_as_uint(f.z), __float_as_uint(f.w));
+        } else {
+          const int16_t* src = static_cast<const int16_t*>(a.in) + d.in_off + (int64_t)r * d.in_stride + c0;
+          if (lch == 3) {
+            v[g] = *reinterpret_cast<const uint4*>(src);
+          } else {
+            const uint2 h = *reinterpret_cast<const uint2*>(src);
+            v[g] = make_uint4(h.x, h.y, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int ch = ch0 + 256 * g;
+      if (ch < nch) {
+        const int b = ch >> (lh + lq), r = (ch >> lq) & ((1 << lh) - 1), c0 = (ch & ((1 << lq) - 1)) << lch;
+        if constexpr (F32) {
+          float* dst = static_cast<float*>(lds_raw) + b * bs + r * rp + c0;
+          dst[0] = __uint_as_float(v[g].x); dst[1] = __uint_as_float(v[g].y);
+          dst[2] = __uint_as_float(v[g].z); dst[3] = __uint_as_float(v[g].w);
+        } else {
+          uint32_t* dst = reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(lds_raw) + b * bs + r * rp + c0);
+          dst[0] = v[g].x; dst[1] = v[g].y;
+          if (lch == 3) { dst[2] = v[g].z; dst[3] = v[g].w; }
+        }
       }
     }
   }
