@@ -217,6 +217,9 @@ def _table1(ctx, ids, x32, res):
         "band_6tap_32": (x32, ta.DST3, ta.ADJ_BAND, "band_S3_S7_N32_K6"),
         "subblock_8x8_32": (x32, ta.DCT2, ta.ADJ_POST, "post_C2_S7_N32_B8"),
         "subblock_16x16_64": (x64, ta.DCT2, ta.ADJ_POST, "post_C2_S7_N64_B16"),
+        "band_4tap_64": (x64, ta.DST3, ta.ADJ_BAND, "band_S3_S7_N64_K4"),
+        "band_6tap_64": (x64, ta.DST3, ta.ADJ_BAND, "band_S3_S7_N64_K6"),
+        "subblock_8x8_64": (x64, ta.DCT2, ta.ADJ_POST, "post_C2_S7_N64_B8"),
     }
     s7 = ctx.axis(40, ta.DST7)
     out = {}

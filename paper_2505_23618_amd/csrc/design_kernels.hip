@@ -60,7 +60,14 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a
   constexpr int NC = N / CW;                 // threads per slot
   constexpr int T = (N / 2) * NC;
   constexpr int NA = N * (N - 1) / 2;
-  __shared__ double Ms[N * N], Gs[N * N], Bs[N * N], Xs[N * N];
+  // N x N matrices in LDS with a row pitch LP = 4 mod 8 doubles.  The LDS
+  // serves 64-bit accesses 16 lanes at a time; 16 consecutive lanes are at
+  // most two pair slots r, r + 1, whose rows 2r and 2r + 2 are then 4 LP = 16
+  // mod 32 dwords apart: the slots' column runs (layer updates) and their
+  // same-column reads of rows 2r fall in distinct banks.
+  constexpr int LP = N + (12 - N % 8) % 8;
+  static_assert(LP % 8 == 4, "row pitch");
+  __shared__ double Ms[N * LP], Gs[N * LP], Bs[N * LP], Xs[N * LP];
   __shared__ double th[NA], mo[NA], ve[NA], cs_c[NA], cs_s[NA], gr[NA];
   __shared__ double red[T / 64 > 0 ? 2 * (T / 64) : 2];
   __shared__ int bad;
@@ -88,7 +95,7 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a
   const double* bm = a.mats + (int64_t)c[0] * N * N;
   const double* dm = a.mats + (int64_t)c[1] * N * N;
   double* theta = a.theta + (int64_t)cand * NA;
-  for (int k = t; k < N * N; k += T) Bs[k] = bm[k];
+  for (int k = t; k < N * N; k += T) Bs[(k / N) * LP + k % N] = bm[k];
   double d0[CW], d1[CW];
 #pragma unroll
   for (int q = 0; q < CW; ++q) {
@@ -112,8 +119,8 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a
 #pragma unroll
     for (int q = 0; q < CW; ++q) {
       const int j = jg + q * NC;
-      Ms[i0 * N + j] = (i0 == j) ? 1.0 : 0.0;
-      Ms[i1 * N + j] = (i1 == j) ? 1.0 : 0.0;
+      Ms[i0 * LP + j] = (i0 == j) ? 1.0 : 0.0;
+      Ms[i1 * LP + j] = (i1 == j) ? 1.0 : 0.0;
     }
     group_sync<T>();
     // forward: M = G_{N-1} ... G_0 I
@@ -125,9 +132,9 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a
 #pragma unroll
         for (int q = 0; q < CW; ++q) {
           const int j = jg + q * NC;
-          const double up = Ms[p * N + j], uq = Ms[(p + 1) * N + j];
-          Ms[p * N + j] = cc * up - ss * uq;
-          Ms[(p + 1) * N + j] = ss * up + cc * uq;
+          const double up = Ms[p * LP + j], uq = Ms[(p + 1) * LP + j];
+          Ms[p * LP + j] = cc * up - ss * uq;
+          Ms[(p + 1) * LP + j] = ss * up + cc * uq;
         }
       }
       group_sync<T>();
@@ -144,24 +151,24 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a
       if (mode == 0) {   // H = B M
 #pragma unroll 8
         for (int k = 0; k < N; ++k) {
-          const double mk = Ms[k * N + j];
-          h0 += Bs[i0 * N + k] * mk;
-          h1 += Bs[i1 * N + k] * mk;
+          const double mk = Ms[k * LP + j];
+          h0 += Bs[i0 * LP + k] * mk;
+          h1 += Bs[i1 * LP + k] * mk;
         }
         h0 *= js;
         h1 *= js;
       } else {           // H = M B: H[i][j] = sum_k M[i][k] B[k][j], M[i][0] scaled by sigma
 #pragma unroll 8
         for (int k = 0; k < N; ++k) {
-          const double bk = Bs[k * N + j];
+          const double bk = Bs[k * LP + j];
           const double sk = k == 0 ? sigma : 1.0;
-          h0 += sk * Ms[i0 * N + k] * bk;
-          h1 += sk * Ms[i1 * N + k] * bk;
+          h0 += sk * Ms[i0 * LP + k] * bk;
+          h1 += sk * Ms[i1 * LP + k] * bk;
         }
       }
       const double e0 = h0 - d0[q], e1 = h1 - d1[q];
-      m0[q] = js * Ms[i0 * N + j];   // entries of M = G J
-      m1[q] = js * Ms[i1 * N + j];
+      m0[q] = js * Ms[i0 * LP + j];   // entries of M = G J
+      m1[q] = js * Ms[i1 * LP + j];
       if (last) {
         sp += m0[q] * m0[q] / (kSparseEps + fabs(m0[q])) + m1[q] * m1[q] / (kSparseEps + fabs(m1[q]));
         er += w0 * e0 * e0 + w1 * e1 * e1;
@@ -171,8 +178,8 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a
           out[i1 * N + j] = m1[q];
         }
       }
-      Xs[i0 * N + j] = 2.0 * w0 * e0;
-      Xs[i1 * N + j] = 2.0 * w1 * e1;
+      Xs[i0 * LP + j] = 2.0 * w0 * e0;
+      Xs[i1 * LP + j] = 2.0 * w1 * e1;
     }
     if (last) {
       // objective: sparsity of M and weighted error, reduced in a fixed order
@@ -208,23 +215,23 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a
       if (mode == 0) {   // dM = B^T X: dM[i][j] = sum_k B[k][i] X[k][j]
 #pragma unroll 8
         for (int k = 0; k < N; ++k) {
-          const double xk = Xs[k * N + j];
-          g0 += Bs[k * N + i0] * xk;
-          g1 += Bs[k * N + i1] * xk;
+          const double xk = Xs[k * LP + j];
+          g0 += Bs[k * LP + i0] * xk;
+          g1 += Bs[k * LP + i1] * xk;
         }
       } else {           // dM = X B^T: dM[i][j] = sum_k X[i][k] B[j][k]
 #pragma unroll 8
         for (int k = 0; k < N; ++k) {
-          const double bj = Bs[j * N + k];
-          g0 += Xs[i0 * N + k] * bj;
-          g1 += Xs[i1 * N + k] * bj;
+          const double bj = Bs[j * LP + k];
+          g0 += Xs[i0 * LP + k] * bj;
+          g1 += Xs[i1 * LP + k] * bj;
         }
       }
       const double a0 = fabs(m0[q]), a1 = fabs(m1[q]);
       g0 += a.lam * m0[q] * (2.0 * kSparseEps + a0) / ((kSparseEps + a0) * (kSparseEps + a0));
       g1 += a.lam * m1[q] * (2.0 * kSparseEps + a1) / ((kSparseEps + a1) * (kSparseEps + a1));
-      Gs[i0 * N + j] = js * g0;
-      Gs[i1 * N + j] = js * g1;
+      Gs[i0 * LP + j] = js * g0;
+      Gs[i1 * LP + j] = js * g1;
     }
     group_sync<T>();
     // backward through the layers: angle gradient from each layer's outputs,
@@ -239,13 +246,13 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a
 #pragma unroll
         for (int q = 0; q < CW; ++q) {
           const int j = jg + q * NC;
-          const double vp = Ms[p * N + j], vq = Ms[(p + 1) * N + j];
-          const double gp = Gs[p * N + j], gq = Gs[(p + 1) * N + j];
+          const double vp = Ms[p * LP + j], vq = Ms[(p + 1) * LP + j];
+          const double gp = Gs[p * LP + j], gq = Gs[(p + 1) * LP + j];
           contrib += -gp * vq + gq * vp;
-          Ms[p * N + j] = cc * vp + ss * vq;
-          Ms[(p + 1) * N + j] = -ss * vp + cc * vq;
-          Gs[p * N + j] = cc * gp + ss * gq;
-          Gs[(p + 1) * N + j] = -ss * gp + cc * gq;
+          Ms[p * LP + j] = cc * vp + ss * vq;
+          Ms[(p + 1) * LP + j] = -ss * vp + cc * vq;
+          Gs[p * LP + j] = cc * gp + ss * gq;
+          Gs[(p + 1) * LP + j] = -ss * gp + cc * gq;
         }
       }
       const double sum = slot_sum<NC>(contrib);

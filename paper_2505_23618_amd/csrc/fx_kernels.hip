@@ -345,6 +345,9 @@ const KernelEntry kTable[] = {
     TA_FX(5, 5, A_C2P8, A_C2P8),     // 32x32 DCT-2 + 8x8 sub-block
     TA_FX(4, 4, A_C2B4, A_C2B4),     // 16x16 DCT-2 + 4-tap band
     TA_FX(6, 6, A_C2P16, A_C2P16),   // 64x64 DCT-2 + 16x16 sub-block
+    TA_FX(6, 6, A_C2P8, A_C2P8),     // 64x64 DCT-2 + 8x8 sub-block (Table 1, 64 points)
+    TA_FX(6, 6, A_S3B4, A_S3B4),     // 64x64 adjusted DST-7, 4-tap band
+    TA_FX(6, 6, A_S3B6, A_S3B6),     // 64x64 DST-3 + 6-tap band
     TA_FX(6, 6, A_S7, A_S7),         // 64x64 direct DST-7
     TA_FX(2, 2, A_S3B4, A_S3B4),     // 4x4 adjusted DST-7
     TA_FX(3, 3, A_S3, A_C3),         // 8x8 plain DST-3 / DCT-3

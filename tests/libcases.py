@@ -45,6 +45,12 @@ CASES = {
     "cfg3_post16_64": (64, 64, (ta.DCT2, ta.ADJ_POST, True, "post_C2_S7_N64_B16"),
                        (ta.DCT2, ta.ADJ_POST, False, "post_C2_S7_N64_B16")),
     "direct_dst7_64": (64, 64, (ta.DST7, ta.ADJ_NONE, False, None), (ta.DST7, ta.ADJ_NONE, False, None)),
+    "band4_64": (64, 64, (ta.DST3, ta.ADJ_BAND, False, "band_S3_S7_N64_K4"),
+                 (ta.DST3, ta.ADJ_BAND, True, "band_S3_S7_N64_K4")),
+    "band6_64": (64, 64, (ta.DST3, ta.ADJ_BAND, False, "band_S3_S7_N64_K6"),
+                 (ta.DST3, ta.ADJ_BAND, False, "band_S3_S7_N64_K6")),
+    "post8_64": (64, 64, (ta.DCT2, ta.ADJ_POST, True, "post_C2_S7_N64_B8"),
+                 (ta.DCT2, ta.ADJ_POST, False, "post_C2_S7_N64_B8")),
     "dst7_band_4": (4, 4, (ta.DST3, ta.ADJ_BAND, False, "band_S3_S7_N4_K4"),
                     (ta.DST3, ta.ADJ_BAND, False, "band_S3_S7_N4_K4")),
     "dst3_dct3_8": (8, 8, (ta.DST3, ta.ADJ_NONE, False, None), (ta.DCT3, ta.ADJ_NONE, False, None)),
