@@ -61,6 +61,12 @@ constexpr bool tile_chunks_fit() {
 }
 static_assert(tile_chunks_fit(), "a tile has more chunks than the loads issue");
 
+// Workgroup barrier that orders LDS only.  The planned kernels keep global
+// loads into LDS (the LDS DMA path) in flight across the barriers of the
+// tile before; the workgroup-scope fence of __syncthreads would wait for
+// them (they write LDS), this waits for the wave's own LDS accesses alone.
+TA_DEV void tile_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <int W>
 TA_DEV void load_strided_row(const int16_t* __restrict__ src, fx::Packed<W>& x) {
   if constexpr (W >= 8) {
@@ -113,7 +119,7 @@ TA_DEV void fwd_cols(const BatchArgs& a, const BatchTile& t, uint32_t* lds, int 
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
   }
-  __syncthreads();
+  tile_sync();
   if (act) {
     uint16_t* rm = reinterpret_cast<uint16_t*>(lds);
 #pragma unroll
@@ -193,19 +199,6 @@ TA_DEV void fwd_tile(const BatchArgs& a, const BatchTile& t, const ta_block* blo
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_fwd(BatchArgs a) {
-  __shared__ __align__(16) uint32_t lds[kBatchLds];
-  __shared__ BDesc desc[kMaxTileBlocks];
-  // this workgroup's XCD list and its stride within that list
-  const int xcd = blockIdx.x % kXcds;
-  const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
-  const int64_t end = a.xstart[xcd + 1];
-  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd) {
-    const BatchTile t = a.tiles[ti];   // a register copy: a reference would be re-read after every store
-    fwd_tile(a, t, a.blocks, lds, desc);
-  }
-}
-
 // ---------------------------------------------------------------- inverse
 template <int H, class KV, int LH>
 TA_DEV void inv_cols(const BatchArgs& a, const BatchTile& t, uint32_t* lds, int s_col) {
@@ -221,7 +214,7 @@ TA_DEV void inv_cols(const BatchArgs& a, const BatchTile& t, uint32_t* lds, int 
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) o[i] = y.pair(2 * i, 2 * i + 1);
   }
-  __syncthreads();
+  tile_sync();
   if (act) {
     uint16_t* rm = reinterpret_cast<uint16_t*>(lds);
 #pragma unroll
@@ -364,17 +357,326 @@ TA_DEV void inv_tile(const BatchArgs& a, const BatchTile& t, const ta_block* blo
   __syncthreads();
 }
 
+// ---------------------------------------------------------------- planned, pipelined
+// The planned kernels overlap a tile's global loads with the work on the
+// tile before.  Loads go straight to LDS (global_load_lds, the LDS DMA path)
+// and complete on their own: while tile k runs its column phase and stores,
+// the data of tile k+1 streams into the staging buffer and the descriptors
+// of tile k+2 into the descriptor staging slot; the tile records of k+2 are
+// read (plain loads) right after tile k's stores.  One vmcnt(0) wait and
+// barrier at the head of each tile publishes all of it.
+//
+// Staging layout: the tile's rows in order (row = b * H + r), in 16-byte
+// units (4-byte units for 4-wide blocks), so one wave's loads cover whole
+// rows; the units of a row are XOR-permuted by swz(row) so that the wide
+// LDS reads of the forward row phase (thread = row) fall in distinct banks
+// for 8- and 16-unit bank periods alike.
+using lds_void = __attribute__((address_space(3))) void;
+constexpr int kStageDwords = 4096;             // the largest tile: 8192 halfwords
+
+constexpr bool tile_stage_fits() {
+  for (int lw = 2; lw <= 6; ++lw)
+    for (int lh = 2; lh <= 6; ++lh) {
+      const int elems = BatchGeo::nb_for(lw, lh) << (lw + lh);
+      if (elems > 2 * kStageDwords) return false;
+      if (lw == 2 && elems / 2 > 512) return false;      // two rounds of 4-byte units
+      if (lw >= 3 && elems / 8 > 1024) return false;     // four rounds of 16-byte units
+      if ((BatchGeo::nb_for(lw, lh) << lh) > 256) return false;   // one thread per row
+    }
+  return true;
+}
+static_assert(tile_stage_fits(), "a tile does not fit the staging buffer");
+static_assert(kMaxTileBlocks * sizeof(ta_block) <= 256 * 16, "descriptor staging: one 16-byte unit per thread");
+
+TA_DEV int swz(int row, int lcpr) { return ((row >> (4 - lcpr)) ^ (row >> (3 - lcpr))) & ((1 << lcpr) - 1); }
+
+TA_DEV void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
+
+// The thread index, opaque to the compiler: addresses derived from it are
+// computed where they are used instead of being hoisted out of the tile
+// loop and spilled (a spill reload waits on vmcnt, that is, on the loads
+// in flight into LDS).
+TA_DEV int tid_here() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// What the loads of a tile need: its size, block count and first block.
+// Tile records are read through the constant address space (the kernel
+// never writes them): scalar loads, counted apart from the vector loads and
+// stores, so fetching the next record waits on neither.
+struct TileHead {
+  int lw, lh, count;
+  int64_t first;
+};
+
+typedef const __attribute__((address_space(4))) uint32_t* ConstWords;
+
+TA_DEV TileHead tile_head(const BatchTile* p) {
+  const ConstWords w = (ConstWords)p;
+  static_assert(offsetof(BatchTile, lw) == 0 && offsetof(BatchTile, lh) == 4 && offsetof(BatchTile, first) == 16 &&
+                    offsetof(BatchTile, count) == 24, "tile record layout");
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(w[4]), hi = __builtin_amdgcn_readfirstlane(w[5]);
+  return TileHead{__builtin_amdgcn_readfirstlane((int)w[0]), __builtin_amdgcn_readfirstlane((int)w[1]),
+                  __builtin_amdgcn_readfirstlane((int)w[6]), (int64_t)(((uint64_t)hi << 32) | lo)};
+}
+TA_DEV TileHead tile_head(const BatchTile& t) { return TileHead{t.lw, t.lh, t.count, t.first}; }
+TA_DEV BatchTile uniform_tile(const BatchTile* p) {
+  const ConstWords w = (ConstWords)p;
+  BatchTile t;
+  uint32_t* d = reinterpret_cast<uint32_t*>(&t);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(BatchTile) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  return t;
+}
+
+// descriptors of tile t -> dst (2 units of 16 bytes per block)
+TA_DEV void stage_descs(const BatchArgs& a, const TileHead& t, ta_block* dst) {
+  const int s = tid_here(), base = s & ~63;
+  if (s < 2 * t.count)
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint4*>(a.blocks + t.first) + s,
+                                     (lds_void*)(reinterpret_cast<uint4*>(dst) + base), 16, 0, 0);
+}
+
+// data of tile t -> stage, through its descriptors dl (in LDS)
+TA_DEV void stage_data(const BatchArgs& a, const TileHead& t, const ta_block* dl, uint32_t* stage) {
+  const int tx = tid_here(), wb = tx & ~63, lane = tx & 63;
+  const int hm = (1 << t.lh) - 1;
+  if (t.lw >= 3) {
+    const int lcpr = t.lw - 3, nu = t.count << (t.lh + lcpr);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int base = g * 256 + wb, s = base + lane;
+      if (s < nu) {
+        const int row = s >> lcpr;
+        const int c = (s & ((1 << lcpr) - 1)) ^ swz(row, lcpr);
+        const ta_block& d = dl[row >> t.lh];
+        const int16_t* src = a.in + d.in_off + (int64_t)(row & hm) * d.in_stride + c * 8;
+        __builtin_amdgcn_global_load_lds(src, (lds_void*)(stage + base * 4), 16, 0, 0);
+      }
+    }
+  } else {
+    const int nu = t.count << (t.lh + 1);
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int base = g * 256 + wb, s = base + lane;
+      if (s < nu) {
+        const int row = s >> 1;
+        const ta_block& d = dl[row >> t.lh];
+        const int16_t* src = a.in + d.in_off + (int64_t)(row & hm) * d.in_stride + (s & 1) * 2;
+        __builtin_amdgcn_global_load_lds(src, (lds_void*)(stage + base), 4, 0, 0);
+      }
+    }
+  }
+}
+
+TA_DEV void copy_descs(const TileHead& t, const ta_block* src, ta_block* dst) {
+  const int tx = tid_here();
+  if (tx < 2 * t.count) reinterpret_cast<uint4*>(dst)[tx] = reinterpret_cast<const uint4*>(src)[tx];
+}
+
+// forward row phase from the staged rows
+template <int W, class KH>
+TA_DEV void fwd_rows_st(const BatchArgs& a, const BatchTile& t, const uint32_t* stage, uint16_t* pch, int s_row) {
+  const int tid = tid_here();
+  if (tid >= (t.count << t.lh)) return;
+  const int b = tid >> t.lh, r = tid & ((1 << t.lh) - 1);
+  fx::Packed<W> x;
+  if constexpr (W >= 8) {
+    constexpr int LC = W == 8 ? 0 : W == 16 ? 1 : W == 32 ? 2 : 3;
+    const uint4* row = reinterpret_cast<const uint4*>(stage) + (tid << LC);
+    const int f = swz(tid, LC);
+#pragma unroll
+    for (int q = 0; q < W / 8; ++q) {
+      const uint4 v = row[q ^ f];
+      x.p[4 * q] = v.x; x.p[4 * q + 1] = v.y; x.p[4 * q + 2] = v.z; x.p[4 * q + 3] = v.w;
+    }
+  } else {
+    const uint2 v = reinterpret_cast<const uint2*>(stage)[tid];
+    x.p[0] = v.x; x.p[1] = v.y;
+  }
+  const auto y = fx::run_pass<W, KH, false>(x, as_cparam(t.ph_f), as_cparam(t.ph_i), s_row, a.a);
+  const int base = ((r >> 1) * BatchGeo::pc_pitch(t.lh) + b * W) * 2 + (r & 1);
+#pragma unroll
+  for (int j = 0; j < W / 2; ++j) {
+    const uint32_t v = y.pair(2 * j, 2 * j + 1);
+    pch[base + (2 * j) * 2] = (uint16_t)v;
+    pch[base + (2 * j + 1) * 2] = (uint16_t)(v >> 16);
+  }
+}
+
+template <class KH>
+TA_DEV void fwd_rows_st_w(const BatchArgs& a, const BatchTile& t, const uint32_t* stage, uint16_t* pch, int s) {
+  switch (t.lw) {
+    case 2: fwd_rows_st<4, KH>(a, t, stage, pch, s); break;
+    case 3: fwd_rows_st<8, KH>(a, t, stage, pch, s); break;
+    case 4: fwd_rows_st<16, KH>(a, t, stage, pch, s); break;
+    case 5: fwd_rows_st<32, KH>(a, t, stage, pch, s); break;
+    default: fwd_rows_st<64, KH>(a, t, stage, pch, s); break;
+  }
+}
+
+// inverse: the staged rows -> pair-row layout
+TA_DEV void inv_scatter(const BatchTile& t, const uint32_t* stage, uint16_t* pch) {
+  const int p = BatchGeo::pc_pitch(t.lh), hm = (1 << t.lh) - 1, tx = tid_here();
+  if (t.lw >= 3) {
+    const int lcpr = t.lw - 3, nu = t.count << (t.lh + lcpr);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int s = tx + 256 * g;
+      if (s < nu) {
+        const uint4 v = reinterpret_cast<const uint4*>(stage)[s];
+        const int row = s >> lcpr;
+        const int c0 = ((s & ((1 << lcpr) - 1)) ^ swz(row, lcpr)) * 8;
+        const int r = row & hm;
+        const int base = ((r >> 1) * p + ((row >> t.lh) << t.lw) + c0) * 2 + (r & 1);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          pch[base + 4 * j] = (uint16_t)w[j];
+          pch[base + 4 * j + 2] = (uint16_t)(w[j] >> 16);
+        }
+      }
+    }
+  } else {
+    const int nu = t.count << (t.lh + 1);
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int s = tx + 256 * g;
+      if (s < nu) {
+        const uint32_t v = stage[s];
+        const int row = s >> 1, r = row & hm;
+        const int base = ((r >> 1) * p + ((row >> t.lh) << 2) + (s & 1) * 2) * 2 + (r & 1);
+        pch[base] = (uint16_t)v;
+        pch[base + 2] = (uint16_t)(v >> 16);
+      }
+    }
+  }
+}
+
+// coalesced store of the row-major layout through the descriptors dl (LDS);
+// a tile has at most 1024 chunks: four rounds, the LDS reads issued first
+TA_DEV void store_tile(const BatchArgs& a, const BatchTile& t, const uint16_t* rm, const ta_block* dl) {
+  const int lch = t.lw >= 3 ? 3 : 2, tx = tid_here();
+  const int q = BatchGeo::rm_pitch(t.lh);
+  const int nch = t.count << (t.lw + t.lh - lch);
+  uint4 v[4];
+  int64_t off[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int ch = tx + 256 * g;
+    if (ch < nch) {
+      const Chunk k(ch, t.lw, t.lh, lch);
+      const ta_block& d = dl[k.b];
+      off[g] = d.out_off + (int64_t)k.r * d.out_stride + k.c0;
+      const uint16_t* src = rm + k.r * q + (k.b << t.lw) + k.c0;
+      if (lch == 3) {
+        v[g] = *reinterpret_cast<const uint4*>(src);
+      } else {
+        const uint2 h = *reinterpret_cast<const uint2*>(src);
+        v[g] = make_uint4(h.x, h.y, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int ch = tx + 256 * g;
+    if (ch < nch) {
+      if (lch == 3)
+        *reinterpret_cast<uint4*>(a.out + off[g]) = v[g];
+      else
+        *reinterpret_cast<uint2*>(a.out + off[g]) = make_uint2(v[g].x, v[g].y);
+    }
+  }
+}
+
+// The walk of one workgroup over its XCD's tile list (grid stride P):
+// tile k is processed while the data of k+1 and the descriptors of k+2 load.
+template <bool INV>
+TA_DEV void planned_tiles(const BatchArgs& a, uint32_t* lds, uint32_t* stage, ta_block (*ring)[kMaxTileBlocks],
+                          ta_block* dnext) {
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t P = (gridDim.x + kXcds - 1 - xcd) / kXcds;
+  const int64_t end = a.xstart[xcd + 1];
+  int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds;
+  if (ti >= end) return;
+  uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
+  BatchTile t = uniform_tile(a.tiles + ti);
+  bool has_n = ti + P < end, has_nn = ti + 2 * P < end;
+  TileHead n = has_n ? tile_head(a.tiles + ti + P) : tile_head(t);
+  stage_descs(a, tile_head(t), ring[0]);
+  dma_wait();
+  tile_sync();
+  stage_data(a, tile_head(t), ring[0], stage);
+  if (has_n) stage_descs(a, n, dnext);
+  TileHead nn = has_nn ? tile_head(a.tiles + ti + 2 * P) : n;
+  int cur = 0;
+  for (;;) {
+    dma_wait();                          // this tile's data, the next descriptors, the last stores
+    tile_sync();
+    if (has_n) copy_descs(n, dnext, ring[cur ^ 1]);
+    if (INV) {
+      inv_scatter(t, stage, pch);
+    } else {
+      const int s_row = t.lw + a.bd + a.m - 15;
+      switch (t.kind_h) {
+        case 0: fwd_rows_st_w<KC2>(a, t, stage, pch, s_row); break;
+        case 1: fwd_rows_st_w<KS3>(a, t, stage, pch, s_row); break;
+        default: fwd_rows_st_w<KC3>(a, t, stage, pch, s_row); break;
+      }
+    }
+    tile_sync();                         // stage and dnext are free
+    if (has_n) stage_data(a, n, ring[cur ^ 1], stage);
+    if (has_nn) stage_descs(a, nn, dnext);
+    if (INV) {
+      const int s_col = a.m + 1, s_row = a.m + 14 - a.bd;
+      switch (t.kind_v) {
+        case 0: inv_cols_h<KC2>(a, t, lds, s_col); break;
+        case 1: inv_cols_h<KS3>(a, t, lds, s_col); break;
+        default: inv_cols_h<KC3>(a, t, lds, s_col); break;
+      }
+      tile_sync();
+      switch (t.kind_h) {
+        case 0: inv_rows_w<KC2>(a, t, pch, s_row); break;
+        case 1: inv_rows_w<KS3>(a, t, pch, s_row); break;
+        default: inv_rows_w<KC3>(a, t, pch, s_row); break;
+      }
+    } else {
+      const int s_col = t.lh + a.m;
+      switch (t.kind_v) {
+        case 0: fwd_cols_h<KC2>(a, t, lds, s_col); break;
+        case 1: fwd_cols_h<KS3>(a, t, lds, s_col); break;
+        default: fwd_cols_h<KC3>(a, t, lds, s_col); break;
+      }
+    }
+    tile_sync();
+    store_tile(a, t, pch, ring[cur]);
+    if (!has_n) break;
+    ti += P;
+    t = uniform_tile(a.tiles + ti);
+    n = nn;
+    has_n = has_nn;
+    has_nn = ti + 2 * P < end;
+    if (has_nn) nn = tile_head(a.tiles + ti + 2 * P);
+    cur ^= 1;
+  }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_fwd(BatchArgs a) {
+  __shared__ __align__(16) uint32_t lds[kBatchLds];
+  __shared__ __align__(16) uint32_t stage[kStageDwords];
+  __shared__ __align__(16) ta_block ring[2][kMaxTileBlocks];
+  __shared__ __align__(16) ta_block dnext[kMaxTileBlocks];
+  planned_tiles<false>(a, lds, stage, ring, dnext);
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_inv(BatchArgs a) {
   __shared__ __align__(16) uint32_t lds[kBatchLds];
-  __shared__ BDesc desc[kMaxTileBlocks];
-  // this workgroup's XCD list and its stride within that list
-  const int xcd = blockIdx.x % kXcds;
-  const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
-  const int64_t end = a.xstart[xcd + 1];
-  for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd) {
-    const BatchTile t = a.tiles[ti];   // a register copy: a reference would be re-read after every store
-    inv_tile(a, t, a.blocks, lds, desc);
-  }
+  __shared__ __align__(16) uint32_t stage[kStageDwords];
+  __shared__ __align__(16) ta_block ring[2][kMaxTileBlocks];
+  __shared__ __align__(16) ta_block dnext[kMaxTileBlocks];
+  planned_tiles<true>(a, lds, stage, ring, dnext);
 }
 
 // ---------------------------------------------------------------- fp32 tiles

@@ -884,7 +884,8 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
 
 // Group the plan's blocks by (frame region of 2^region_log2 input elements,
 // size, class) and cut the groups into tiles; regions go round-robin to the
-// XCD lists, and within a region larger blocks come first.  Replaces the
+// XCD lists, and within a region the tiles are listed by the position of
+// their first block.  Replaces the
 // plan's device descriptor and tile arrays (synchronous, allocates).
 int build_tiles(ta_plan* plan, int region_log2) {
   typedef std::tuple<int64_t, int, int, uint32_t> Key;   // region, log2w, log2h, class
@@ -904,11 +905,26 @@ int build_tiles(ta_plan* plan, int region_log2) {
   std::vector<ta::BatchTile> lists[ta::kXcds];
   ordered.reserve((size_t)n);
   std::map<int64_t, int> region_xcd;
+  // the tiles of one region, listed by the frame position of their first
+  // block: tiles of different sizes and classes that share cache lines run
+  // at about the same time on the region's XCD
+  std::vector<std::pair<int64_t, ta::BatchTile>> pending;
+  int pending_xcd = 0;
+  auto flush_region = [&]() {
+    std::stable_sort(pending.begin(), pending.end(),
+                     [](const std::pair<int64_t, ta::BatchTile>& x, const std::pair<int64_t, ta::BatchTile>& y) {
+                       return x.first < y.first;
+                     });
+    for (const auto& pt : pending) lists[pending_xcd].push_back(pt.second);
+    pending.clear();
+  };
   for (const Key& k : keys) {
     const int64_t region = std::get<0>(k);
     if (!region_xcd.count(region)) {
+      flush_region();
       const int next = (int)region_xcd.size() % ta::kXcds;
       region_xcd[region] = next;
+      pending_xcd = next;
     }
     const int lw = std::get<1>(k), lh = std::get<2>(k);
     const bool f32 = plan->dtype == TA_F32;
@@ -938,10 +954,11 @@ int build_tiles(ta_plan* plan, int region_log2) {
         t.pv_f = static_cast<const uint32_t*>(cl.rv.pf);
         t.pv_i = static_cast<const uint32_t*>(cl.rv.pi);
       }
-      lists[region_xcd[region]].push_back(t);
+      pending.push_back({plan->host[(size_t)idx[s]].in_off, t});
       for (size_t j = s; j < s + t.count; ++j) ordered.push_back(plan->host[(size_t)idx[j]]);
     }
   }
+  flush_region();
   std::vector<ta::BatchTile> tiles;
   for (int x = 0; x < ta::kXcds; ++x) {
     plan->xstart[x] = (int64_t)tiles.size();
