@@ -23,6 +23,8 @@
 // The same tile walk runs on fp32 data with the orthonormal fp32 stages
 // (batch_f32, BatchGeoF32 layout), and both data types also run unplanned,
 // straight from a device array of descriptors (batch_desc).
+#include <type_traits>
+
 #include "fp.hpp"
 #include "fx.hpp"
 #include "kernels.hpp"
@@ -358,168 +360,299 @@ TA_DEV void inv_tile(const BatchArgs& a, const BatchTile& t, const ta_block* blo
 }
 
 // ---------------------------------------------------------------- planned, pipelined
-// The planned kernels overlap a tile's global loads with the work on the
-// tile before.  Loads go straight to LDS (global_load_lds, the LDS DMA path)
-// and complete on their own: while tile k runs its column phase and stores,
-// the data of tile k+1 streams into the staging buffer and the descriptors
-// of tile k+2 into the descriptor staging slot; the tile records of k+2 are
-// read (plain loads) right after tile k's stores.  One vmcnt(0) wait and
-// barrier at the head of each tile publishes all of it.
+// The planned int16 kernels run tiles of up to 8192 coefficients
+// (BatchGeo::nb_planned blocks) and overlap each tile's global loads with
+// the work on the tile before.  Loads go straight to LDS (global_load_lds,
+// the LDS DMA path) and complete on their own: while tile k runs its column
+// phase and stores, the data of tile k+1 streams into the staging buffer and
+// the block deltas of tile k+2 into the delta staging slot.  One vmcnt(0)
+// wait and barrier at the head of each tile publishes all of it.
 //
 // Staging layout: the tile's rows in order (row = b * H + r), in 16-byte
 // units (4-byte units for 4-wide blocks), so one wave's loads cover whole
 // rows; the units of a row are XOR-permuted by swz(row) so that the wide
 // LDS reads of the forward row phase (thread = row) fall in distinct banks
 // for 8- and 16-unit bank periods alike.
+//
+// Compute layout: as the smaller tiles (pair rows, then rows, block b at
+// column b * W) with the pitches BatchGeo::pl_pc(H) dwords and pl_rm(H)
+// halfwords; the phases loop over rows (at most 4 a thread) and columns (at
+// most 8 a thread, H = 4).
 using lds_void = __attribute__((address_space(3))) void;
-constexpr int kStageDwords = 4096;             // the largest tile: 8192 halfwords
+constexpr int kStageDwords = 4096;             // 8192 halfwords
+constexpr int kPB = BatchGeo::kPlannedBlocks;
 
-constexpr bool tile_stage_fits() {
+constexpr bool planned_fits() {
   for (int lw = 2; lw <= 6; ++lw)
     for (int lh = 2; lh <= 6; ++lh) {
-      const int elems = BatchGeo::nb_for(lw, lh) << (lw + lh);
-      if (elems > 2 * kStageDwords) return false;
-      if (lw == 2 && elems / 2 > 512) return false;      // two rounds of 4-byte units
-      if (lw >= 3 && elems / 8 > 1024) return false;     // four rounds of 16-byte units
-      if ((BatchGeo::nb_for(lw, lh) << lh) > 256) return false;   // one thread per row
+      const int nb = BatchGeo::nb_planned(lw, lh), elems = nb << (lw + lh);
+      if (nb < 1 || elems > 2 * kStageDwords) return false;
+      if (lw == 2 && elems / 2 > 8 * 256) return false;     // eight rounds of 4-byte units
+      if (lw >= 3 && elems / 8 > 4 * 256) return false;     // four rounds of 16-byte units
+      if ((nb << lh) > 4 * 256) return false;                // rows: four a thread
+      if (lw >= 5 && (nb << lh) > 256) return false;         // one for W >= 32
+      if ((nb << lw) > (32 >> lh) * 256 && lh < 5) return false;   // columns: 32 / H a thread
+      if ((nb << lw) > 256 && lh >= 5) return false;
+      if (elems / (lw >= 3 ? 8 : 4) > 4 * 256) return false;        // store chunks: four a thread
+      if ((nb << lw) > (8192 >> lh)) return false;                   // within the pitches
+      if (BatchGeo::planned_lds_dwords(lh) > kBatchLds) return false;
     }
   return true;
 }
-static_assert(tile_stage_fits(), "a tile does not fit the staging buffer");
-static_assert(kMaxTileBlocks * sizeof(ta_block) <= 256 * 16, "descriptor staging: one 16-byte unit per thread");
+static_assert(planned_fits(), "a planned tile does not fit its buffers or loops");
 
 TA_DEV int swz(int row, int lcpr) { return ((row >> (4 - lcpr)) ^ (row >> (3 - lcpr))) & ((1 << lcpr) - 1); }
 
 TA_DEV void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
 
-// The thread index, opaque to the compiler: addresses derived from it are
-// computed where they are used instead of being hoisted out of the tile
-// loop and spilled (a spill reload waits on vmcnt, that is, on the loads
-// in flight into LDS).
-TA_DEV int tid_here() {
-  int t = threadIdx.x;
-  asm volatile("" : "+v"(t));
-  return t;
+// LDS DMA loads of 16 or 4 bytes a lane from base (scalar) + voff (bytes,
+// per lane, below 2^31) into the wave's LDS window at lds (wave-uniform byte
+// address; lane i lands at lds + i * size).  Issued from inline assembly so
+// that the compiler, which does not see them, inserts no waits of its own
+// for them (it would wait on every LDS store it cannot tell apart from the
+// window); dma_wait() and the tile barrier order them.  No other code of
+// these kernels uses M0.
+TA_DEV uint32_t lds_addr(const void* p) { return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)p); }
+TA_DEV void dma16(const void* base, uint32_t voff, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(base), "s"(lds)
+               : "memory", "m0");
+}
+TA_DEV void dma4(const void* base, uint32_t voff, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %0, %1" ::"v"(voff), "s"(base), "s"(lds)
+               : "memory", "m0");
 }
 
-// What the loads of a tile need: its size, block count and first block.
-// Tile records are read through the constant address space (the kernel
-// never writes them): scalar loads, counted apart from the vector loads and
-// stores, so fetching the next record waits on neither.
+// The thread index, rebuilt where it is used from the wave's base (a scalar)
+// and the lane number (computed in place by an opaque instruction pair), so
+// that neither it nor the addresses derived from it are kept across the
+// tile loop and spilled: a spill reload waits on vmcnt, that is, on the
+// loads in flight into LDS.
+TA_DEV int tid_here(int wb) {
+  int lane;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lane));
+  return wb + lane;
+}
+
+// What the loads of a tile need.  Tile records are read through the
+// constant address space (the kernel never writes them): scalar loads,
+// counted apart from the vector loads and stores, so fetching the next
+// record waits on neither.
 struct TileHead {
-  int lw, lh, count;
-  int64_t first;
+  int lw, lh, count, in_stride;
+  int64_t first, in_base;
 };
 
 typedef const __attribute__((address_space(4))) uint32_t* ConstWords;
 
+TA_DEV uint32_t sload(ConstWords w, int i) { return __builtin_amdgcn_readfirstlane(w[i]); }
+TA_DEV int64_t sload64(ConstWords w, int i) { return (int64_t)(((uint64_t)sload(w, i + 1) << 32) | sload(w, i)); }
+
 TA_DEV TileHead tile_head(const BatchTile* p) {
-  const ConstWords w = (ConstWords)p;
   static_assert(offsetof(BatchTile, lw) == 0 && offsetof(BatchTile, lh) == 4 && offsetof(BatchTile, first) == 16 &&
-                    offsetof(BatchTile, count) == 24, "tile record layout");
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(w[4]), hi = __builtin_amdgcn_readfirstlane(w[5]);
-  return TileHead{__builtin_amdgcn_readfirstlane((int)w[0]), __builtin_amdgcn_readfirstlane((int)w[1]),
-                  __builtin_amdgcn_readfirstlane((int)w[6]), (int64_t)(((uint64_t)hi << 32) | lo)};
+                    offsetof(BatchTile, count) == 24 && offsetof(BatchTile, in_stride) == 28 &&
+                    offsetof(BatchTile, in_base) == 64,
+                "tile record layout");
+  const ConstWords w = (ConstWords)p;
+  return TileHead{(int)sload(w, 0), (int)sload(w, 1), (int)sload(w, 6), (int)sload(w, 7), sload64(w, 4), sload64(w, 16)};
 }
-TA_DEV TileHead tile_head(const BatchTile& t) { return TileHead{t.lw, t.lh, t.count, t.first}; }
+TA_DEV TileHead tile_head(const BatchTile& t) { return TileHead{t.lw, t.lh, t.count, t.in_stride, t.first, t.in_base}; }
 TA_DEV BatchTile uniform_tile(const BatchTile* p) {
   const ConstWords w = (ConstWords)p;
   BatchTile t;
   uint32_t* d = reinterpret_cast<uint32_t*>(&t);
 #pragma unroll
-  for (int i = 0; i < (int)(sizeof(BatchTile) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  for (int i = 0; i < (int)(sizeof(BatchTile) / 4); ++i) d[i] = sload(w, i);
   return t;
 }
 
-// descriptors of tile t -> dst (2 units of 16 bytes per block)
-TA_DEV void stage_descs(const BatchArgs& a, const TileHead& t, ta_block* dst) {
-  const int s = tid_here(), base = s & ~63;
-  if (s < 2 * t.count)
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const uint4*>(a.blocks + t.first) + s,
-                                     (lds_void*)(reinterpret_cast<uint4*>(dst) + base), 16, 0, 0);
+// block deltas of tile t -> dst (two 4-byte units per block)
+TA_DEV void stage_deltas(const BatchArgs& a, const TileHead& t, int2* dst, int wb) {
+  const int tx = tid_here(wb);
+  const int32_t* src = a.deltas + 2 * t.first;
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int s = tx + 256 * g;
+    if (s < 2 * t.count) dma4(src, 4 * s, lds_addr(reinterpret_cast<uint32_t*>(dst) + 256 * g + wb));
+  }
 }
 
-// data of tile t -> stage, through its descriptors dl (in LDS)
-TA_DEV void stage_data(const BatchArgs& a, const TileHead& t, const ta_block* dl, uint32_t* stage) {
-  const int tx = tid_here(), wb = tx & ~63, lane = tx & 63;
+// data of tile t -> stage, through its deltas dl (in LDS); a block's rows
+// lie within 2^30 elements of the tile's base (the planner's rule)
+TA_DEV void stage_data(const BatchArgs& a, const TileHead& t, const int2* dl, uint32_t* stage, int wb) {
+  const int tx = tid_here(wb), lane = tx & 63;
   const int hm = (1 << t.lh) - 1;
+  const int16_t* base = a.in + t.in_base;
   if (t.lw >= 3) {
     const int lcpr = t.lw - 3, nu = t.count << (t.lh + lcpr);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      const int base = g * 256 + wb, s = base + lane;
+      const int s = g * 256 + wb + lane;
       if (s < nu) {
         const int row = s >> lcpr;
         const int c = (s & ((1 << lcpr) - 1)) ^ swz(row, lcpr);
-        const ta_block& d = dl[row >> t.lh];
-        const int16_t* src = a.in + d.in_off + (int64_t)(row & hm) * d.in_stride + c * 8;
-        __builtin_amdgcn_global_load_lds(src, (lds_void*)(stage + base * 4), 16, 0, 0);
+        const uint32_t e = (uint32_t)dl[row >> t.lh].x + (uint32_t)((row & hm) * t.in_stride) + c * 8;
+        dma16(base, 2 * e, lds_addr(stage + (g * 256 + wb) * 4));
       }
     }
   } else {
     const int nu = t.count << (t.lh + 1);
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      const int base = g * 256 + wb, s = base + lane;
+    for (int g = 0; g < 8; ++g) {
+      const int s = g * 256 + wb + lane;
       if (s < nu) {
         const int row = s >> 1;
-        const ta_block& d = dl[row >> t.lh];
-        const int16_t* src = a.in + d.in_off + (int64_t)(row & hm) * d.in_stride + (s & 1) * 2;
-        __builtin_amdgcn_global_load_lds(src, (lds_void*)(stage + base), 4, 0, 0);
+        const uint32_t e = (uint32_t)dl[row >> t.lh].x + (uint32_t)((row & hm) * t.in_stride) + (s & 1) * 2;
+        dma4(base, 2 * e, lds_addr(stage + g * 256 + wb));
       }
     }
   }
 }
 
-TA_DEV void copy_descs(const TileHead& t, const ta_block* src, ta_block* dst) {
-  const int tx = tid_here();
-  if (tx < 2 * t.count) reinterpret_cast<uint4*>(dst)[tx] = reinterpret_cast<const uint4*>(src)[tx];
+TA_DEV void copy_deltas(const TileHead& t, const int2* src, int2* dst, int wb) {
+  const int tx = tid_here(wb);
+  if (2 * tx < t.count) reinterpret_cast<int4*>(dst)[tx] = reinterpret_cast<const int4*>(src)[tx];
 }
 
 // forward row phase from the staged rows
 template <int W, class KH>
-TA_DEV void fwd_rows_st(const BatchArgs& a, const BatchTile& t, const uint32_t* stage, uint16_t* pch, int s_row) {
-  const int tid = tid_here();
-  if (tid >= (t.count << t.lh)) return;
-  const int b = tid >> t.lh, r = tid & ((1 << t.lh) - 1);
-  fx::Packed<W> x;
-  if constexpr (W >= 8) {
-    constexpr int LC = W == 8 ? 0 : W == 16 ? 1 : W == 32 ? 2 : 3;
-    const uint4* row = reinterpret_cast<const uint4*>(stage) + (tid << LC);
-    const int f = swz(tid, LC);
+TA_DEV void fwd_rows_pl(const BatchArgs& a, const BatchTile& t, const uint32_t* stage, uint16_t* pch, int P,
+                        int s_row, int wb) {
+  constexpr int LC = W == 4 ? 0 : W == 8 ? 0 : W == 16 ? 1 : W == 32 ? 2 : 3;
+  const int nrows = t.count << t.lh;
+  // rows: at most 8192 / W, so one round for W >= 32
+#pragma unroll 1
+  for (int row = tid_here(wb); row < nrows; row += (W >= 32 ? 1 << 30 : 256)) {
+    const int b = row >> t.lh, r = row & ((1 << t.lh) - 1);
+    fx::Packed<W> x;
+    if constexpr (W >= 8) {
+      const uint4* src = reinterpret_cast<const uint4*>(stage) + (row << LC);
+      const int f = swz(row, LC);
 #pragma unroll
-    for (int q = 0; q < W / 8; ++q) {
-      const uint4 v = row[q ^ f];
-      x.p[4 * q] = v.x; x.p[4 * q + 1] = v.y; x.p[4 * q + 2] = v.z; x.p[4 * q + 3] = v.w;
+      for (int q = 0; q < W / 8; ++q) {
+        const uint4 v = src[q ^ f];
+        x.p[4 * q] = v.x; x.p[4 * q + 1] = v.y; x.p[4 * q + 2] = v.z; x.p[4 * q + 3] = v.w;
+      }
+    } else {
+      const uint2 v = reinterpret_cast<const uint2*>(stage)[row];
+      x.p[0] = v.x; x.p[1] = v.y;
     }
-  } else {
-    const uint2 v = reinterpret_cast<const uint2*>(stage)[tid];
-    x.p[0] = v.x; x.p[1] = v.y;
-  }
-  const auto y = fx::run_pass<W, KH, false>(x, as_cparam(t.ph_f), as_cparam(t.ph_i), s_row, a.a);
-  const int base = ((r >> 1) * BatchGeo::pc_pitch(t.lh) + b * W) * 2 + (r & 1);
+    const auto y = fx::run_pass<W, KH, false>(x, as_cparam(t.ph_f), as_cparam(t.ph_i), s_row, a.a);
+    const int base = ((r >> 1) * P + b * W) * 2 + (r & 1);
 #pragma unroll
-  for (int j = 0; j < W / 2; ++j) {
-    const uint32_t v = y.pair(2 * j, 2 * j + 1);
-    pch[base + (2 * j) * 2] = (uint16_t)v;
-    pch[base + (2 * j + 1) * 2] = (uint16_t)(v >> 16);
+    for (int j = 0; j < W / 2; ++j) {
+      const uint32_t v = y.pair(2 * j, 2 * j + 1);
+      pch[base + (2 * j) * 2] = (uint16_t)v;
+      pch[base + (2 * j + 1) * 2] = (uint16_t)(v >> 16);
+    }
   }
 }
 
 template <class KH>
-TA_DEV void fwd_rows_st_w(const BatchArgs& a, const BatchTile& t, const uint32_t* stage, uint16_t* pch, int s) {
+TA_DEV void fwd_rows_pl_w(const BatchArgs& a, const BatchTile& t, const uint32_t* stage, uint16_t* pch, int P, int s,
+                          int wb) {
   switch (t.lw) {
-    case 2: fwd_rows_st<4, KH>(a, t, stage, pch, s); break;
-    case 3: fwd_rows_st<8, KH>(a, t, stage, pch, s); break;
-    case 4: fwd_rows_st<16, KH>(a, t, stage, pch, s); break;
-    case 5: fwd_rows_st<32, KH>(a, t, stage, pch, s); break;
-    default: fwd_rows_st<64, KH>(a, t, stage, pch, s); break;
+    case 2: fwd_rows_pl<4, KH>(a, t, stage, pch, P, s, wb); break;
+    case 3: fwd_rows_pl<8, KH>(a, t, stage, pch, P, s, wb); break;
+    case 4: fwd_rows_pl<16, KH>(a, t, stage, pch, P, s, wb); break;
+    case 5: fwd_rows_pl<32, KH>(a, t, stage, pch, P, s, wb); break;
+    default: fwd_rows_pl<64, KH>(a, t, stage, pch, P, s, wb); break;
+  }
+}
+
+// column phase (either direction): pair rows -> transform -> barrier (they
+// are dead) -> rows; a thread holds the results of its (up to 32 / H)
+// columns across the barrier
+template <int H, class KV, bool INV, int LH>
+TA_DEV void cols_pl(const BatchArgs& a, const BatchTile& t, uint32_t* lds, int s_col, int wb) {
+  constexpr int K = H >= 32 ? 1 : 32 / H;
+  constexpr int P = BatchGeo::pl_pc(LH), Q = BatchGeo::pl_rm(LH);
+  const int cols = t.count << t.lw, tx = tid_here(wb);
+  uint32_t o[K][H / 2];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int c = tx + 256 * k;
+    if (c < cols) {
+      fx::Packed<H> z;
+#pragma unroll
+      for (int i = 0; i < H / 2; ++i) z.p[i] = lds[i * P + c];
+      const auto y = fx::run_pass<H, KV, INV>(z, as_cparam(t.pv_f), as_cparam(t.pv_i), s_col, a.a);
+#pragma unroll
+      for (int i = 0; i < H / 2; ++i) o[k][i] = y.pair(2 * i, 2 * i + 1);
+    }
+  }
+  tile_sync();
+  uint16_t* rm = reinterpret_cast<uint16_t*>(lds);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int c = tx + 256 * k;
+    if (c < cols) {
+#pragma unroll
+      for (int i = 0; i < H / 2; ++i) {
+        rm[(2 * i) * Q + c] = (uint16_t)o[k][i];
+        rm[(2 * i + 1) * Q + c] = (uint16_t)(o[k][i] >> 16);
+      }
+    }
+  }
+}
+
+template <class KV, bool INV>
+TA_DEV void cols_pl_h(const BatchArgs& a, const BatchTile& t, uint32_t* lds, int s, int wb) {
+  switch (t.lh) {
+    case 2: cols_pl<4, KV, INV, 2>(a, t, lds, s, wb); break;
+    case 3: cols_pl<8, KV, INV, 3>(a, t, lds, s, wb); break;
+    case 4: cols_pl<16, KV, INV, 4>(a, t, lds, s, wb); break;
+    case 5: cols_pl<32, KV, INV, 5>(a, t, lds, s, wb); break;
+    default: cols_pl<64, KV, INV, 6>(a, t, lds, s, wb); break;
+  }
+}
+
+// inverse row phase, in place in the row layout
+template <int W, class KH>
+TA_DEV void inv_rows_pl(const BatchArgs& a, const BatchTile& t, uint16_t* rm, int Q, int s_row, int wb) {
+  const int nrows = t.count << t.lh;
+#pragma unroll 1
+  for (int row = tid_here(wb); row < nrows; row += (W >= 32 ? 1 << 30 : 256)) {
+    const int b = row >> t.lh, r = row & ((1 << t.lh) - 1);
+    uint16_t* s = rm + r * Q + b * W;
+    fx::Packed<W> x;
+    if constexpr (W >= 8) {
+#pragma unroll
+      for (int q = 0; q < W / 8; ++q) {
+        const uint4 v = reinterpret_cast<const uint4*>(s)[q];
+        x.p[4 * q] = v.x; x.p[4 * q + 1] = v.y; x.p[4 * q + 2] = v.z; x.p[4 * q + 3] = v.w;
+      }
+    } else {
+      const uint2 v = *reinterpret_cast<const uint2*>(s);
+      x.p[0] = v.x; x.p[1] = v.y;
+    }
+    const auto y = fx::run_pass<W, KH, true>(x, as_cparam(t.ph_f), as_cparam(t.ph_i), s_row, a.a);
+    uint32_t o[W / 2];
+#pragma unroll
+    for (int j = 0; j < W / 2; ++j) o[j] = y.pair(2 * j, 2 * j + 1);
+    if constexpr (W >= 8) {
+#pragma unroll
+      for (int q = 0; q < W / 8; ++q)
+        reinterpret_cast<uint4*>(s)[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    } else {
+      *reinterpret_cast<uint2*>(s) = make_uint2(o[0], o[1]);
+    }
+  }
+}
+
+template <class KH>
+TA_DEV void inv_rows_pl_w(const BatchArgs& a, const BatchTile& t, uint16_t* rm, int Q, int s, int wb) {
+  switch (t.lw) {
+    case 2: inv_rows_pl<4, KH>(a, t, rm, Q, s, wb); break;
+    case 3: inv_rows_pl<8, KH>(a, t, rm, Q, s, wb); break;
+    case 4: inv_rows_pl<16, KH>(a, t, rm, Q, s, wb); break;
+    case 5: inv_rows_pl<32, KH>(a, t, rm, Q, s, wb); break;
+    default: inv_rows_pl<64, KH>(a, t, rm, Q, s, wb); break;
   }
 }
 
 // inverse: the staged rows -> pair-row layout
-TA_DEV void inv_scatter(const BatchTile& t, const uint32_t* stage, uint16_t* pch) {
-  const int p = BatchGeo::pc_pitch(t.lh), hm = (1 << t.lh) - 1, tx = tid_here();
+TA_DEV void inv_scatter(const BatchTile& t, const uint32_t* stage, uint16_t* pch, int P, int wb) {
+  const int hm = (1 << t.lh) - 1, tx = tid_here(wb);
   if (t.lw >= 3) {
     const int lcpr = t.lw - 3, nu = t.count << (t.lh + lcpr);
 #pragma unroll
@@ -530,7 +663,7 @@ TA_DEV void inv_scatter(const BatchTile& t, const uint32_t* stage, uint16_t* pch
         const int row = s >> lcpr;
         const int c0 = ((s & ((1 << lcpr) - 1)) ^ swz(row, lcpr)) * 8;
         const int r = row & hm;
-        const int base = ((r >> 1) * p + ((row >> t.lh) << t.lw) + c0) * 2 + (r & 1);
+        const int base = ((r >> 1) * P + ((row >> t.lh) << t.lw) + c0) * 2 + (r & 1);
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -542,12 +675,12 @@ TA_DEV void inv_scatter(const BatchTile& t, const uint32_t* stage, uint16_t* pch
   } else {
     const int nu = t.count << (t.lh + 1);
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < 8; ++g) {
       const int s = tx + 256 * g;
       if (s < nu) {
         const uint32_t v = stage[s];
         const int row = s >> 1, r = row & hm;
-        const int base = ((r >> 1) * p + ((row >> t.lh) << 2) + (s & 1) * 2) * 2 + (r & 1);
+        const int base = ((r >> 1) * P + ((row >> t.lh) << 2) + (s & 1) * 2) * 2 + (r & 1);
         pch[base] = (uint16_t)v;
         pch[base + 2] = (uint16_t)(v >> 16);
       }
@@ -555,110 +688,97 @@ TA_DEV void inv_scatter(const BatchTile& t, const uint32_t* stage, uint16_t* pch
   }
 }
 
-// coalesced store of the row-major layout through the descriptors dl (LDS);
-// a tile has at most 1024 chunks: four rounds, the LDS reads issued first
-TA_DEV void store_tile(const BatchArgs& a, const BatchTile& t, const uint16_t* rm, const ta_block* dl) {
-  const int lch = t.lw >= 3 ? 3 : 2, tx = tid_here();
-  const int q = BatchGeo::rm_pitch(t.lh);
-  const int nch = t.count << (t.lw + t.lh - lch);
-  uint4 v[4];
+// coalesced store of the row layout through the deltas dl (LDS); a tile has
+// at most 1024 chunks: four rounds, the LDS reads issued first
+template <int LCH>
+TA_DEV void store_chunks(const BatchArgs& a, const BatchTile& t, const uint16_t* rm, int Q, const int2* dl, int tx) {
+  typedef typename std::conditional<LCH == 3, uint4, uint2>::type V;
+  const int nch = t.count << (t.lw + t.lh - LCH);
+  // every round reads a valid chunk (threads past the end repeat the last)
+  // and stores only its own, so nothing is defined conditionally
+  V v[4];
   int64_t off[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
-    const int ch = tx + 256 * g;
-    if (ch < nch) {
-      const Chunk k(ch, t.lw, t.lh, lch);
-      const ta_block& d = dl[k.b];
-      off[g] = d.out_off + (int64_t)k.r * d.out_stride + k.c0;
-      const uint16_t* src = rm + k.r * q + (k.b << t.lw) + k.c0;
-      if (lch == 3) {
-        v[g] = *reinterpret_cast<const uint4*>(src);
-      } else {
-        const uint2 h = *reinterpret_cast<const uint2*>(src);
-        v[g] = make_uint4(h.x, h.y, 0, 0);
-      }
-    }
+    const Chunk k(min(tx + 256 * g, nch - 1), t.lw, t.lh, LCH);
+    off[g] = t.out_base + dl[k.b].y + (int64_t)k.r * t.out_stride + k.c0;
+    v[g] = *reinterpret_cast<const V*>(rm + k.r * Q + (k.b << t.lw) + k.c0);
   }
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const int ch = tx + 256 * g;
-    if (ch < nch) {
-      if (lch == 3)
-        *reinterpret_cast<uint4*>(a.out + off[g]) = v[g];
-      else
-        *reinterpret_cast<uint2*>(a.out + off[g]) = make_uint2(v[g].x, v[g].y);
-    }
-  }
+  for (int g = 0; g < 4; ++g)
+    if (tx + 256 * g < nch) *reinterpret_cast<V*>(a.out + off[g]) = v[g];
+}
+
+TA_DEV void store_tile(const BatchArgs& a, const BatchTile& t, const uint16_t* rm, int Q, const int2* dl, int wb) {
+  if (t.lw >= 3)
+    store_chunks<3>(a, t, rm, Q, dl, tid_here(wb));
+  else
+    store_chunks<2>(a, t, rm, Q, dl, tid_here(wb));
 }
 
 // The walk of one workgroup over its XCD's tile list (grid stride P):
-// tile k is processed while the data of k+1 and the descriptors of k+2 load.
+// tile k is processed while the data of k+1 and the deltas of k+2 load.
 template <bool INV>
-TA_DEV void planned_tiles(const BatchArgs& a, uint32_t* lds, uint32_t* stage, ta_block (*ring)[kMaxTileBlocks],
-                          ta_block* dnext) {
+TA_DEV void planned_tiles(const BatchArgs& a, uint32_t* lds, uint32_t* stage, int2 (*ring)[kPB], int2* dnext) {
+  // tile indices fit int32 (the planner's rule), so the loop tests are scalar
   const int xcd = blockIdx.x % kXcds;
-  const int64_t P = (gridDim.x + kXcds - 1 - xcd) / kXcds;
-  const int64_t end = a.xstart[xcd + 1];
-  int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds;
+  const int P = (gridDim.x + kXcds - 1 - xcd) / kXcds;
+  const int end = (int)a.xstart[xcd + 1];
+  int ti = (int)a.xstart[xcd] + blockIdx.x / kXcds;
   if (ti >= end) return;
   uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
-  BatchTile t = uniform_tile(a.tiles + ti);
-  bool has_n = ti + P < end, has_nn = ti + 2 * P < end;
-  TileHead n = has_n ? tile_head(a.tiles + ti + P) : tile_head(t);
-  stage_descs(a, tile_head(t), ring[0]);
-  dma_wait();
-  tile_sync();
-  stage_data(a, tile_head(t), ring[0], stage);
-  if (has_n) stage_descs(a, n, dnext);
-  TileHead nn = has_nn ? tile_head(a.tiles + ti + 2 * P) : n;
+  const int wb = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;   // this wave's first thread
+  // prologue: deltas and data of the first tile, deltas of the second
+  {
+    const TileHead h0 = tile_head(a.tiles + ti);
+    stage_deltas(a, h0, ring[0], wb);
+    dma_wait();
+    tile_sync();
+    stage_data(a, h0, ring[0], stage, wb);
+    if (ti + P < end) stage_deltas(a, tile_head(a.tiles + ti + P), dnext, wb);
+  }
   int cur = 0;
   for (;;) {
-    dma_wait();                          // this tile's data, the next descriptors, the last stores
+    // tile records are re-read each step (scalar loads, cheap) rather than
+    // carried across the loop in scalar registers
+    const BatchTile t = uniform_tile(a.tiles + ti);
+    const bool has_n = ti + P < end, has_nn = ti + 2 * P < end;
+    dma_wait();                          // this tile's data, the next deltas, the last stores
     tile_sync();
-    if (has_n) copy_descs(n, dnext, ring[cur ^ 1]);
+    if (has_n) copy_deltas(tile_head(a.tiles + ti + P), dnext, ring[cur ^ 1], wb);
+    const int PP = BatchGeo::pl_pc(t.lh), Q = BatchGeo::pl_rm(t.lh);
     if (INV) {
-      inv_scatter(t, stage, pch);
+      inv_scatter(t, stage, pch, PP, wb);
     } else {
       const int s_row = t.lw + a.bd + a.m - 15;
       switch (t.kind_h) {
-        case 0: fwd_rows_st_w<KC2>(a, t, stage, pch, s_row); break;
-        case 1: fwd_rows_st_w<KS3>(a, t, stage, pch, s_row); break;
-        default: fwd_rows_st_w<KC3>(a, t, stage, pch, s_row); break;
+        case 0: fwd_rows_pl_w<KC2>(a, t, stage, pch, PP, s_row, wb); break;
+        case 1: fwd_rows_pl_w<KS3>(a, t, stage, pch, PP, s_row, wb); break;
+        default: fwd_rows_pl_w<KC3>(a, t, stage, pch, PP, s_row, wb); break;
       }
     }
     tile_sync();                         // stage and dnext are free
-    if (has_n) stage_data(a, n, ring[cur ^ 1], stage);
-    if (has_nn) stage_descs(a, nn, dnext);
-    if (INV) {
-      const int s_col = a.m + 1, s_row = a.m + 14 - a.bd;
-      switch (t.kind_v) {
-        case 0: inv_cols_h<KC2>(a, t, lds, s_col); break;
-        case 1: inv_cols_h<KS3>(a, t, lds, s_col); break;
-        default: inv_cols_h<KC3>(a, t, lds, s_col); break;
-      }
-      tile_sync();
-      switch (t.kind_h) {
-        case 0: inv_rows_w<KC2>(a, t, pch, s_row); break;
-        case 1: inv_rows_w<KS3>(a, t, pch, s_row); break;
-        default: inv_rows_w<KC3>(a, t, pch, s_row); break;
-      }
-    } else {
-      const int s_col = t.lh + a.m;
-      switch (t.kind_v) {
-        case 0: fwd_cols_h<KC2>(a, t, lds, s_col); break;
-        case 1: fwd_cols_h<KS3>(a, t, lds, s_col); break;
-        default: fwd_cols_h<KC3>(a, t, lds, s_col); break;
-      }
+    if (has_n) stage_data(a, tile_head(a.tiles + ti + P), ring[cur ^ 1], stage, wb);
+    if (has_nn) stage_deltas(a, tile_head(a.tiles + ti + 2 * P), dnext, wb);
+    const int s_col = INV ? a.m + 1 : t.lh + a.m;
+    switch (t.kind_v) {
+      case 0: cols_pl_h<KC2, INV>(a, t, lds, s_col, wb); break;
+      case 1: cols_pl_h<KS3, INV>(a, t, lds, s_col, wb); break;
+      default: cols_pl_h<KC3, INV>(a, t, lds, s_col, wb); break;
     }
     tile_sync();
-    store_tile(a, t, pch, ring[cur]);
+    if (INV) {
+      const int s_row = a.m + 14 - a.bd;
+      switch (t.kind_h) {
+        case 0: inv_rows_pl_w<KC2>(a, t, pch, Q, s_row, wb); break;
+        case 1: inv_rows_pl_w<KS3>(a, t, pch, Q, s_row, wb); break;
+        default: inv_rows_pl_w<KC3>(a, t, pch, Q, s_row, wb); break;
+      }
+      tile_sync();
+    }
+    store_tile(a, t, pch, Q, ring[cur], wb);
     if (!has_n) break;
     ti += P;
-    t = uniform_tile(a.tiles + ti);
-    n = nn;
-    has_n = has_nn;
-    has_nn = ti + 2 * P < end;
-    if (has_nn) nn = tile_head(a.tiles + ti + 2 * P);
     cur ^= 1;
   }
 }
@@ -666,16 +786,16 @@ TA_DEV void planned_tiles(const BatchArgs& a, uint32_t* lds, uint32_t* stage, ta
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_fwd(BatchArgs a) {
   __shared__ __align__(16) uint32_t lds[kBatchLds];
   __shared__ __align__(16) uint32_t stage[kStageDwords];
-  __shared__ __align__(16) ta_block ring[2][kMaxTileBlocks];
-  __shared__ __align__(16) ta_block dnext[kMaxTileBlocks];
+  __shared__ __align__(16) int2 ring[2][kPB];
+  __shared__ __align__(16) int2 dnext[kPB];
   planned_tiles<false>(a, lds, stage, ring, dnext);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_inv(BatchArgs a) {
   __shared__ __align__(16) uint32_t lds[kBatchLds];
   __shared__ __align__(16) uint32_t stage[kStageDwords];
-  __shared__ __align__(16) ta_block ring[2][kMaxTileBlocks];
-  __shared__ __align__(16) ta_block dnext[kMaxTileBlocks];
+  __shared__ __align__(16) int2 ring[2][kPB];
+  __shared__ __align__(16) int2 dnext[kPB];
   planned_tiles<true>(a, lds, stage, ring, dnext);
 }
 

@@ -6,6 +6,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <climits>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -803,16 +805,18 @@ struct ta_plan {
   ta_plan(const ta_plan&) = delete;
   ta_plan& operator=(const ta_plan&) = delete;
   ~ta_plan() {
-    if (!blocks_dev && !tiles_dev && !progs_dev) return;
+    if (!blocks_dev && !tiles_dev && !progs_dev && !deltas_dev) return;
     DeviceGuard device_guard_;
     (void)device_guard_.enter(device);
     if (blocks_dev) (void)hipFree(blocks_dev);
     if (tiles_dev) (void)hipFree(tiles_dev);
     if (progs_dev) (void)hipFree(progs_dev);
+    if (deltas_dev) (void)hipFree(deltas_dev);
   }
   int64_t nblocks = 0, ntiles = 0;
   int grid = 2048;                 // persistent workgroups (autotuned)
   ta_block* blocks_dev = nullptr;  // block descriptors in plan order
+  int32_t* deltas_dev = nullptr;   // (in_off - tile in_base, out_off - tile out_base) per block, plan order
   ta::BatchTile* tiles_dev = nullptr;
   int64_t max_in_elem = 0, max_out_elem = 0;   // extents touched (for validation)
   int64_t xstart[ta::kXcds + 1] = {};            // per-XCD tile lists
@@ -870,6 +874,7 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
   args.ntiles = p->ntiles;
   for (int x = 0; x <= ta::kXcds; ++x) args.xstart[x] = p->xstart[x];
   args.blocks = p->blocks_dev;
+  args.deltas = p->deltas_dev;
   args.in = static_cast<const int16_t*>(in);
   args.out = static_cast<int16_t*>(out);
   args.bd = c->bd;
@@ -888,12 +893,12 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
 // their first block.  Replaces the
 // plan's device descriptor and tile arrays (synchronous, allocates).
 int build_tiles(ta_plan* plan, int region_log2) {
-  typedef std::tuple<int64_t, int, int, uint32_t> Key;   // region, log2w, log2h, class
+  typedef std::tuple<int64_t, int, int, uint32_t, int32_t, int32_t> Key;   // region, log2w, log2h, class, strides
   std::map<Key, std::vector<int64_t>> groups;
   const int64_t n = plan->nblocks;
   for (int64_t i = 0; i < n; ++i) {
     const ta_block& b = plan->host[(size_t)i];
-    groups[Key{b.in_off >> region_log2, b.log2w, b.log2h, plan->cls[(size_t)i]}].push_back(i);
+    groups[Key{b.in_off >> region_log2, b.log2w, b.log2h, plan->cls[(size_t)i], b.in_stride, b.out_stride}].push_back(i);
   }
   std::vector<Key> keys;
   for (auto& kv : groups) keys.push_back(kv.first);
@@ -902,8 +907,10 @@ int build_tiles(ta_plan* plan, int region_log2) {
     return std::get<1>(x) + std::get<2>(x) > std::get<1>(y) + std::get<2>(y);
   });
   std::vector<ta_block> ordered;
+  std::vector<int32_t> deltas;
   std::vector<ta::BatchTile> lists[ta::kXcds];
   ordered.reserve((size_t)n);
+  deltas.reserve(2 * (size_t)n);
   std::map<int64_t, int> region_xcd;
   // the tiles of one region, listed by the frame position of their first
   // block: tiles of different sizes and classes that share cache lines run
@@ -927,20 +934,39 @@ int build_tiles(ta_plan* plan, int region_log2) {
       pending_xcd = next;
     }
     const int lw = std::get<1>(k), lh = std::get<2>(k);
+    const int32_t in_stride = std::get<4>(k), out_stride = std::get<5>(k);
     const bool f32 = plan->dtype == TA_F32;
-    const int nb = plan->general ? ta::GenGeo::nb_for(lw, lh, f32)
-                                 : f32 ? ta::BatchGeoF32::nb_for(lw, lh) : ta::BatchGeo::nb_for(lw, lh);
+    const size_t nb = (size_t)(plan->general ? ta::GenGeo::nb_for(lw, lh, f32)
+                                             : f32 ? ta::BatchGeoF32::nb_for(lw, lh) : ta::BatchGeo::nb_planned(lw, lh));
     const uint32_t ci = std::get<3>(k);
     const ta_plan::Class& cl = plan->classes[ci];
     const auto& idx = groups[k];
-    for (size_t s = 0; s < idx.size(); s += nb) {
+    // a tile's blocks lie within 2^30 input elements of its base, counting
+    // each block's extent, and within 2^31 output elements (int32 deltas)
+    const int64_t ext_in = (int64_t)((1 << lh) - 1) * in_stride + (1 << lw);
+    size_t s = 0;
+    while (s < idx.size()) {
+      int64_t in_lo = INT64_MAX, in_hi = INT64_MIN, out_lo = INT64_MAX, out_hi = INT64_MIN;
+      size_t e = s;
+      while (e < idx.size() && e - s < nb) {
+        const ta_block& b = plan->host[(size_t)idx[e]];
+        const int64_t il = std::min(in_lo, b.in_off), ih = std::max(in_hi, b.in_off);
+        const int64_t ol = std::min(out_lo, b.out_off), oh = std::max(out_hi, b.out_off);
+        if (e > s && (ih - il + ext_in > ((int64_t)1 << 30) || oh - ol > INT32_MAX)) break;
+        in_lo = il, in_hi = ih, out_lo = ol, out_hi = oh;
+        ++e;
+      }
       ta::BatchTile t{};
       t.lw = lw;
       t.lh = lh;
       t.kind_h = cl.kh;
       t.kind_v = cl.kv;
       t.first = (int64_t)ordered.size();
-      t.count = (int32_t)std::min<size_t>(nb, idx.size() - s);
+      t.count = (int32_t)(e - s);
+      t.in_stride = in_stride;
+      t.out_stride = out_stride;
+      t.in_base = in_lo;
+      t.out_base = out_lo;
       if (plan->general) {
         // the class's stage programs (forward / inverse of each axis)
         const ta::GenProg* pr = plan->progs_dev + 4 * (size_t)ci;
@@ -954,8 +980,14 @@ int build_tiles(ta_plan* plan, int region_log2) {
         t.pv_f = static_cast<const uint32_t*>(cl.rv.pf);
         t.pv_i = static_cast<const uint32_t*>(cl.rv.pi);
       }
-      pending.push_back({plan->host[(size_t)idx[s]].in_off, t});
-      for (size_t j = s; j < s + t.count; ++j) ordered.push_back(plan->host[(size_t)idx[j]]);
+      pending.push_back({in_lo, t});
+      for (size_t j = s; j < e; ++j) {
+        const ta_block& b = plan->host[(size_t)idx[j]];
+        ordered.push_back(b);
+        deltas.push_back((int32_t)(b.in_off - in_lo));
+        deltas.push_back((int32_t)(b.out_off - out_lo));
+      }
+      s = e;
     }
   }
   flush_region();
@@ -965,6 +997,7 @@ int build_tiles(ta_plan* plan, int region_log2) {
     tiles.insert(tiles.end(), lists[x].begin(), lists[x].end());
   }
   plan->xstart[ta::kXcds] = (int64_t)tiles.size();
+  if (tiles.size() > (size_t)INT32_MAX) return fail(TA_EUNSUPPORTED, "more than 2^31 tiles");
   plan->ntiles = (int64_t)tiles.size();
   plan->region_log2 = region_log2;
   TA_ON_DEVICE(plan->device);
@@ -973,7 +1006,9 @@ int build_tiles(ta_plan* plan, int region_log2) {
     // that re-planning never moves them
     if (!plan->blocks_dev) TA_HIP(hipMalloc(&plan->blocks_dev, (size_t)n * sizeof(ta_block)));
     if (!plan->tiles_dev) TA_HIP(hipMalloc(&plan->tiles_dev, (size_t)n * sizeof(ta::BatchTile)));
+    if (!plan->deltas_dev) TA_HIP(hipMalloc(&plan->deltas_dev, 2 * (size_t)n * sizeof(int32_t)));
     TA_HIP(hipMemcpy(plan->blocks_dev, ordered.data(), ordered.size() * sizeof(ta_block), hipMemcpyHostToDevice));
+    TA_HIP(hipMemcpy(plan->deltas_dev, deltas.data(), deltas.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     TA_HIP(hipMemcpy(plan->tiles_dev, tiles.data(), tiles.size() * sizeof(ta::BatchTile), hipMemcpyHostToDevice));
   }
   return TA_OK;
@@ -1012,6 +1047,10 @@ int ta_plan_create(ta_ctx* c, const ta_block* blocks, int64_t n, int dtype, ta_p
       }
       plan->cls[(size_t)i] = it->second;
       const int w = 1 << b.log2w, h = 1 << b.log2h;
+      // the planned int16 kernels address a block's rows with 32-bit byte
+      // offsets from their tile's base; rows further apart run on the
+      // general kernel
+      if (dtype == TA_I16 && (int64_t)(h - 1) * b.in_stride + w > ((int64_t)1 << 30)) plan->general = true;
       plan->max_in_elem = std::max<int64_t>(plan->max_in_elem, b.in_off + (int64_t)(h - 1) * b.in_stride + w);
       plan->max_out_elem = std::max<int64_t>(plan->max_out_elem, b.out_off + (int64_t)(h - 1) * b.out_stride + w);
     }

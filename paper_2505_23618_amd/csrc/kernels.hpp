@@ -44,16 +44,23 @@ struct KernelEntry {
 };
 
 // One tile of a batched plan (device memory, written by the host planner):
-// up to 256 / max(W, H) blocks of one size and one pair of axis kinds.
+// blocks of one size and one pair of axis kinds.  The blocks of a tile share
+// their row strides, and each block's offsets are int32 deltas from the
+// tile's bases (the planner cuts tiles so that they fit), kept in the plan's
+// delta array (in_delta, out_delta per block, in block order).
 struct BatchTile {
   int32_t lw, lh, kind_h, kind_v;
-  int64_t first;          // index of the first block descriptor of the tile
+  int64_t first;          // index of the first block (descriptors and deltas) of the tile
   int32_t count;          // blocks in this tile
-  int32_t pad;
+  int32_t in_stride;      // input row stride of every block of the tile
   const uint32_t* ph_f;   // band taps of the horizontal axis (forward / transposed)
   const uint32_t* ph_i;
   const uint32_t* pv_f;   // band taps of the vertical axis
   const uint32_t* pv_i;
+  int64_t in_base;        // block b's input at in_base + in_delta[first + b]
+  int64_t out_base;
+  int32_t out_stride;
+  int32_t pad;
 };
 
 // The plan's tiles form one list per XCD (8 lists, concatenated; list x is
@@ -89,6 +96,25 @@ struct BatchGeo {
     int m = 0;
     for (int lh = 2; lh <= 6; ++lh) m = lds_dwords(lh) > m ? lds_dwords(lh) : m;
     return m;
+  }
+  // Planned int16 tiles (batch_fwd / batch_inv) are larger: up to 8192
+  // coefficients (4096 for 4-wide blocks, whose loads move 4 bytes a lane),
+  // the row and column phases looping over their rows and columns.  The
+  // tile's columns (NB * W) never exceed 8192 / H, and the pitches are those
+  // of that width whatever the tile holds: pl_pc(H) = 8192 / H + 1 dwords
+  // (pair rows) and pl_rm(H) = 8192 / H + 8 halfwords (rows), compile-time
+  // per H so that a column thread's accesses are immediate offsets.
+  static constexpr int kPlannedBlocks = 256;
+  static constexpr int nb_planned(int lw, int lh) {
+    const int nb = (lw == 2 ? 4096 : 8192) >> (lw + lh);
+    return nb < kPlannedBlocks ? nb : kPlannedBlocks;
+  }
+  static constexpr int pl_pc(int lh) { return (8192 >> lh) + 1; }
+  static constexpr int pl_rm(int lh) { return (8192 >> lh) + 8; }
+  static constexpr int planned_lds_dwords(int lh) {
+    const int h = 1 << lh;
+    const int pc = (h / 2) * pl_pc(lh), rm = (h * pl_rm(lh) + 1) / 2;
+    return pc > rm ? pc : rm;
   }
 };
 
@@ -134,6 +160,7 @@ struct BatchArgs {
   int64_t ntiles;
   int64_t xstart[kXcds + 1];
   const ta_block* blocks;
+  const int32_t* deltas;  // planned int16: (in_delta, out_delta) per block
   const int16_t* in;      // int16 data; the fp32 kernels read these as float*
   int16_t* out;
   int bd, m, a;

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.batchcase import descriptors, oracle_frames, register_axes
+from tests.batchcase import axis_id, descriptors, oracle_frames, register_axes
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -156,3 +156,61 @@ def test_set_tuning_keeps_outputs_bitwise(env):
         with pytest.raises(ta.TadjError) as e:
             plan.set_tuning(grid, region)
         assert e.value.code == ta.TA_EINVAL
+
+
+def test_planned_strides_offsets_and_order(env):
+    """One plan over two frames of different widths (448 and 320) read from one
+    buffer and written at other offsets with another stride (512), the
+    descriptors shuffled: tiles group blocks by strides, offsets go through
+    per-block deltas from each tile's base; bit-exact forward and inverse."""
+    from tests.cfgs import type_axis
+    from oracle import fixed as F
+
+    ctx, params = env
+    rng = np.random.Generator(np.random.PCG64(61))
+    geo = [(448, 128), (320, 96)]
+    in_base, out_base, parts = [0], [0], []
+    for w, h in geo:
+        in_base.append(in_base[-1] + w * h)
+        out_base.append(out_base[-1] + 512 * h)
+        parts.append(synth.partition_frame(w, h, int(rng.integers(1 << 30))))
+    src = (rng.standard_normal(in_base[-1]) * 60).round().astype(np.int16)
+    d, meta = [], []
+    for f, part in enumerate(parts):
+        wf = geo[f][0]
+        for x, y, w, h in part:
+            th, tv = (int(v) for v in rng.integers(0, 3, 2))
+            d.append((in_base[f] + y * wf + x, out_base[f] + y * 512 + x, wf, 512, int(np.log2(w)), int(np.log2(h)),
+                      axis_id(th, int(w)), axis_id(tv, int(h)), 0))
+            meta.append((f, int(x), int(y), int(w), int(h), th, tv))
+    perm = rng.permutation(len(d))
+    desc = np.array([d[i] for i in perm], ta.BLOCK_DTYPE)
+    meta = [meta[i] for i in perm]
+    print(f"planned layouts: {len(desc)} blocks", flush=True)
+    plan = ta.Plan(ctx, desc)
+    x = torch.from_numpy(src).cuda()
+    y = torch.full((out_base[-1],), 7, dtype=torch.int16, device="cuda")
+    plan.fwd(x, y)
+    torch.cuda.synchronize()
+    yc = y.cpu().numpy()
+    # the inverse reads the coefficients at the output layout and writes the input layout
+    inv_desc = desc.copy()
+    inv_desc["in_off"], inv_desc["out_off"] = desc["out_off"], desc["in_off"]
+    inv_desc["in_stride"], inv_desc["out_stride"] = desc["out_stride"], desc["in_stride"]
+    iplan = ta.Plan(ctx, inv_desc)
+    z = torch.full((in_base[-1],), -7, dtype=torch.int16, device="cuda")
+    iplan.inv(y, z)
+    torch.cuda.synchronize()
+    zc = z.cpu().numpy()
+    groups = {}
+    for k, (f, bx, by, w, h, th, tv) in enumerate(meta):
+        groups.setdefault((f, w, h, th, tv), []).append(k)
+    for (f, w, h, th, tv), ks in groups.items():
+        ah, av = type_axis(params, th, w), type_axis(params, tv, h)
+        def blk(buf, off, stride):
+            return np.stack([buf[o + np.arange(h)[:, None] * stride + np.arange(w)[None, :]] for o in off])
+        xin = blk(src, [int(desc["in_off"][k]) for k in ks], int(desc["in_stride"][ks[0]]))
+        got = blk(yc, [int(desc["out_off"][k]) for k in ks], 512)
+        assert (got == F.fwd2d(xin, ah, av)).all(), f"forward frame {f} {w}x{h} types {th},{tv}"
+        gi = blk(zc, [int(desc["in_off"][k]) for k in ks], int(desc["in_stride"][ks[0]]))
+        assert (gi == F.inv2d(got, ah, av)).all(), f"inverse frame {f} {w}x{h} types {th},{tv}"
