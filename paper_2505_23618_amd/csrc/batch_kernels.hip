@@ -413,6 +413,8 @@ TA_DEV void dma_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
 // window); dma_wait() and the tile barrier order them.  No other code of
 // these kernels uses M0.
 TA_DEV uint32_t lds_addr(const void* p) { return __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void*)p); }
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"   // M0 is reserved: it is named as clobbered on purpose
 TA_DEV void dma16(const void* base, uint32_t voff, uint32_t lds) {
   asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(base), "s"(lds)
                : "memory", "m0");
@@ -421,6 +423,7 @@ TA_DEV void dma4(const void* base, uint32_t voff, uint32_t lds) {
   asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %0, %1" ::"v"(voff), "s"(base), "s"(lds)
                : "memory", "m0");
 }
+#pragma clang diagnostic pop
 
 // The thread index, rebuilt where it is used from the wave's base (a scalar)
 // and the lane number (computed in place by an opaque instruction pair), so

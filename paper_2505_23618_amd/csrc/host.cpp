@@ -887,52 +887,43 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
   return TA_OK;
 }
 
-// Group the plan's blocks by (frame region of 2^region_log2 input elements,
-// size, class) and cut the groups into tiles; regions go round-robin to the
-// XCD lists, and within a region the tiles are listed by the position of
-// their first block.  Replaces the
-// plan's device descriptor and tile arrays (synchronous, allocates).
+// Cut the plan's blocks into tiles: frame regions of 2^region_log2 input
+// elements go round-robin to the XCD lists, an XCD's blocks are grouped by
+// (size, class, strides) and cut into tiles of consecutive positions, and
+// each list is ordered by tile position.  Replaces the plan's device
+// descriptor, delta and tile arrays (synchronous, allocates).
 int build_tiles(ta_plan* plan, int region_log2) {
-  typedef std::tuple<int64_t, int, int, uint32_t, int32_t, int32_t> Key;   // region, log2w, log2h, class, strides
-  std::map<Key, std::vector<int64_t>> groups;
+  // regions (by input offset) go round-robin to the XCDs; an XCD's blocks are
+  // grouped by (size, class, strides) across its regions, so that a group
+  // leaves at most one partial tile, and each group is ordered by position
   const int64_t n = plan->nblocks;
+  std::map<int64_t, int> region_xcd;
+  for (int64_t i = 0; i < n; ++i) region_xcd.emplace(plan->host[(size_t)i].in_off >> region_log2, 0);
+  {
+    int r = 0;
+    for (auto& kv : region_xcd) kv.second = r++ % ta::kXcds;
+  }
+  typedef std::tuple<int, int, int, uint32_t, int32_t, int32_t> Key;   // xcd, log2w, log2h, class, strides
+  std::map<Key, std::vector<int64_t>> groups;
   for (int64_t i = 0; i < n; ++i) {
     const ta_block& b = plan->host[(size_t)i];
-    groups[Key{b.in_off >> region_log2, b.log2w, b.log2h, plan->cls[(size_t)i], b.in_stride, b.out_stride}].push_back(i);
+    groups[Key{region_xcd[b.in_off >> region_log2], b.log2w, b.log2h, plan->cls[(size_t)i], b.in_stride,
+               b.out_stride}]
+        .push_back(i);
   }
-  std::vector<Key> keys;
-  for (auto& kv : groups) keys.push_back(kv.first);
-  std::stable_sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
-    if (std::get<0>(x) != std::get<0>(y)) return std::get<0>(x) < std::get<0>(y);
-    return std::get<1>(x) + std::get<2>(x) > std::get<1>(y) + std::get<2>(y);
-  });
   std::vector<ta_block> ordered;
   std::vector<int32_t> deltas;
-  std::vector<ta::BatchTile> lists[ta::kXcds];
+  // each XCD's tiles with the position of their first block
+  std::vector<std::pair<int64_t, ta::BatchTile>> lists[ta::kXcds];
   ordered.reserve((size_t)n);
   deltas.reserve(2 * (size_t)n);
-  std::map<int64_t, int> region_xcd;
-  // the tiles of one region, listed by the frame position of their first
-  // block: tiles of different sizes and classes that share cache lines run
-  // at about the same time on the region's XCD
-  std::vector<std::pair<int64_t, ta::BatchTile>> pending;
-  int pending_xcd = 0;
-  auto flush_region = [&]() {
-    std::stable_sort(pending.begin(), pending.end(),
-                     [](const std::pair<int64_t, ta::BatchTile>& x, const std::pair<int64_t, ta::BatchTile>& y) {
-                       return x.first < y.first;
-                     });
-    for (const auto& pt : pending) lists[pending_xcd].push_back(pt.second);
-    pending.clear();
-  };
-  for (const Key& k : keys) {
-    const int64_t region = std::get<0>(k);
-    if (!region_xcd.count(region)) {
-      flush_region();
-      const int next = (int)region_xcd.size() % ta::kXcds;
-      region_xcd[region] = next;
-      pending_xcd = next;
-    }
+  for (auto& kv : groups) {
+    const Key& k = kv.first;
+    auto& idx = kv.second;
+    std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+      return plan->host[(size_t)x].in_off < plan->host[(size_t)y].in_off;
+    });
+    const int xcd = std::get<0>(k);
     const int lw = std::get<1>(k), lh = std::get<2>(k);
     const int32_t in_stride = std::get<4>(k), out_stride = std::get<5>(k);
     const bool f32 = plan->dtype == TA_F32;
@@ -940,7 +931,6 @@ int build_tiles(ta_plan* plan, int region_log2) {
                                              : f32 ? ta::BatchGeoF32::nb_for(lw, lh) : ta::BatchGeo::nb_planned(lw, lh));
     const uint32_t ci = std::get<3>(k);
     const ta_plan::Class& cl = plan->classes[ci];
-    const auto& idx = groups[k];
     // a tile's blocks lie within 2^30 input elements of its base, counting
     // each block's extent, and within 2^31 output elements (int32 deltas)
     const int64_t ext_in = (int64_t)((1 << lh) - 1) * in_stride + (1 << lw);
@@ -980,7 +970,7 @@ int build_tiles(ta_plan* plan, int region_log2) {
         t.pv_f = static_cast<const uint32_t*>(cl.rv.pf);
         t.pv_i = static_cast<const uint32_t*>(cl.rv.pi);
       }
-      pending.push_back({in_lo, t});
+      lists[xcd].push_back({in_lo, t});
       for (size_t j = s; j < e; ++j) {
         const ta_block& b = plan->host[(size_t)idx[j]];
         ordered.push_back(b);
@@ -990,11 +980,16 @@ int build_tiles(ta_plan* plan, int region_log2) {
       s = e;
     }
   }
-  flush_region();
+  // an XCD's tiles by position: tiles of different sizes and classes that
+  // share cache lines run at about the same time on that XCD
   std::vector<ta::BatchTile> tiles;
   for (int x = 0; x < ta::kXcds; ++x) {
+    std::stable_sort(lists[x].begin(), lists[x].end(),
+                     [](const std::pair<int64_t, ta::BatchTile>& a, const std::pair<int64_t, ta::BatchTile>& b) {
+                       return a.first < b.first;
+                     });
     plan->xstart[x] = (int64_t)tiles.size();
-    tiles.insert(tiles.end(), lists[x].begin(), lists[x].end());
+    for (const auto& pt : lists[x]) tiles.push_back(pt.second);
   }
   plan->xstart[ta::kXcds] = (int64_t)tiles.size();
   if (tiles.size() > (size_t)INT32_MAX) return fail(TA_EUNSUPPORTED, "more than 2^31 tiles");
