@@ -14,8 +14,8 @@
 // pass walks the layers in reverse, recovering each layer's input by the
 // transposed rotation (orthogonal, so nothing is stored), and sums each
 // angle's gradient over the columns, first within a thread, then with
-// shuffles across the slot's consecutive lanes, in a fixed order.  Up to
-// N = 16 a candidate is a single wave, whose steps need no barrier.
+// shuffles across the slot's consecutive lanes, in a fixed order.  (N = 32;
+// the smaller sizes run design_search_reg below.)
 // Everything is FP64.
 #include <math.h>
 
@@ -281,8 +281,10 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a
 
 
 // ---------------------------------------------------------------------------
-// One-wave candidates (N <= 16) with the matrices of the layer chain in
-// registers.  Thread t is (slot r, column group jg) = (t mod N/2, t div N/2),
+// Candidates of N <= 16 with the matrices of the layer chain in registers
+// (two columns a thread at N = 16, one wave a candidate: the second column
+// gives each thread independent work between the dependent steps, which
+// measured faster than one column a thread on twice the waves).  Thread t is (slot r, column group jg) = (t mod N/2, t div N/2),
 // so the N/2 slots of a column group are consecutive lanes inside one 16-lane
 // DPP row.  An even layer rotates rows (2r, 2r+1), both the thread's own; an
 // odd layer rotates rows (2r+1, 2r+2), and the row owned by the next slot
@@ -303,19 +305,25 @@ __device__ inline double dpp_f64(double x) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
+// (three waves per SIMD: the 3,072 waves of the N = 16 study are resident at once)
 template <int N, int CW>
-__global__ __launch_bounds__((N / 2) * (N / CW)) void design_search_reg(DesignArgs a) {
+__global__ __launch_bounds__((N / 2) * (N / CW)) void design_search_reg(
+    DesignArgs a) {
   constexpr int HN = N / 2;                  // pair slots
   constexpr int NC = N / CW;                 // column groups (threads per slot)
   constexpr int T = HN * NC;
-  static_assert(T <= 64 && 16 % HN == 0, "one wave, slots inside a DPP row");
+  static_assert((T <= 1024 && T % 64 == 0) || T < 64, "whole waves, or one partial wave");
+  static_assert(16 % HN == 0, "the slots of a column group inside one DPP row");
   constexpr int NA = N * (N - 1) / 2;
   constexpr int LP = N + (12 - N % 8) % 8;   // row pitch 4 mod 8 doubles
   static_assert(LP % 8 == 4, "row pitch");
   __shared__ double Ms[N * LP], Bs[N * LP], Xs[N * LP];
-  __shared__ double th[NA], mo[NA], ve[NA], cs_c[NA], cs_s[NA], gr[NA];
+  // cs_c / cs_s hold one more entry, the identity rotation (1, 0), which the
+  // threads of a missing pair slot (the ends of an odd layer) apply: the
+  // layers then run without selects
+  __shared__ double th[NA], mo[NA], ve[NA], cs_c[NA + 1], cs_s[NA + 1], gr[NA];
   __shared__ double terms[NA * NC];          // angle-gradient term of each (angle, column group)
-  __shared__ double part[2];
+  __shared__ double part[T >= 64 ? 2 * (T / 64) : 2];   // per-wave objective partials
   __shared__ int bad;
 
   const int cand = blockIdx.x;
@@ -354,6 +362,10 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search_reg(DesignAr
     mo[k] = 0.0;
     ve[k] = 0.0;
   }
+  if (t == 0) {
+    cs_c[NA] = 1.0;
+    cs_s[NA] = 0.0;
+  }
   const double alpha = log(100.0) / N;
   const double w0 = exp(-alpha * i0), w1 = exp(-alpha * i1);
   double b1t = 1.0, b2t = 1.0;   // beta1^t, beta2^t
@@ -383,21 +395,17 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search_reg(DesignAr
           m1[q] = ss * u0 + cc * u1;
         }
       } else {
-        double below[CW], above[CW];
+        // straight-line code so that the angle loads of later layers can be
+        // issued early; a missing slot rotates by the identity entry
+        const int ku = r + 1 < HN ? k : NA, kl = r >= 1 ? k - 1 : NA;   // upper row of slot r, lower of r - 1
+        const double cu = cs_c[ku], su = cs_s[ku], cl = cs_c[kl], sl = cs_s[kl];
 #pragma unroll
         for (int q = 0; q < CW; ++q) {
-          below[q] = dpp_f64<kRowShl1>(m0[q]);   // row 2r + 2
-          above[q] = dpp_f64<kRowShr1>(m1[q]);   // row 2r - 1
-        }
-        if (r + 1 < HN) {                        // upper row of pair slot r
-          const double cc = cs_c[k], ss = cs_s[k];
-#pragma unroll
-          for (int q = 0; q < CW; ++q) m1[q] = cc * m1[q] - ss * below[q];
-        }
-        if (r >= 1) {                            // lower row of pair slot r - 1
-          const double cc = cs_c[k - 1], ss = cs_s[k - 1];
-#pragma unroll
-          for (int q = 0; q < CW; ++q) m0[q] = ss * above[q] + cc * m0[q];
+          const double below = dpp_f64<kRowShl1>(m0[q]);   // row 2r + 2
+          const double above = dpp_f64<kRowShr1>(m1[q]);   // row 2r - 1
+          const double n1 = cu * m1[q] - su * below, n0 = sl * above + cl * m0[q];
+          m1[q] = n1;
+          m0[q] = n0;
         }
       }
     }
@@ -459,16 +467,21 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search_reg(DesignAr
           er += __shfl_xor(er, m);
         }
       }
-      if (t == 0) {
-        part[0] = sp;
-        part[1] = er;
+      if ((t & 63) == 0) {
+        part[2 * (t >> 6)] = sp;
+        part[2 * (t >> 6) + 1] = er;
       }
     }
     group_sync<T>();
     if (last && t == 0) {
-      a.obj[3 * (int64_t)cand] = a.lam * part[0] + part[1];
-      a.obj[3 * (int64_t)cand + 1] = part[0];
-      a.obj[3 * (int64_t)cand + 2] = part[1];
+      double sps = 0.0, ers = 0.0;
+      for (int w = 0; w < (T + 63) / 64; ++w) {
+        sps += part[2 * w];
+        ers += part[2 * w + 1];
+      }
+      a.obj[3 * (int64_t)cand] = a.lam * sps + ers;
+      a.obj[3 * (int64_t)cand + 1] = sps;
+      a.obj[3 * (int64_t)cand + 2] = ers;
     }
     // adjoint of M = G J at (i, j): lam phi'(M) + (B^T X or X B^T), then times J
     double g0[CW], g1[CW];
@@ -517,34 +530,22 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search_reg(DesignAr
         }
         terms[k * NC + jg] = term;
       } else {
-        double bm_[CW], bg_[CW], am_[CW], ag_[CW];
+        const bool up = r + 1 < HN;             // upper row of slot r; lower row of slot r - 1 if r >= 1
+        const int ku = up ? k : NA, kl = r >= 1 ? k - 1 : NA;
+        const double cu = cs_c[ku], su = cs_s[ku], cl = cs_c[kl], sl = cs_s[kl];
+        double term = 0.0;
 #pragma unroll
         for (int q = 0; q < CW; ++q) {
-          bm_[q] = dpp_f64<kRowShl1>(m0[q]);     // rows 2r + 2 of M and of the adjoint
-          bg_[q] = dpp_f64<kRowShl1>(g0[q]);
-          am_[q] = dpp_f64<kRowShr1>(m1[q]);     // rows 2r - 1
-          ag_[q] = dpp_f64<kRowShr1>(g1[q]);
+          const double bm_ = dpp_f64<kRowShl1>(m0[q]), bg_ = dpp_f64<kRowShl1>(g0[q]);   // rows 2r + 2
+          const double am_ = dpp_f64<kRowShr1>(m1[q]), ag_ = dpp_f64<kRowShr1>(g1[q]);   // rows 2r - 1
+          const double vp = m1[q], gp = g1[q];
+          term += -gp * bm_ + bg_ * vp;
+          m1[q] = cu * vp + su * bm_;
+          g1[q] = cu * gp + su * bg_;
+          m0[q] = -sl * am_ + cl * m0[q];
+          g0[q] = -sl * ag_ + cl * g0[q];
         }
-        if (r + 1 < HN) {                        // upper row of pair slot r
-          const double cc = cs_c[k], ss = cs_s[k];
-          double term = 0.0;
-#pragma unroll
-          for (int q = 0; q < CW; ++q) {
-            const double vp = m1[q], vq = bm_[q], gp = g1[q], gq = bg_[q];
-            term += -gp * vq + gq * vp;
-            m1[q] = cc * vp + ss * vq;
-            g1[q] = cc * gp + ss * gq;
-          }
-          terms[k * NC + jg] = term;
-        }
-        if (r >= 1) {                            // lower row of pair slot r - 1
-          const double cc = cs_c[k - 1], ss = cs_s[k - 1];
-#pragma unroll
-          for (int q = 0; q < CW; ++q) {
-            m0[q] = -ss * am_[q] + cc * m0[q];
-            g0[q] = -ss * ag_[q] + cc * g0[q];
-          }
-        }
+        if (up) terms[k * NC + jg] = term;
       }
     }
     group_sync<T>();
