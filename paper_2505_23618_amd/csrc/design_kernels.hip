@@ -8,14 +8,18 @@
 // order layer by layer) and J = diag(sigma, 1, ..., 1).  Each candidate runs
 // `steps` Adam updates and a final evaluation inside one launch.
 //
-// One workgroup per candidate: thread (r, g) = (pair slot, column group)
-// owns rows 2r, 2r+1 of its columns of every N x N matrix in LDS.  A layer
-// rotates rows (p, p+1), p = (l mod 2) + 2r, of each column.  The backward
-// pass walks the layers in reverse, recovering each layer's input by the
-// transposed rotation (orthogonal, so nothing is stored), and sums each
-// angle's gradient over the columns, first within a thread, then with
-// shuffles across the slot's consecutive lanes, in a fixed order.  (N = 32;
-// the smaller sizes run design_search_reg below.)
+// One workgroup per candidate; thread t is (pair slot r, column group jg) =
+// (t mod N/2, t div N/2) and owns rows 2r, 2r+1 of its CW columns (jg + q N/CW).
+// The N/2 slots of a column group are consecutive lanes inside one 16-lane
+// DPP row, so the matrices of the layer chain stay in registers: an even
+// layer rotates rows (2r, 2r+1), both the thread's own; an odd layer rotates
+// rows (2r+1, 2r+2), and the row owned by the next slot arrives by a
+// row_shl:1 DPP move (row 2r-1 of the previous slot by row_shr:1).  The 2N
+// layers of a step (forward, and backward recovering each layer's input by
+// the transposed rotation, orthogonal so nothing is stored) touch no LDS.
+// LDS holds what is shared: the products with B (M and the error adjoint X),
+// the angle tables, and each thread's angle-gradient terms, summed per angle
+// over the column groups in a fixed order once the backward pass is done.
 // Everything is FP64.
 #include <math.h>
 
@@ -32,14 +36,6 @@ __device__ inline int layer_start(int l) {
   return (l >> 1) * (N - 1) + ((l & 1) ? N / 2 : 0);
 }
 
-// sum over the NC consecutive lanes of one slot (NC divides 64), fixed order
-template <int NC>
-__device__ inline double slot_sum(double v) {
-#pragma unroll
-  for (int m = NC / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, NC);
-  return v;
-}
-
 // Workgroup-wide barrier; a one-wave workgroup only needs its LDS traffic
 // ordered, which a wavefront-scope fence gives.
 template <int T>
@@ -53,246 +49,9 @@ __device__ inline void group_sync() {
   }
 }
 
-// CW columns per thread: thread (r, g) owns rows 2r, 2r+1 of the columns
-// g + k N / CW, k < CW, so that N = 16 fits one wave (CW = 2)
-template <int N, int CW>
-__global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a) {
-  constexpr int NC = N / CW;                 // threads per slot
-  constexpr int T = (N / 2) * NC;
-  constexpr int NA = N * (N - 1) / 2;
-  // N x N matrices in LDS with a row pitch LP = 4 mod 8 doubles.  The LDS
-  // serves 64-bit accesses 16 lanes at a time; 16 consecutive lanes are at
-  // most two pair slots r, r + 1, whose rows 2r and 2r + 2 are then 4 LP = 16
-  // mod 32 dwords apart: the slots' column runs (layer updates) and their
-  // same-column reads of rows 2r fall in distinct banks.
-  constexpr int LP = N + (12 - N % 8) % 8;
-  static_assert(LP % 8 == 4, "row pitch");
-  __shared__ double Ms[N * LP], Gs[N * LP], Bs[N * LP], Xs[N * LP];
-  __shared__ double th[NA], mo[NA], ve[NA], cs_c[NA], cs_s[NA], gr[NA];
-  __shared__ double red[T / 64 > 0 ? 2 * (T / 64) : 2];
-  __shared__ int bad;
-
-  const int cand = blockIdx.x;
-  const int t = threadIdx.x, r = t / NC, jg = t % NC;
-  const int i0 = 2 * r, i1 = 2 * r + 1;   // rows owned in each of the thread's columns
-
-  if (t == 0) {
-    const int* c = a.cands + 4 * (int64_t)cand;
-    const int b = c[0], d = c[1], mode = c[2], sg = c[3];
-    bad = (b < 0 || b >= a.nmat || d < 0 || d >= a.nmat || (mode != 0 && mode != 1) || (sg != 1 && sg != -1));
-  }
-  group_sync<T>();
-  if (bad) {
-    if (t == 0) {
-      const double nan = __builtin_nan("");
-      for (int k = 0; k < 3; ++k) a.obj[3 * (int64_t)cand + k] = nan;
-    }
-    return;
-  }
-  const int* c = a.cands + 4 * (int64_t)cand;
-  const int mode = c[2];
-  const double sigma = (double)c[3];
-  const double* bm = a.mats + (int64_t)c[0] * N * N;
-  const double* dm = a.mats + (int64_t)c[1] * N * N;
-  double* theta = a.theta + (int64_t)cand * NA;
-  for (int k = t; k < N * N; k += T) Bs[(k / N) * LP + k % N] = bm[k];
-  double d0[CW], d1[CW];
-#pragma unroll
-  for (int q = 0; q < CW; ++q) {
-    const int j = jg + q * NC;
-    d0[q] = dm[i0 * N + j];
-    d1[q] = dm[i1 * N + j];
-  }
-  for (int k = t; k < NA; k += T) {
-    th[k] = theta[k];
-    mo[k] = 0.0;
-    ve[k] = 0.0;
-  }
-  const double alpha = log(100.0) / N;
-  const double w0 = exp(-alpha * i0), w1 = exp(-alpha * i1);
-  double b1t = 1.0, b2t = 1.0;   // beta1^t, beta2^t
-  group_sync<T>();
-
-  for (int step = 0; step <= a.steps; ++step) {
-    const bool last = step == a.steps;
-    for (int k = t; k < NA; k += T) sincos(th[k], &cs_s[k], &cs_c[k]);
-#pragma unroll
-    for (int q = 0; q < CW; ++q) {
-      const int j = jg + q * NC;
-      Ms[i0 * LP + j] = (i0 == j) ? 1.0 : 0.0;
-      Ms[i1 * LP + j] = (i1 == j) ? 1.0 : 0.0;
-    }
-    group_sync<T>();
-    // forward: M = G_{N-1} ... G_0 I
-    for (int l = 0; l < N; ++l) {
-      const int p = (l & 1) + 2 * r;
-      if (p + 1 < N) {
-        const int k = layer_start<N>(l) + r;
-        const double cc = cs_c[k], ss = cs_s[k];
-#pragma unroll
-        for (int q = 0; q < CW; ++q) {
-          const int j = jg + q * NC;
-          const double up = Ms[p * LP + j], uq = Ms[(p + 1) * LP + j];
-          Ms[p * LP + j] = cc * up - ss * uq;
-          Ms[(p + 1) * LP + j] = ss * up + cc * uq;
-        }
-      }
-      group_sync<T>();
-    }
-    // M = G J, J = diag(sigma, 1, ...): kept as G in Ms; the J factor is
-    // applied where M is read (column 0 times sigma).  Per column: H rows
-    // i0, i1, the error and its adjoint 2 w (H - D)
-    double m0[CW], m1[CW], sp = 0.0, er = 0.0;
-#pragma unroll
-    for (int q = 0; q < CW; ++q) {
-      const int j = jg + q * NC;
-      const double js = j == 0 ? sigma : 1.0;
-      double h0 = 0.0, h1 = 0.0;
-      if (mode == 0) {   // H = B M
-#pragma unroll 8
-        for (int k = 0; k < N; ++k) {
-          const double mk = Ms[k * LP + j];
-          h0 += Bs[i0 * LP + k] * mk;
-          h1 += Bs[i1 * LP + k] * mk;
-        }
-        h0 *= js;
-        h1 *= js;
-      } else {           // H = M B: H[i][j] = sum_k M[i][k] B[k][j], M[i][0] scaled by sigma
-#pragma unroll 8
-        for (int k = 0; k < N; ++k) {
-          const double bk = Bs[k * LP + j];
-          const double sk = k == 0 ? sigma : 1.0;
-          h0 += sk * Ms[i0 * LP + k] * bk;
-          h1 += sk * Ms[i1 * LP + k] * bk;
-        }
-      }
-      const double e0 = h0 - d0[q], e1 = h1 - d1[q];
-      m0[q] = js * Ms[i0 * LP + j];   // entries of M = G J
-      m1[q] = js * Ms[i1 * LP + j];
-      if (last) {
-        sp += m0[q] * m0[q] / (kSparseEps + fabs(m0[q])) + m1[q] * m1[q] / (kSparseEps + fabs(m1[q]));
-        er += w0 * e0 * e0 + w1 * e1 * e1;
-        if (a.adj) {
-          double* out = a.adj + (int64_t)cand * N * N;
-          out[i0 * N + j] = m0[q];
-          out[i1 * N + j] = m1[q];
-        }
-      }
-      Xs[i0 * LP + j] = 2.0 * w0 * e0;
-      Xs[i1 * LP + j] = 2.0 * w1 * e1;
-    }
-    if (last) {
-      // objective: sparsity of M and weighted error, reduced in a fixed order
-#pragma unroll
-      for (int m = 32; m > 0; m >>= 1) {
-        if (m < T) {
-          sp += __shfl_xor(sp, m);
-          er += __shfl_xor(er, m);
-        }
-      }
-      if ((t & 63) == 0) {
-        red[2 * (t >> 6)] = sp;
-        red[2 * (t >> 6) + 1] = er;
-      }
-    }
-    group_sync<T>();
-    if (last && t == 0) {
-      double sps = 0.0, ers = 0.0;
-      for (int w = 0; w < (T + 63) / 64; ++w) {
-        sps += red[2 * w];
-        ers += red[2 * w + 1];
-      }
-      a.obj[3 * (int64_t)cand] = a.lam * sps + ers;
-      a.obj[3 * (int64_t)cand + 1] = sps;
-      a.obj[3 * (int64_t)cand + 2] = ers;
-    }
-    // adjoint of M = G J at (i, j): lam phi'(M) + (B^T X or X B^T), then times J
-#pragma unroll
-    for (int q = 0; q < CW; ++q) {
-      const int j = jg + q * NC;
-      const double js = j == 0 ? sigma : 1.0;
-      double g0 = 0.0, g1 = 0.0;
-      if (mode == 0) {   // dM = B^T X: dM[i][j] = sum_k B[k][i] X[k][j]
-#pragma unroll 8
-        for (int k = 0; k < N; ++k) {
-          const double xk = Xs[k * LP + j];
-          g0 += Bs[k * LP + i0] * xk;
-          g1 += Bs[k * LP + i1] * xk;
-        }
-      } else {           // dM = X B^T: dM[i][j] = sum_k X[i][k] B[j][k]
-#pragma unroll 8
-        for (int k = 0; k < N; ++k) {
-          const double bj = Bs[j * LP + k];
-          g0 += Xs[i0 * LP + k] * bj;
-          g1 += Xs[i1 * LP + k] * bj;
-        }
-      }
-      const double a0 = fabs(m0[q]), a1 = fabs(m1[q]);
-      g0 += a.lam * m0[q] * (2.0 * kSparseEps + a0) / ((kSparseEps + a0) * (kSparseEps + a0));
-      g1 += a.lam * m1[q] * (2.0 * kSparseEps + a1) / ((kSparseEps + a1) * (kSparseEps + a1));
-      Gs[i0 * LP + j] = js * g0;
-      Gs[i1 * LP + j] = js * g1;
-    }
-    group_sync<T>();
-    // backward through the layers: angle gradient from each layer's outputs,
-    // then step both the activations and the adjoint back through it
-    for (int l = N - 1; l >= 0; --l) {
-      const int p = (l & 1) + 2 * r;
-      const bool valid = p + 1 < N;
-      const int k = layer_start<N>(l) + r;
-      double contrib = 0.0;
-      if (valid) {
-        const double cc = cs_c[k], ss = cs_s[k];
-#pragma unroll
-        for (int q = 0; q < CW; ++q) {
-          const int j = jg + q * NC;
-          const double vp = Ms[p * LP + j], vq = Ms[(p + 1) * LP + j];
-          const double gp = Gs[p * LP + j], gq = Gs[(p + 1) * LP + j];
-          contrib += -gp * vq + gq * vp;
-          Ms[p * LP + j] = cc * vp + ss * vq;
-          Ms[(p + 1) * LP + j] = -ss * vp + cc * vq;
-          Gs[p * LP + j] = cc * gp + ss * gq;
-          Gs[(p + 1) * LP + j] = -ss * gp + cc * gq;
-        }
-      }
-      const double sum = slot_sum<NC>(contrib);
-      if (valid && jg == 0) gr[k] = sum;
-      group_sync<T>();
-    }
-    if (last) break;
-    // Adam (Kingma and Ba) with bias correction
-    b1t *= a.beta1;
-    b2t *= a.beta2;
-    for (int k = t; k < NA; k += T) {
-      const double g = gr[k];
-      mo[k] = a.beta1 * mo[k] + (1.0 - a.beta1) * g;
-      ve[k] = a.beta2 * ve[k] + (1.0 - a.beta2) * g * g;
-      const double mh = mo[k] / (1.0 - b1t);
-      const double vh = ve[k] / (1.0 - b2t);
-      th[k] -= a.lr * mh / (sqrt(vh) + a.eps);
-    }
-    group_sync<T>();
-  }
-  for (int k = t; k < NA; k += T) {
-    theta[k] = th[k];
-    if (a.grad) a.grad[(int64_t)cand * NA + k] = gr[k];
-  }
-}
-
-
-// ---------------------------------------------------------------------------
-// Candidates of N <= 16 with the matrices of the layer chain in registers
-// (two columns a thread at N = 16, one wave a candidate: the second column
-// gives each thread independent work between the dependent steps, which
-// measured faster than one column a thread on twice the waves).  Thread t is (slot r, column group jg) = (t mod N/2, t div N/2),
-// so the N/2 slots of a column group are consecutive lanes inside one 16-lane
-// DPP row.  An even layer rotates rows (2r, 2r+1), both the thread's own; an
-// odd layer rotates rows (2r+1, 2r+2), and the row owned by the next slot
-// arrives by a row_shl:1 DPP move (row 2r-1 of the previous slot by
-// row_shr:1), so the 2N layers of a step (forward and backward) touch no LDS.
-// LDS holds what is shared: the products with B (M and the error adjoint X),
-// the angle tables, and each thread's angle-gradient terms, summed per angle
-// over its column groups once the backward pass is done.
+// Two columns a thread: the second column gives each thread independent
+// work between the dependent steps of the chain, which measured faster than
+// one column a thread on twice the waves (N = 16: 3.6 against 5.3 ms).
 
 constexpr int kRowShl1 = 0x101;   // DPP: lane i reads lane i + 1 of its row
 constexpr int kRowShr1 = 0x111;   // DPP: lane i reads lane i - 1 of its row
@@ -305,24 +64,28 @@ __device__ inline double dpp_f64(double x) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// (three waves per SIMD: the 3,072 waves of the N = 16 study are resident at once)
 template <int N, int CW>
-__global__ __launch_bounds__((N / 2) * (N / CW)) void design_search_reg(
-    DesignArgs a) {
+__global__ __launch_bounds__((N / 2) * (N / CW)) void design_search(DesignArgs a) {
   constexpr int HN = N / 2;                  // pair slots
   constexpr int NC = N / CW;                 // column groups (threads per slot)
   constexpr int T = HN * NC;
   static_assert((T <= 1024 && T % 64 == 0) || T < 64, "whole waves, or one partial wave");
   static_assert(16 % HN == 0, "the slots of a column group inside one DPP row");
   constexpr int NA = N * (N - 1) / 2;
-  constexpr int LP = N + (12 - N % 8) % 8;   // row pitch 4 mod 8 doubles
-  static_assert(LP % 8 == 4, "row pitch");
+  // Row pitch N + 1 doubles: the 16 lanes an LDS access serves together are
+  // up to 16 slots r of one or two column groups, and rows 2r then start
+  // 4r dwords (mod 64) apart, in distinct banks
+  constexpr int LP = N + 1;
   __shared__ double Ms[N * LP], Bs[N * LP], Xs[N * LP];
   // cs_c / cs_s hold one more entry, the identity rotation (1, 0), which the
   // threads of a missing pair slot (the ends of an odd layer) apply: the
   // layers then run without selects
   __shared__ double th[NA], mo[NA], ve[NA], cs_c[NA + 1], cs_s[NA + 1], gr[NA];
-  __shared__ double terms[NA * NC];          // angle-gradient term of each (angle, column group)
+  // angle-gradient term of each (column group g, angle k) at g * TP + k:
+  // the slots of a group write consecutive angles, and TP = 8 mod 32 doubles
+  // puts a second group's run right after the first in the banks
+  constexpr int TP = NA + (40 - NA % 32) % 32;
+  __shared__ double terms[NC * TP];
   __shared__ double part[T >= 64 ? 2 * (T / 64) : 2];   // per-wave objective partials
   __shared__ int bad;
 
@@ -528,7 +291,7 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search_reg(
           g0[q] = cc * gp + ss * gq;
           g1[q] = -ss * gp + cc * gq;
         }
-        terms[k * NC + jg] = term;
+        terms[jg * TP + k] = term;
       } else {
         const bool up = r + 1 < HN;             // upper row of slot r; lower row of slot r - 1 if r >= 1
         const int ku = up ? k : NA, kl = r >= 1 ? k - 1 : NA;
@@ -545,7 +308,7 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search_reg(
           m0[q] = -sl * am_ + cl * m0[q];
           g0[q] = -sl * ag_ + cl * g0[q];
         }
-        if (up) terms[k * NC + jg] = term;
+        if (up) terms[jg * TP + k] = term;
       }
     }
     group_sync<T>();
@@ -553,7 +316,7 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search_reg(
     for (int k = t; k < NA; k += T) {
       double s = 0.0;
 #pragma unroll
-      for (int g = 0; g < NC; ++g) s += terms[k * NC + g];
+      for (int g = 0; g < NC; ++g) s += terms[g * TP + k];
       gr[k] = s;
     }
     if (last) break;
@@ -578,14 +341,14 @@ __global__ __launch_bounds__((N / 2) * (N / CW)) void design_search_reg(
 
 }  // namespace
 
-// threads per workgroup: (n / 2) x (n / CW); n = 16 runs two columns per
-// thread so that one candidate is one wave
+// threads per workgroup: (n / 2) x (n / CW); n = 16 and 32 run two columns
+// a thread (one wave, four waves a candidate)
 const void* design_kernel(int n, int* threads) {
   switch (n) {
-    case 4: *threads = 8; return reinterpret_cast<const void*>(&design_search_reg<4, 1>);
-    case 8: *threads = 32; return reinterpret_cast<const void*>(&design_search_reg<8, 1>);
-    case 16: *threads = 64; return reinterpret_cast<const void*>(&design_search_reg<16, 2>);
-    case 32: *threads = 512; return reinterpret_cast<const void*>(&design_search<32, 1>);
+    case 4: *threads = 8; return reinterpret_cast<const void*>(&design_search<4, 1>);
+    case 8: *threads = 32; return reinterpret_cast<const void*>(&design_search<8, 1>);
+    case 16: *threads = 64; return reinterpret_cast<const void*>(&design_search<16, 2>);
+    case 32: *threads = 256; return reinterpret_cast<const void*>(&design_search<32, 2>);
     default: return nullptr;
   }
 }
