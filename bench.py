@@ -355,6 +355,12 @@ def _subblock(ctx, ids, res):
     torch.cuda.empty_cache()
 
 
+def _tile_blocks(plan):
+    """The plan's blocks per tile, by size group (larger block side)."""
+    tb = plan.tile_blocks()
+    return {str(side): [tb[k] for k in sorted(tb) if max(k) == side] for side in (4, 8, 16, 32, 64)}
+
+
 def _batched(ctx, ids, res):
     import torch
     import synth
@@ -382,7 +388,7 @@ def _batched(ctx, ids, res):
     ui = _events_mean(lambda i: ctx.transform_inv(dev, Y[i % 4], Z[i % 4]), 12)
     res["batched_uneven"] = {"value": nco / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
                              "blocks": len(rows), "coefficients": nco, "tiles": info["tiles"], "grid": info["grid"],
-                             "region_log2": info["region_log2"],
+                             "region_log2": info["region_log2"], "tile_blocks": _tile_blocks(plan),
                              "GB/s_fwd": (4 * nco + 32 * len(rows)) / tf / 1e9,
                              "unplanned_value": nco / (uf + ui), "unplanned_fwd_us": uf * 1e6,
                              "unplanned_inv_us": ui * 1e6,
@@ -401,6 +407,7 @@ def _batched(ctx, ids, res):
     ui = _events_mean(lambda i: ctx.transform_inv(dev, Y[i % 4], Z[i % 4]), 12)
     res["batched_uneven_f32"] = {"value": nco / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
                                  "tiles": infof["tiles"], "grid": infof["grid"], "region_log2": infof["region_log2"],
+                                 "tile_blocks": _tile_blocks(planf),
                                  "GB/s_fwd": (8 * nco + 32 * len(rows)) / tf / 1e9,
                                  "unplanned_value": nco / (uf + ui), "unplanned_fwd_us": uf * 1e6,
                                  "unplanned_inv_us": ui * 1e6}

@@ -223,15 +223,23 @@ int ta_fwd_multi(ta_ctx* ctx, int param_id, int log2n, int64_t nblocks, const vo
  * (asynchronous, no allocation, capturable in a HIP graph).
  * ta_plan_autotune times the tile mappings (frame regions of 2^18 .. 2^22
  * input elements per XCD tile list) times the persistent grid sizes (256 ..
- * 8192 workgroups) on the given buffers, each launch after a 512 MiB cache
- * flush (a batch streams through HBM once per call), checks that every
- * candidate's output is bitwise identical, and keeps the fastest
- * (synchronous; allocates 512 MiB of scratch while it runs; runs the
- * forward).  ta_plan_set_tuning applies a known grid (>= 8) and region
+ * 8192 workgroups) on the given buffers, then, at the fastest of those, the
+ * blocks per tile of each size group (blocks whose larger side is 4, 8, 16,
+ * 32 or 64: the kernels' maximum, half of it or a quarter, one group after
+ * the other), each launch after a 512 MiB cache flush (a batch streams
+ * through HBM once per call); it checks that every candidate's output is
+ * bitwise identical and keeps the fastest (synchronous; allocates 512 MiB of
+ * scratch while it runs; runs the forward).  ta_plan_set_tuning applies a known grid (>= 8) and region
  * (log2 input elements, 12..40) without timing (synchronous).  Both rewrite
  * the plan's device tile list in place: launches captured in a HIP graph
  * before must be captured again.  ta_plan_tuning reports the grid and
- * region in use.  Blocks must not overlap in `out`.  A plan runs only with
+ * region in use.  ta_plan_tile_blocks reports how many blocks of size
+ * 2^log2w x 2^log2h (log2 sizes 2..6) one tile holds at most, and
+ * ta_plan_set_tile_blocks sets it: 1 .. the kernels' maximum for that size
+ * and dtype, or 0 for that maximum (synchronous; rebuilds the tile list like
+ * ta_plan_set_tuning; TA_EINVAL outside those ranges).  Fewer blocks per tile
+ * give more, smaller tiles: better balance across the grid, less overlap of
+ * one tile's loads with the previous tile's arithmetic.  Blocks must not overlap in `out`.  A plan runs only with
  * the context that created it (TA_EINVAL otherwise) and must be destroyed
  * before that context: its tiles point into the context's parameter
  * tables. */
@@ -248,6 +256,8 @@ int ta_plan_inv(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream
 int ta_plan_autotune(ta_ctx* ctx, ta_plan* plan, const void* in, void* out, ta_stream_t stream, int reps);
 int ta_plan_tuning(const ta_plan* plan, int* grid, int* region_log2);
 int ta_plan_set_tuning(ta_plan* plan, int grid, int region_log2);
+int ta_plan_tile_blocks(const ta_plan* plan, int log2w, int log2h, int* blocks);
+int ta_plan_set_tile_blocks(ta_plan* plan, int log2w, int log2h, int blocks);
 
 /* Unplanned block lists.  ta_transform_fwd / _inv run nblocks descriptors
  * that are already in device memory (blocks_dev, 8-byte aligned, read as

@@ -40,7 +40,8 @@ EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis
            "ta_fwd_multi", "ta_coef_stats_workspace", "ta_coef_stats", "ta_design_search",
            "ta_transform_fwd", "ta_transform_inv", "ta_validate_blocks", "ta_set_axis_cfg", "ta_set_params",
            "ta_plan_tuning", "ta_plan_set_tuning", "ta_plan_extents", "ta_givens_bwd_noalloc",
-           "ta_int_table", "ta_set_band_angles", "ta_set_post_angles", "ta_transform_bwd")
+           "ta_int_table", "ta_set_band_angles", "ta_set_post_angles", "ta_transform_bwd",
+           "ta_plan_tile_blocks", "ta_plan_set_tile_blocks")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -98,6 +99,8 @@ def lib() -> ctypes.CDLL:
     L.ta_plan_autotune.argtypes = [vp, vp, vp, vp, vp, i32]
     L.ta_plan_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.ta_plan_set_tuning.argtypes = [vp, i32, i32]
+    L.ta_plan_tile_blocks.argtypes = [vp, i32, i32, ctypes.POINTER(i32)]
+    L.ta_plan_set_tile_blocks.argtypes = [vp, i32, i32, i32]
     L.ta_plan_extents.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.ta_givens_workspace.argtypes = [i64, ctypes.POINTER(i64)]
     L.ta_givens_fwd.argtypes = [vp, i32, i32, i32, vp, i64, vp, vp, vp]
@@ -477,6 +480,23 @@ class Plan:
 
     def set_tuning(self, grid: int, region_log2: int):
         _check(lib().ta_plan_set_tuning(self._h, grid, region_log2))
+        return self.info()
+
+    def tile_blocks(self):
+        """Blocks per tile for each block size {(w, h): n} (the plan's choice)."""
+        n = ctypes.c_int()
+        res = {}
+        for lw in range(2, 7):
+            for lh in range(2, 7):
+                _check(lib().ta_plan_tile_blocks(self._h, lw, lh, ctypes.byref(n)))
+                res[(1 << lw, 1 << lh)] = n.value
+        return res
+
+    def set_tile_blocks(self, w: int, h: int, blocks: int):
+        """Blocks per tile for w x h blocks (0: the kernels' maximum)."""
+        _check_side(w)
+        _check_side(h)
+        _check(lib().ta_plan_set_tile_blocks(self._h, w.bit_length() - 1, h.bit_length() - 1, blocks))
         return self.info()
 
     def autotune(self, x, out, reps: int = 3):

@@ -820,6 +820,7 @@ struct ta_plan {
   ta::BatchTile* tiles_dev = nullptr;
   int64_t max_in_elem = 0, max_out_elem = 0;   // extents touched (for validation)
   int64_t xstart[ta::kXcds + 1] = {};            // per-XCD tile lists
+  int tile_blocks[7][7] = {};                    // blocks per tile by (log2 w, log2 h); 0: the kernels' maximum
 };
 
 namespace {
@@ -887,6 +888,19 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
   return TA_OK;
 }
 
+// The most blocks a tile of size (lw, lh) holds in the plan's kernel.
+int max_tile_blocks(const ta_plan* plan, int lw, int lh) {
+  const bool f32 = plan->dtype == TA_F32;
+  return plan->general ? ta::GenGeo::nb_for(lw, lh, f32)
+                       : f32 ? ta::BatchGeoF32::nb_for(lw, lh) : ta::BatchGeo::nb_planned(lw, lh);
+}
+
+// Blocks per tile for size (lw, lh): the per-size choice, else the maximum.
+int tile_blocks(const ta_plan* plan, int lw, int lh) {
+  const int m = max_tile_blocks(plan, lw, lh), c = plan->tile_blocks[lw][lh];
+  return c > 0 && c < m ? c : m;
+}
+
 // Cut the plan's blocks into tiles: frame regions of 2^region_log2 input
 // elements go round-robin to the XCD lists, an XCD's blocks are grouped by
 // (size, class, strides) and cut into tiles of consecutive positions, and
@@ -926,9 +940,7 @@ int build_tiles(ta_plan* plan, int region_log2) {
     const int xcd = std::get<0>(k);
     const int lw = std::get<1>(k), lh = std::get<2>(k);
     const int32_t in_stride = std::get<4>(k), out_stride = std::get<5>(k);
-    const bool f32 = plan->dtype == TA_F32;
-    const size_t nb = (size_t)(plan->general ? ta::GenGeo::nb_for(lw, lh, f32)
-                                             : f32 ? ta::BatchGeoF32::nb_for(lw, lh) : ta::BatchGeo::nb_planned(lw, lh));
+    const size_t nb = (size_t)tile_blocks(plan, lw, lh);
     const uint32_t ci = std::get<3>(k);
     const ta_plan::Class& cl = plan->classes[ci];
     // a tile's blocks lie within 2^30 input elements of its base, counting
@@ -1141,48 +1153,99 @@ int ta_plan_autotune(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = TA_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(TA_EHIP, "event create failed");
+    bool have_ref = false;
+    // reps timed launches of the current tiles at grid g, each after the
+    // flush; the output is checked against the first candidate's
+    auto time_grid = [&](int g, float* total) -> int {
+      int r0;
+      if ((r0 = launch_plan(c, p, 0, in, out, stream, g))) return r0;
+      *total = 0.0f;
+      for (int r = 0; r < reps; ++r) {
+        if (hipMemsetAsync(flush, r & 0xff, kFlush, s) != hipSuccess) return fail(TA_EHIP, "autotune flush failed");
+        (void)hipEventRecord(e0, s);
+        if ((r0 = launch_plan(c, p, 0, in, out, stream, g))) return r0;
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) return fail(TA_EHIP, "autotune sync failed");
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        *total += ms;
+      }
+      if (hipMemcpy(have_ref ? got.data() : ref.data(), out, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(TA_EHIP, "autotune copy failed");
+      if (have_ref && memcmp(ref.data(), got.data(), bytes) != 0)
+        return fail(TA_EHIP, "autotune candidate (region 2^%d, grid %d) disagrees", p->region_log2, g);
+      have_ref = true;
+      return TA_OK;
+    };
     float best = 1e30f;
     const int orig_region = p->region_log2;
+    int orig_tiles[7][7];
+    memcpy(orig_tiles, p->tile_blocks, sizeof orig_tiles);
     int best_grid = p->grid, best_region = orig_region;
-    bool have_ref = false;
     for (int region : regions) {
       if (rc != TA_OK) break;
       if ((rc = build_tiles(p, region))) break;
       for (int g : grids) {
-        if ((rc = launch_plan(c, p, 0, in, out, stream, g))) break;
         float total = 0.0f;
-        for (int r = 0; r < reps && rc == TA_OK; ++r) {
-          if (hipMemsetAsync(flush, r & 0xff, kFlush, s) != hipSuccess) { rc = fail(TA_EHIP, "autotune flush failed"); break; }
-          (void)hipEventRecord(e0, s);
-          if ((rc = launch_plan(c, p, 0, in, out, stream, g))) break;
-          (void)hipEventRecord(e1, s);
-          if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(TA_EHIP, "autotune sync failed"); break; }
-          float ms = 0.0f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          total += ms;
-        }
-        if (rc != TA_OK) break;
-        if (hipMemcpy(have_ref ? got.data() : ref.data(), out, bytes, hipMemcpyDeviceToHost) != hipSuccess) {
-          rc = fail(TA_EHIP, "autotune copy failed");
-          break;
-        }
-        if (have_ref && memcmp(ref.data(), got.data(), bytes) != 0) {
-          rc = fail(TA_EHIP, "autotune candidate (region 2^%d, grid %d) disagrees", region, g);
-          break;
-        }
-        have_ref = true;
+        if ((rc = time_grid(g, &total))) break;
         if (total < best) { best = total; best_grid = g; best_region = region; }
       }
+    }
+    // then the blocks per tile of each size group (larger side 4 .. 64), by
+    // coordinate descent at the chosen grid and region: the kernels'
+    // maximum, half of it or a quarter
+    if (rc == TA_OK) rc = build_tiles(p, best_region);
+    for (int ls = 2; ls <= 6 && rc == TA_OK; ++ls) {
+      bool present = false;
+      for (const ta_plan::Class& cl : p->classes) present |= std::max(cl.lw, cl.lh) == ls;
+      if (!present) continue;
+      int keep[7][7];
+      memcpy(keep, p->tile_blocks, sizeof keep);
+      int best_div = 0;
+      for (int div : {2, 4}) {
+        for (int lw = 2; lw <= 6; ++lw)
+          for (int lh = 2; lh <= 6; ++lh)
+            if (std::max(lw, lh) == ls) p->tile_blocks[lw][lh] = std::max(1, max_tile_blocks(p, lw, lh) / div);
+        float total = 0.0f;
+        if ((rc = build_tiles(p, best_region)) || (rc = time_grid(best_grid, &total))) break;
+        if (total < best) { best = total; best_div = div; }
+      }
+      if (rc != TA_OK) break;
+      memcpy(p->tile_blocks, keep, sizeof keep);
+      if (best_div)
+        for (int lw = 2; lw <= 6; ++lw)
+          for (int lh = 2; lh <= 6; ++lh)
+            if (std::max(lw, lh) == ls) p->tile_blocks[lw][lh] = std::max(1, max_tile_blocks(p, lw, lh) / best_div);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(s);
     (void)hipFree(flush);
-    // keep the fastest mapping (rebuilt also when a candidate failed, so the
-    // plan stays consistent)
+    // keep the fastest mapping (on a failure the plan returns to what it was;
+    // either way it is rebuilt so that it stays consistent)
+    if (rc != TA_OK) memcpy(p->tile_blocks, orig_tiles, sizeof orig_tiles);
     const int rc2 = build_tiles(p, rc == TA_OK ? best_region : orig_region);
     if (rc == TA_OK && rc2 == TA_OK) p->grid = best_grid;
     return rc != TA_OK ? rc : rc2;
+  });
+}
+
+int ta_plan_tile_blocks(const ta_plan* p, int log2w, int log2h, int* blocks) {
+  if (!p || !blocks) return fail(TA_EINVAL, "null argument");
+  if (log2w < 2 || log2w > 6 || log2h < 2 || log2h > 6) return fail(TA_EINVAL, "size outside 4..64");
+  *blocks = tile_blocks(p, log2w, log2h);
+  return TA_OK;
+}
+
+int ta_plan_set_tile_blocks(ta_plan* p, int log2w, int log2h, int blocks) {
+  return guard([&]() -> int {
+    if (!p) return fail(TA_EINVAL, "null plan");
+    if (log2w < 2 || log2w > 6 || log2h < 2 || log2h > 6) return fail(TA_EINVAL, "size outside 4..64");
+    const int m = max_tile_blocks(p, log2w, log2h);
+    if (blocks < 0 || blocks > m)
+      return fail(TA_EINVAL, "%d blocks per tile outside 0..%d for %dx%d", blocks, m, 1 << log2w, 1 << log2h);
+    p->tile_blocks[log2w][log2h] = blocks;
+    return build_tiles(p, p->region_log2);
   });
 }
 

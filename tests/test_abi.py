@@ -83,6 +83,9 @@ def test_block_list_entry_points_reject_bad_arguments_without_gpu():
     assert lib.ta_set_axis_cfg(None, 0, None) == ta.TA_EINVAL
     assert lib.ta_plan_tuning(None, None, None) == ta.TA_EINVAL
     assert lib.ta_plan_set_tuning(None, 1024, 20) == ta.TA_EINVAL
+    nb = ctypes.c_int(0)
+    assert lib.ta_plan_tile_blocks(None, 3, 3, ctypes.byref(nb)) == ta.TA_EINVAL
+    assert lib.ta_plan_set_tile_blocks(None, 3, 3, 1) == ta.TA_EINVAL
     lay = np.array([ta.ADJ_BAND, 8, 4], np.int32)
     a = np.zeros(64, np.int16)
     f = np.zeros(64, np.float32)

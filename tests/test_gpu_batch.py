@@ -214,3 +214,53 @@ def test_planned_strides_offsets_and_order(env):
         assert (got == F.fwd2d(xin, ah, av)).all(), f"forward frame {f} {w}x{h} types {th},{tv}"
         gi = blk(zc, [int(desc["in_off"][k]) for k in ks], int(desc["in_stride"][ks[0]]))
         assert (gi == F.inv2d(got, ah, av)).all(), f"inverse frame {f} {w}x{h} types {th},{tv}"
+
+
+@pytest.mark.parametrize("dtype", ["i16", "f32"])
+def test_tile_blocks_keep_outputs_bitwise(env, dtype):
+    """Blocks per tile by size: every setting gives the same outputs (the
+    tiling only changes which workgroup runs a block), smaller tiles give
+    more of them, and settings outside 0 .. the maximum are refused."""
+    ctx, params = env
+    frames, rows = small_workload()
+    dt = ta.I16 if dtype == "i16" else ta.F32
+    plan = ta.Plan(ctx, descriptors(rows, frames.shape[1], frames.shape[2]), dtype=dt)
+    x = torch.from_numpy(frames).cuda()
+    if dt == ta.F32:
+        x = x.float()
+    y0, z0 = torch.zeros_like(x), torch.zeros_like(x)
+    plan.fwd(x, y0)
+    plan.inv(y0, z0)
+    default = plan.tile_blocks()
+    assert len(default) == 25 and all(v >= 1 for v in default.values())
+    tiles0 = plan.info()["tiles"]
+    settings = [
+        {(w, h): 1 for (w, h) in default},                                  # one block a tile
+        {(w, h): max(1, n // 2) for (w, h), n in default.items()},
+        {(w, h): (max(1, n // 4) if max(w, h) in (4, 16) else 0) for (w, h), n in default.items()},
+    ]
+    for k, setting in enumerate(settings):
+        for (w, h), n in setting.items():
+            plan.set_tile_blocks(w, h, n)
+        got = plan.tile_blocks()
+        for key, n in setting.items():
+            assert got[key] == (n if n else default[key]), (k, key)
+        assert plan.info()["tiles"] >= tiles0
+        if k == 0:
+            assert plan.info()["tiles"] == len(rows)
+        y, z = torch.full_like(x, 5), torch.full_like(x, -5)
+        plan.fwd(x, y)
+        plan.inv(y0, z)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y0) and torch.equal(z, z0), f"setting {k}"
+    for (w, h) in default:
+        plan.set_tile_blocks(w, h, 0)
+    assert plan.tile_blocks() == default and plan.info()["tiles"] == tiles0
+    for w, h, n in ((8, 8, -1), (8, 8, default[(8, 8)] + 1)):
+        with pytest.raises(ta.TadjError) as e:
+            plan.set_tile_blocks(w, h, n)
+        assert e.value.code == ta.TA_EINVAL
+    with pytest.raises(ValueError):
+        plan.set_tile_blocks(128, 8, 1)
+    if dt == ta.I16:
+        assert (y0.cpu().numpy() == oracle_frames(frames, rows, params)).all()
