@@ -220,7 +220,11 @@ int ta_fwd_multi(ta_ctx* ctx, int param_id, int log2n, int64_t nblocks, const vo
  * ta_plan_create copies the descriptors to device memory, grouped by
  * (size, kinds) into tiles (synchronous, allocates).  ta_plan_fwd/_inv run
  * the whole plan as one persistent kernel launch on the stream
- * (asynchronous, no allocation, capturable in a HIP graph).
+ * (asynchronous, no allocation, capturable in a HIP graph).  With an int16
+ * plan whose grid is resident at once, the workgroups take tiles from
+ * counters the plan holds (one set per direction, reset by each launch at its
+ * end): two launches of one plan in the same direction must not run at the
+ * same time (serialise them on one stream, or use two plans).
  * ta_plan_autotune times the tile mappings (frame regions of 2^18 .. 2^22
  * input elements per XCD tile list) times the persistent grid sizes (256 ..
  * 8192 workgroups) on the given buffers, then, at the fastest of those, the

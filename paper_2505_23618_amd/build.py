@@ -26,6 +26,12 @@ HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
 
+# Per-file additions.  The pipelined batched kernels take tile indices with
+# single-lane atomics whose results are consumed after a wait of their own;
+# the atomic optimizer would rewrite them into wave-wide forms that read the
+# result at once, waiting on the loads in flight.
+FILE_FLAGS = {"batch_kernels.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+
 
 def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,7 +50,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> Path:
 
     def compile_one(src: Path) -> Path:
         obj = BUILD / (src.stem + ".o")
-        msg = _run([hipcc, *HIP_FLAGS, "-c", str(src), "-o", str(obj)])
+        msg = _run([hipcc, *HIP_FLAGS, *FILE_FLAGS.get(src.name, []), "-c", str(src), "-o", str(obj)])
         if verbose and msg:
             print(msg)
         return obj

@@ -721,34 +721,88 @@ TA_DEV void store_tile(const BatchArgs& a, const BatchTile& t, const uint16_t* r
 
 // The walk of one workgroup over its XCD's tile list (grid stride P):
 // tile k is processed while the data of k+1 and the deltas of k+2 load.
+// Dynamic tile schedule.  Workgroup w of an XCD starts with tile w of its
+// XCD's list; the later tiles of the list are handed out in list order by
+// that list's counter, so a workgroup that draws small tiles takes more of
+// them and all finish together.  A workgroup takes its next tile two tiles
+// ahead of use (the pipeline stages the deltas of tile k+2 while running
+// tile k) and only once the one before exists; the last workgroup to finish
+// sets the counters back to zero for the next launch.  Two launches that use
+// the same counters must therefore not run at the same time.
+// The counters sit kSchedPitch dwords apart (own cache lines): counter x
+// at sched[x * kSchedPitch], the finished-workgroup count after the eight.
+TA_DEV int sched_take(int32_t* sched, int xcd, int k) {
+  return __hip_atomic_fetch_add(sched + xcd * kSchedPitch, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// one lane per workgroup, after the last take of the workgroup has returned
+TA_DEV void sched_done(int32_t* sched) {
+  if (__hip_atomic_fetch_add(sched + kXcds * kSchedPitch, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+      (int)gridDim.x - 1) {
+#pragma unroll
+    for (int x = 0; x <= kXcds; ++x)
+      __hip_atomic_store(sched + x * kSchedPitch, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 template <bool INV>
-TA_DEV void planned_tiles(const BatchArgs& a, uint32_t* lds, uint32_t* stage, int2 (*ring)[kPB], int2* dnext) {
+TA_DEV void planned_tiles(const BatchArgs& a, uint32_t* lds, uint32_t* stage, int2 (*ring)[kPB], int2* dnext,
+                          int* slot) {
   // tile indices fit int32 (the planner's rule), so the loop tests are scalar
   const int xcd = blockIdx.x % kXcds;
   const int P = (gridDim.x + kXcds - 1 - xcd) / kXcds;
   const int end = (int)a.xstart[xcd + 1];
+  const int dyn0 = (int)a.xstart[xcd] + P;     // the first tile the counter hands out
+  int32_t* const sched = a.sched;
   int ti = (int)a.xstart[xcd] + blockIdx.x / kXcds;
-  if (ti >= end) return;
-  uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
   const int wb = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;   // this wave's first thread
+  if (ti >= end) {
+    if (sched && tid_here(wb) == 0) sched_done(sched);
+    return;
+  }
+  uint16_t* pch = reinterpret_cast<uint16_t*>(lds);
+  // n1, n2: the next two tiles (end or beyond: none)
+  int n1, n2;
   // prologue: deltas and data of the first tile, deltas of the second
   {
+    int got = 0;
+    if (sched && tid_here(wb) == 0) got = sched_take(sched, xcd, 2);
     const TileHead h0 = tile_head(a.tiles + ti);
     stage_deltas(a, h0, ring[0], wb);
     dma_wait();
+    if (sched && tid_here(wb) == 0) *slot = got;
     tile_sync();
+    if (sched) {
+      n1 = dyn0 + __builtin_amdgcn_readfirstlane(*slot);
+      n2 = n1 + 1;
+    } else {
+      n1 = ti + P;
+      n2 = ti + 2 * P;
+    }
     stage_data(a, h0, ring[0], stage, wb);
-    if (ti + P < end) stage_deltas(a, tile_head(a.tiles + ti + P), dnext, wb);
+    if (n1 < end) stage_deltas(a, tile_head(a.tiles + n1), dnext, wb);
   }
   int cur = 0;
+  bool pending = false;   // the take of n2 has landed in *slot
   for (;;) {
     // tile records are re-read each step (scalar loads, cheap) rather than
     // carried across the loop in scalar registers
     const BatchTile t = uniform_tile(a.tiles + ti);
-    const bool has_n = ti + P < end, has_nn = ti + 2 * P < end;
     dma_wait();                          // this tile's data, the next deltas, the last stores
     tile_sync();
-    if (has_n) copy_deltas(tile_head(a.tiles + ti + P), dnext, ring[cur ^ 1], wb);
+    if (pending) n2 = dyn0 + __builtin_amdgcn_readfirstlane(*slot);
+    const bool has_n = n1 < end, has_nn = n2 < end;
+    // the tile after n2 (once n2 exists), taken a whole tile ahead of use so
+    // that its round trip overlaps this tile's work
+    // The take goes out where its result costs least: in the inverse at the
+    // tile head, its result written to *slot after the stores (a whole tile
+    // later); in the forward, whose phases hold every register, after the
+    // stores, written at once (the wait then also covers the loads and stores
+    // in flight, which the next tile head waits for anyway).
+    [[maybe_unused]] int got = 0;
+    if constexpr (INV) {
+      if (sched && has_nn && tid_here(wb) == 0) got = sched_take(sched, xcd, 1);
+    }
+    if (has_n) copy_deltas(tile_head(a.tiles + n1), dnext, ring[cur ^ 1], wb);
     const int PP = BatchGeo::pl_pc(t.lh), Q = BatchGeo::pl_rm(t.lh);
     if (INV) {
       inv_scatter(t, stage, pch, PP, wb);
@@ -761,8 +815,8 @@ TA_DEV void planned_tiles(const BatchArgs& a, uint32_t* lds, uint32_t* stage, in
       }
     }
     tile_sync();                         // stage and dnext are free
-    if (has_n) stage_data(a, tile_head(a.tiles + ti + P), ring[cur ^ 1], stage, wb);
-    if (has_nn) stage_deltas(a, tile_head(a.tiles + ti + 2 * P), dnext, wb);
+    if (has_n) stage_data(a, tile_head(a.tiles + n1), ring[cur ^ 1], stage, wb);
+    if (has_nn) stage_deltas(a, tile_head(a.tiles + n2), dnext, wb);
     const int s_col = INV ? a.m + 1 : t.lh + a.m;
     switch (t.kind_v) {
       case 0: cols_pl_h<KC2, INV>(a, t, lds, s_col, wb); break;
@@ -780,10 +834,24 @@ TA_DEV void planned_tiles(const BatchArgs& a, uint32_t* lds, uint32_t* stage, in
       tile_sync();
     }
     store_tile(a, t, pch, Q, ring[cur], wb);
-    if (!has_n) break;
-    ti += P;
+    if constexpr (INV) {
+      if (sched && has_nn && tid_here(wb) == 0) *slot = got;
+    }
+    if (!has_n) break;   // (then n2 does not exist either and nothing was taken)
+    ti = n1;
+    n1 = n2;
+    if (sched) {
+      pending = n1 < end;
+      if constexpr (!INV) {
+        if (pending && tid_here(wb) == 0) *slot = sched_take(sched, xcd, 1);
+      }
+      if (!pending) n2 = end;   // the counter only grows: once past the end, always past it
+    } else {
+      n2 = n1 + P;
+    }
     cur ^= 1;
   }
+  if (sched && tid_here(wb) == 0) sched_done(sched);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_fwd(BatchArgs a) {
@@ -791,7 +859,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
   __shared__ __align__(16) uint32_t stage[kStageDwords];
   __shared__ __align__(16) int2 ring[2][kPB];
   __shared__ __align__(16) int2 dnext[kPB];
-  planned_tiles<false>(a, lds, stage, ring, dnext);
+  __shared__ int slot;
+  planned_tiles<false>(a, lds, stage, ring, dnext, &slot);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void batch_inv(BatchArgs a) {
@@ -799,7 +868,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
   __shared__ __align__(16) uint32_t stage[kStageDwords];
   __shared__ __align__(16) int2 ring[2][kPB];
   __shared__ __align__(16) int2 dnext[kPB];
-  planned_tiles<true>(a, lds, stage, ring, dnext);
+  __shared__ int slot;
+  planned_tiles<true>(a, lds, stage, ring, dnext, &slot);
 }
 
 // ---------------------------------------------------------------- fp32 tiles

@@ -805,18 +805,23 @@ struct ta_plan {
   ta_plan(const ta_plan&) = delete;
   ta_plan& operator=(const ta_plan&) = delete;
   ~ta_plan() {
-    if (!blocks_dev && !tiles_dev && !progs_dev && !deltas_dev) return;
+    if (!blocks_dev && !tiles_dev && !progs_dev && !deltas_dev && !sched_dev) return;
     DeviceGuard device_guard_;
     (void)device_guard_.enter(device);
     if (blocks_dev) (void)hipFree(blocks_dev);
     if (tiles_dev) (void)hipFree(tiles_dev);
     if (progs_dev) (void)hipFree(progs_dev);
     if (deltas_dev) (void)hipFree(deltas_dev);
+    if (sched_dev) (void)hipFree(sched_dev);
   }
   int64_t nblocks = 0, ntiles = 0;
   int grid = 2048;                 // persistent workgroups (autotuned)
   ta_block* blocks_dev = nullptr;  // block descriptors in plan order
   int32_t* deltas_dev = nullptr;   // (in_off - tile in_base, out_off - tile out_base) per block, plan order
+  // tile counters of the int16 kernels' dynamic schedule: forward at 0,
+  // inverse at kSchedStride (zero between launches)
+  int32_t* sched_dev = nullptr;
+  static constexpr int kSchedStride = ta::kSchedDwords;
   ta::BatchTile* tiles_dev = nullptr;
   int64_t max_in_elem = 0, max_out_elem = 0;   // extents touched (for validation)
   int64_t xstart[ta::kXcds + 1] = {};            // per-XCD tile lists
@@ -870,12 +875,23 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
                            reinterpret_cast<hipStream_t>(stream)));
     return TA_OK;
   }
-  ta::BatchArgs args;
+  ta::BatchArgs args{};
   args.tiles = p->tiles_dev;
   args.ntiles = p->ntiles;
   for (int x = 0; x <= ta::kXcds; ++x) args.xstart[x] = p->xstart[x];
   args.blocks = p->blocks_dev;
   args.deltas = p->deltas_dev;
+  // The int16 kernels hand out tiles dynamically (per-direction counters)
+  // when the whole grid is resident at once; a larger grid keeps the static
+  // stride (its later workgroups start only as earlier ones finish, which
+  // balances the load by itself).
+  const void* fn = ta::batch_kernel(inv, 0, p->dtype == TA_F32);
+  args.sched = nullptr;
+  if (p->dtype == TA_I16) {
+    int res = 0, e;
+    if ((e = resident_groups(fn, 256, c->device, &res))) return e;
+    if (g <= res) args.sched = p->sched_dev + (inv ? ta_plan::kSchedStride : 0);
+  }
   args.in = static_cast<const int16_t*>(in);
   args.out = static_cast<int16_t*>(out);
   args.bd = c->bd;
@@ -883,8 +899,7 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
   args.a = c->a;
   void* kargs[] = {&args};
   TA_ON_DEVICE(c->device);
-  TA_HIP(hipLaunchKernel(ta::batch_kernel(inv, 0, p->dtype == TA_F32), dim3((unsigned)g), dim3(256), kargs, 0,
-                         reinterpret_cast<hipStream_t>(stream)));
+  TA_HIP(hipLaunchKernel(fn, dim3((unsigned)g), dim3(256), kargs, 0, reinterpret_cast<hipStream_t>(stream)));
   return TA_OK;
 }
 
@@ -1014,6 +1029,10 @@ int build_tiles(ta_plan* plan, int region_log2) {
     if (!plan->blocks_dev) TA_HIP(hipMalloc(&plan->blocks_dev, (size_t)n * sizeof(ta_block)));
     if (!plan->tiles_dev) TA_HIP(hipMalloc(&plan->tiles_dev, (size_t)n * sizeof(ta::BatchTile)));
     if (!plan->deltas_dev) TA_HIP(hipMalloc(&plan->deltas_dev, 2 * (size_t)n * sizeof(int32_t)));
+    if (!plan->sched_dev) {
+      TA_HIP(hipMalloc(&plan->sched_dev, 2 * ta_plan::kSchedStride * sizeof(int32_t)));
+      TA_HIP(hipMemset(plan->sched_dev, 0, 2 * ta_plan::kSchedStride * sizeof(int32_t)));
+    }
     TA_HIP(hipMemcpy(plan->blocks_dev, ordered.data(), ordered.size() * sizeof(ta_block), hipMemcpyHostToDevice));
     TA_HIP(hipMemcpy(plan->deltas_dev, deltas.data(), deltas.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     TA_HIP(hipMemcpy(plan->tiles_dev, tiles.data(), tiles.size() * sizeof(ta::BatchTile), hipMemcpyHostToDevice));

@@ -155,12 +155,19 @@ constexpr int kAxisSizes = 7;   // indexed by log2 of the size (2..6 used)
 constexpr int kDescWindow = 256;
 constexpr int kSortQuarters = 4;
 
+constexpr int kSchedPitch = 32;     // dwords between schedule counters (128 B)
+constexpr int kSchedDwords = (kXcds + 1) * kSchedPitch;
+
 struct BatchArgs {
   const BatchTile* tiles;
   int64_t ntiles;
   int64_t xstart[kXcds + 1];
   const ta_block* blocks;
   const int32_t* deltas;  // planned int16: (in_delta, out_delta) per block
+  // planned int16: the tile counters of the dynamic schedule (one per XCD
+  // list, then the count of finished workgroups, kSchedPitch dwords apart;
+  // zero between launches), or null for a static grid stride
+  int32_t* sched;
   const int16_t* in;      // int16 data; the fp32 kernels read these as float*
   int16_t* out;
   int bd, m, a;

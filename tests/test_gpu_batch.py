@@ -74,24 +74,34 @@ def test_autotune_and_graph_replay(env):
     assert info["grid"] in (256, 512, 1024, 2048, 4096, 8192)
     assert 18 <= info["region_log2"] <= 22
     ref = oracle_frames(frames, rows, params)
-    # capture forward + inverse in a graph; replay with eager work in between
-    z = torch.zeros_like(x)
-    s = torch.cuda.Stream()
-    torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(s):
-        with torch.cuda.graph(g, stream=s):
-            plan.fwd(x, y, stream_handle=s.cuda_stream)
-            plan.inv(y, z, stream_handle=s.cuda_stream)
     refi = oracle_frames(ref.astype(np.int16), rows, params, inverse=True)
-    for rep in range(3):
-        y.fill_(7)
-        z.fill_(-7)
+    # capture forward + inverse in a graph; replay with eager work in between.
+    # Second round: 256 workgroups, all resident, so the tiles go through the
+    # plan's counters, which every launch must leave at zero for the next.
+    for tuning in (None, (256, 19)):
+        if tuning:
+            plan.set_tuning(*tuning)
+        z = torch.zeros_like(x)
+        s = torch.cuda.Stream()
         torch.cuda.synchronize()
-        g.replay()
-        torch.cuda.synchronize()
-        assert (y.cpu().numpy() == ref).all(), f"replay {rep} forward"
-        assert (z.cpu().numpy() == refi).all(), f"replay {rep} inverse"
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                plan.fwd(x, y, stream_handle=s.cuda_stream)
+                plan.inv(y, z, stream_handle=s.cuda_stream)
+        for rep in range(3):
+            y.fill_(7)
+            z.fill_(-7)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert (y.cpu().numpy() == ref).all(), f"{tuning} replay {rep} forward"
+            assert (z.cpu().numpy() == refi).all(), f"{tuning} replay {rep} inverse"
+            # eager launches between the replays use the same counters
+            y2 = torch.full_like(x, 3)
+            plan.fwd(x, y2)
+            torch.cuda.synchronize()
+            assert (y2.cpu().numpy() == ref).all(), f"{tuning} eager {rep}"
 
 
 def test_plan_errors(env):
