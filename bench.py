@@ -380,8 +380,10 @@ def _batched(ctx, ids, res):
     Z = [torch.empty_like(X[0]) for _ in range(4)]
     info = plan.autotune(X[0], Y[0], reps=3)
     nco = int((rows[:, 3].astype(np.int64) * rows[:, 4]).sum())
-    tf = _events_mean(lambda i: plan.fwd(X[i % 4], Y[i % 4]), 12)
-    ti = _events_mean(lambda i: plan.inv(Y[i % 4], Z[i % 4]), 12)
+    # (the first launches after a change of kernel run slower while the
+    # clocks settle: six untimed ones before each timed series)
+    tf = _events_mean(lambda i: plan.fwd(X[i % 4], Y[i % 4]), 12, warm=6)
+    ti = _events_mean(lambda i: plan.inv(Y[i % 4], Z[i % 4]), 12, warm=6)
     # the same list unplanned: descriptors in device memory, in frame order
     dev = ctx.blocks_to_device(desc)
     uf = _events_mean(lambda i: ctx.transform_fwd(dev, X[i % 4], Y[i % 4]), 12)
@@ -401,8 +403,8 @@ def _batched(ctx, ids, res):
     Y = [torch.empty_like(X[0]) for _ in range(4)]
     Z = [torch.empty_like(X[0]) for _ in range(4)]
     infof = planf.autotune(X[0], Y[0], reps=3)
-    tf = _events_mean(lambda i: planf.fwd(X[i % 4], Y[i % 4]), 12)
-    ti = _events_mean(lambda i: planf.inv(Y[i % 4], Z[i % 4]), 12)
+    tf = _events_mean(lambda i: planf.fwd(X[i % 4], Y[i % 4]), 12, warm=6)
+    ti = _events_mean(lambda i: planf.inv(Y[i % 4], Z[i % 4]), 12, warm=6)
     uf = _events_mean(lambda i: ctx.transform_fwd(dev, X[i % 4], Y[i % 4]), 12)
     ui = _events_mean(lambda i: ctx.transform_inv(dev, Y[i % 4], Z[i % 4]), 12)
     res["batched_uneven_f32"] = {"value": nco / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,

@@ -230,11 +230,22 @@ int ta_fwd_multi(ta_ctx* ctx, int param_id, int log2n, int64_t nblocks, const vo
  * 8192 workgroups) on the given buffers, then, at the fastest of those, the
  * blocks per tile of each size group (blocks whose larger side is 4, 8, 16,
  * 32 or 64: the kernels' maximum, half of it or a quarter, one group after
- * the other), each launch after a 512 MiB cache flush (a batch streams
- * through HBM once per call); it checks that every candidate's output is
- * bitwise identical and keeps the fastest (synchronous; allocates 512 MiB of
- * scratch while it runs; runs the forward).  ta_plan_set_tuning applies a known grid (>= 8) and region
- * (log2 input elements, 12..40) without timing (synchronous).  Both rewrite
+ * the other).  Each candidate runs twelve forward launches, then twelve
+ * inverse ones (the last six of each timed), on three buffer sets in turn,
+ * so that every launch finds the caches holding the other sets' data, as
+ * when batches stream through HBM once per call: set 0 is the
+ * caller's `in` and `out`, sets 1 and 2 copies of `in` in scratch, and every
+ * set's inverse output goes to scratch (the inverse reads its set's forward
+ * output, or its set's input when `out` is smaller than the plan's input
+ * extent).  The candidates are timed in `reps` interleaved rounds (clocks
+ * drift under load) and scored by the sum of their median forward and
+ * inverse times; scores within 1 % of the best count as equal, and the
+ * smallest grid among them wins.  The tuner checks that every candidate's outputs are
+ * bitwise identical and keeps the fastest (synchronous; allocates scratch of
+ * twice the plan's input extent plus five times its output extent while it
+ * runs; leaves the forward of `in` in `out`).  ta_plan_set_tuning applies
+ * a known grid (>= 8) and region (log2 input elements, 12..40) without
+ * timing (synchronous).  Both rewrite
  * the plan's device tile list in place: launches captured in a HIP graph
  * before must be captured again.  ta_plan_tuning reports the grid and
  * region in use.  ta_plan_tile_blocks reports how many blocks of size
@@ -243,7 +254,8 @@ int ta_fwd_multi(ta_ctx* ctx, int param_id, int log2n, int64_t nblocks, const vo
  * and dtype, or 0 for that maximum (synchronous; rebuilds the tile list like
  * ta_plan_set_tuning; TA_EINVAL outside those ranges).  Fewer blocks per tile
  * give more, smaller tiles: better balance across the grid, less overlap of
- * one tile's loads with the previous tile's arithmetic.  Blocks must not overlap in `out`.  A plan runs only with
+ * one tile's loads with the previous tile's arithmetic.  Blocks must not
+ * overlap in `out`.  A plan runs only with
  * the context that created it (TA_EINVAL otherwise) and must be destroyed
  * before that context: its tiles point into the context's parameter
  * tables. */

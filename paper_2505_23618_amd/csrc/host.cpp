@@ -1158,88 +1158,174 @@ int ta_plan_autotune(ta_ctx* c, ta_plan* p, const void* in, void* out, ta_stream
     if (reps < 1) reps = 3;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     TA_ON_DEVICE(c->device);
-    // every candidate's output is checked bitwise against the first one's
-    const size_t bytes = (size_t)p->max_out_elem * (p->dtype == TA_F32 ? sizeof(float) : sizeof(int16_t));
-    std::vector<char> ref(bytes), got(bytes);
-    // A frame batch streams through HBM once per call, so each timed launch
-    // starts from cold caches: a 512 MiB write (more than the L2s and the
-    // Infinity Cache hold) runs before it.
-    constexpr size_t kFlush = size_t(512) << 20;
-    void* flush = nullptr;
-    TA_HIP(hipMalloc(&flush, kFlush));
+    // every candidate's outputs are checked bitwise against the first one's
+    const size_t esz = p->dtype == TA_F32 ? sizeof(float) : sizeof(int16_t);
+    const size_t in_bytes = ((size_t)p->max_in_elem * esz + 255) & ~(size_t)255;
+    const size_t bytes = (size_t)p->max_out_elem * esz, out_bytes = (bytes + 255) & ~(size_t)255;
+    std::vector<char> ref(bytes), got(bytes), refi(bytes), goti(bytes);
+    // A frame batch streams through HBM once per call.  The candidates are
+    // timed on kSets buffer sets in turn, so that each launch finds the
+    // caches holding the other sets' data, as in a stream of batches: set 0
+    // is (in, out, inverse output), the others a copy of `in` with their own
+    // forward and inverse outputs, all in one scratch allocation.  The
+    // inverse reads its set's forward output when that covers the input
+    // extent, else its set's input (the timing barely depends on the values).
+    constexpr int kSets = 3;
+    char* scratch = nullptr;
+    TA_HIP(hipMalloc(&scratch, (kSets - 1) * (in_bytes + out_bytes) + kSets * out_bytes));
+    const void* set_in[kSets];
+    void* set_out[kSets];
+    void* set_inv[kSets];
+    set_in[0] = in;
+    set_out[0] = out;
+    char* sp = scratch;
+    for (int k = 1; k < kSets; ++k) {
+      set_in[k] = sp;
+      set_out[k] = sp + in_bytes;
+      sp += in_bytes + out_bytes;
+    }
+    for (int k = 0; k < kSets; ++k, sp += out_bytes) set_inv[k] = sp;
+    const bool inv_from_out = p->max_in_elem <= p->max_out_elem;
+    int rc = TA_OK;
+    for (int k = 1; k < kSets && rc == TA_OK; ++k)
+      if (hipMemcpyAsync(const_cast<void*>(set_in[k]), in, (size_t)p->max_in_elem * esz, hipMemcpyDeviceToDevice, s) !=
+          hipSuccess)
+        rc = fail(TA_EHIP, "autotune copy failed");
     const int regions[] = {18, 19, 20, 21, 22};     // tile mapping: frame-region size of the XCD lists
     const int grids[] = {256, 512, 1024, 2048, 4096, 8192};
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    int rc = TA_OK;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(TA_EHIP, "event create failed");
+    // events around the timed launches of one direction, recorded back to
+    // back (the launches follow each other without a host round trip)
+    constexpr int kWarm = 6, kTimed = 6, kEv = kTimed + 1;
+    hipEvent_t ev[kEv] = {};
+    for (int i = 0; i < kEv && rc == TA_OK; ++i)
+      if (hipEventCreate(&ev[i]) != hipSuccess) rc = fail(TA_EHIP, "event create failed");
     bool have_ref = false;
-    // reps timed launches of the current tiles at grid g, each after the
-    // flush; the output is checked against the first candidate's
-    auto time_grid = [&](int g, float* total) -> int {
-      int r0;
-      if ((r0 = launch_plan(c, p, 0, in, out, stream, g))) return r0;
-      *total = 0.0f;
-      for (int r = 0; r < reps; ++r) {
-        if (hipMemsetAsync(flush, r & 0xff, kFlush, s) != hipSuccess) return fail(TA_EHIP, "autotune flush failed");
-        (void)hipEventRecord(e0, s);
-        if ((r0 = launch_plan(c, p, 0, in, out, stream, g))) return r0;
-        (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) return fail(TA_EHIP, "autotune sync failed");
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        *total += ms;
+    // Per candidate, the launch times of each direction (samples[0] forward,
+    // samples[1] inverse); a candidate scores the sum of the two medians.
+    struct Samples {
+      std::vector<float> t[2];
+      float score() const {
+        float sc = 0.0f;
+        for (std::vector<float> v : t) {
+          if (v.empty()) return 1e30f;
+          std::sort(v.begin(), v.end());
+          sc += v.size() % 2 ? v[v.size() / 2] : 0.5f * (v[v.size() / 2 - 1] + v[v.size() / 2]);
+        }
+        return sc;
       }
-      if (hipMemcpy(have_ref ? got.data() : ref.data(), out, bytes, hipMemcpyDeviceToHost) != hipSuccess)
+    };
+    // A run of one direction, as a codec streams batches: kWarm untimed and
+    // kTimed timed launches back to back over the sets in turn.  The first
+    // launches after a change of kernel run slower while the clocks settle.
+    auto run = [&](int g, int inv, Samples* smp) -> int {
+      int r0;
+      for (int i = 0; i < kWarm + kTimed; ++i) {
+        if (i >= kWarm) (void)hipEventRecord(ev[i - kWarm], s);
+        const int k = i % kSets;
+        const void* src = inv ? (inv_from_out ? set_out[k] : set_in[k]) : set_in[k];
+        if ((r0 = launch_plan(c, p, inv, src, inv ? set_inv[k] : set_out[k], stream, g))) return r0;
+      }
+      (void)hipEventRecord(ev[kTimed], s);
+      if (hipEventSynchronize(ev[kTimed]) != hipSuccess) return fail(TA_EHIP, "autotune sync failed");
+      for (int i = 0; i < kTimed; ++i) {
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        smp->t[inv].push_back(ms);
+      }
+      return TA_OK;
+    };
+    // After the host rebuilds the tile list the GPU has idled and its clocks
+    // have dropped: untimed launches bring them back before the next
+    // candidate is timed.
+    auto settle = [&](int g) -> int {
+      int r0;
+      for (int i = 0; i < 64; ++i)
+        if ((r0 = launch_plan(c, p, 0, set_in[i % kSets], set_out[i % kSets], stream, g))) return r0;
+      return TA_OK;
+    };
+    // a forward run and an inverse run of the current tiles at grid g (the
+    // forward writes every set's output before any inverse reads it); with
+    // `check`, the outputs are compared with the first candidate's
+    auto time_grid = [&](int g, Samples* smp, bool check) -> int {
+      int r0;
+      if ((r0 = run(g, 0, smp)) || (r0 = run(g, 1, smp))) return r0;
+      if (!check) return TA_OK;
+      if (hipMemcpy(have_ref ? got.data() : ref.data(), out, bytes, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(have_ref ? goti.data() : refi.data(), set_inv[0], bytes, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(TA_EHIP, "autotune copy failed");
-      if (have_ref && memcmp(ref.data(), got.data(), bytes) != 0)
+      if (have_ref && (memcmp(ref.data(), got.data(), bytes) != 0 || memcmp(refi.data(), goti.data(), bytes) != 0))
         return fail(TA_EHIP, "autotune candidate (region 2^%d, grid %d) disagrees", p->region_log2, g);
       have_ref = true;
       return TA_OK;
     };
-    float best = 1e30f;
+    // Clocks drift under sustained load, so the candidates are timed in
+    // `reps` interleaved rounds (each round visits all of them).
+    constexpr int kRegions = sizeof(regions) / sizeof(regions[0]), kGrids = sizeof(grids) / sizeof(grids[0]);
+    std::vector<Samples> sums(kRegions * kGrids);
     const int orig_region = p->region_log2;
     int orig_tiles[7][7];
     memcpy(orig_tiles, p->tile_blocks, sizeof orig_tiles);
     int best_grid = p->grid, best_region = orig_region;
-    for (int region : regions) {
-      if (rc != TA_OK) break;
-      if ((rc = build_tiles(p, region))) break;
-      for (int g : grids) {
-        float total = 0.0f;
-        if ((rc = time_grid(g, &total))) break;
-        if (total < best) { best = total; best_grid = g; best_region = region; }
+    for (int r = 0; r < reps && rc == TA_OK; ++r)
+      for (int i = 0; i < kRegions && rc == TA_OK; ++i) {
+        if ((rc = build_tiles(p, regions[i])) || (rc = settle(grids[0]))) break;
+        for (int j = 0; j < kGrids; ++j)
+          if ((rc = time_grid(grids[j], &sums[i * kGrids + j], r == 0))) break;
       }
+    // Scores within 1 % of the best are taken as equal (that is about the
+    // spread of the measurement); among them the smallest grid wins: the
+    // fewest workgroup launches, and tiles handed out by the counters once
+    // the grid is resident, which keeps the load balanced when a batch's
+    // timing varies.
+    if (rc == TA_OK) {
+      float best = 1e30f;
+      for (const Samples& sm : sums) best = std::min(best, sm.score());
+      float pick = 1e30f;
+      for (int j = 0; j < kGrids && pick > 1e29f; ++j)
+        for (int i = 0; i < kRegions; ++i) {
+          const float sc = sums[i * kGrids + j].score();
+          if (sc <= best * 1.01f && sc < pick) { pick = sc; best_region = regions[i]; best_grid = grids[j]; }
+        }
     }
     // then the blocks per tile of each size group (larger side 4 .. 64), by
     // coordinate descent at the chosen grid and region: the kernels'
-    // maximum, half of it or a quarter
-    if (rc == TA_OK) rc = build_tiles(p, best_region);
+    // maximum, half of it or a quarter, timed in interleaved rounds against
+    // the current choice
     for (int ls = 2; ls <= 6 && rc == TA_OK; ++ls) {
       bool present = false;
       for (const ta_plan::Class& cl : p->classes) present |= std::max(cl.lw, cl.lh) == ls;
       if (!present) continue;
       int keep[7][7];
       memcpy(keep, p->tile_blocks, sizeof keep);
-      int best_div = 0;
-      for (int div : {2, 4}) {
-        for (int lw = 2; lw <= 6; ++lw)
-          for (int lh = 2; lh <= 6; ++lh)
-            if (std::max(lw, lh) == ls) p->tile_blocks[lw][lh] = std::max(1, max_tile_blocks(p, lw, lh) / div);
-        float total = 0.0f;
-        if ((rc = build_tiles(p, best_region)) || (rc = time_grid(best_grid, &total))) break;
-        if (total < best) { best = total; best_div = div; }
-      }
+      const int divs[] = {0, 2, 4};   // 0: the current choice
+      Samples sum[3];
+      auto apply = [&](int div) {
+        memcpy(p->tile_blocks, keep, sizeof keep);
+        if (div)
+          for (int lw = 2; lw <= 6; ++lw)
+            for (int lh = 2; lh <= 6; ++lh)
+              if (std::max(lw, lh) == ls) p->tile_blocks[lw][lh] = std::max(1, max_tile_blocks(p, lw, lh) / div);
+      };
+      for (int r = 0; r < reps && rc == TA_OK; ++r)
+        for (int d = 0; d < 3; ++d) {
+          apply(divs[d]);
+          if ((rc = build_tiles(p, best_region)) || (rc = settle(best_grid)) ||
+              (rc = time_grid(best_grid, &sum[d], r == 0)))
+            break;
+        }
       if (rc != TA_OK) break;
-      memcpy(p->tile_blocks, keep, sizeof keep);
-      if (best_div)
-        for (int lw = 2; lw <= 6; ++lw)
-          for (int lh = 2; lh <= 6; ++lh)
-            if (std::max(lw, lh) == ls) p->tile_blocks[lw][lh] = std::max(1, max_tile_blocks(p, lw, lh) / best_div);
+      int bd = 0;
+      float bs = sum[0].score();
+      for (int d = 1; d < 3; ++d) {
+        const float sc = sum[d].score();
+        if (sc < bs) { bs = sc; bd = d; }
+      }
+      apply(divs[bd]);
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
+    for (hipEvent_t x : ev)
+      if (x) (void)hipEventDestroy(x);
     (void)hipStreamSynchronize(s);
-    (void)hipFree(flush);
+    (void)hipFree(scratch);
     // keep the fastest mapping (on a failure the plan returns to what it was;
     // either way it is rebuilt so that it stays consistent)
     if (rc != TA_OK) memcpy(p->tile_blocks, orig_tiles, sizeof orig_tiles);
