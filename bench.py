@@ -356,9 +356,8 @@ def _subblock(ctx, ids, res):
 
 
 def _tile_blocks(plan):
-    """The plan's blocks per tile, by size group (larger block side)."""
-    tb = plan.tile_blocks()
-    return {str(side): [tb[k] for k in sorted(tb) if max(k) == side] for side in (4, 8, 16, 32, 64)}
+    """The plan's blocks per tile for each block size, as {"WxH": n}."""
+    return {f"{w}x{h}": n for (w, h), n in sorted(plan.tile_blocks().items())}
 
 
 def _batched(ctx, ids, res):
