@@ -387,14 +387,20 @@ def _batched(ctx, ids, res):
     dev = ctx.blocks_to_device(desc)
     uf = _events_mean(lambda i: ctx.transform_fwd(dev, X[i % 4], Y[i % 4]), 12)
     ui = _events_mean(lambda i: ctx.transform_inv(dev, Y[i % 4], Z[i % 4]), 12)
+    # the same list planned on the device (planner kernel + planned kernel)
+    wsb = ctx.transform_workspace(len(desc))
+    df = _events_mean(lambda i: ctx.transform_fwd_ws(dev, X[i % 4], Y[i % 4], wsb), 12, warm=6)
+    di = _events_mean(lambda i: ctx.transform_inv_ws(dev, Y[i % 4], Z[i % 4], wsb), 12, warm=6)
     res["batched_uneven"] = {"value": nco / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
                              "blocks": len(rows), "coefficients": nco, "tiles": info["tiles"], "grid": info["grid"],
                              "region_log2": info["region_log2"], "tile_blocks": _tile_blocks(plan),
                              "GB/s_fwd": (4 * nco + 32 * len(rows)) / tf / 1e9,
                              "unplanned_value": nco / (uf + ui), "unplanned_fwd_us": uf * 1e6,
                              "unplanned_inv_us": ui * 1e6,
+                             "device_planned_value": nco / (df + di), "device_planned_fwd_us": df * 1e6,
+                             "device_planned_inv_us": di * 1e6,
                              "workload": "8 frames 3840x2160, QT/BT blocks 4..64, per-axis DCT-2 / adj. DST-7 / adj. DCT-8"}
-    del X, Y, Z, plan
+    del X, Y, Z, plan, wsb
     torch.cuda.empty_cache()
     # the same frames in fp32 (orthonormal transforms), planned and unplanned
     planf = ta.Plan(ctx, desc, dtype=ta.F32)

@@ -303,6 +303,31 @@ int ta_transform_fwd(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, c
 int ta_transform_inv(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out,
                      int dtype, ta_stream_t stream);
 
+/* Unplanned block lists planned on the device.  ta_transform_fwd_ws / _inv_ws
+ * take the same arguments and rules as ta_transform_fwd / _inv plus a
+ * workspace in device memory (256-byte aligned, at least the size that
+ * ta_transform_workspace gives for nblocks; the caller owns it; its contents
+ * need no initialisation and are scratch after the call).  For int16 at m = 8
+ * a first kernel plans the list: windows of 4096 consecutive descriptors are
+ * sorted by configuration (size and axis ids) in list order and cut into
+ * tiles of equal configuration and row strides, which the pipelined planned
+ * kernels then run in one launch.  The tiles are larger than the in-window
+ * groups of ta_transform_fwd, so throughput is closer to a plan's.  One more
+ * rule applies here: a block whose rows span more than 2^30 input or 2^31
+ * output elements ((h - 1) * stride + w) is skipped.  fp32 lists and
+ * contexts with m != 8 run exactly as ta_transform_fwd / _inv (the workspace
+ * is not used).  Asynchronous on the stream, allocates nothing, capturable
+ * in a HIP graph; two calls that share a workspace must not run at the same
+ * time.  Errors: those of ta_transform_fwd, and TA_EINVAL for a missing,
+ * misaligned or short workspace.  ta_transform_workspace: bytes of workspace
+ * for nblocks descriptors (about 8 + 80 bytes a descriptor; 0 for none);
+ * TA_EINVAL for a null pointer or a negative count. */
+int ta_transform_workspace(int64_t nblocks, int64_t* bytes);
+int ta_transform_fwd_ws(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out,
+                        int dtype, void* workspace, int64_t workspace_bytes, ta_stream_t stream);
+int ta_transform_inv_ws(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out,
+                        int dtype, void* workspace, int64_t workspace_bytes, ta_stream_t stream);
+
 /* Check n device descriptors against the block-list rules and against
  * buffers of in_elems input and out_elems output elements (a debugging aid:
  * copies the list to the host and synchronises).  On the first descriptor

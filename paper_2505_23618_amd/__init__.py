@@ -41,7 +41,8 @@ EXPORTS = ("ta_create", "ta_destroy", "ta_set_band", "ta_set_post", "ta_set_axis
            "ta_transform_fwd", "ta_transform_inv", "ta_validate_blocks", "ta_set_axis_cfg", "ta_set_params",
            "ta_plan_tuning", "ta_plan_set_tuning", "ta_plan_extents", "ta_givens_bwd_noalloc",
            "ta_int_table", "ta_set_band_angles", "ta_set_post_angles", "ta_transform_bwd",
-           "ta_plan_tile_blocks", "ta_plan_set_tile_blocks")
+           "ta_plan_tile_blocks", "ta_plan_set_tile_blocks", "ta_transform_workspace", "ta_transform_fwd_ws",
+           "ta_transform_inv_ws")
 
 # ta_block (32 bytes), as a numpy structured dtype
 BLOCK_DTYPE = np.dtype([("in_off", "<i8"), ("out_off", "<i8"), ("in_stride", "<i4"), ("out_stride", "<i4"),
@@ -112,6 +113,9 @@ def lib() -> ctypes.CDLL:
     L.ta_transform_bwd.argtypes = [vp, vp, i64, vp, vp, vp, vp, i32, vp]
     for f in (L.ta_transform_fwd, L.ta_transform_inv):
         f.argtypes = [vp, vp, i64, vp, vp, i32, vp]
+    for f in (L.ta_transform_fwd_ws, L.ta_transform_inv_ws):
+        f.argtypes = [vp, vp, i64, vp, vp, i32, vp, i64, vp]
+    L.ta_transform_workspace.argtypes = [i64, ctypes.POINTER(i64)]
     L.ta_validate_blocks.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(i64)]
     L.ta_set_axis_cfg.argtypes = [vp, i32, ctypes.POINTER(_AxisCfg)]
     L.ta_set_params.argtypes = [vp, i32, vp, vp, vp, i64]
@@ -364,6 +368,36 @@ class Context:
         _check(fn(self._h, ctypes.c_void_p(blocks_dev.data_ptr()), n, ctypes.c_void_p(x.data_ptr()),
                   ctypes.c_void_p(out.data_ptr()), dt, sh))
         return out
+
+    def transform_workspace(self, nblocks: int, device=None):
+        """A uint8 device tensor of ta_transform_workspace(nblocks) bytes (256-byte aligned)."""
+        import torch
+        b = ctypes.c_int64(0)
+        _check(lib().ta_transform_workspace(nblocks, ctypes.byref(b)))
+        return torch.empty(max(b.value, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def _run_blocks_ws(self, fn, blocks_dev, x, out, ws, stream_handle):
+        import torch
+        n = self._nblocks(blocks_dev)
+        if x.dtype != out.dtype or x.dtype not in (torch.int16, torch.float32):
+            raise ValueError("block lists run on int16 (fixed point) or float32 buffers of one dtype")
+        if not (x.is_contiguous() and out.is_contiguous()):
+            raise ValueError("block lists need contiguous buffers")
+        if ws.dtype != torch.uint8 or not ws.is_contiguous():
+            raise ValueError("the workspace is a contiguous uint8 device tensor (transform_workspace)")
+        dt = I16 if x.dtype == torch.int16 else F32
+        sh = _stream_handle(None) if stream_handle is None else ctypes.c_void_p(stream_handle)
+        _check(fn(self._h, ctypes.c_void_p(blocks_dev.data_ptr()), n, ctypes.c_void_p(x.data_ptr()),
+                  ctypes.c_void_p(out.data_ptr()), dt, ctypes.c_void_p(ws.data_ptr()), ws.numel(), sh))
+        return out
+
+    def transform_fwd_ws(self, blocks_dev, x, out, ws, stream_handle=None):
+        """ta_transform_fwd_ws: the list planned on the device, then the planned kernel."""
+        return self._run_blocks_ws(lib().ta_transform_fwd_ws, blocks_dev, x, out, ws, stream_handle)
+
+    def transform_inv_ws(self, blocks_dev, y, out, ws, stream_handle=None):
+        """ta_transform_inv_ws: the list planned on the device, then the planned kernel."""
+        return self._run_blocks_ws(lib().ta_transform_inv_ws, blocks_dev, y, out, ws, stream_handle)
 
     def transform_fwd(self, blocks_dev, x, out, stream_handle=None):
         """ta_transform_fwd over descriptors already in device memory."""

@@ -750,7 +750,7 @@ TA_DEV void planned_tiles(const BatchArgs& a, uint32_t* lds, uint32_t* stage, in
   // tile indices fit int32 (the planner's rule), so the loop tests are scalar
   const int xcd = blockIdx.x % kXcds;
   const int P = (gridDim.x + kXcds - 1 - xcd) / kXcds;
-  const int end = (int)a.xstart[xcd + 1];
+  const int end = a.xcount ? (int)a.xstart[xcd] + a.xcount[xcd] : (int)a.xstart[xcd + 1];
   const int dyn0 = (int)a.xstart[xcd] + P;     // the first tile the counter hands out
   int32_t* const sched = a.sched;
   int ti = (int)a.xstart[xcd] + blockIdx.x / kXcds;
@@ -1100,13 +1100,13 @@ static_assert(kDescWindow == 256 && kSortWin % kDescWindow == 0, "one sorted ent
 static_assert(kAxisIds <= 256, "axis ids take 8 key bits");
 
 // 22-bit configuration key of a descriptor, or -1 when it breaks a rule
-TA_DEV int config_key(const BatchArgs& a, const ta_block& d) {
+TA_DEV int config_key(const AxisDev* axes, const ta_block& d) {
   const int ch = d.log2w >= 3 ? 8 : 4;                  // elements per vector access
   if (d.log2w < 2 || d.log2w > 6 || d.log2h < 2 || d.log2h > 6 || d.in_off < 0 || d.out_off < 0 ||
       d.in_stride < (1 << d.log2w) || d.out_stride < (1 << d.log2w) || d.axis_h >= kAxisIds ||
       d.axis_v >= kAxisIds || ((d.in_off | d.out_off | (int64_t)d.in_stride | (int64_t)d.out_stride) & (ch - 1)))
     return -1;
-  if (a.axes[d.axis_h * kAxisSizes + d.log2w].kind < 0 || a.axes[d.axis_v * kAxisSizes + d.log2h].kind < 0) return -1;
+  if (axes[d.axis_h * kAxisSizes + d.log2w].kind < 0 || axes[d.axis_v * kAxisSizes + d.log2h].kind < 0) return -1;
   return d.log2w | (d.log2h << 3) | (d.axis_h << 6) | (d.axis_v << 14);
 }
 
@@ -1132,7 +1132,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 3 : 4
       const int i = tid + r * 256;
       uint32_t sk = kInvalid;
       if (i < cnt) {
-        const int k = config_key(a, a.blocks[w0 + i]);
+        const int k = config_key(a.axes, a.blocks[w0 + i]);
         if (k >= 0) sk = ((uint32_t)k << 10) | (uint32_t)i;
       }
       skey[i] = sk;
@@ -1190,6 +1190,226 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 3 : 4
   }
 }
 
+
+// ---------------------------------------------------------------- device planning
+// Block lists planned on the device (ta_transform_fwd_ws / _inv_ws).  One
+// workgroup per window of kPlanWin consecutive descriptors:
+//  1. keys (configuration << 12 | position) of the valid descriptors (the
+//     block-list rules, an axis kind of the fast kernels, and rows that span
+//     at most 2^30 elements in the input and the output); the others sort
+//     last and are skipped;
+//  2. a bitonic sort of the window, which groups equal configurations in
+//     list order;
+//  3. tile cuts where the configuration or the row strides change and after
+//     every nb_planned(size) blocks of a run (two scans over the window:
+//     the start of each entry's run, then the tile index of each entry);
+//  4. the tiles go to the list of XCD (window mod kXcds), at slots taken
+//     from that list's counter; each block's deltas are its offsets minus
+//     the window's smallest input and output offsets.  A window whose blocks
+//     span more than 2^30 input or 2^31 output elements makes every block a
+//     tile of its own, based at its own offsets.
+constexpr int kPlanPer = kPlanWin / 256;       // sorted entries per thread (consecutive)
+static_assert(kPlanWin == 4096, "12 position bits in the keys");
+constexpr int64_t kSpanIn = int64_t(1) << 30, kSpanOut = int64_t(1) << 31;
+
+TA_DEV void bitonic_sort_u64(uint64_t* key, int tid) {
+#pragma unroll 1
+  for (int k = 2; k <= kPlanWin; k <<= 1)
+#pragma unroll 1
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kPlanWin / 512; ++r) {
+        const int pr = tid + r * 256;
+        const int lo = ((pr & ~(j - 1)) << 1) | (pr & (j - 1)), hi = lo + j;
+        const uint64_t x = key[lo], y = key[hi];
+        if ((x > y) == ((lo & k) == 0)) {
+          key[lo] = y;
+          key[hi] = x;
+        }
+      }
+    }
+}
+
+// Inclusive scan of the 256 threads' values in part[] (sum, or maximum with
+// MAX), in place (Hillis-Steele).  Barriers before and after.
+template <bool MAX>
+TA_DEV void scan256(int* part, int tid) {
+  __syncthreads();
+#pragma unroll 1
+  for (int o = 1; o < 256; o <<= 1) {
+    const int y = tid >= o ? part[tid - o] : (MAX ? -1 : 0);
+    __syncthreads();
+    part[tid] = MAX ? max(part[tid], y) : part[tid] + y;
+    __syncthreads();
+  }
+}
+
+// the rules of the fast int16 kernels plus the row spans the deltas can hold
+TA_DEV int plan_key(const AxisDev* axes, const ta_block& d) {
+  const int k = config_key(axes, d);
+  if (k < 0) return -1;
+  const int64_t w = int64_t(1) << d.log2w, hm1 = (int64_t(1) << d.log2h) - 1;
+  if (hm1 * d.in_stride + w > kSpanIn || hm1 * d.out_stride + w > kSpanOut) return -1;
+  return k;
+}
+
+__global__ __launch_bounds__(256) void desc_plan(PlanArgs a) {
+  __shared__ uint64_t key[kPlanWin];
+  __shared__ int sc[kPlanWin + 1];     // tile start positions
+  __shared__ int part[256];
+  __shared__ int64_t red[4][4];        // per wave: min in, max in end, min out, max out end
+  __shared__ int base_slot;
+  const int tid = threadIdx.x;
+  const int64_t w0 = (int64_t)blockIdx.x * kPlanWin;
+  const int cnt = (int)min<int64_t>(kPlanWin, a.nblocks - w0);
+  const int xcd = (int)(blockIdx.x % kXcds);
+  // 1. keys, and the window's offset range over its valid blocks
+  int64_t mn_i = INT64_MAX, mx_i = INT64_MIN, mn_o = INT64_MAX, mx_o = INT64_MIN;
+  int nv = 0;
+#pragma unroll 1
+  for (int r = 0; r < kPlanPer; ++r) {
+    const int i = tid + 256 * r;
+    uint64_t k = ~uint64_t(0);
+    if (i < cnt) {
+      const ta_block d = a.blocks[w0 + i];
+      const int c = plan_key(a.axes, d);
+      if (c >= 0) {
+        k = ((uint64_t)c << 12) | (uint64_t)i;
+        ++nv;
+        const int64_t hm1 = (int64_t(1) << d.log2h) - 1, w = int64_t(1) << d.log2w;
+        mn_i = min(mn_i, d.in_off);
+        mx_i = max(mx_i, d.in_off + hm1 * d.in_stride + w);
+        mn_o = min(mn_o, d.out_off);
+        mx_o = max(mx_o, d.out_off + hm1 * d.out_stride + w);
+      }
+    }
+    key[i] = k;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mn_i = min(mn_i, (int64_t)__shfl_xor((long long)mn_i, o));
+    mx_i = max(mx_i, (int64_t)__shfl_xor((long long)mx_i, o));
+    mn_o = min(mn_o, (int64_t)__shfl_xor((long long)mn_o, o));
+    mx_o = max(mx_o, (int64_t)__shfl_xor((long long)mx_o, o));
+  }
+  if ((tid & 63) == 0) {
+    red[tid >> 6][0] = mn_i;
+    red[tid >> 6][1] = mx_i;
+    red[tid >> 6][2] = mn_o;
+    red[tid >> 6][3] = mx_o;
+  }
+  part[tid] = nv;
+  scan256<false>(part, tid);
+  const int nvalid = part[255];
+  // 2. sort (valid keys first, in configuration and list order)
+  bitonic_sort_u64(key, tid);
+  __syncthreads();
+  const int64_t wmin_i = min(min(red[0][0], red[1][0]), min(red[2][0], red[3][0]));
+  const int64_t wmax_i = max(max(red[0][1], red[1][1]), max(red[2][1], red[3][1]));
+  const int64_t wmin_o = min(min(red[0][2], red[1][2]), min(red[2][2], red[3][2]));
+  const int64_t wmax_o = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3]));
+  const bool own = nvalid > 0 && (wmax_i - wmin_i > kSpanIn || wmax_o - wmin_o > kSpanOut);
+  // 3. this thread's consecutive sorted entries [e0, e0 + kPlanPer): run starts
+  const int e0 = tid * kPlanPer;
+  int last_start = -1;                 // the last run start among this thread's entries
+  uint32_t starts = 0;                 // bit e: entry e0 + e starts a run
+#pragma unroll 1
+  for (int e = 0; e < kPlanPer; ++e) {
+    const int i = e0 + e;
+    if (i >= nvalid) break;
+    bool st = i == 0 || own;
+    if (!st) {
+      const uint64_t k1 = key[i], k0 = key[i - 1];
+      if ((k1 >> 12) != (k0 >> 12)) {
+        st = true;
+      } else {
+        const ta_block& d1 = a.blocks[w0 + (int)(k1 & (kPlanWin - 1))];
+        const ta_block& d0 = a.blocks[w0 + (int)(k0 & (kPlanWin - 1))];
+        st = d1.in_stride != d0.in_stride || d1.out_stride != d0.out_stride;
+      }
+    }
+    if (st) {
+      starts |= 1u << e;
+      last_start = i;
+    }
+  }
+  part[tid] = last_start;
+  scan256<true>(part, tid);
+  int run0 = tid > 0 ? part[tid - 1] : -1;   // the run start before this thread's entries
+  __syncthreads();
+  // tile cuts: a run start, or every nb_planned blocks into a run
+  uint32_t cuts = 0;
+  int ncut = 0;
+#pragma unroll 1
+  for (int e = 0; e < kPlanPer; ++e) {
+    const int i = e0 + e;
+    if (i >= nvalid) break;
+    if (starts & (1u << e)) run0 = i;
+    const uint32_t c = (uint32_t)(key[i] >> 12);
+    const int cap = BatchGeo::nb_planned((int)(c & 7), (int)((c >> 3) & 7));
+    if ((i - run0) % cap == 0) {
+      cuts |= 1u << e;
+      ++ncut;
+    }
+  }
+  part[tid] = ncut;
+  scan256<false>(part, tid);
+  const int ntiles = part[255];
+  int tile = (tid > 0 ? part[tid - 1] : 0) - 1;     // tile index of the entry being visited
+  // 4. slots in this XCD's list; tile start positions
+  if (tid == 0) base_slot = ntiles > 0 ? __hip_atomic_fetch_add(a.count + xcd, ntiles, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT)
+                                       : 0;
+#pragma unroll 1
+  for (int e = 0; e < kPlanPer; ++e) {
+    const int i = e0 + e;
+    if (i >= nvalid) break;
+    if (cuts & (1u << e)) sc[++tile] = i;
+  }
+  if (tid == 0) sc[ntiles] = nvalid;
+  __syncthreads();
+  const int64_t slot0 = (int64_t)xcd * a.cap + base_slot;
+  if (base_slot + ntiles > a.cap) return;   // (cannot happen: the lists hold every window's blocks)
+  tile = (tid > 0 ? part[tid - 1] : 0) - 1;
+#pragma unroll 1
+  for (int e = 0; e < kPlanPer; ++e) {
+    const int i = e0 + e;
+    if (i >= nvalid) break;
+    const uint64_t k = key[i];
+    const ta_block d = a.blocks[w0 + (int)(k & (kPlanWin - 1))];
+    const int64_t ib = own ? d.in_off : wmin_i, ob = own ? d.out_off : wmin_o;
+    a.deltas[2 * (w0 + i)] = (int32_t)(d.in_off - ib);
+    a.deltas[2 * (w0 + i) + 1] = (int32_t)(d.out_off - ob);
+    if (cuts & (1u << e)) {
+      ++tile;
+      const int lw = d.log2w, lh = d.log2h;
+      const AxisDev& h = a.axes[d.axis_h * kAxisSizes + lw];
+      const AxisDev& v = a.axes[d.axis_v * kAxisSizes + lh];
+      BatchTile t;
+      t.lw = lw;
+      t.lh = lh;
+      t.kind_h = h.kind;
+      t.kind_v = v.kind;
+      t.first = w0 + i;
+      t.count = sc[tile + 1] - i;
+      t.in_stride = d.in_stride;
+      t.ph_f = h.pf;
+      t.ph_i = h.pi;
+      t.pv_f = v.pf;
+      t.pv_i = v.pi;
+      t.in_base = ib;
+      t.out_base = ob;
+      t.out_stride = d.out_stride;
+      t.pad = 0;
+      a.tiles[slot0 + tile] = t;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void zero_words(int32_t* p, int n) {
+  for (int i = threadIdx.x; i < n; i += 256) p[i] = 0;
+}
 }  // namespace
 
 const void* batch_kernel(int inv, int desc, int f32) {
@@ -1202,5 +1422,8 @@ const void* batch_kernel(int inv, int desc, int f32) {
   if (f32) return inv ? reinterpret_cast<const void*>(&batch_f32<true>) : reinterpret_cast<const void*>(&batch_f32<false>);
   return inv ? reinterpret_cast<const void*>(&batch_inv) : reinterpret_cast<const void*>(&batch_fwd);
 }
+
+const void* desc_plan_kernel() { return reinterpret_cast<const void*>(&desc_plan); }
+const void* zero_words_kernel() { return reinterpret_cast<const void*>(&zero_words); }
 
 }  // namespace ta

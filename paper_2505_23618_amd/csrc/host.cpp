@@ -1427,6 +1427,106 @@ int run_blocks(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void
   return TA_OK;
 }
 
+// Workspace of a device-planned block list: tile counters per XCD list, the
+// consumer's schedule counters, block deltas, then kXcds tile lists of `cap`
+// tiles (a window's tiles go to one list; a list holds every tile its
+// windows can produce).
+struct WsLayout {
+  int64_t cap, sched_off, deltas_off, tiles_off, bytes;
+};
+WsLayout ws_layout(int64_t n) {
+  WsLayout L;
+  const int64_t nwin = (n + ta::kPlanWin - 1) / ta::kPlanWin;
+  L.cap = (nwin + ta::kXcds - 1) / ta::kXcds * ta::kPlanWin;
+  auto up = [](int64_t v) { return (v + 255) & ~int64_t(255); };
+  L.sched_off = 256;
+  L.deltas_off = up(L.sched_off + 4 * ta::kSchedDwords);
+  L.tiles_off = up(L.deltas_off + 8 * n);
+  L.bytes = L.tiles_off + (int64_t)sizeof(ta::BatchTile) * ta::kXcds * L.cap;
+  return L;
+}
+
+int run_blocks_ws(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void* in, void* out, int dtype,
+                  void* ws, int64_t ws_bytes, ta_stream_t stream) {
+  if (!c) return fail(TA_EINVAL, "null context");
+  if (n < 0) return fail(TA_EINVAL, "negative block count");
+  if (dtype != TA_I16 && dtype != TA_F32) return fail(TA_EINVAL, "unknown dtype %d", dtype);
+  if (n == 0) return TA_OK;
+  // fp32, and m != 8 (no fast kinds), run as the unplanned lists do
+  if (dtype == TA_F32 || c->m != 8) return run_blocks(c, inv, blocks, n, in, out, dtype, stream);
+  if (!blocks || !in || !out) return fail(TA_EINVAL, "null buffer");
+  if (in == out) return fail(TA_EINVAL, "input and output alias");
+  if ((uintptr_t)blocks & 7) return fail(TA_EINVAL, "descriptors must be 8-byte aligned");
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return fail(TA_EINVAL, "buffers must be 16-byte aligned");
+  const WsLayout L = ws_layout(n);
+  if (!ws || ((uintptr_t)ws & 255)) return fail(TA_EINVAL, "workspace must be non-null and 256-byte aligned");
+  if (ws_bytes < L.bytes)
+    return fail(TA_EINVAL, "workspace of %lld bytes, %lld needed", (long long)ws_bytes, (long long)L.bytes);
+  if (ta::kXcds * L.cap > INT32_MAX) return fail(TA_EUNSUPPORTED, "block list too long for int32 tile indices");
+  char* w = static_cast<char*>(ws);
+  int32_t* counts = reinterpret_cast<int32_t*>(w);
+  int32_t* sched = reinterpret_cast<int32_t*>(w + L.sched_off);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  TA_ON_DEVICE(c->device);
+  // counters to zero (a kernel, so that the call stays capturable)
+  int32_t* zp = counts;
+  int zn = (int)(L.deltas_off / 4);
+  void* zargs[] = {&zp, &zn};
+  TA_HIP(hipLaunchKernel(ta::zero_words_kernel(), dim3(1), dim3(256), zargs, 0, s));
+  ta::PlanArgs pa{};
+  pa.blocks = blocks;
+  pa.nblocks = n;
+  pa.axes = c->axes_dev;
+  pa.tiles = reinterpret_cast<ta::BatchTile*>(w + L.tiles_off);
+  pa.deltas = reinterpret_cast<int32_t*>(w + L.deltas_off);
+  pa.count = counts;
+  pa.cap = L.cap;
+  void* pargs[] = {&pa};
+  const int64_t nwin = (n + ta::kPlanWin - 1) / ta::kPlanWin;
+  if (nwin > INT32_MAX) return fail(TA_EUNSUPPORTED, "block list too long");
+  TA_HIP(hipLaunchKernel(ta::desc_plan_kernel(), dim3((unsigned)nwin), dim3(256), pargs, 0, s));
+  // the planned kernel over the lists, one resident grid taking tiles from
+  // the schedule counters
+  const void* fn = ta::batch_kernel(inv, 0, 0);
+  int res = 0, e;
+  if ((e = resident_groups(fn, 256, c->device, &res))) return e;
+  ta::BatchArgs args{};
+  args.tiles = pa.tiles;
+  args.ntiles = ta::kXcds * L.cap;
+  for (int x = 0; x <= ta::kXcds; ++x) args.xstart[x] = x * L.cap;
+  args.xcount = counts;
+  args.deltas = pa.deltas;
+  args.sched = sched;
+  args.in = static_cast<const int16_t*>(in);
+  args.out = static_cast<int16_t*>(out);
+  args.bd = c->bd;
+  args.m = c->m;
+  args.a = c->a;
+  void* kargs[] = {&args};
+  TA_HIP(hipLaunchKernel(fn, dim3((unsigned)std::max(res, ta::kXcds)), dim3(256), kargs, 0, s));
+  if (c->ngeneral > 0) {
+    // descriptors with an axis outside the fast kinds: the general kernel
+    // over the same list (it skips the others), as for unplanned lists
+    const int64_t sortwin = (int64_t)ta::kDescWindow * ta::kSortQuarters;
+    const int64_t units = (n + sortwin - 1) / sortwin * ta::kSortQuarters;
+    const int64_t g = std::max<int64_t>(ta::kXcds, std::min<int64_t>(units, 0x7fffffff));
+    ta::GenArgs ga{};
+    ga.blocks = blocks;
+    ga.in = in;
+    ga.out = out;
+    ga.inv = inv;
+    ga.bd = c->bd;
+    ga.m = c->m;
+    ga.a = c->a;
+    ga.nblocks = n;
+    ga.progs = c->gprogs_dev[0];
+    ga.fast = c->axes_dev;
+    void* gargs[] = {&ga};
+    TA_HIP(hipLaunchKernel(ta::gen_kernel(1, 0), dim3((unsigned)g), dim3(256), gargs, 0, s));
+  }
+  return TA_OK;
+}
+
 // Last element (exclusive) a block touches at (off, stride), or -1 past `limit`.
 int64_t block_end(int64_t off, int32_t stride, int w, int h, int64_t limit) {
   if (off > limit) return -1;
@@ -1446,6 +1546,23 @@ int ta_transform_fwd(ta_ctx* c, const ta_block* blocks_dev, int64_t nblocks, con
 int ta_transform_inv(ta_ctx* c, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out, int dtype,
                      ta_stream_t stream) {
   return run_blocks(c, 1, blocks_dev, nblocks, in, out, dtype, stream);
+}
+
+int ta_transform_workspace(int64_t nblocks, int64_t* bytes) {
+  if (!bytes || nblocks < 0) return fail(TA_EINVAL, "null argument or negative block count");
+  if (nblocks > (int64_t(1) << 40)) return fail(TA_EINVAL, "block count above 2^40");
+  *bytes = nblocks ? ws_layout(nblocks).bytes : 0;
+  return TA_OK;
+}
+
+int ta_transform_fwd_ws(ta_ctx* c, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out, int dtype,
+                        void* workspace, int64_t workspace_bytes, ta_stream_t stream) {
+  return run_blocks_ws(c, 0, blocks_dev, nblocks, in, out, dtype, workspace, workspace_bytes, stream);
+}
+
+int ta_transform_inv_ws(ta_ctx* c, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out, int dtype,
+                        void* workspace, int64_t workspace_bytes, ta_stream_t stream) {
+  return run_blocks_ws(c, 1, blocks_dev, nblocks, in, out, dtype, workspace, workspace_bytes, stream);
 }
 
 int ta_validate_blocks(ta_ctx* c, const ta_block* blocks_dev, int64_t n, int64_t in_elems, int64_t out_elems,

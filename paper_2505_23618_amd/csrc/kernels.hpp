@@ -164,6 +164,9 @@ struct BatchArgs {
   int64_t xstart[kXcds + 1];
   const ta_block* blocks;
   const int32_t* deltas;  // planned int16: (in_delta, out_delta) per block
+  // planned int16: tiles per XCD list in device memory (list x is
+  // tiles[xstart[x] .. xstart[x] + xcount[x])), or null for xstart[x + 1]
+  const int32_t* xcount;
   // planned int16: the tile counters of the dynamic schedule (one per XCD
   // list, then the count of finished workgroups, kSchedPitch dwords apart;
   // zero between launches), or null for a static grid stride
@@ -181,6 +184,23 @@ struct BatchArgs {
 // (desc = 0) or directly over a device array of block descriptors (desc = 1);
 // int16 fixed point, or fp32 with f32 = 1.
 const void* batch_kernel(int inv, int desc = 0, int f32 = 0);
+
+// Block lists planned on the device (ta_transform_fwd_ws / _inv_ws): one
+// workgroup per window of kPlanWin consecutive descriptors writes the
+// window's tiles and block deltas for the planned int16 kernels.
+constexpr int kPlanWin = 4096;
+struct PlanArgs {
+  const ta_block* blocks;
+  int64_t nblocks;
+  const AxisDev* axes;    // kAxisIds x kAxisSizes
+  BatchTile* tiles;       // kXcds lists of `cap` tiles (list x from x * cap)
+  int32_t* deltas;        // (in_delta, out_delta) by window and sorted position
+  int32_t* count;         // tiles written to each list (zero before the launch)
+  int64_t cap;
+};
+const void* desc_plan_kernel();
+// zeroes n dwords (one workgroup; the counters of a device-planned call)
+const void* zero_words_kernel();
 
 // Encoder evaluation of the five separable transforms (multi_kernels.hip):
 // out holds 5 consecutive packed batches of nblocks N x N int16 blocks.

@@ -86,6 +86,18 @@ def test_block_list_entry_points_reject_bad_arguments_without_gpu():
     nb = ctypes.c_int(0)
     assert lib.ta_plan_tile_blocks(None, 3, 3, ctypes.byref(nb)) == ta.TA_EINVAL
     assert lib.ta_plan_set_tile_blocks(None, 3, 3, 1) == ta.TA_EINVAL
+    assert lib.ta_transform_fwd_ws(None, None, 1, None, None, ta.I16, None, 0, None) == ta.TA_EINVAL
+    assert lib.ta_transform_inv_ws(None, None, 1, None, None, ta.I16, None, 0, None) == ta.TA_EINVAL
+    ws = ctypes.c_int64(-1)
+    assert lib.ta_transform_workspace(-1, ctypes.byref(ws)) == ta.TA_EINVAL
+    assert lib.ta_transform_workspace(5, None) == ta.TA_EINVAL
+    assert lib.ta_transform_workspace(0, ctypes.byref(ws)) == ta.TA_OK and ws.value == 0
+    sizes = []
+    for n in (1, 4096, 4097, 582094):
+        assert lib.ta_transform_workspace(n, ctypes.byref(ws)) == ta.TA_OK
+        sizes.append(ws.value)
+    # 8 bytes of deltas and at least one 80-byte tile slot per block
+    assert all(s >= 88 * n for s, n in zip(sizes, (1, 4096, 4097, 582094))) and sizes == sorted(sizes)
     lay = np.array([ta.ADJ_BAND, 8, 4], np.int32)
     a = np.zeros(64, np.int16)
     f = np.zeros(64, np.float32)
