@@ -309,9 +309,9 @@ int ta_transform_inv(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, c
  * ta_transform_workspace gives for nblocks; the caller owns it; its contents
  * need no initialisation and are scratch after the call).  For int16 at m = 8
  * a first kernel plans the list: windows of 4096 consecutive descriptors are
- * sorted by configuration (size and axis ids) in list order and cut into
- * tiles of equal configuration and row strides, which the pipelined planned
- * kernels then run in one launch.  The tiles are larger than the in-window
+ * grouped by configuration (size and axis ids) and cut into tiles of equal
+ * configuration and row strides, which the pipelined planned kernels then
+ * run in one launch.  The tiles are larger than the in-window
  * groups of ta_transform_fwd, so throughput is closer to a plan's.  One more
  * rule applies here: a block whose rows span more than 2^30 input or 2^31
  * output elements ((h - 1) * stride + w) is skipped.  fp32 lists and

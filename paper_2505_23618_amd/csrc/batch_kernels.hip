@@ -1194,55 +1194,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F32 ? 3 : 4
 // ---------------------------------------------------------------- device planning
 // Block lists planned on the device (ta_transform_fwd_ws / _inv_ws).  One
 // workgroup per window of kPlanWin consecutive descriptors:
-//  1. keys (configuration << 12 | position) of the valid descriptors (the
-//     block-list rules, an axis kind of the fast kernels, and rows that span
-//     at most 2^30 elements in the input and the output); the others sort
-//     last and are skipped;
-//  2. a bitonic sort of the window, which groups equal configurations in
-//     list order;
+//  1. the valid descriptors (the block-list rules, an axis kind of the fast
+//     kernels, and rows that span at most 2^30 input and 2^31 output
+//     elements) enter their configuration (size and axis ids) in a hash
+//     table in LDS and take a rank in its slot; the others are skipped;
+//  2. a scan over the slots' counts groups the window by configuration;
 //  3. tile cuts where the configuration or the row strides change and after
-//     every nb_planned(size) blocks of a run (two scans over the window:
-//     the start of each entry's run, then the tile index of each entry);
+//     every nb_planned(size) blocks of a run (two scans: the start of each
+//     entry's run, then the tile index of each entry);
 //  4. the tiles go to the list of XCD (window mod kXcds), at slots taken
 //     from that list's counter; each block's deltas are its offsets minus
 //     the window's smallest input and output offsets.  A window whose blocks
 //     span more than 2^30 input or 2^31 output elements makes every block a
 //     tile of its own, based at its own offsets.
-constexpr int kPlanPer = kPlanWin / 256;       // sorted entries per thread (consecutive)
-static_assert(kPlanWin == 4096, "12 position bits in the keys");
+constexpr int kPlanPer = kPlanWin / kPlanThreads;     // grouped entries per thread (consecutive)
 constexpr int64_t kSpanIn = int64_t(1) << 30, kSpanOut = int64_t(1) << 31;
 
-TA_DEV void bitonic_sort_u64(uint64_t* key, int tid) {
-#pragma unroll 1
-  for (int k = 2; k <= kPlanWin; k <<= 1)
-#pragma unroll 1
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < kPlanWin / 512; ++r) {
-        const int pr = tid + r * 256;
-        const int lo = ((pr & ~(j - 1)) << 1) | (pr & (j - 1)), hi = lo + j;
-        const uint64_t x = key[lo], y = key[hi];
-        if ((x > y) == ((lo & k) == 0)) {
-          key[lo] = y;
-          key[hi] = x;
-        }
-      }
-    }
-}
-
-// Inclusive scan of the 256 threads' values in part[] (sum, or maximum with
-// MAX), in place (Hillis-Steele).  Barriers before and after.
+// Scan of the threads' values (sum, or maximum with MAX) across the
+// workgroup: within each wave by shuffles, then over the wave totals in
+// wsum.  Returns the exclusive result (0, or -1 with MAX, for thread 0) and
+// the total in *total.  Two barriers.
 template <bool MAX>
-TA_DEV void scan256(int* part, int tid) {
-  __syncthreads();
-#pragma unroll 1
-  for (int o = 1; o < 256; o <<= 1) {
-    const int y = tid >= o ? part[tid - o] : (MAX ? -1 : 0);
-    __syncthreads();
-    part[tid] = MAX ? max(part[tid], y) : part[tid] + y;
-    __syncthreads();
+TA_DEV int scan_excl(int v, int* wsum, int tid, int* total) {
+  constexpr int kWaves = kPlanThreads / 64, kId = MAX ? -1 : 0;
+  const int lane = tid & 63, wave = tid >> 6;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if (lane >= o) inc = MAX ? max(inc, y) : inc + y;
   }
+  int exc = __shfl_up(inc, 1);
+  if (lane == 0) exc = kId;
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  int pre = kId, tot = kId;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const int x = wsum[w];
+    if (w < wave) pre = MAX ? max(pre, x) : pre + x;
+    tot = MAX ? max(tot, x) : tot + x;
+  }
+  __syncthreads();                     // wsum is free for the next scan
+  *total = tot;
+  return MAX ? max(pre, exc) : pre + exc;
 }
 
 // the rules of the fast int16 kernels plus the row spans the deltas can hold
@@ -1254,38 +1249,64 @@ TA_DEV int plan_key(const AxisDev* axes, const ta_block& d) {
   return k;
 }
 
-__global__ __launch_bounds__(256) void desc_plan(PlanArgs a) {
-  __shared__ uint64_t key[kPlanWin];
-  __shared__ int sc[kPlanWin + 1];     // tile start positions
-  __shared__ int part[256];
-  __shared__ int64_t red[4][4];        // per wave: min in, max in end, min out, max out end
+__global__ __launch_bounds__(kPlanThreads) void desc_plan(PlanArgs a) {
+  constexpr int kWaves = kPlanThreads / 64;
+  constexpr uint32_t kEmpty = ~0u;     // above every configuration key (22 bits)
+  __shared__ uint32_t hkey[kPlanWin + 1];   // hash table of configurations; later the tile starts
+  __shared__ int hcnt[kPlanWin];            // blocks per table slot, then the slot's first position
+  __shared__ int order[kPlanWin];           // grouped position -> window entry
+  __shared__ int wsum[kWaves];
+  __shared__ int64_t red[kWaves][4];   // per wave: min in, max in end, min out, max out end
   __shared__ int base_slot;
+  int* sc = reinterpret_cast<int*>(hkey);
   const int tid = threadIdx.x;
   const int64_t w0 = (int64_t)blockIdx.x * kPlanWin;
   const int cnt = (int)min<int64_t>(kPlanWin, a.nblocks - w0);
   const int xcd = (int)(blockIdx.x % kXcds);
-  // 1. keys, and the window's offset range over its valid blocks
-  int64_t mn_i = INT64_MAX, mx_i = INT64_MIN, mn_o = INT64_MAX, mx_o = INT64_MIN;
-  int nv = 0;
-#pragma unroll 1
+#pragma unroll
   for (int r = 0; r < kPlanPer; ++r) {
-    const int i = tid + 256 * r;
-    uint64_t k = ~uint64_t(0);
-    if (i < cnt) {
-      const ta_block d = a.blocks[w0 + i];
-      const int c = plan_key(a.axes, d);
-      if (c >= 0) {
-        k = ((uint64_t)c << 12) | (uint64_t)i;
-        ++nv;
-        const int64_t hm1 = (int64_t(1) << d.log2h) - 1, w = int64_t(1) << d.log2w;
-        mn_i = min(mn_i, d.in_off);
-        mx_i = max(mx_i, d.in_off + hm1 * d.in_stride + w);
-        mn_o = min(mn_o, d.out_off);
-        mx_o = max(mx_o, d.out_off + hm1 * d.out_stride + w);
+    hkey[tid + kPlanThreads * r] = kEmpty;
+    hcnt[tid + kPlanThreads * r] = 0;
+  }
+  __syncthreads();
+  // 1. each valid descriptor finds its configuration's slot in the table
+  //    (open addressing: at most kPlanWin keys in kPlanWin slots, so a free
+  //    slot always exists) and takes a rank in it; the window's offset range
+  //    over its valid blocks.  The loads of a thread's descriptors are
+  //    issued together.
+  int64_t mn_i = INT64_MAX, mx_i = INT64_MIN, mn_o = INT64_MAX, mx_o = INT64_MIN;
+  uint32_t slot_rank[kPlanPer];        // slot << 12 | rank, or kEmpty
+  {
+    ta_block d[kPlanPer];
+#pragma unroll
+    for (int r = 0; r < kPlanPer; ++r) {
+      const int i = tid + kPlanThreads * r;
+      if (i < cnt) d[r] = a.blocks[w0 + i];
+    }
+#pragma unroll
+    for (int r = 0; r < kPlanPer; ++r) {
+      const int i = tid + kPlanThreads * r;
+      slot_rank[r] = kEmpty;
+      if (i < cnt) {
+        const int c = plan_key(a.axes, d[r]);
+        if (c >= 0) {
+          uint32_t sl = ((uint32_t)c * 0x9E3779B1u) >> (32 - 12);
+          for (;;) {
+            const uint32_t old = atomicCAS(&hkey[sl], kEmpty, (uint32_t)c);
+            if (old == kEmpty || old == (uint32_t)c) break;
+            sl = (sl + 1) & (kPlanWin - 1);
+          }
+          slot_rank[r] = (sl << 12) | (uint32_t)atomicAdd(&hcnt[sl], 1);
+          const int64_t hm1 = (int64_t(1) << d[r].log2h) - 1, w = int64_t(1) << d[r].log2w;
+          mn_i = min(mn_i, d[r].in_off);
+          mx_i = max(mx_i, d[r].in_off + hm1 * d[r].in_stride + w);
+          mn_o = min(mn_o, d[r].out_off);
+          mx_o = max(mx_o, d[r].out_off + hm1 * d[r].out_stride + w);
+        }
       }
     }
-    key[i] = k;
   }
+  static_assert(kPlanWin == 1 << 12, "12-bit slots and ranks");
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     mn_i = min(mn_i, (int64_t)__shfl_xor((long long)mn_i, o));
@@ -1299,93 +1320,111 @@ __global__ __launch_bounds__(256) void desc_plan(PlanArgs a) {
     red[tid >> 6][2] = mn_o;
     red[tid >> 6][3] = mx_o;
   }
-  part[tid] = nv;
-  scan256<false>(part, tid);
-  const int nvalid = part[255];
-  // 2. sort (valid keys first, in configuration and list order)
-  bitonic_sort_u64(key, tid);
   __syncthreads();
-  const int64_t wmin_i = min(min(red[0][0], red[1][0]), min(red[2][0], red[3][0]));
-  const int64_t wmax_i = max(max(red[0][1], red[1][1]), max(red[2][1], red[3][1]));
-  const int64_t wmin_o = min(min(red[0][2], red[1][2]), min(red[2][2], red[3][2]));
-  const int64_t wmax_o = max(max(red[0][3], red[1][3]), max(red[2][3], red[3][3]));
-  const bool own = nvalid > 0 && (wmax_i - wmin_i > kSpanIn || wmax_o - wmin_o > kSpanOut);
-  // 3. this thread's consecutive sorted entries [e0, e0 + kPlanPer): run starts
-  const int e0 = tid * kPlanPer;
-  int last_start = -1;                 // the last run start among this thread's entries
-  uint32_t starts = 0;                 // bit e: entry e0 + e starts a run
-#pragma unroll 1
-  for (int e = 0; e < kPlanPer; ++e) {
-    const int i = e0 + e;
-    if (i >= nvalid) break;
-    bool st = i == 0 || own;
-    if (!st) {
-      const uint64_t k1 = key[i], k0 = key[i - 1];
-      if ((k1 >> 12) != (k0 >> 12)) {
-        st = true;
-      } else {
-        const ta_block& d1 = a.blocks[w0 + (int)(k1 & (kPlanWin - 1))];
-        const ta_block& d0 = a.blocks[w0 + (int)(k0 & (kPlanWin - 1))];
-        st = d1.in_stride != d0.in_stride || d1.out_stride != d0.out_stride;
-      }
+  // 2. group the entries by slot: the slots' first positions (a scan over the
+  //    table, this thread's slots 4 tid .. 4 tid + 3), then each entry's
+  //    grouped position
+  int nvalid;
+  {
+    int c4[kPlanPer], sum = 0;
+#pragma unroll
+    for (int e = 0; e < kPlanPer; ++e) {
+      c4[e] = hcnt[tid * kPlanPer + e];
+      sum += c4[e];
     }
-    if (st) {
-      starts |= 1u << e;
-      last_start = i;
+    int pre = scan_excl<false>(sum, wsum, tid, &nvalid);
+#pragma unroll
+    for (int e = 0; e < kPlanPer; ++e) {
+      hcnt[tid * kPlanPer + e] = pre;
+      pre += c4[e];
     }
   }
-  part[tid] = last_start;
-  scan256<true>(part, tid);
-  int run0 = tid > 0 ? part[tid - 1] : -1;   // the run start before this thread's entries
   __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kPlanPer; ++r)
+    if (slot_rank[r] != kEmpty)
+      order[hcnt[slot_rank[r] >> 12] + (int)(slot_rank[r] & (kPlanWin - 1))] = tid + kPlanThreads * r;
+  __syncthreads();
+  int64_t wmin_i = INT64_MAX, wmax_i = INT64_MIN, wmin_o = INT64_MAX, wmax_o = INT64_MIN;
+#pragma unroll
+  for (int v = 0; v < kWaves; ++v) {
+    wmin_i = min(wmin_i, red[v][0]);
+    wmax_i = max(wmax_i, red[v][1]);
+    wmin_o = min(wmin_o, red[v][2]);
+    wmax_o = max(wmax_o, red[v][3]);
+  }
+  const bool own = nvalid > 0 && (wmax_i - wmin_i > kSpanIn || wmax_o - wmin_o > kSpanOut);
+  // 3. this thread's consecutive grouped entries [e0, e0 + kPlanPer): their
+  //    descriptors (and the one before the first), run starts
+  const int e0 = tid * kPlanPer;
+  ta_block d[kPlanPer + 1];            // d[0]: entry e0 - 1
+#pragma unroll
+  for (int e = 0; e <= kPlanPer; ++e) {
+    const int i = e0 + e - 1;
+    if (i >= 0 && i < nvalid) d[e] = a.blocks[w0 + order[i]];
+  }
+  int last_start = -1;                 // the last run start among this thread's entries
+  uint32_t starts = 0;                 // bit e: entry e0 + e starts a run
+#pragma unroll
+  for (int e = 0; e < kPlanPer; ++e) {
+    const int i = e0 + e;
+    if (i < nvalid) {
+      const ta_block &p = d[e], &q = d[e + 1];
+      const bool st = i == 0 || own || q.log2w != p.log2w || q.log2h != p.log2h || q.axis_h != p.axis_h ||
+                      q.axis_v != p.axis_v || q.in_stride != p.in_stride || q.out_stride != p.out_stride;
+      if (st) {
+        starts |= 1u << e;
+        last_start = i;
+      }
+    }
+  }
+  int last_any;
+  int run0 = scan_excl<true>(last_start, wsum, tid, &last_any);   // the run start before this thread's entries
   // tile cuts: a run start, or every nb_planned blocks into a run
   uint32_t cuts = 0;
   int ncut = 0;
-#pragma unroll 1
+#pragma unroll
   for (int e = 0; e < kPlanPer; ++e) {
     const int i = e0 + e;
-    if (i >= nvalid) break;
-    if (starts & (1u << e)) run0 = i;
-    const uint32_t c = (uint32_t)(key[i] >> 12);
-    const int cap = BatchGeo::nb_planned((int)(c & 7), (int)((c >> 3) & 7));
-    if ((i - run0) % cap == 0) {
-      cuts |= 1u << e;
-      ++ncut;
+    if (i < nvalid) {
+      if (starts & (1u << e)) run0 = i;
+      const int cap = BatchGeo::nb_planned(d[e + 1].log2w, d[e + 1].log2h);
+      if ((i - run0) % cap == 0) {
+        cuts |= 1u << e;
+        ++ncut;
+      }
     }
   }
-  part[tid] = ncut;
-  scan256<false>(part, tid);
-  const int ntiles = part[255];
-  int tile = (tid > 0 ? part[tid - 1] : 0) - 1;     // tile index of the entry being visited
+  int ntiles;
+  const int tile0 = scan_excl<false>(ncut, wsum, tid, &ntiles) - 1;   // tile index before this thread's entries
   // 4. slots in this XCD's list; tile start positions
-  if (tid == 0) base_slot = ntiles > 0 ? __hip_atomic_fetch_add(a.count + xcd, ntiles, __ATOMIC_RELAXED,
-                                                                 __HIP_MEMORY_SCOPE_AGENT)
-                                       : 0;
-#pragma unroll 1
-  for (int e = 0; e < kPlanPer; ++e) {
-    const int i = e0 + e;
-    if (i >= nvalid) break;
-    if (cuts & (1u << e)) sc[++tile] = i;
+  if (tid == 0)
+    base_slot = ntiles > 0 ? __hip_atomic_fetch_add(a.count + xcd, ntiles, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : 0;
+  {
+    int tile = tile0;
+#pragma unroll
+    for (int e = 0; e < kPlanPer; ++e)
+      if (cuts & (1u << e)) sc[++tile] = e0 + e;
   }
   if (tid == 0) sc[ntiles] = nvalid;
   __syncthreads();
   const int64_t slot0 = (int64_t)xcd * a.cap + base_slot;
   if (base_slot + ntiles > a.cap) return;   // (cannot happen: the lists hold every window's blocks)
-  tile = (tid > 0 ? part[tid - 1] : 0) - 1;
-#pragma unroll 1
+  int tile = tile0;
+#pragma unroll
   for (int e = 0; e < kPlanPer; ++e) {
     const int i = e0 + e;
-    if (i >= nvalid) break;
-    const uint64_t k = key[i];
-    const ta_block d = a.blocks[w0 + (int)(k & (kPlanWin - 1))];
-    const int64_t ib = own ? d.in_off : wmin_i, ob = own ? d.out_off : wmin_o;
-    a.deltas[2 * (w0 + i)] = (int32_t)(d.in_off - ib);
-    a.deltas[2 * (w0 + i) + 1] = (int32_t)(d.out_off - ob);
+    if (i >= nvalid) continue;
+    const ta_block& b = d[e + 1];
+    const int64_t ib = own ? b.in_off : wmin_i, ob = own ? b.out_off : wmin_o;
+    a.deltas[2 * (w0 + i)] = (int32_t)(b.in_off - ib);
+    a.deltas[2 * (w0 + i) + 1] = (int32_t)(b.out_off - ob);
     if (cuts & (1u << e)) {
       ++tile;
-      const int lw = d.log2w, lh = d.log2h;
-      const AxisDev& h = a.axes[d.axis_h * kAxisSizes + lw];
-      const AxisDev& v = a.axes[d.axis_v * kAxisSizes + lh];
+      const int lw = b.log2w, lh = b.log2h;
+      const AxisDev& h = a.axes[b.axis_h * kAxisSizes + lw];
+      const AxisDev& v = a.axes[b.axis_v * kAxisSizes + lh];
       BatchTile t;
       t.lw = lw;
       t.lh = lh;
@@ -1393,14 +1432,14 @@ __global__ __launch_bounds__(256) void desc_plan(PlanArgs a) {
       t.kind_v = v.kind;
       t.first = w0 + i;
       t.count = sc[tile + 1] - i;
-      t.in_stride = d.in_stride;
+      t.in_stride = b.in_stride;
       t.ph_f = h.pf;
       t.ph_i = h.pi;
       t.pv_f = v.pf;
       t.pv_i = v.pi;
       t.in_base = ib;
       t.out_base = ob;
-      t.out_stride = d.out_stride;
+      t.out_stride = b.out_stride;
       t.pad = 0;
       a.tiles[slot0 + tile] = t;
     }

@@ -1484,7 +1484,7 @@ int run_blocks_ws(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const v
   void* pargs[] = {&pa};
   const int64_t nwin = (n + ta::kPlanWin - 1) / ta::kPlanWin;
   if (nwin > INT32_MAX) return fail(TA_EUNSUPPORTED, "block list too long");
-  TA_HIP(hipLaunchKernel(ta::desc_plan_kernel(), dim3((unsigned)nwin), dim3(256), pargs, 0, s));
+  TA_HIP(hipLaunchKernel(ta::desc_plan_kernel(), dim3((unsigned)nwin), dim3(ta::kPlanThreads), pargs, 0, s));
   // the planned kernel over the lists, one resident grid taking tiles from
   // the schedule counters
   const void* fn = ta::batch_kernel(inv, 0, 0);

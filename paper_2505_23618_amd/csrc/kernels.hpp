@@ -189,12 +189,13 @@ const void* batch_kernel(int inv, int desc = 0, int f32 = 0);
 // workgroup per window of kPlanWin consecutive descriptors writes the
 // window's tiles and block deltas for the planned int16 kernels.
 constexpr int kPlanWin = 4096;
+constexpr int kPlanThreads = 1024;   // threads of a planning workgroup
 struct PlanArgs {
   const ta_block* blocks;
   int64_t nblocks;
   const AxisDev* axes;    // kAxisIds x kAxisSizes
   BatchTile* tiles;       // kXcds lists of `cap` tiles (list x from x * cap)
-  int32_t* deltas;        // (in_delta, out_delta) by window and sorted position
+  int32_t* deltas;        // (in_delta, out_delta) by window and grouped position
   int32_t* count;         // tiles written to each list (zero before the launch)
   int64_t cap;
 };
