@@ -377,6 +377,12 @@ def _batched(ctx, ids, res):
     X = [torch.from_numpy(frames).cuda() for _ in range(4)]
     Y = [torch.empty_like(X[0]) for _ in range(4)]
     Z = [torch.empty_like(X[0]) for _ in range(4)]
+    # the list planned on the device (planner kernel + planned kernel), timed
+    # first so that the planned kernels' last launches in a trace are the plan's
+    dev = ctx.blocks_to_device(desc)
+    wsb = ctx.transform_workspace(len(desc))
+    df = _events_mean(lambda i: ctx.transform_fwd_ws(dev, X[i % 4], Y[i % 4], wsb), 12, warm=6)
+    di = _events_mean(lambda i: ctx.transform_inv_ws(dev, Y[i % 4], Z[i % 4], wsb), 12, warm=6)
     info = plan.autotune(X[0], Y[0], reps=3)
     nco = int((rows[:, 3].astype(np.int64) * rows[:, 4]).sum())
     # (the first launches after a change of kernel run slower while the
@@ -384,13 +390,8 @@ def _batched(ctx, ids, res):
     tf = _events_mean(lambda i: plan.fwd(X[i % 4], Y[i % 4]), 12, warm=6)
     ti = _events_mean(lambda i: plan.inv(Y[i % 4], Z[i % 4]), 12, warm=6)
     # the same list unplanned: descriptors in device memory, in frame order
-    dev = ctx.blocks_to_device(desc)
     uf = _events_mean(lambda i: ctx.transform_fwd(dev, X[i % 4], Y[i % 4]), 12)
     ui = _events_mean(lambda i: ctx.transform_inv(dev, Y[i % 4], Z[i % 4]), 12)
-    # the same list planned on the device (planner kernel + planned kernel)
-    wsb = ctx.transform_workspace(len(desc))
-    df = _events_mean(lambda i: ctx.transform_fwd_ws(dev, X[i % 4], Y[i % 4], wsb), 12, warm=6)
-    di = _events_mean(lambda i: ctx.transform_inv_ws(dev, Y[i % 4], Z[i % 4], wsb), 12, warm=6)
     res["batched_uneven"] = {"value": nco / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
                              "blocks": len(rows), "coefficients": nco, "tiles": info["tiles"], "grid": info["grid"],
                              "region_log2": info["region_log2"], "tile_blocks": _tile_blocks(plan),
