@@ -413,12 +413,18 @@ def _batched(ctx, ids, res):
     ti = _events_mean(lambda i: planf.inv(Y[i % 4], Z[i % 4]), 12, warm=6)
     uf = _events_mean(lambda i: ctx.transform_fwd(dev, X[i % 4], Y[i % 4]), 12)
     ui = _events_mean(lambda i: ctx.transform_inv(dev, Y[i % 4], Z[i % 4]), 12)
+    wsb = ctx.transform_workspace(len(desc))
+    df = _events_mean(lambda i: ctx.transform_fwd_ws(dev, X[i % 4], Y[i % 4], wsb), 12, warm=6)
+    di = _events_mean(lambda i: ctx.transform_inv_ws(dev, Y[i % 4], Z[i % 4], wsb), 12, warm=6)
+    del wsb
     res["batched_uneven_f32"] = {"value": nco / (tf + ti), "unit": "coef/s", "fwd_us": tf * 1e6, "inv_us": ti * 1e6,
                                  "tiles": infof["tiles"], "grid": infof["grid"], "region_log2": infof["region_log2"],
                                  "tile_blocks": _tile_blocks(planf),
                                  "GB/s_fwd": (8 * nco + 32 * len(rows)) / tf / 1e9,
                                  "unplanned_value": nco / (uf + ui), "unplanned_fwd_us": uf * 1e6,
-                                 "unplanned_inv_us": ui * 1e6}
+                                 "unplanned_inv_us": ui * 1e6,
+                                 "device_planned_value": nco / (df + di), "device_planned_fwd_us": df * 1e6,
+                                 "device_planned_inv_us": di * 1e6}
     del X, Y, Z, planf, dev
     torch.cuda.empty_cache()
 

@@ -307,20 +307,20 @@ int ta_transform_inv(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, c
  * take the same arguments and rules as ta_transform_fwd / _inv plus a
  * workspace in device memory (256-byte aligned, at least the size that
  * ta_transform_workspace gives for nblocks; the caller owns it; its contents
- * need no initialisation and are scratch after the call).  For int16 at m = 8
- * a first kernel plans the list: windows of 4096 consecutive descriptors are
- * grouped by configuration (size and axis ids) and cut into tiles of equal
- * configuration and row strides, which the pipelined planned kernels then
- * run in one launch.  The tiles are larger than the in-window
- * groups of ta_transform_fwd, so throughput is closer to a plan's.  One more
- * rule applies here: a block whose rows span more than 2^30 input or 2^31
- * output elements ((h - 1) * stride + w) is skipped.  fp32 lists and
- * contexts with m != 8 run exactly as ta_transform_fwd / _inv (the workspace
+ * need no initialisation and are scratch after the call).  At m = 8 a first
+ * kernel plans the list: windows of 4096 consecutive descriptors are grouped
+ * by configuration (size and axis ids) and cut into tiles of equal
+ * configuration and row strides, which the planned kernels (int16 or fp32)
+ * then run in one launch.  The tiles are larger than the in-window groups of
+ * ta_transform_fwd, so throughput is closer to a plan's.  One more rule
+ * applies to int16 lists here: a block whose rows span more than 2^30 input
+ * or 2^31 output elements ((h - 1) * stride + w) is skipped.  Contexts with
+ * m != 8 run exactly as ta_transform_fwd / _inv (the workspace
  * is not used).  Asynchronous on the stream, allocates nothing, capturable
  * in a HIP graph; two calls that share a workspace must not run at the same
  * time.  Errors: those of ta_transform_fwd, and TA_EINVAL for a missing,
  * misaligned or short workspace.  ta_transform_workspace: bytes of workspace
- * for nblocks descriptors (about 8 + 80 bytes a descriptor; 0 for none);
+ * for nblocks descriptors (about 32 + 80 bytes a descriptor; 0 for none);
  * TA_EINVAL for a null pointer or a negative count. */
 int ta_transform_workspace(int64_t nblocks, int64_t* bytes);
 int ta_transform_fwd_ws(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out,

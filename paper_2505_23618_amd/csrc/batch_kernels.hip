@@ -1069,7 +1069,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void b
   __shared__ BDesc desc[kMaxTileBlocks];
   const int xcd = blockIdx.x % kXcds;
   const int64_t per_xcd = (gridDim.x + kXcds - 1 - xcd) / kXcds;
-  const int64_t end = a.xstart[xcd + 1];
+  const int64_t end = a.xcount ? a.xstart[xcd] + a.xcount[xcd] : a.xstart[xcd + 1];
   for (int64_t ti = a.xstart[xcd] + blockIdx.x / kXcds; ti < end; ti += per_xcd) {
     const BatchTile t = a.tiles[ti];
     if (INV)
@@ -1240,15 +1240,20 @@ TA_DEV int scan_excl(int v, int* wsum, int tid, int* total) {
   return MAX ? max(pre, exc) : pre + exc;
 }
 
-// the rules of the fast int16 kernels plus the row spans the deltas can hold
+// the rules of the fast kernels, plus (int16) the row spans the deltas can hold
+template <bool F32>
 TA_DEV int plan_key(const AxisDev* axes, const ta_block& d) {
   const int k = config_key(axes, d);
-  if (k < 0) return -1;
+  if (k < 0 || F32) return k;
   const int64_t w = int64_t(1) << d.log2w, hm1 = (int64_t(1) << d.log2h) - 1;
   if (hm1 * d.in_stride + w > kSpanIn || hm1 * d.out_stride + w > kSpanOut) return -1;
   return k;
 }
 
+// (fp32: the tiles are those of batch_f32, which reads each block's
+// descriptor; the window's descriptors are written in grouped order instead
+// of deltas, and the span fallback does not apply)
+template <bool F32>
 __global__ __launch_bounds__(kPlanThreads) void desc_plan(PlanArgs a) {
   constexpr int kWaves = kPlanThreads / 64;
   constexpr uint32_t kEmpty = ~0u;     // above every configuration key (22 bits)
@@ -1288,7 +1293,7 @@ __global__ __launch_bounds__(kPlanThreads) void desc_plan(PlanArgs a) {
       const int i = tid + kPlanThreads * r;
       slot_rank[r] = kEmpty;
       if (i < cnt) {
-        const int c = plan_key(a.axes, d[r]);
+        const int c = plan_key<F32>(a.axes, d[r]);
         if (c >= 0) {
           uint32_t sl = ((uint32_t)c * 0x9E3779B1u) >> (32 - 12);
           for (;;) {
@@ -1353,7 +1358,7 @@ __global__ __launch_bounds__(kPlanThreads) void desc_plan(PlanArgs a) {
     wmin_o = min(wmin_o, red[v][2]);
     wmax_o = max(wmax_o, red[v][3]);
   }
-  const bool own = nvalid > 0 && (wmax_i - wmin_i > kSpanIn || wmax_o - wmin_o > kSpanOut);
+  const bool own = !F32 && nvalid > 0 && (wmax_i - wmin_i > kSpanIn || wmax_o - wmin_o > kSpanOut);
   // 3. this thread's consecutive grouped entries [e0, e0 + kPlanPer): their
   //    descriptors (and the one before the first), run starts
   const int e0 = tid * kPlanPer;
@@ -1388,7 +1393,8 @@ __global__ __launch_bounds__(kPlanThreads) void desc_plan(PlanArgs a) {
     const int i = e0 + e;
     if (i < nvalid) {
       if (starts & (1u << e)) run0 = i;
-      const int cap = BatchGeo::nb_planned(d[e + 1].log2w, d[e + 1].log2h);
+      const int cap = F32 ? BatchGeoF32::nb_for(d[e + 1].log2w, d[e + 1].log2h)
+                          : BatchGeo::nb_planned(d[e + 1].log2w, d[e + 1].log2h);
       if ((i - run0) % cap == 0) {
         cuts |= 1u << e;
         ++ncut;
@@ -1418,8 +1424,12 @@ __global__ __launch_bounds__(kPlanThreads) void desc_plan(PlanArgs a) {
     if (i >= nvalid) continue;
     const ta_block& b = d[e + 1];
     const int64_t ib = own ? b.in_off : wmin_i, ob = own ? b.out_off : wmin_o;
-    a.deltas[2 * (w0 + i)] = (int32_t)(b.in_off - ib);
-    a.deltas[2 * (w0 + i) + 1] = (int32_t)(b.out_off - ob);
+    if (F32) {
+      a.grouped[w0 + i] = b;
+    } else {
+      a.deltas[2 * (w0 + i)] = (int32_t)(b.in_off - ib);
+      a.deltas[2 * (w0 + i) + 1] = (int32_t)(b.out_off - ob);
+    }
     if (cuts & (1u << e)) {
       ++tile;
       const int lw = b.log2w, lh = b.log2h;
@@ -1433,10 +1443,17 @@ __global__ __launch_bounds__(kPlanThreads) void desc_plan(PlanArgs a) {
       t.first = w0 + i;
       t.count = sc[tile + 1] - i;
       t.in_stride = b.in_stride;
-      t.ph_f = h.pf;
-      t.ph_i = h.pi;
-      t.pv_f = v.pf;
-      t.pv_i = v.pi;
+      if (F32) {
+        t.ph_f = reinterpret_cast<const uint32_t*>(h.ff);
+        t.ph_i = reinterpret_cast<const uint32_t*>(h.fi);
+        t.pv_f = reinterpret_cast<const uint32_t*>(v.ff);
+        t.pv_i = reinterpret_cast<const uint32_t*>(v.fi);
+      } else {
+        t.ph_f = h.pf;
+        t.ph_i = h.pi;
+        t.pv_f = v.pf;
+        t.pv_i = v.pi;
+      }
       t.in_base = ib;
       t.out_base = ob;
       t.out_stride = b.out_stride;
@@ -1462,7 +1479,9 @@ const void* batch_kernel(int inv, int desc, int f32) {
   return inv ? reinterpret_cast<const void*>(&batch_inv) : reinterpret_cast<const void*>(&batch_fwd);
 }
 
-const void* desc_plan_kernel() { return reinterpret_cast<const void*>(&desc_plan); }
+const void* desc_plan_kernel(int f32) {
+  return f32 ? reinterpret_cast<const void*>(&desc_plan<true>) : reinterpret_cast<const void*>(&desc_plan<false>);
+}
 const void* zero_words_kernel() { return reinterpret_cast<const void*>(&zero_words); }
 
 }  // namespace ta

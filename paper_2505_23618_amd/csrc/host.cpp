@@ -1428,7 +1428,8 @@ int run_blocks(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void
 }
 
 // Workspace of a device-planned block list: tile counters per XCD list, the
-// consumer's schedule counters, block deltas, then kXcds tile lists of `cap`
+// consumer's schedule counters, per-block data (int16: deltas, 8 bytes;
+// fp32: the grouped descriptors, 32 bytes), then kXcds tile lists of `cap`
 // tiles (a window's tiles go to one list; a list holds every tile its
 // windows can produce).
 struct WsLayout {
@@ -1441,7 +1442,7 @@ WsLayout ws_layout(int64_t n) {
   auto up = [](int64_t v) { return (v + 255) & ~int64_t(255); };
   L.sched_off = 256;
   L.deltas_off = up(L.sched_off + 4 * ta::kSchedDwords);
-  L.tiles_off = up(L.deltas_off + 8 * n);
+  L.tiles_off = up(L.deltas_off + (int64_t)sizeof(ta_block) * n);
   L.bytes = L.tiles_off + (int64_t)sizeof(ta::BatchTile) * ta::kXcds * L.cap;
   return L;
 }
@@ -1452,8 +1453,9 @@ int run_blocks_ws(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const v
   if (n < 0) return fail(TA_EINVAL, "negative block count");
   if (dtype != TA_I16 && dtype != TA_F32) return fail(TA_EINVAL, "unknown dtype %d", dtype);
   if (n == 0) return TA_OK;
-  // fp32, and m != 8 (no fast kinds), run as the unplanned lists do
-  if (dtype == TA_F32 || c->m != 8) return run_blocks(c, inv, blocks, n, in, out, dtype, stream);
+  // with m != 8 no axis has a fast kind: as the unplanned lists (all general)
+  if (c->m != 8) return run_blocks(c, inv, blocks, n, in, out, dtype, stream);
+  const bool f32 = dtype == TA_F32;
   if (!blocks || !in || !out) return fail(TA_EINVAL, "null buffer");
   if (in == out) return fail(TA_EINVAL, "input and output alias");
   if ((uintptr_t)blocks & 7) return fail(TA_EINVAL, "descriptors must be 8-byte aligned");
@@ -1479,24 +1481,30 @@ int run_blocks_ws(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const v
   pa.axes = c->axes_dev;
   pa.tiles = reinterpret_cast<ta::BatchTile*>(w + L.tiles_off);
   pa.deltas = reinterpret_cast<int32_t*>(w + L.deltas_off);
+  pa.grouped = reinterpret_cast<ta_block*>(w + L.deltas_off);
   pa.count = counts;
   pa.cap = L.cap;
   void* pargs[] = {&pa};
   const int64_t nwin = (n + ta::kPlanWin - 1) / ta::kPlanWin;
   if (nwin > INT32_MAX) return fail(TA_EUNSUPPORTED, "block list too long");
-  TA_HIP(hipLaunchKernel(ta::desc_plan_kernel(), dim3((unsigned)nwin), dim3(ta::kPlanThreads), pargs, 0, s));
-  // the planned kernel over the lists, one resident grid taking tiles from
-  // the schedule counters
-  const void* fn = ta::batch_kernel(inv, 0, 0);
+  TA_HIP(hipLaunchKernel(ta::desc_plan_kernel(f32), dim3((unsigned)nwin), dim3(ta::kPlanThreads), pargs, 0, s));
+  // the planned kernel over the lists: int16, one resident grid taking tiles
+  // from the schedule counters; fp32 (its kernel has a static stride), 8,192
+  // workgroups
+  const void* fn = ta::batch_kernel(inv, 0, f32);
   int res = 0, e;
-  if ((e = resident_groups(fn, 256, c->device, &res))) return e;
+  if (f32)
+    res = 8192;
+  else if ((e = resident_groups(fn, 256, c->device, &res)))
+    return e;
   ta::BatchArgs args{};
   args.tiles = pa.tiles;
   args.ntiles = ta::kXcds * L.cap;
   for (int x = 0; x <= ta::kXcds; ++x) args.xstart[x] = x * L.cap;
   args.xcount = counts;
   args.deltas = pa.deltas;
-  args.sched = sched;
+  args.blocks = pa.grouped;
+  args.sched = f32 ? nullptr : sched;
   args.in = static_cast<const int16_t*>(in);
   args.out = static_cast<int16_t*>(out);
   args.bd = c->bd;
@@ -1519,10 +1527,10 @@ int run_blocks_ws(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const v
     ga.m = c->m;
     ga.a = c->a;
     ga.nblocks = n;
-    ga.progs = c->gprogs_dev[0];
+    ga.progs = c->gprogs_dev[f32];
     ga.fast = c->axes_dev;
     void* gargs[] = {&ga};
-    TA_HIP(hipLaunchKernel(ta::gen_kernel(1, 0), dim3((unsigned)g), dim3(256), gargs, 0, s));
+    TA_HIP(hipLaunchKernel(ta::gen_kernel(1, f32), dim3((unsigned)g), dim3(256), gargs, 0, s));
   }
   return TA_OK;
 }

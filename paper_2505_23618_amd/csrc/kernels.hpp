@@ -195,11 +195,12 @@ struct PlanArgs {
   int64_t nblocks;
   const AxisDev* axes;    // kAxisIds x kAxisSizes
   BatchTile* tiles;       // kXcds lists of `cap` tiles (list x from x * cap)
-  int32_t* deltas;        // (in_delta, out_delta) by window and grouped position
+  int32_t* deltas;        // int16: (in_delta, out_delta) by window and grouped position
+  ta_block* grouped;      // fp32: the descriptors by window and grouped position
   int32_t* count;         // tiles written to each list (zero before the launch)
   int64_t cap;
 };
-const void* desc_plan_kernel();
+const void* desc_plan_kernel(int f32);
 // zeroes n dwords (one workgroup; the counters of a device-planned call)
 const void* zero_words_kernel();
 

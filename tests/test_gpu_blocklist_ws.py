@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.batchcase import descriptors, oracle_frames, register_axes
+from tests.batchcase import block_rel_errors, descriptors, oracle_frames, oracle_frames_fp, register_axes
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -221,3 +221,33 @@ def test_full_workload_equals_plan_and_oracle(env):
     for i in sel:
         f, bx, by, w, h = (int(v) for v in rows[i, :5])
         assert (yc[f, by:by + h, bx:bx + w] == ref[f, by:by + h, bx:bx + w]).all(), f"block {i}"
+
+
+@pytest.mark.parametrize("workload", ["small", "full"])
+def test_fp32_device_planned_equals_plan_and_oracle(env, workload):
+    """fp32 lists: the device-planned tiles run batch_f32 like a host plan's,
+    so the outputs are bitwise equal to the plan's; the small case is also
+    checked against the FP64 oracle (per block, 1e-5 of the block's largest
+    reference value)."""
+    ctx, _, params = env
+    frames, rows = small_workload() if workload == "small" else synth.frames_workload()
+    print(f"fp32 device-planned, {len(rows)} blocks", flush=True)
+    d = descriptors(rows, frames.shape[1], frames.shape[2])
+    dev = ctx.blocks_to_device(d)
+    ws = ctx.transform_workspace(len(d))
+    x = torch.from_numpy(frames.astype(np.float32)).cuda()
+    y, z = torch.zeros_like(x), torch.zeros_like(x)
+    ctx.transform_fwd_ws(dev, x, y, ws)
+    ctx.transform_inv_ws(dev, y, z, ws)
+    plan = ta.Plan(ctx, d, dtype=ta.F32)
+    yp, zp = torch.zeros_like(x), torch.zeros_like(x)
+    plan.fwd(x, yp)
+    plan.inv(yp, zp)
+    torch.cuda.synchronize()
+    assert torch.equal(y, yp) and torch.equal(z, zp)
+    if workload == "small":
+        yc = y.cpu().numpy()
+        err = block_rel_errors(yc, oracle_frames_fp(frames.astype(np.float32), rows, params), rows)
+        assert err.max() <= 1e-5, f"forward: worst block {err.argmax()} rel err {err.max():.3e}"
+        err = block_rel_errors(z.cpu().numpy(), oracle_frames_fp(yc, rows, params, inverse=True), rows)
+        assert err.max() <= 1e-5, f"inverse: worst block {err.argmax()} rel err {err.max():.3e}"
