@@ -320,7 +320,7 @@ int ta_transform_inv(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, c
  * in a HIP graph; two calls that share a workspace must not run at the same
  * time.  Errors: those of ta_transform_fwd, and TA_EINVAL for a missing,
  * misaligned or short workspace.  ta_transform_workspace: bytes of workspace
- * for nblocks descriptors (about 32 + 80 bytes a descriptor; 0 for none);
+ * for nblocks descriptors (about 8 + 80 bytes a descriptor; 0 for none);
  * TA_EINVAL for a null pointer or a negative count. */
 int ta_transform_workspace(int64_t nblocks, int64_t* bytes);
 int ta_transform_fwd_ws(ta_ctx* ctx, const ta_block* blocks_dev, int64_t nblocks, const void* in, void* out,

@@ -890,13 +890,19 @@ TA_DEV void load_rowf(const float* __restrict__ src, fp::Vec<W>& x) {
   }
 }
 
+// descriptor of block b of an fp32 tile: entry first + b of the list, or of
+// the list's index when one is given (device-planned lists)
+TA_DEV ta_block tile_block_f(const BatchArgs& a, const ta_block* blocks, const BatchTile& t, int b) {
+  return a.order ? blocks[a.order[t.first + b]] : blocks[t.first + b];
+}
+
 // forward row phase: global row -> transform -> column-major LDS
 template <int W, class KH>
 TA_DEV void fwd_rows_f(const BatchArgs& a, const BatchTile& t, const ta_block* blocks, float* lds, BDesc* desc) {
   const int tid = threadIdx.x;
   if (tid >= (t.count << t.lh)) return;
   const int b = tid >> t.lh, r = tid & ((1 << t.lh) - 1), h1 = (1 << t.lh) + 1;
-  const ta_block d = blocks[t.first + b];
+  const ta_block d = tile_block_f(a, blocks, t, b);
   if (r == 0) desc[b] = BDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
   fp::Vec<W> x;
   load_rowf<W>(reinterpret_cast<const float*>(a.in) + d.in_off + (int64_t)r * d.in_stride, x);
@@ -1016,7 +1022,7 @@ TA_DEV void fwd_tile_f(const BatchArgs& a, const BatchTile& t, const ta_block* b
 // a barrier.
 TA_DEV void inv_tile_f(const BatchArgs& a, const BatchTile& t, const ta_block* blocks, float* lds, BDesc* desc) {
   if ((int)threadIdx.x < t.count) {
-    const ta_block d = blocks[t.first + threadIdx.x];
+    const ta_block d = tile_block_f(a, blocks, t, (int)threadIdx.x);
     desc[threadIdx.x] = BDesc{d.in_off, d.out_off, d.in_stride, d.out_stride};
   }
   __syncthreads();
@@ -1251,8 +1257,8 @@ TA_DEV int plan_key(const AxisDev* axes, const ta_block& d) {
 }
 
 // (fp32: the tiles are those of batch_f32, which reads each block's
-// descriptor; the window's descriptors are written in grouped order instead
-// of deltas, and the span fallback does not apply)
+// descriptor; the list indices of the window's blocks are written in grouped
+// order instead of deltas, and the span fallback does not apply)
 template <bool F32>
 __global__ __launch_bounds__(kPlanThreads) void desc_plan(PlanArgs a) {
   constexpr int kWaves = kPlanThreads / 64;
@@ -1425,7 +1431,7 @@ __global__ __launch_bounds__(kPlanThreads) void desc_plan(PlanArgs a) {
     const ta_block& b = d[e + 1];
     const int64_t ib = own ? b.in_off : wmin_i, ob = own ? b.out_off : wmin_o;
     if (F32) {
-      a.grouped[w0 + i] = b;
+      a.index[w0 + i] = (int32_t)(w0 + order[i]);
     } else {
       a.deltas[2 * (w0 + i)] = (int32_t)(b.in_off - ib);
       a.deltas[2 * (w0 + i) + 1] = (int32_t)(b.out_off - ob);

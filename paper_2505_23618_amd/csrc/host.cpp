@@ -1428,8 +1428,8 @@ int run_blocks(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const void
 }
 
 // Workspace of a device-planned block list: tile counters per XCD list, the
-// consumer's schedule counters, per-block data (int16: deltas, 8 bytes;
-// fp32: the grouped descriptors, 32 bytes), then kXcds tile lists of `cap`
+// consumer's schedule counters, per-block data (int16: deltas; fp32: list
+// indices in grouped order; 8 bytes), then kXcds tile lists of `cap`
 // tiles (a window's tiles go to one list; a list holds every tile its
 // windows can produce).
 struct WsLayout {
@@ -1442,7 +1442,7 @@ WsLayout ws_layout(int64_t n) {
   auto up = [](int64_t v) { return (v + 255) & ~int64_t(255); };
   L.sched_off = 256;
   L.deltas_off = up(L.sched_off + 4 * ta::kSchedDwords);
-  L.tiles_off = up(L.deltas_off + (int64_t)sizeof(ta_block) * n);
+  L.tiles_off = up(L.deltas_off + 8 * n);
   L.bytes = L.tiles_off + (int64_t)sizeof(ta::BatchTile) * ta::kXcds * L.cap;
   return L;
 }
@@ -1481,7 +1481,7 @@ int run_blocks_ws(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const v
   pa.axes = c->axes_dev;
   pa.tiles = reinterpret_cast<ta::BatchTile*>(w + L.tiles_off);
   pa.deltas = reinterpret_cast<int32_t*>(w + L.deltas_off);
-  pa.grouped = reinterpret_cast<ta_block*>(w + L.deltas_off);
+  pa.index = reinterpret_cast<int32_t*>(w + L.deltas_off);
   pa.count = counts;
   pa.cap = L.cap;
   void* pargs[] = {&pa};
@@ -1503,7 +1503,8 @@ int run_blocks_ws(ta_ctx* c, int inv, const ta_block* blocks, int64_t n, const v
   for (int x = 0; x <= ta::kXcds; ++x) args.xstart[x] = x * L.cap;
   args.xcount = counts;
   args.deltas = pa.deltas;
-  args.blocks = pa.grouped;
+  args.blocks = blocks;
+  args.order = f32 ? pa.index : nullptr;
   args.sched = f32 ? nullptr : sched;
   args.in = static_cast<const int16_t*>(in);
   args.out = static_cast<int16_t*>(out);

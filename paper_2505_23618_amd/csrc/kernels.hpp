@@ -167,6 +167,9 @@ struct BatchArgs {
   // planned int16: tiles per XCD list in device memory (list x is
   // tiles[xstart[x] .. xstart[x] + xcount[x])), or null for xstart[x + 1]
   const int32_t* xcount;
+  // planned fp32: block b of a tile is blocks[order[first + b]], or null for
+  // blocks[first + b]
+  const int32_t* order;
   // planned int16: the tile counters of the dynamic schedule (one per XCD
   // list, then the count of finished workgroups, kSchedPitch dwords apart;
   // zero between launches), or null for a static grid stride
@@ -196,7 +199,7 @@ struct PlanArgs {
   const AxisDev* axes;    // kAxisIds x kAxisSizes
   BatchTile* tiles;       // kXcds lists of `cap` tiles (list x from x * cap)
   int32_t* deltas;        // int16: (in_delta, out_delta) by window and grouped position
-  ta_block* grouped;      // fp32: the descriptors by window and grouped position
+  int32_t* index;         // fp32: list index of each block, by window and grouped position
   int32_t* count;         // tiles written to each list (zero before the launch)
   int64_t cap;
 };

@@ -96,8 +96,8 @@ def test_block_list_entry_points_reject_bad_arguments_without_gpu():
     for n in (1, 4096, 4097, 582094):
         assert lib.ta_transform_workspace(n, ctypes.byref(ws)) == ta.TA_OK
         sizes.append(ws.value)
-    # 32 bytes of per-block data and at least one 80-byte tile slot per block
-    assert all(s >= 112 * n for s, n in zip(sizes, (1, 4096, 4097, 582094))) and sizes == sorted(sizes)
+    # 8 bytes of per-block data and at least one 80-byte tile slot per block
+    assert all(s >= 88 * n for s, n in zip(sizes, (1, 4096, 4097, 582094))) and sizes == sorted(sizes)
     lay = np.array([ta.ADJ_BAND, 8, 4], np.int32)
     a = np.zeros(64, np.int16)
     f = np.zeros(64, np.float32)
