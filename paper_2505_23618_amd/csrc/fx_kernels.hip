@@ -163,8 +163,12 @@ __global__ __launch_bounds__(256) void fx_fwd(PackedArgs p) {
   }
 }
 
+// The inverse holds more live values than the forward (84 VGPRs at the
+// compiler's choice, five waves per SIMD); asking for six waves fits the
+// 32-point kernels in 80 without spills, about 1.4 % faster in interleaved
+// timing.  Larger instantiations keep what they need.
 template <int LW, int LH, class AH, class AV>
-__global__ __launch_bounds__(256) void fx_inv(PackedArgs p) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void fx_inv(PackedArgs p) {
   using T = Tile<LW, LH>;
   constexpr int W = T::W, H = T::H, NB = T::NB;
   __shared__ __align__(16) uint32_t lds[T::LDS_I];
