@@ -887,7 +887,7 @@ int launch_plan(ta_ctx* c, ta_plan* p, int inv, const void* in, void* out, ta_st
   // balances the load by itself).
   const void* fn = ta::batch_kernel(inv, 0, p->dtype == TA_F32);
   args.sched = nullptr;
-  if (p->dtype == TA_I16) {
+  if (p->dtype == TA_I16 && p->sched_dev) {
     int res = 0, e;
     if ((e = resident_groups(fn, 256, c->device, &res))) return e;
     if (g <= res) args.sched = p->sched_dev + (inv ? ta_plan::kSchedStride : 0);
